@@ -1,0 +1,511 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each check is a closed form, an invariant, a
+special case that reduces to a textbook or library routine, finite differences, or a plain-loop /
+dense-matrix brute force written separately (``oracle.loops``).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import loops
+from oracle import rgp
+
+ALPHA, BETA = 300.0, 1e-4
+
+
+def _tiny(seed=0, shape=(3, 4, 5), hc=(1.1, 0.9, 1.3), base=0.3, amp=0.05):
+    """Tiny column-form problem whose sample positions stay away from knots."""
+    rng = np.random.default_rng(seed)
+    na, nb, m = shape
+    Ip = rng.uniform(0.2, 1.0, shape)
+    Im = rng.uniform(0.2, 1.0, shape)
+    b = base * hc[2] + amp * rng.standard_normal((na, nb, m + 1))
+    return Ip, Im, b, hc
+
+
+def _knot_distance(b, hc):
+    Ab = rgp.avg(b)
+    m = Ab.shape[-1]
+    j = np.arange(m)
+    xi = np.concatenate([j + Ab / hc[2], j - Ab / hc[2]])
+    return float(np.min(np.abs(xi - np.round(xi))))
+
+
+# ------------------------------------------------------------------------------------------
+# Zero field is the identity (Eq. 1 with b = 0)
+# ------------------------------------------------------------------------------------------
+
+def test_zero_field_is_identity():
+    rng = np.random.default_rng(1)
+    Ip = rng.uniform(-0.1, 1.0, (5, 6, 7))
+    Im = rng.uniform(-0.1, 1.0, (5, 6, 7))
+    for pe in range(3):
+        nshape = list(Ip.shape)
+        nshape[pe] += 1
+        b = np.zeros(nshape)
+        h = (1.0, 1.5, 0.75)
+        Tp = rgp.transform(Ip, b, pe, h, +1.0)
+        Tm = rgp.transform(Im, b, pe, h, -1.0)
+        assert np.array_equal(Tp, Ip) and np.array_equal(Tm, Im)
+        o = rgp.objective(Ip, Im, b, pe, h)
+        vol = h[0] * h[1] * h[2]
+        assert o.S == 0.0 and o.P == 0.0
+        assert o.D == pytest.approx(0.5 * vol * np.sum((Ip - Im) ** 2), rel=1e-14)
+        res = rgp.solve(Ip, Im, pe, h, levels=1, gn_iters=0, b_init=b)
+        assert np.array_equal(res.T_plus, Ip) and np.array_equal(res.T_minus, Im)
+
+
+# ------------------------------------------------------------------------------------------
+# Mass conservation of the modulated transform (Eq. 1)
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("c", [2.0, -3.0, 1.37, -0.61])
+def test_mass_constant_shift(c):
+    rng = np.random.default_rng(2)
+    m = 40
+    I = np.zeros((3, 4, m))
+    I[..., 8:30] = rng.uniform(0.1, 1.0, (3, 4, 22))  # support >= |c| + 1 cells from both ends
+    b = np.full((3, 4, m + 1), c)
+    T, _, _, _ = rgp.transform_cols(I, b, 1.0, +1.0)
+    np.testing.assert_allclose(T.sum(axis=-1), I.sum(axis=-1), rtol=1e-14)
+    T, _, _, _ = rgp.transform_cols(I, b, 1.0, -1.0)
+    np.testing.assert_allclose(T.sum(axis=-1), I.sum(axis=-1), rtol=1e-14)
+
+
+def test_mass_smooth_field_second_order():
+    """h sum_j T_j -> int_0^L I(y) dy at O(h^2) for a smooth field vanishing at both ends.
+
+    Change of variables y = x + b(x) makes the continuous corrected mass equal to the mass of
+    I over [b(0), L + b(L)] = [0, L].  The linear-interpolation error oscillates with the
+    sub-cell sample position, so the pin is an h^2 error bound over six refinements rather than a
+    fixed ratio; dropping the (1 + D b) modulation gives an O(1) error and fails it.
+    """
+    L = 10.0
+
+    def err(m, mu, sig, amp, modulate=True):
+        h = L / m
+        xc = (np.arange(m) + 0.5) * h
+        xn = np.arange(m + 1) * h
+        I = np.exp(-((xc - mu) ** 2) / (2 * sig * sig))[None, None, :]
+        b = (amp * np.sin(np.pi * xn / L) + 0.3 * np.sin(2 * np.pi * xn / L))[None, None, :]
+        T, val, _, _ = rgp.transform_cols(I, b, h, +1.0)
+        if not modulate:
+            T = val
+        ex = sig * math.sqrt(math.pi / 2) * (math.erf((L - mu) / (sig * math.sqrt(2)))
+                                             - math.erf(-mu / (sig * math.sqrt(2))))
+        return abs(h * T.sum() - ex) / ex
+
+    for mu, sig, amp in [(4.7, 0.9, 0.8), (5.0, 1.2, 0.8), (5.0, 0.8, 1.0)]:
+        ms = [40, 80, 160, 320, 640, 1280]
+        es = [err(m, mu, sig, amp) for m in ms]
+        scaled = [e * m * m for m, e in zip(ms, es)]   # bounded iff the error is O(h^2)
+        assert max(scaled[3:]) <= max(scaled[:3])
+        assert es[-1] < 1e-5
+        assert err(320, mu, sig, amp, modulate=False) > 1e-2
+
+
+# ------------------------------------------------------------------------------------------
+# Symmetry J(b; I+, I-) = J(-b; I-, I+)
+# ------------------------------------------------------------------------------------------
+
+def test_polarity_swap_symmetry_exact():
+    Ip, Im, b, hc = _tiny(3, shape=(4, 5, 9), base=0.7, amp=0.2)
+    o1, g1, _ = rgp.objective_gradient_cols(Ip, Im, b, hc)
+    o2, g2, _ = rgp.objective_gradient_cols(Im, Ip, -b, hc)
+    assert o1.J == o2.J and o1.D == o2.D and o1.S == o2.S and o1.P == o2.P
+    assert np.array_equal(g2, -g1)
+
+
+# ------------------------------------------------------------------------------------------
+# Smoothness term (Eq. 5) and the Laplacian
+# ------------------------------------------------------------------------------------------
+
+def test_laplacian_closed_forms():
+    rng = np.random.default_rng(4)
+    hc = (1.2, 0.8, 1.7)
+    shape = (3, 4, 6)
+    b = rng.standard_normal(shape)
+    # b^T L b equals the plain sum of squared neighbour differences
+    sq = 0.0
+    for ia in range(shape[0]):
+        for ib in range(shape[1]):
+            for k in range(shape[2]):
+                if ia + 1 < shape[0]:
+                    sq += (b[ia + 1, ib, k] - b[ia, ib, k]) ** 2 / hc[0] ** 2
+                if ib + 1 < shape[1]:
+                    sq += (b[ia, ib + 1, k] - b[ia, ib, k]) ** 2 / hc[1] ** 2
+                if k + 1 < shape[2]:
+                    sq += (b[ia, ib, k + 1] - b[ia, ib, k]) ** 2 / hc[2] ** 2
+    assert float(np.sum(b * rgp.laplacian(b, hc))) == pytest.approx(sq, rel=1e-13)
+    assert rgp.smooth_sq(b, hc) == pytest.approx(sq, rel=1e-13)
+    # constants are in the kernel
+    assert np.max(np.abs(rgp.laplacian(np.full(shape, 3.5), hc))) < 1e-13
+    # dense matrix: symmetric, PSD, one-dimensional kernel, diagonal as stated
+    n = b.size
+    Lm = np.zeros((n, n))
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        Lm[:, i] = rgp.laplacian(e.reshape(shape), hc).ravel()
+    np.testing.assert_allclose(Lm, Lm.T, atol=1e-14)
+    ev = np.linalg.eigvalsh(Lm)
+    assert ev[0] > -1e-12 and abs(ev[0]) < 1e-12 and ev[1] > 1e-3
+    np.testing.assert_allclose(np.diag(Lm), rgp.laplacian_diag(shape, hc).ravel(), rtol=1e-14)
+    # directional derivative of S is exactly vol (L b) . v
+    v = rng.standard_normal(shape)
+    vol = hc[0] * hc[1] * hc[2]
+    eps = 1e-3
+    Sp = 0.5 * vol * rgp.smooth_sq(b + eps * v, hc)
+    Sm = 0.5 * vol * rgp.smooth_sq(b - eps * v, hc)
+    assert (Sp - Sm) / (2 * eps) == pytest.approx(vol * float(np.sum(rgp.laplacian(b, hc) * v)),
+                                                  rel=1e-10)
+
+
+# ------------------------------------------------------------------------------------------
+# Barrier phi (Eq. 3)
+# ------------------------------------------------------------------------------------------
+
+def test_phi_closed_forms():
+    z = np.linspace(-0.95, 0.95, 381)
+    np.testing.assert_allclose(rgp.phi(z), 1.0 / (1.0 - z * z) - 1.0 - z * z, atol=1e-12,
+                               rtol=1e-12)
+    assert np.all(rgp.phi(z) >= 0.0)
+    assert np.all(rgp.d2phi(z) >= 0.0)
+    assert np.all(np.isinf(rgp.phi(np.array([-1.0, 1.0, 1.5, -7.0]))))
+    zs = np.linspace(-0.1, 0.1, 41)
+    series = sum((4 + 2 * n) * (3 + 2 * n) * zs ** (2 + 2 * n) for n in range(12))
+    np.testing.assert_allclose(rgp.d2phi(zs), series, rtol=1e-14, atol=1e-300)
+    e = 1e-6
+    zz = np.linspace(-0.9, 0.9, 37)
+    np.testing.assert_allclose((rgp.phi(zz + e) - rgp.phi(zz - e)) / (2 * e), rgp.dphi(zz),
+                               rtol=1e-7, atol=1e-9)
+    np.testing.assert_allclose((rgp.dphi(zz + e) - rgp.dphi(zz - e)) / (2 * e), rgp.d2phi(zz),
+                               rtol=1e-7, atol=1e-9)
+
+
+# ------------------------------------------------------------------------------------------
+# Gradient, residual Jacobian and GN operator
+# ------------------------------------------------------------------------------------------
+
+def test_gradient_matches_central_differences():
+    Ip, Im, b, hc = _tiny(5, shape=(4, 5, 8))
+    hfd = 1e-6
+    assert _knot_distance(b, hc) > 10 * hfd * 2
+    obj, g, _ = rgp.objective_gradient_cols(Ip, Im, b, hc, ALPHA, BETA)
+    rng = np.random.default_rng(50)
+    for _ in range(6):
+        v = rng.standard_normal(b.shape)
+        Jp = rgp.objective_cols(Ip, Im, b + hfd * v, hc, ALPHA, BETA).J
+        Jm = rgp.objective_cols(Ip, Im, b - hfd * v, hc, ALPHA, BETA).J
+        fd = (Jp - Jm) / (2 * hfd)
+        assert fd == pytest.approx(float(np.sum(g * v)), rel=1e-7)
+
+
+def test_residual_jacobian_fd_and_adjoint():
+    Ip, Im, b, hc = _tiny(6, shape=(3, 4, 7))
+    _, _, lin = rgp.objective_gradient_cols(Ip, Im, b, hc)
+    hp = hc[2]
+
+    def resid(bb):
+        Tp, _, _, _ = rgp.transform_cols(Ip, bb, hp, +1.0)
+        Tm, _, _, _ = rgp.transform_cols(Im, bb, hp, -1.0)
+        return Tp - Tm
+
+    rng = np.random.default_rng(60)
+    v = rng.standard_normal(b.shape)
+    e = 1e-6
+    fd = (resid(b + e * v) - resid(b - e * v)) / (2 * e)
+    Jv = lin.c1 * rgp.avg(v) + lin.c2 * rgp.dif(v, hp)
+    np.testing.assert_allclose(fd, Jv, rtol=1e-6, atol=1e-7 * np.max(np.abs(Jv)))
+    w = rng.standard_normal(lin.c1.shape)
+    JTw = rgp.avg_T(lin.c1 * w) + rgp.dif_T(lin.c2 * w, hp)
+    assert float(np.sum(Jv * w)) == pytest.approx(float(np.sum(v * JTw)), rel=1e-13)
+    # adjoints of the two PE operators on their own
+    u = rng.standard_normal(lin.c1.shape)
+    assert float(np.sum(rgp.avg(v) * u)) == pytest.approx(float(np.sum(v * rgp.avg_T(u))), rel=1e-13)
+    assert float(np.sum(rgp.dif(v, hp) * u)) == pytest.approx(
+        float(np.sum(v * rgp.dif_T(u, hp))), rel=1e-13)
+
+
+@pytest.mark.parametrize("seed", [7, 8])
+def test_loops_match_vectorised(seed):
+    Ip, Im, b, hc = _tiny(seed, shape=(3, 4, 5), base=0.9, amp=0.3)
+    o = rgp.objective_cols(Ip, Im, b, hc, ALPHA, BETA)
+    Jl, Dl, Sl, Pl = loops.objective(Ip, Im, b, hc, ALPHA, BETA)
+    assert o.J == pytest.approx(Jl, rel=1e-14)
+    assert o.D == pytest.approx(Dl, rel=1e-14)
+    assert o.S == pytest.approx(Sl, rel=1e-14)
+    assert o.P == pytest.approx(Pl, rel=1e-13)
+    _, g, lin = rgp.objective_gradient_cols(Ip, Im, b, hc, ALPHA, BETA)
+    gl = loops.gradient(Ip, Im, b, hc, ALPHA, BETA)
+    assert np.linalg.norm(g - gl) <= 1e-14 * np.linalg.norm(gl)
+    H = loops.gn_hessian(Ip, Im, b, hc, ALPHA, BETA)
+    v = np.random.default_rng(seed + 100).standard_normal(b.shape)
+    Hv = rgp.gn_matvec_cols(lin, v).ravel()
+    assert np.linalg.norm(Hv - H @ v.ravel()) <= 1e-13 * np.linalg.norm(H @ v.ravel())
+    d = rgp.gn_diag_cols(lin).ravel()
+    np.testing.assert_allclose(d, np.diag(H), rtol=1e-13)
+
+
+def test_gn_operator_dense_4x5x6_with_pe_first():
+    """Brute-force H_J on a 4x5x6 grid with the PE axis first in caller layout."""
+    rng = np.random.default_rng(9)
+    shape = (6, 4, 5)          # pe = 0: six cells along PE
+    pe = 0
+    h = (1.3, 0.9, 1.1)
+    Ip = rng.uniform(0.1, 1.0, shape)
+    Im = rng.uniform(0.1, 1.0, shape)
+    b = 0.4 + 0.1 * rng.standard_normal((7, 4, 5))
+    obj, g, lin = rgp.objective_gradient(Ip, Im, b, pe, h)
+    hc = rgp.col_spacing(h, pe)
+    Pc, Mc, bc = rgp.to_cols(Ip, pe), rgp.to_cols(Im, pe), rgp.to_cols(b, pe)
+    H = loops.gn_hessian(Pc, Mc, bc, hc, ALPHA, BETA)
+    v = rng.standard_normal(b.shape)
+    Hv = rgp.to_cols(rgp.gn_matvec(lin, v, pe), pe).ravel()
+    ref = H @ rgp.to_cols(v, pe).ravel()
+    assert np.linalg.norm(Hv - ref) <= 1e-12 * np.linalg.norm(ref)
+    np.testing.assert_allclose(rgp.to_cols(rgp.gn_diag(lin, pe), pe).ravel(), np.diag(H),
+                               rtol=1e-12)
+    gl = loops.gradient(Pc, Mc, bc, hc, ALPHA, BETA)
+    assert np.linalg.norm(rgp.to_cols(g, pe) - gl) <= 1e-13 * np.linalg.norm(gl)
+    # the GN operator is symmetric positive semi-definite
+    np.testing.assert_allclose(H, H.T, atol=1e-9 * np.max(np.abs(H)))
+    assert np.linalg.eigvalsh(H)[0] > -1e-9 * np.max(np.abs(H))
+
+
+def test_barrier_violation_is_infinite_value():
+    Ip, Im, b, hc = _tiny(10, shape=(2, 3, 6))
+    b = b.copy()
+    b[1, 2, 3] += 1.5 * hc[2]   # slope >= 1 somewhere
+    o = rgp.objective_cols(Ip, Im, b, hc)
+    assert math.isinf(o.J) and math.isinf(o.P) and math.isfinite(o.D)
+    o2, g, lin = rgp.objective_gradient_cols(Ip, Im, b, hc)
+    assert math.isinf(o2.J) and g is None and lin is None
+
+
+# ------------------------------------------------------------------------------------------
+# PCG (Sec. 2.3.1; textbook CG)
+# ------------------------------------------------------------------------------------------
+
+def test_pcg_equals_direct_solve_and_orthogonality():
+    Ip, Im, b, hc = _tiny(11, shape=(3, 4, 6), base=0.6, amp=0.2)
+    _, g, lin = rgp.objective_gradient_cols(Ip, Im, b, hc, ALPHA, BETA)
+    H = loops.gn_hessian(Ip, Im, b, hc, ALPHA, BETA)
+    d = rgp.gn_diag_cols(lin)
+    rec = []
+    res = rgp.pcg(lambda v: rgp.gn_matvec_cols(lin, v), -g, d, g.size, 1e-13, record=rec)
+    x = np.linalg.solve(H, -g.ravel())
+    assert np.linalg.norm(res.x.ravel() - x) <= 1e-8 * np.linalg.norm(x)
+    # preconditioned residuals are mutually orthogonal: r_i^T D^{-1} r_j = 0
+    k = min(len(rec), 8)
+    for i in range(k):
+        for j in range(i):
+            a = float(np.sum(rec[i] * rec[j] / d))
+            s = math.sqrt(float(np.sum(rec[i] ** 2 / d)) * float(np.sum(rec[j] ** 2 / d)))
+            assert abs(a) <= 1e-8 * s
+
+
+def test_pcg_stopping_rules():
+    Ip, Im, b, hc = _tiny(12, shape=(3, 4, 6))
+    _, g, lin = rgp.objective_gradient_cols(Ip, Im, b, hc)
+    d = rgp.gn_diag_cols(lin)
+    H = lambda v: rgp.gn_matvec_cols(lin, v)  # noqa: E731
+    r = rgp.pcg(H, -g, d, 3, 0.0)
+    assert r.iters == 3
+    r = rgp.pcg(H, -g, d, 100, 0.5)
+    assert r.relres < 0.5 and r.iters < 100
+    r = rgp.pcg(H, np.zeros_like(g), d, 10, 0.0)
+    assert r.iters == 0 and np.all(r.x == 0)
+
+
+# ------------------------------------------------------------------------------------------
+# Gauss-Newton with Armijo (Sec. 2.3.1)
+# ------------------------------------------------------------------------------------------
+
+def test_gauss_newton_armijo_and_monotone():
+    import synth
+    p = synth.make_workload("c1", scale=100.0)
+    ot = rgp.ot_init(p.I_plus, p.I_minus, p.pe, p.h)
+    b, hist = rgp.gauss_newton(p.I_plus, p.I_minus, ot.b0, p.pe, p.h, gn_iters=4, pcg_iters=10)
+    Js = [st.J for st in hist] + [rgp.objective(p.I_plus, p.I_minus, b, p.pe, p.h).J]
+    for k, st in enumerate(hist):
+        assert st.accepted
+        assert Js[k + 1] <= st.J + 1e-4 * st.gamma * st.gq + 1e-9 * abs(st.J)
+        assert st.gq < 0
+    assert all(Js[k + 1] < Js[k] for k in range(len(hist)))
+
+
+# ------------------------------------------------------------------------------------------
+# Optimal-transport initialisation (Sec. 2.2)
+# ------------------------------------------------------------------------------------------
+
+def test_ot_identity_and_antisymmetry():
+    import synth
+    p = synth.make_workload("c1")
+    ot = rgp.ot_init(p.I_plus, p.I_plus, p.pe, p.h)
+    assert np.all(ot.b0 == 0.0)
+    a = rgp.ot_init(p.I_plus, p.I_minus, p.pe, p.h)
+    s = rgp.ot_init(p.I_minus, p.I_plus, p.pe, p.h)
+    assert np.array_equal(s.b0, -a.b0)
+    assert a.guarded_cells == s.guarded_cells
+    # b0 vanishes at both column ends (C_0 and C_m are fixed)
+    b0 = np.moveaxis(a.b0, p.pe, -1)
+    assert np.all(b0[..., 0] == 0.0)
+
+
+@pytest.mark.parametrize("c", [1, 2, 3])
+def test_ot_known_integer_shift(c):
+    m = 64
+    j = np.arange(m)
+    f = np.where((j >= 20) & (j < 44), 1.0 + np.sin(0.3 * j) ** 2, 0.0)
+    ip = np.roll(f, c)
+    im = np.roll(f, -c)
+    I_p = np.broadcast_to(ip, (2, 3, m)).copy()
+    I_m = np.broadcast_to(im, (2, 3, m)).copy()
+    ot = rgp.ot_init(I_p, I_m, 2, (1.0, 1.0, 1.0), eps=1e-12, guard=False)
+    Cp = rgp.nodal_cdf(ip + ot.shift)
+    Cm = rgp.nodal_cdf(im + ot.shift)
+    sel = (Cp > 1e-6) & (Cp < 1 - 1e-6) & (Cm > 1e-6) & (Cm < 1 - 1e-6)
+    assert np.count_nonzero(sel) > 10
+    np.testing.assert_allclose(ot.b0[0, 0][sel], float(c), atol=1e-9)
+
+
+def test_ot_gaussians_closed_form():
+    """1D W2 between Gaussians: b0(X) = [(mu+ - mu-) + s+(X-mu-)/s- - s-(X-mu+)/s+] / 4."""
+    Lx = 60.0
+    mup, sp, mum, sm = 31.0, 3.0, 28.5, 4.0
+
+    def err(m):
+        h = Lx / m
+        xc = (np.arange(m) + 0.5) * h
+        X = np.arange(m + 1) * h
+        ip = np.exp(-((xc - mup) ** 2) / (2 * sp * sp)) / sp
+        im = np.exp(-((xc - mum) ** 2) / (2 * sm * sm)) / sm
+        ot = rgp.ot_init(ip[None, None, :], im[None, None, :], 2, (1.0, 1.0, h), eps=0.0,
+                         guard=False)
+        ref = 0.25 * ((mup - mum) + sp * (X - mum) / sm - sm * (X - mup) / sp)
+        bulk = np.abs(X - 0.5 * (mup + mum)) < 5.0
+        return float(np.max(np.abs(ot.b0[0, 0][bulk] - ref[bulk])))
+
+    e1, e2 = err(300), err(600)
+    assert e1 < 5e-3
+    assert 3.0 < e1 / e2 < 5.0
+
+
+def test_ot_inverse_matches_library_interp_and_min_rule():
+    rng = np.random.default_rng(13)
+    i = rng.uniform(0.01, 1.0, 37)
+    C = rgp.nodal_cdf(i)
+    X = np.arange(C.size, dtype=np.float64)
+    r = np.concatenate([rng.uniform(0, 1, 500), C, [0.0, 1.0]])
+    np.testing.assert_allclose(rgp.cdf_inverse_index(C, r), np.interp(r, C, X), rtol=0,
+                               atol=1e-13)
+    # min-rule of the pseudo-inverse: smallest node x with C(x) >= r is ceil of the spline value
+    rs = rng.uniform(1e-9, 1.0, 10000)
+    brute = np.array([np.min(np.nonzero(C >= t)[0]) for t in rs])
+    np.testing.assert_array_equal(np.ceil(rgp.cdf_inverse_index(C, rs) - 1e-12), brute)
+
+
+def test_ot_guard_clips_and_reintegrates():
+    m = 30
+    ip = np.full(m, 1e-3)
+    ip[10] = 50.0                      # a spike: the transport has steep slopes
+    im = np.full(m, 1e-3)
+    im[14] = 50.0
+    I_p = ip[None, None, :]
+    I_m = im[None, None, :]
+    raw = rgp.ot_init(I_p, I_m, 2, (1.0, 1.0, 1.0), guard=False)
+    gd = rgp.ot_init(I_p, I_m, 2, (1.0, 1.0, 1.0), guard=True)
+    slope_raw = np.diff(raw.b0[0, 0])
+    assert np.max(np.abs(slope_raw)) > 0.99
+    slope = np.diff(gd.b0[0, 0])
+    assert np.max(np.abs(slope)) <= 0.99 + 1e-15
+    assert gd.guarded_cells == int(np.count_nonzero(np.abs(slope_raw) > 0.99))
+    np.testing.assert_allclose(slope, np.clip(slope_raw, -0.99, 0.99), atol=1e-12)
+    assert gd.b0[0, 0, 0] == 0.0
+
+
+def test_ot_zero_column_gives_zero_field():
+    rng = np.random.default_rng(14)
+    Ip = rng.uniform(0.0, 1.0, (3, 8, 4))
+    Im = rng.uniform(0.0, 1.0, (3, 8, 4))
+    Ip[1, :, 2] = 0.0
+    Im[1, :, 2] = 0.0
+    ot = rgp.ot_init(Ip, Im, 1, (1.0, 1.0, 1.0))
+    assert np.all(ot.b0[1, :, 2] == 0.0)
+    z = rgp.ot_init(np.zeros((2, 5, 3)), np.zeros((2, 5, 3)), 1, (1.0, 1.0, 1.0))
+    assert np.all(z.b0 == 0.0) and z.shift == 0.0
+
+
+# ------------------------------------------------------------------------------------------
+# Pyramid transfers
+# ------------------------------------------------------------------------------------------
+
+def test_restrict_invariants():
+    rng = np.random.default_rng(15)
+    I = rng.standard_normal((6, 8, 4))
+    R = rgp.restrict_image(I)
+    assert R.shape == (3, 4, 2)
+    assert float(R.sum()) == pytest.approx(float(I.sum()) / 8.0, rel=1e-13)
+    assert R[1, 2, 1] == pytest.approx(I[2:4, 4:6, 2:4].mean(), rel=1e-14)
+    odd = rgp.restrict_image(np.full((5, 7, 3), 2.5))
+    assert odd.shape == (3, 4, 2) and np.allclose(odd, 2.5, rtol=0, atol=1e-15)
+    I2 = rng.standard_normal((5, 7, 3))
+    R2 = rgp.restrict_image(I2)
+    assert R2[2, 3, 1] == pytest.approx(I2[4, 6, 2], rel=1e-15)   # corner block of one cell
+
+
+@pytest.mark.parametrize("pe", [0, 1, 2])
+def test_prolong_reproduces_linear_fields(pe):
+    mf = [10, 9, 7]
+    mc = [(s + 1) // 2 for s in mf]
+    hf = 1.0
+    hcoarse = 2.0 * hf
+
+    def coords(m, h, nodes):
+        k = np.arange(m + (1 if nodes else 0), dtype=np.float64)
+        return k * h if nodes else (k + 0.5) * h
+
+    def field(m, h):
+        ax = [coords(m[d], h, d == pe) for d in range(3)]
+        X = np.meshgrid(*ax, indexing="ij")
+        return 0.3 * X[0] - 0.2 * X[1] + 0.1 * X[2] + 1.0, ax
+
+    bc, _ = field(mc, hcoarse)
+    bf_true, axf = field(mf, hf)
+    bf = rgp.prolong_field(bc, mf, pe)
+    assert bf.shape == bf_true.shape
+    # exact where no clamping happens: cross-axis fine centres inside the coarse centre range
+    sel = []
+    for d in range(3):
+        if d == pe:
+            sel.append(np.ones(axf[d].size, bool))
+        else:
+            lo, hi = 0.5 * hcoarse, (mc[d] - 0.5) * hcoarse
+            sel.append((axf[d] >= lo) & (axf[d] <= hi))
+    mask = sel[0][:, None, None] & sel[1][None, :, None] & sel[2][None, None, :]
+    np.testing.assert_allclose(bf[mask], bf_true[mask], rtol=0, atol=1e-12)
+    const = rgp.prolong_field(np.full(bc.shape, -1.25), mf, pe)
+    assert np.allclose(const, -1.25, rtol=0, atol=1e-15)
+
+
+# ------------------------------------------------------------------------------------------
+# End to end: a pair distorted with a known field gets that field back
+# ------------------------------------------------------------------------------------------
+
+def test_known_field_recovery():
+    import synth
+    p = synth.make_workload("c1", scale=1000.0)
+    res = rgp.solve(p.I_plus, p.I_minus, p.pe, p.h, levels=1, gn_iters=5, pcg_iters=10)
+    Itc = np.moveaxis(p.I_true, p.pe, -1)
+    thr = 0.1 * Itc.max()
+    mk = np.zeros(Itc.shape[:-1] + (Itc.shape[-1] + 1,), bool)
+    mk[..., :-1] |= Itc > thr
+    mk[..., 1:] |= Itc > thr
+    mask = np.moveaxis(mk, -1, p.pe)
+    rel, mx, rms = rgp.field_errors(res.b, p.b_true, mask)
+    assert rms <= 0.25
+    ri = rgp.relative_improvement(p.I_plus, p.I_minus, res.T_plus, res.T_minus)
+    assert ri > 90.0
