@@ -1,0 +1,165 @@
+/*
+ * librgp: reversed-gradient-polarity (RGP) susceptibility-distortion correction on one MI355X.
+ *
+ * C ABI of the hot path of PyHySCO (Julian and Ruthotto): column-wise 1D optimal-transport
+ * initialisation, objective and gradient of the discretised problem, Gauss-Newton
+ * Hessian-vector products, Jacobi-preconditioned CG, and the coarse-to-fine Gauss-Newton solve
+ * that ends in the Jacobian-modulation correction.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Volumes are C-contiguous [m0][m1][m2] arrays in DEVICE memory owned by the caller.  Images
+ *    are cell-centred (m0*m1*m2 values).  The field map b and every vector of the Gauss-Newton
+ *    solve live on the staggered grid of Sec. 2.1: cell centres across the phase-encoding (PE)
+ *    axis and nodes along it, i.e. shape [m0][m1][m2] with m[pe] replaced by m[pe] + 1.
+ *  - "field" arrays (b, gradients, Hessian data, PCG vectors) have the arithmetic type
+ *    (RGP_F64 or RGP_F32); images may also be RGP_BF16 (storage only; arithmetic stays in the
+ *    field type).  Inner products and reductions are always accumulated in FP64.
+ *  - Scalars produced on the device (J, iteration counts, ...) are written to caller-owned
+ *    DEVICE memory; no call synchronises the host.  Every call is enqueued on `stream` (a
+ *    hipStream_t; NULL is the default stream) and returns as soon as the work is enqueued.
+ *  - `ws`/`ws_bytes` is a caller-owned device workspace of at least rgp_workspace_size() bytes.
+ *    The library never allocates device memory.  Calls that share a workspace must not overlap.
+ *  - Argument errors are reported synchronously through the return value; nothing is enqueued
+ *    then.  A violated barrier (|d b / d v| >= 1 somewhere) is a value, J = +inf, not an error.
+ */
+#ifndef RGP_H
+#define RGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RGP_OK = 0,
+  RGP_EINVAL = -1,      /* null pointer, bad option value or enum */
+  RGP_ESHAPE = -2,      /* grid extents out of range */
+  RGP_EDTYPE = -3,      /* unsupported dtype combination */
+  RGP_EHIP = -7,        /* a HIP runtime call failed (see rgp_last_hip_error) */
+  RGP_EWORKSPACE = -8   /* workspace missing or smaller than rgp_workspace_size() */
+} rgp_status;
+
+typedef enum { RGP_F64 = 0, RGP_F32 = 1, RGP_BF16 = 2 } rgp_dtype;
+
+/* Grid of one volume.  m: cells per axis (caller order, each >= 1, product < 2^31, m[pe] >= 2);
+ * pe: phase-encoding axis 0..2; h: voxel sizes (> 0).  b is measured in the units of h. */
+typedef struct {
+  int64_t m[3];
+  int32_t pe;
+  int32_t reserved;
+  double h[3];
+} rgp_grid;
+
+/* Options of the full solve (rgp_correct).  rgp_default_opts() fills the paper's defaults. */
+typedef struct {
+  double alpha;          /* smoothness weight (300 in Sec. 2.1) */
+  double beta;           /* barrier weight (1e-4 in Sec. 2.1) */
+  int32_t levels;        /* pyramid levels, >= 1; coarse-to-fine */
+  int32_t gn_iters;      /* Gauss-Newton iterations per level, >= 0 */
+  int32_t pcg_iters;     /* PCG iterations per GN step, 1..1000 (10 in Sec. 2.3.1) */
+  int32_t ls_max_trials; /* Armijo trials gamma = 1, 1/2, ..., at most 10 */
+  double pcg_rtol;       /* PCG stops when |r|/|grad J| < pcg_rtol (0.1 in Sec. 2.3.1; 0 = never) */
+  double armijo_c;       /* sufficient-decrease constant (1e-4) */
+  double ot_eps;         /* positivity shift of the OT init: eps * max|I| (1e-3) */
+  int32_t ot_guard;      /* clip OT slopes to +-0.99 and re-integrate (1) */
+  int32_t use_b_init;    /* 1: start from b_init on the coarsest level instead of OT */
+} rgp_solver_opts;
+
+/* Number of doubles per Gauss-Newton record in the stats buffer of rgp_correct. */
+#define RGP_STAT_FIELDS 12
+/* Stats buffer layout: [0] OT guarded cells, [1] OT shift, [2..3] reserved, then one record of
+ * RGP_STAT_FIELDS doubles per GN step, coarsest level first:
+ * J, D, S, P, |grad J|, grad.q, PCG iterations, PCG relative residual, gamma, Armijo trials,
+ * accepted (0/1), reserved.  Records of steps that did not run (the solve stopped) are NaN. */
+#define RGP_STAT_HEADER 4
+
+typedef enum {
+  RGP_OP_OT_INIT = 0,
+  RGP_OP_LOSS_GRAD = 1,
+  RGP_OP_GN_HVP = 2,
+  RGP_OP_PCG_SOLVE = 3,
+  RGP_OP_CORRECT = 4,
+  RGP_OP_APPLY_CORRECTION = 5
+} rgp_op;
+
+const char* rgp_status_string(rgp_status s);
+/* Last HIP error code seen by the library on this thread (0 if none). */
+int rgp_last_hip_error(void);
+void rgp_default_opts(rgp_solver_opts* o);
+
+/* Workspace bytes needed by `op` on `grid` (opts is read for RGP_OP_CORRECT and
+ * RGP_OP_PCG_SOLVE only; real_t is the field type).  Writes *bytes. */
+rgp_status rgp_workspace_size(rgp_op op, const rgp_grid* grid, rgp_dtype real_t,
+                              const rgp_solver_opts* opts, size_t* bytes);
+
+/* Column-wise 1D optimal-transport initialisation (Sec. 2.2, and Fig. 2).
+ * Per PE column: images shifted positive by s = max(0, -min I) + ot_eps * max|I| (one global
+ * scalar over both images), nodal CDFs C+ and C- (FP64 scans), linear-spline pseudo-inverses,
+ * and b0_k = h_pe/4 [C+^{-1}(C-_k) - C-^{-1}(C+_k)] - the average of the displacement of the
+ * halfway map T- and the negated displacement of T+.  Columns with no mass get b0 = 0.  If
+ * `guard` is set, a column whose slope |D b0| exceeds 0.99 somewhere gets its slopes clipped to
+ * +-0.99 and is re-integrated from b0_0 = 0; the number of clipped cells is written to
+ * *n_guarded_dev (nullable, uint64 on the device).  b0: field array (real_t) written in full. */
+rgp_status rgp_ot_init(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                       const void* I_minus, rgp_dtype real_t, void* b0, double ot_eps,
+                       int32_t guard, uint64_t* n_guarded_dev, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/* Objective J = D + alpha S + beta P of Eq. (6) at b, with D the SSD of the mass-preserving
+ * transforms of Eq. (1)-(2), S the smoothness term of Eq. (5) (seven-point negative Laplacian on
+ * the staggered field, Neumann boundaries) and P the barrier of Eq. (3); all with weight vol/2.
+ * jdsp_dev (device, 4 doubles): J, D, S, P (J = P = +inf when the barrier is violated).
+ * Optional outputs (field arrays, nullable): grad = grad J; hdiag/hoff = the Gauss-Newton
+ * Hessian of Sec. 2.3.1 in banded form - hdiag its diagonal (the Jacobi preconditioner) and
+ * hoff[k] the coupling of PE nodes k and k+1 (0 at the last node); the cross-axis couplings are
+ * -alpha vol / h_d^2.  hdiag and hoff are both given or both NULL.  Their contents are
+ * unspecified when J = +inf. */
+rgp_status rgp_loss_grad(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                         const void* I_minus, rgp_dtype real_t, const void* b, double alpha,
+                         double beta, double* jdsp_dev, void* grad, void* hdiag, void* hoff,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Gauss-Newton Hessian-vector product Hv = H_J v (Sec. 2.3.1, Eq. 7) with H_J given by the
+ * hdiag/hoff produced by rgp_loss_grad at the same grid and alpha.  vHv_dev (nullable, device
+ * double) receives v^T H v. */
+rgp_status rgp_gn_hvp(const rgp_grid* grid, rgp_dtype real_t, const void* hdiag,
+                      const void* hoff, double alpha, const void* v, void* Hv, double* vHv_dev,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Jacobi-preconditioned CG for H_J x = rhs from x0 = 0 (Sec. 2.3.1): at most maxit iterations,
+ * stopping early when |r| / |rhs| < rtol or when p^T H p <= 0.  x: field array written in full.
+ * iters_dev (int32) and relres_dev (double): device outputs, nullable. */
+rgp_status rgp_pcg_solve(const rgp_grid* grid, rgp_dtype real_t, const void* hdiag,
+                         const void* hoff, double alpha, const void* rhs, void* x, int32_t maxit,
+                         double rtol, int32_t* iters_dev, double* relres_dev, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* Jacobian-modulation correction (Sec. 2.4.7): T+ = I+(x + b v)(1 + d_v b) and
+ * T- = I-(x - b v)(1 - d_v b) at the cell centres, with the 1D linear image model (zero outside
+ * the column).  T_plus/T_minus: arrays of img_t (nullable). */
+rgp_status rgp_apply_correction(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                                const void* I_minus, rgp_dtype real_t, const void* b,
+                                void* T_plus, void* T_minus, void* stream);
+
+/* The whole hot path: image pyramid (2x2x2 means, `levels` levels), OT initialisation on the
+ * coarsest level (or b_init there when opts->use_b_init; b_init has the coarsest level's
+ * staggered shape), then on every level from coarse to fine `gn_iters` Gauss-Newton steps
+ * b <- b + gamma q with H_J q = -grad J solved by `pcg_iters` PCG iterations and gamma chosen by
+ * Armijo backtracking (Sec. 2.3.1), linear prolongation of b between levels, and finally the
+ * Jacobian-modulation correction of the finest images.  A step that no trial accepts stops the
+ * level with b unchanged.  b_out: finest field (real_t); T_plus/T_minus (nullable, img_t);
+ * stats_dev: nullable device buffer of RGP_STAT_HEADER + levels*gn_iters*RGP_STAT_FIELDS
+ * doubles. */
+rgp_status rgp_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                       const void* I_minus, rgp_dtype real_t, const rgp_solver_opts* opts,
+                       const void* b_init, void* b_out, void* T_plus, void* T_minus,
+                       double* stats_dev, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RGP_H */

@@ -1,0 +1,667 @@
+// C ABI of librgp: argument validation, workspace layout and the launch sequences of the hot path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "../../include/rgp.h"
+#include "rgp_internal.hpp"
+#include "rgp_launch.hpp"
+
+namespace rgp {
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_stats_header(double* stats, const State* st, const unsigned long long* guarded,
+                               hipStream_t s);
+}  // namespace rgp
+
+using namespace rgp;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+constexpr size_t kAlign = 256;
+constexpr double kGuardSlope = 0.99;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool dtype_of(rgp_dtype t, DType* out) {
+  switch (t) {
+    case RGP_F64: *out = DType::F64; return true;
+    case RGP_F32: *out = DType::F32; return true;
+    case RGP_BF16: *out = DType::BF16; return true;
+  }
+  return false;
+}
+
+size_t dsize(DType t) { return t == DType::F64 ? 8 : (t == DType::F32 ? 4 : 2); }
+
+rgp_status check_types(rgp_dtype img, rgp_dtype real, DType* di, DType* dr) {
+  if (!dtype_of(img, di) || !dtype_of(real, dr)) return RGP_EINVAL;
+  if (*dr == DType::BF16) return RGP_EDTYPE;
+  if (*dr == DType::F32 && *di == DType::F64) return RGP_EDTYPE;
+  return RGP_OK;
+}
+
+rgp_status check_grid(const rgp_grid* g) {
+  if (!g) return RGP_EINVAL;
+  if (g->pe < 0 || g->pe > 2) return RGP_EINVAL;
+  int64_t cells = 1, nodes = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (g->m[d] < 1 || g->m[d] > (int64_t(1) << 24)) return RGP_ESHAPE;
+    if (!(g->h[d] > 0.0) || !std::isfinite(g->h[d])) return RGP_EINVAL;
+    cells *= g->m[d];
+    nodes *= g->m[d] + (d == g->pe ? 1 : 0);
+    if (nodes >= (int64_t(1) << 31)) return RGP_ESHAPE;
+  }
+  if (g->m[g->pe] < 2) return RGP_ESHAPE;
+  (void)cells;
+  return RGP_OK;
+}
+
+Geom make_geom(const int64_t m[3], int pe, const double h[3]) {
+  Geom g{};
+  int ax[2], k = 0;
+  for (int d = 0; d < 3; ++d)
+    if (d != pe) ax[k++] = d;
+  int64_t n[3];
+  for (int d = 0; d < 3; ++d) n[d] = m[d] + (d == pe ? 1 : 0);
+  const int64_t cst[3] = {m[1] * m[2], m[2], 1};
+  const int64_t nst[3] = {n[1] * n[2], n[2], 1};
+  g.mp = (int32_t)m[pe];
+  g.nx = (int32_t)m[ax[0]];
+  g.ny = (int32_t)m[ax[1]];
+  g.pe = pe;
+  g.ncol = (int64_t)g.nx * g.ny;
+  g.cxs = cst[ax[0]];
+  g.cys = cst[ax[1]];
+  g.cps = cst[pe];
+  g.nxs = nst[ax[0]];
+  g.nys = nst[ax[1]];
+  g.nps = nst[pe];
+  g.ncell = m[0] * m[1] * m[2];
+  g.nnode = n[0] * n[1] * n[2];
+  g.hx = h[ax[0]];
+  g.hy = h[ax[1]];
+  g.hp = h[pe];
+  g.vol = h[0] * h[1] * h[2];
+  return g;
+}
+
+Geom geom_of(const rgp_grid* gr) { return make_geom(gr->m, gr->pe, gr->h); }
+
+// Bump allocator over the caller's workspace (sizes computed with a null base).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  void* take(size_t bytes) {
+    off = align_up(off);
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+struct Control {
+  State* st;
+  unsigned* counter;
+  unsigned long long* guarded;
+  double* partials;
+};
+
+size_t partial_doubles(const Geom& g) {
+  size_t n = 0;
+  n = std::max(n, (size_t)5 * loss_grad_blocks(g));
+  n = std::max(n, (size_t)18 * trial_blocks(g));
+  n = std::max(n, (size_t)7 * pcg_blocks(g));
+  n = std::max(n, (size_t)1 * hvp_blocks(g));
+  n = std::max(n, (size_t)2 * shift_blocks(g.ncell));
+  return n;
+}
+
+Control carve_control(Carver& c, const Geom& finest) {
+  Control k;
+  k.st = static_cast<State*>(c.take(sizeof(State)));
+  k.counter = static_cast<unsigned*>(c.take(sizeof(unsigned)));
+  k.guarded = static_cast<unsigned long long*>(c.take(sizeof(unsigned long long)));
+  k.partials = static_cast<double*>(c.take(partial_doubles(finest) * sizeof(double)));
+  return k;
+}
+
+// Level geometry of the pyramid: level 0 is the caller's grid.
+struct Level {
+  int64_t m[3];
+  double h[3];
+  Geom g;
+};
+
+int make_levels(const rgp_grid* gr, int levels, Level* out) {
+  for (int l = 0; l < levels; ++l) {
+    for (int d = 0; d < 3; ++d) {
+      out[l].m[d] = l == 0 ? gr->m[d] : (out[l - 1].m[d] + 1) / 2;
+      out[l].h[d] = l == 0 ? gr->h[d] : 2.0 * out[l - 1].h[d];
+    }
+    if (out[l].m[gr->pe] < 2) return -1;
+    out[l].g = make_geom(out[l].m, gr->pe, out[l].h);
+  }
+  return 0;
+}
+
+constexpr int kMaxLevels = 12;
+
+struct CorrectWs {
+  Control ctl;
+  void* img[kMaxLevels][2];  // levels >= 1 (real type)
+  void* B[2];
+  void* G;
+  void* Dg;
+  void* Of;
+  void* X;
+  void* R[2];
+  void* P[2];
+  void* W[2];
+};
+
+CorrectWs carve_correct(void* ws, const Level* lv, int levels, DType real) {
+  Carver c(ws);
+  CorrectWs w;
+  w.ctl = carve_control(c, lv[0].g);
+  const size_t rs = dsize(real);
+  for (int l = 0; l < kMaxLevels; ++l) w.img[l][0] = w.img[l][1] = nullptr;
+  for (int l = 1; l < levels; ++l) {
+    w.img[l][0] = c.take(lv[l].g.ncell * rs);
+    w.img[l][1] = c.take(lv[l].g.ncell * rs);
+  }
+  const size_t nb = lv[0].g.nnode * rs;
+  w.B[0] = c.take(nb);
+  w.B[1] = c.take(nb);
+  w.G = c.take(nb);
+  w.Dg = c.take(nb);
+  w.Of = c.take(nb);
+  w.X = c.take(nb);
+  for (int i = 0; i < 2; ++i) {
+    w.R[i] = c.take(nb);
+    w.P[i] = c.take(nb);
+    w.W[i] = c.take(nb);
+  }
+  // total recorded in c.off by the caller through carve size
+  (void)c;
+  return w;
+}
+
+size_t correct_bytes(const Level* lv, int levels, DType real) {
+  Carver c(nullptr);
+  carve_control(c, lv[0].g);
+  const size_t rs = dsize(real);
+  for (int l = 1; l < levels; ++l) {
+    c.take(lv[l].g.ncell * rs);
+    c.take(lv[l].g.ncell * rs);
+  }
+  const size_t nb = lv[0].g.nnode * rs;
+  for (int i = 0; i < 12; ++i) c.take(nb);
+  return align_up(c.off);
+}
+
+#define RGP_HIP(call)                          \
+  do {                                         \
+    hipError_t e_ = (call);                    \
+    if (e_ != hipSuccess) {                    \
+      g_last_hip = (int)e_;                    \
+      return RGP_EHIP;                         \
+    }                                          \
+  } while (0)
+
+rgp_status check_opts(const rgp_solver_opts* o) {
+  if (!o) return RGP_EINVAL;
+  if (!(o->alpha >= 0.0) || !(o->beta >= 0.0) || !std::isfinite(o->alpha) ||
+      !std::isfinite(o->beta))
+    return RGP_EINVAL;
+  if (o->levels < 1 || o->levels > kMaxLevels) return RGP_EINVAL;
+  if (o->gn_iters < 0 || o->gn_iters > 10000) return RGP_EINVAL;
+  if (o->pcg_iters < 1 || o->pcg_iters > 1000) return RGP_EINVAL;
+  if (o->ls_max_trials < 1 || o->ls_max_trials > 10) return RGP_EINVAL;
+  if (!(o->pcg_rtol >= 0.0) || !(o->armijo_c >= 0.0) || !(o->ot_eps >= 0.0)) return RGP_EINVAL;
+  return RGP_OK;
+}
+
+// One Gauss-Newton solve of `iters` steps on one level.  b enters in B[cur]; on return the final
+// field is in B[cur].
+hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const void* Im, DType img,
+                     DType real, const rgp_solver_opts* o, int& cur, double* records,
+                     hipStream_t s) {
+  hipError_t e;
+  for (int it = 0; it < o->gn_iters; ++it) {
+    LossGradArgs la{};
+    la.g = g;
+    la.Ip = Ip;
+    la.Im = Im;
+    la.b_in = w.B[cur];
+    la.q = w.X;
+    la.step = it > 0;
+    la.b_out = it > 0 ? w.B[1 - cur] : nullptr;
+    la.grad = w.G;
+    la.diag = w.Dg;
+    la.off = w.Of;
+    la.alpha = o->alpha;
+    la.beta = o->beta;
+    la.st = w.ctl.st;
+    la.partials = w.ctl.partials;
+    la.counter = w.ctl.counter;
+    la.record = records ? records + (size_t)it * kStatFields : nullptr;
+    la.gn_mode = 1;
+    if ((e = launch_loss_grad(la, img, real, s)) != hipSuccess) return e;
+    if (it > 0) cur = 1 - cur;
+
+    for (int i = 0; i <= o->pcg_iters; ++i) {
+      PcgArgs pa{};
+      pa.g = g;
+      pa.diag = w.Dg;
+      pa.off = w.Of;
+      pa.rhs = w.G;
+      pa.rhs_sign = -1.0;
+      pa.x = w.X;
+      const int in = (i + 1) & 1, out = i & 1;
+      pa.r_in = w.R[in];
+      pa.p_in = w.P[in];
+      pa.w_in = w.W[in];
+      pa.r_out = w.R[out];
+      pa.p_out = w.P[out];
+      pa.w_out = w.W[out];
+      pa.alpha = o->alpha;
+      pa.st = w.ctl.st;
+      pa.partials = w.ctl.partials;
+      pa.counter = w.ctl.counter;
+      pa.iter = i;
+      pa.maxit = o->pcg_iters;
+      pa.rtol = o->pcg_rtol;
+      pa.gn_mode = 1;
+      if ((e = launch_pcg_step(pa, real, s)) != hipSuccess) return e;
+    }
+
+    int first = 0;
+    const int passes[3] = {1, 4, 5};
+    for (int p = 0; p < 3 && first < o->ls_max_trials; ++p) {
+      const int nc = std::min(passes[p], o->ls_max_trials - first);
+      TrialArgs ta{};
+      ta.g = g;
+      ta.Ip = Ip;
+      ta.Im = Im;
+      ta.b = w.B[cur];
+      ta.q = w.X;
+      ta.grad = w.G;
+      ta.alpha = o->alpha;
+      ta.beta = o->beta;
+      ta.armijo_c = o->armijo_c;
+      ta.st = w.ctl.st;
+      ta.partials = w.ctl.partials;
+      ta.counter = w.ctl.counter;
+      ta.record = records ? records + (size_t)it * kStatFields : nullptr;
+      ta.first = first;
+      ta.last_pass = (first + nc >= o->ls_max_trials) ? 1 : 0;
+      if ((e = launch_trial(ta, nc, img, real, s)) != hipSuccess) return e;
+      first += nc;
+    }
+  }
+  if (o->gn_iters > 0) {
+    ApplyArgs aa{};
+    aa.b = w.B[cur];
+    aa.q = w.X;
+    aa.st = w.ctl.st;
+    aa.n = g.nnode;
+    if ((e = launch_apply_step(aa, real, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rgp_status_string(rgp_status s) {
+  switch (s) {
+    case RGP_OK: return "ok";
+    case RGP_EINVAL: return "invalid argument";
+    case RGP_ESHAPE: return "grid extents out of range";
+    case RGP_EDTYPE: return "unsupported dtype combination";
+    case RGP_EHIP: return "HIP runtime error";
+    case RGP_EWORKSPACE: return "workspace missing or too small";
+  }
+  return "unknown status";
+}
+
+int rgp_last_hip_error(void) { return g_last_hip; }
+
+void rgp_default_opts(rgp_solver_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->alpha = 300.0;
+  o->beta = 1e-4;
+  o->levels = 1;
+  o->gn_iters = 5;
+  o->pcg_iters = 10;
+  o->ls_max_trials = 10;
+  o->pcg_rtol = 0.1;
+  o->armijo_c = 1e-4;
+  o->ot_eps = 1e-3;
+  o->ot_guard = 1;
+  o->use_b_init = 0;
+}
+
+rgp_status rgp_workspace_size(rgp_op op, const rgp_grid* grid, rgp_dtype real_t,
+                              const rgp_solver_opts* opts, size_t* bytes) {
+  if (!bytes) return RGP_EINVAL;
+  rgp_status st = check_grid(grid);
+  if (st != RGP_OK) return st;
+  DType dr;
+  if (!dtype_of(real_t, &dr) || dr == DType::BF16) return RGP_EDTYPE;
+  const Geom g = geom_of(grid);
+  Carver c(nullptr);
+  switch (op) {
+    case RGP_OP_OT_INIT:
+    case RGP_OP_LOSS_GRAD:
+    case RGP_OP_GN_HVP:
+    case RGP_OP_APPLY_CORRECTION:
+      carve_control(c, g);
+      break;
+    case RGP_OP_PCG_SOLVE:
+      carve_control(c, g);
+      for (int i = 0; i < 6; ++i) c.take(g.nnode * dsize(dr));
+      break;
+    case RGP_OP_CORRECT: {
+      if ((st = check_opts(opts)) != RGP_OK) return st;
+      Level lv[kMaxLevels];
+      if (make_levels(grid, opts->levels, lv) != 0) return RGP_ESHAPE;
+      *bytes = correct_bytes(lv, opts->levels, dr);
+      return RGP_OK;
+    }
+    default:
+      return RGP_EINVAL;
+  }
+  *bytes = align_up(c.off);
+  return RGP_OK;
+}
+
+static rgp_status need_ws(rgp_op op, const rgp_grid* grid, rgp_dtype real_t,
+                          const rgp_solver_opts* opts, void* ws, size_t ws_bytes) {
+  size_t need = 0;
+  rgp_status st = rgp_workspace_size(op, grid, real_t, opts, &need);
+  if (st != RGP_OK) return st;
+  if (!ws || ws_bytes < need) return RGP_EWORKSPACE;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return RGP_EWORKSPACE;
+  return RGP_OK;
+}
+
+rgp_status rgp_ot_init(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                       const void* I_minus, rgp_dtype real_t, void* b0, double ot_eps,
+                       int32_t guard, uint64_t* n_guarded_dev, void* ws, size_t ws_bytes,
+                       void* stream) {
+  rgp_status st = check_grid(grid);
+  if (st != RGP_OK) return st;
+  DType di, dr;
+  if ((st = check_types(img_t, real_t, &di, &dr)) != RGP_OK) return st;
+  if (!I_plus || !I_minus || !b0 || !(ot_eps >= 0.0)) return RGP_EINVAL;
+  if ((st = need_ws(RGP_OP_OT_INIT, grid, real_t, nullptr, ws, ws_bytes)) != RGP_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const Geom g = geom_of(grid);
+  Carver c(ws);
+  Control k = carve_control(c, g);
+  unsigned long long* gd = n_guarded_dev ? reinterpret_cast<unsigned long long*>(n_guarded_dev)
+                                         : k.guarded;
+  RGP_HIP(launch_reset(SetStateArgs{k.st, k.counter, gd}, s));
+  RGP_HIP(launch_shift(ShiftArgs{I_plus, I_minus, g.ncell, ot_eps, k.st, k.partials, k.counter},
+                       di, s));
+  OtArgs oa{};
+  oa.g = g;
+  oa.Ip = I_plus;
+  oa.Im = I_minus;
+  oa.b0 = b0;
+  oa.st = k.st;
+  oa.guard = guard ? 1 : 0;
+  oa.guard_slope = kGuardSlope;
+  oa.guarded = gd;
+  RGP_HIP(launch_ot(oa, di, dr, s));
+  return RGP_OK;
+}
+
+rgp_status rgp_loss_grad(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                         const void* I_minus, rgp_dtype real_t, const void* b, double alpha,
+                         double beta, double* jdsp_dev, void* grad, void* hdiag, void* hoff,
+                         void* ws, size_t ws_bytes, void* stream) {
+  rgp_status st = check_grid(grid);
+  if (st != RGP_OK) return st;
+  DType di, dr;
+  if ((st = check_types(img_t, real_t, &di, &dr)) != RGP_OK) return st;
+  if (!I_plus || !I_minus || !b || !jdsp_dev) return RGP_EINVAL;
+  if ((hdiag == nullptr) != (hoff == nullptr)) return RGP_EINVAL;
+  if (!(alpha >= 0.0) || !(beta >= 0.0) || !std::isfinite(alpha) || !std::isfinite(beta))
+    return RGP_EINVAL;
+  if ((st = need_ws(RGP_OP_LOSS_GRAD, grid, real_t, nullptr, ws, ws_bytes)) != RGP_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const Geom g = geom_of(grid);
+  Carver c(ws);
+  Control k = carve_control(c, g);
+  RGP_HIP(launch_reset(SetStateArgs{k.st, k.counter, nullptr}, s));
+  LossGradArgs la{};
+  la.g = g;
+  la.Ip = I_plus;
+  la.Im = I_minus;
+  la.b_in = b;
+  la.grad = grad;
+  la.diag = hdiag;
+  la.off = hoff;
+  la.alpha = alpha;
+  la.beta = beta;
+  la.st = k.st;
+  la.partials = k.partials;
+  la.counter = k.counter;
+  la.jdsp = jdsp_dev;
+  RGP_HIP(launch_loss_grad(la, di, dr, s));
+  return RGP_OK;
+}
+
+rgp_status rgp_gn_hvp(const rgp_grid* grid, rgp_dtype real_t, const void* hdiag,
+                      const void* hoff, double alpha, const void* v, void* Hv, double* vHv_dev,
+                      void* ws, size_t ws_bytes, void* stream) {
+  rgp_status st = check_grid(grid);
+  if (st != RGP_OK) return st;
+  DType dr;
+  if (!dtype_of(real_t, &dr)) return RGP_EINVAL;
+  if (dr == DType::BF16) return RGP_EDTYPE;
+  if (!hdiag || !hoff || !v || !Hv || !(alpha >= 0.0) || !std::isfinite(alpha)) return RGP_EINVAL;
+  if ((st = need_ws(RGP_OP_GN_HVP, grid, real_t, nullptr, ws, ws_bytes)) != RGP_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const Geom g = geom_of(grid);
+  Carver c(ws);
+  Control k = carve_control(c, g);
+  RGP_HIP(launch_reset(SetStateArgs{k.st, k.counter, nullptr}, s));
+  HvpArgs ha{};
+  ha.g = g;
+  ha.diag = hdiag;
+  ha.off = hoff;
+  ha.v = v;
+  ha.Hv = Hv;
+  ha.alpha = alpha;
+  ha.partials = k.partials;
+  ha.counter = k.counter;
+  ha.vHv = vHv_dev;
+  RGP_HIP(launch_hvp(ha, dr, s));
+  return RGP_OK;
+}
+
+rgp_status rgp_pcg_solve(const rgp_grid* grid, rgp_dtype real_t, const void* hdiag,
+                         const void* hoff, double alpha, const void* rhs, void* x, int32_t maxit,
+                         double rtol, int32_t* iters_dev, double* relres_dev, void* ws,
+                         size_t ws_bytes, void* stream) {
+  rgp_status st = check_grid(grid);
+  if (st != RGP_OK) return st;
+  DType dr;
+  if (!dtype_of(real_t, &dr)) return RGP_EINVAL;
+  if (dr == DType::BF16) return RGP_EDTYPE;
+  if (!hdiag || !hoff || !rhs || !x || maxit < 1 || maxit > 100000 || !(rtol >= 0.0) ||
+      !(alpha >= 0.0) || !std::isfinite(alpha))
+    return RGP_EINVAL;
+  if ((st = need_ws(RGP_OP_PCG_SOLVE, grid, real_t, nullptr, ws, ws_bytes)) != RGP_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const Geom g = geom_of(grid);
+  Carver c(ws);
+  Control k = carve_control(c, g);
+  void* vec[6];
+  for (int i = 0; i < 6; ++i) vec[i] = c.take(g.nnode * dsize(dr));
+  RGP_HIP(launch_reset(SetStateArgs{k.st, k.counter, nullptr}, s));
+  for (int i = 0; i <= maxit; ++i) {
+    PcgArgs pa{};
+    pa.g = g;
+    pa.diag = hdiag;
+    pa.off = hoff;
+    pa.rhs = rhs;
+    pa.rhs_sign = 1.0;
+    pa.x = x;
+    const int in = (i + 1) & 1, out = i & 1;
+    pa.r_in = vec[3 * in + 0];
+    pa.p_in = vec[3 * in + 1];
+    pa.w_in = vec[3 * in + 2];
+    pa.r_out = vec[3 * out + 0];
+    pa.p_out = vec[3 * out + 1];
+    pa.w_out = vec[3 * out + 2];
+    pa.alpha = alpha;
+    pa.st = k.st;
+    pa.partials = k.partials;
+    pa.counter = k.counter;
+    pa.iter = i;
+    pa.maxit = maxit;
+    pa.rtol = rtol;
+    pa.gn_mode = 0;
+    pa.iters_out = iters_dev;
+    pa.relres_out = relres_dev;
+    RGP_HIP(launch_pcg_step(pa, dr, s));
+  }
+  return RGP_OK;
+}
+
+rgp_status rgp_apply_correction(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                                const void* I_minus, rgp_dtype real_t, const void* b,
+                                void* T_plus, void* T_minus, void* stream) {
+  rgp_status st = check_grid(grid);
+  if (st != RGP_OK) return st;
+  DType di, dr;
+  if ((st = check_types(img_t, real_t, &di, &dr)) != RGP_OK) return st;
+  if (!I_plus || !I_minus || !b) return RGP_EINVAL;
+  if (!T_plus && !T_minus) return RGP_OK;
+  CorrectArgs ca{};
+  ca.g = geom_of(grid);
+  ca.Ip = I_plus;
+  ca.Im = I_minus;
+  ca.b = b;
+  ca.Tp = T_plus;
+  ca.Tm = T_minus;
+  RGP_HIP(launch_correct(ca, di, dr, static_cast<hipStream_t>(stream)));
+  return RGP_OK;
+}
+
+rgp_status rgp_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                       const void* I_minus, rgp_dtype real_t, const rgp_solver_opts* opts,
+                       const void* b_init, void* b_out, void* T_plus, void* T_minus,
+                       double* stats_dev, void* ws, size_t ws_bytes, void* stream) {
+  rgp_status st = check_grid(grid);
+  if (st != RGP_OK) return st;
+  DType di, dr;
+  if ((st = check_types(img_t, real_t, &di, &dr)) != RGP_OK) return st;
+  if ((st = check_opts(opts)) != RGP_OK) return st;
+  if (!I_plus || !I_minus || !b_out) return RGP_EINVAL;
+  if (opts->use_b_init && !b_init) return RGP_EINVAL;
+  if ((st = need_ws(RGP_OP_CORRECT, grid, real_t, opts, ws, ws_bytes)) != RGP_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int L = opts->levels;
+  Level lv[kMaxLevels];
+  if (make_levels(grid, L, lv) != 0) return RGP_ESHAPE;
+  CorrectWs w = carve_correct(ws, lv, L, dr);
+  const size_t rs = dsize(dr);
+
+  RGP_HIP(launch_reset(SetStateArgs{w.ctl.st, w.ctl.counter, w.ctl.guarded}, s));
+  const int64_t nrec = (int64_t)L * opts->gn_iters;
+  if (stats_dev)
+    RGP_HIP(launch_fill(stats_dev, RGP_STAT_HEADER + nrec * kStatFields, std::nan(""), s));
+
+  // Image pyramid (levels >= 1 in the arithmetic type).
+  const void* imgs[kMaxLevels][2];
+  DType ity[kMaxLevels];
+  imgs[0][0] = I_plus;
+  imgs[0][1] = I_minus;
+  ity[0] = di;
+  for (int l = 1; l < L; ++l) {
+    for (int i = 0; i < 2; ++i) {
+      RestrictArgs ra{};
+      ra.src = imgs[l - 1][i];
+      ra.dst = w.img[l][i];
+      for (int d = 0; d < 3; ++d) {
+        ra.mf[d] = (int32_t)lv[l - 1].m[d];
+        ra.mc[d] = (int32_t)lv[l].m[d];
+      }
+      RGP_HIP(launch_restrict(ra, ity[l - 1], dr, s));
+      imgs[l][i] = w.img[l][i];
+    }
+    ity[l] = dr;
+  }
+
+  // Initial field on the coarsest level.
+  const Level& top = lv[L - 1];
+  if (opts->use_b_init) {
+    RGP_HIP(hipMemcpyAsync(w.B[0], b_init, top.g.nnode * rs, hipMemcpyDeviceToDevice, s));
+  } else {
+    RGP_HIP(launch_shift(ShiftArgs{imgs[L - 1][0], imgs[L - 1][1], top.g.ncell, opts->ot_eps,
+                                   w.ctl.st, w.ctl.partials, w.ctl.counter},
+                         ity[L - 1], s));
+    OtArgs oa{};
+    oa.g = top.g;
+    oa.Ip = imgs[L - 1][0];
+    oa.Im = imgs[L - 1][1];
+    oa.b0 = w.B[0];
+    oa.st = w.ctl.st;
+    oa.guard = opts->ot_guard ? 1 : 0;
+    oa.guard_slope = kGuardSlope;
+    oa.guarded = w.ctl.guarded;
+    RGP_HIP(launch_ot(oa, ity[L - 1], dr, s));
+  }
+
+  int cur = 0;
+  for (int l = L - 1; l >= 0; --l) {
+    if (l < L - 1) {
+      ProlongArgs pa{};
+      pa.src = w.B[cur];
+      pa.dst = w.B[1 - cur];
+      for (int d = 0; d < 3; ++d) {
+        pa.mf[d] = (int32_t)lv[l].m[d];
+        pa.mc[d] = (int32_t)lv[l + 1].m[d];
+      }
+      pa.pe = grid->pe;
+      RGP_HIP(launch_prolong(pa, dr, s));
+      cur = 1 - cur;
+    }
+    double* rec = stats_dev ? stats_dev + RGP_STAT_HEADER +
+                                  (size_t)(L - 1 - l) * opts->gn_iters * kStatFields
+                            : nullptr;
+    hipError_t e = run_level(w, lv[l].g, imgs[l][0], imgs[l][1], ity[l], dr, opts, cur, rec, s);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      return RGP_EHIP;
+    }
+  }
+
+  if (T_plus || T_minus) {
+    CorrectArgs ca{};
+    ca.g = lv[0].g;
+    ca.Ip = I_plus;
+    ca.Im = I_minus;
+    ca.b = w.B[cur];
+    ca.Tp = T_plus;
+    ca.Tm = T_minus;
+    RGP_HIP(launch_correct(ca, di, dr, s));
+  }
+  RGP_HIP(hipMemcpyAsync(b_out, w.B[cur], lv[0].g.nnode * rs, hipMemcpyDeviceToDevice, s));
+  if (stats_dev) RGP_HIP(launch_stats_header(stats_dev, w.ctl.st, w.ctl.guarded, s));
+  return RGP_OK;
+}
+
+}  // extern "C"

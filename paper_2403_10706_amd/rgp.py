@@ -1,0 +1,325 @@
+"""Thin ctypes binding of librgp (argument marshalling only; every step runs in the HIP library).
+
+Tensors are PyTorch device tensors used as plain device buffers; the current PyTorch stream is
+passed to the library.  Names follow the C ABI in ``include/rgp.h``.  Loading fails loudly when
+the library has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librgp.so")
+
+RGP_OK = 0
+STATUS = {0: "ok", -1: "invalid argument", -2: "grid extents out of range",
+          -3: "unsupported dtype combination", -7: "HIP runtime error",
+          -8: "workspace missing or too small"}
+F64, F32, BF16 = 0, 1, 2
+OP_OT_INIT, OP_LOSS_GRAD, OP_GN_HVP, OP_PCG_SOLVE, OP_CORRECT, OP_APPLY_CORRECTION = range(6)
+STAT_FIELDS = 12
+STAT_HEADER = 4
+STAT_NAMES = ("J", "D", "S", "P", "gnorm", "gq", "pcg_iters", "pcg_relres", "gamma", "trials",
+              "accepted", "reserved")
+
+
+class RGPError(RuntimeError):
+    def __init__(self, fn: str, code: int, hip: int = 0):
+        msg = f"{fn} failed: {STATUS.get(code, code)}"
+        if code == -7:
+            msg += f" (hip error {hip})"
+        super().__init__(msg)
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64 * 3), ("pe", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("h", ctypes.c_double * 3)]
+
+
+class SolverOpts(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("levels", ctypes.c_int32), ("gn_iters", ctypes.c_int32),
+                ("pcg_iters", ctypes.c_int32), ("ls_max_trials", ctypes.c_int32),
+                ("pcg_rtol", ctypes.c_double), ("armijo_c", ctypes.c_double),
+                ("ot_eps", ctypes.c_double), ("ot_guard", ctypes.c_int32),
+                ("use_b_init", ctypes.c_int32)]
+
+
+EXPORTS = ("rgp_status_string", "rgp_last_hip_error", "rgp_default_opts", "rgp_workspace_size",
+           "rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
+           "rgp_apply_correction", "rgp_correct")
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load librgp.so (built in-tree by ``paper_2403_10706_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"librgp.so not found at {path}; build it with "
+                           "`python -m paper_2403_10706_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+    gp = ctypes.POINTER(Grid)
+    op = ctypes.POINTER(SolverOpts)
+    lib.rgp_status_string.restype = ctypes.c_char_p
+    lib.rgp_status_string.argtypes = [ctypes.c_int]
+    lib.rgp_last_hip_error.restype = ctypes.c_int
+    lib.rgp_default_opts.argtypes = [op]
+    lib.rgp_default_opts.restype = None
+    lib.rgp_workspace_size.argtypes = [ctypes.c_int, gp, ctypes.c_int, op, ctypes.POINTER(sz)]
+    lib.rgp_ot_init.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int, vp, f64, i32, vp, vp, sz, vp]
+    lib.rgp_loss_grad.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int, vp, f64, f64, vp, vp, vp,
+                                  vp, vp, sz, vp]
+    lib.rgp_gn_hvp.argtypes = [gp, ctypes.c_int, vp, vp, f64, vp, vp, vp, vp, sz, vp]
+    lib.rgp_pcg_solve.argtypes = [gp, ctypes.c_int, vp, vp, f64, vp, vp, i32, f64, vp, vp, vp, sz,
+                                  vp]
+    lib.rgp_apply_correction.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp, vp]
+    lib.rgp_correct.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int, op, vp, vp, vp, vp, vp, vp,
+                                sz, vp]
+    for name in ("rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
+                 "rgp_apply_correction", "rgp_correct", "rgp_workspace_size"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(fn: str, code: int):
+    if code != RGP_OK:
+        raise RGPError(fn, code, load().rgp_last_hip_error())
+
+
+_DT = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+
+
+def dtype_code(t: torch.dtype) -> int:
+    if t not in _DT:
+        raise TypeError(f"unsupported dtype {t}")
+    return _DT[t]
+
+
+def make_grid(shape: Sequence[int], pe: int, h: Sequence[float] = (1.0, 1.0, 1.0)) -> Grid:
+    g = Grid()
+    for d in range(3):
+        g.m[d] = int(shape[d])
+        g.h[d] = float(h[d])
+    g.pe = int(pe)
+    return g
+
+
+def field_shape(shape: Sequence[int], pe: int) -> Tuple[int, int, int]:
+    s = [int(x) for x in shape]
+    s[pe] += 1
+    return tuple(s)
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_check(*ts):
+    for t in ts:
+        if t is not None:
+            if not t.is_cuda:
+                raise ValueError("librgp works on device tensors only")
+            if not t.is_contiguous():
+                raise ValueError("tensors must be C-contiguous")
+
+
+def workspace_size(op: int, shape, pe, h, real_dtype, opts: Optional[SolverOpts] = None) -> int:
+    n = ctypes.c_size_t(0)
+    g = make_grid(shape, pe, h)
+    _check("rgp_workspace_size", load().rgp_workspace_size(
+        op, ctypes.byref(g), dtype_code(real_dtype), None if opts is None else ctypes.byref(opts),
+        ctypes.byref(n)))
+    return int(n.value)
+
+
+class Workspace:
+    """Device workspace cache (one buffer per device, grown on demand)."""
+
+    def __init__(self):
+        self._buf = {}
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        dev = torch.device(device)
+        buf = self._buf.get(dev)
+        if buf is None or buf.numel() < nbytes:
+            buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
+            self._buf[dev] = buf
+        return buf
+
+
+_WS = Workspace()
+
+
+def _ws(op, shape, pe, h, real_dtype, device, opts=None, ws=None):
+    need = workspace_size(op, shape, pe, h, real_dtype, opts)
+    if ws is None:
+        ws = _WS.get(need, device)
+    if ws.numel() < need:
+        raise ValueError(f"workspace too small ({ws.numel()} < {need} bytes)")
+    return ws, need
+
+
+def ot_init(I_plus: torch.Tensor, I_minus: torch.Tensor, pe: int, h=(1.0, 1.0, 1.0), *,
+            real_dtype=None, eps: float = 1e-3, guard: bool = True, out=None, ws=None, stream=None):
+    """Column-wise 1D OT initial field (see rgp_ot_init).  Returns (b0, n_guarded device tensor)."""
+    _dev_check(I_plus, I_minus)
+    real_dtype = real_dtype or (torch.float64 if I_plus.dtype == torch.float64 else torch.float32)
+    shape = tuple(I_plus.shape)
+    if out is None:
+        out = torch.empty(field_shape(shape, pe), dtype=real_dtype, device=I_plus.device)
+    ng = torch.zeros(1, dtype=torch.int64, device=I_plus.device)
+    wsb, need = _ws(OP_OT_INIT, shape, pe, h, real_dtype, I_plus.device, ws=ws)
+    g = make_grid(shape, pe, h)
+    _check("rgp_ot_init", load().rgp_ot_init(
+        ctypes.byref(g), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
+        dtype_code(real_dtype), _ptr(out), float(eps), int(bool(guard)), _ptr(ng), _ptr(wsb),
+        wsb.numel(), _stream_ptr(stream)))
+    return out, ng
+
+
+def loss_grad(I_plus, I_minus, b, pe, h=(1.0, 1.0, 1.0), alpha=300.0, beta=1e-4, *,
+              want_grad=True, want_hess=True, ws=None, stream=None):
+    """Objective (device tensor [J, D, S, P] in FP64), gradient and banded GN Hessian."""
+    _dev_check(I_plus, I_minus, b)
+    shape = tuple(I_plus.shape)
+    if tuple(b.shape) != field_shape(shape, pe):
+        raise ValueError(f"field shape {tuple(b.shape)} != {field_shape(shape, pe)}")
+    dev = b.device
+    jdsp = torch.empty(4, dtype=torch.float64, device=dev)
+    grad = torch.empty_like(b) if want_grad else None
+    hd = torch.empty_like(b) if want_hess else None
+    ho = torch.empty_like(b) if want_hess else None
+    wsb, _ = _ws(OP_LOSS_GRAD, shape, pe, h, b.dtype, dev, ws=ws)
+    g = make_grid(shape, pe, h)
+    _check("rgp_loss_grad", load().rgp_loss_grad(
+        ctypes.byref(g), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
+        dtype_code(b.dtype), _ptr(b), float(alpha), float(beta), _ptr(jdsp), _ptr(grad), _ptr(hd),
+        _ptr(ho), _ptr(wsb), wsb.numel(), _stream_ptr(stream)))
+    return jdsp, grad, hd, ho
+
+
+def gn_hvp(hdiag, hoff, v, shape, pe, h=(1.0, 1.0, 1.0), alpha=300.0, *, ws=None, stream=None):
+    """H_J v and v^T H_J v (device FP64 scalar tensor)."""
+    _dev_check(hdiag, hoff, v)
+    Hv = torch.empty_like(v)
+    vhv = torch.empty(1, dtype=torch.float64, device=v.device)
+    wsb, _ = _ws(OP_GN_HVP, shape, pe, h, v.dtype, v.device, ws=ws)
+    g = make_grid(shape, pe, h)
+    _check("rgp_gn_hvp", load().rgp_gn_hvp(
+        ctypes.byref(g), dtype_code(v.dtype), _ptr(hdiag), _ptr(hoff), float(alpha), _ptr(v),
+        _ptr(Hv), _ptr(vhv), _ptr(wsb), wsb.numel(), _stream_ptr(stream)))
+    return Hv, vhv
+
+
+def pcg_solve(hdiag, hoff, rhs, shape, pe, h=(1.0, 1.0, 1.0), alpha=300.0, *, maxit=10,
+              rtol=0.1, ws=None, stream=None):
+    """Jacobi-PCG on H_J x = rhs.  Returns (x, iters int32 device, relres FP64 device)."""
+    _dev_check(hdiag, hoff, rhs)
+    x = torch.empty_like(rhs)
+    it = torch.zeros(1, dtype=torch.int32, device=rhs.device)
+    rr = torch.zeros(1, dtype=torch.float64, device=rhs.device)
+    wsb, _ = _ws(OP_PCG_SOLVE, shape, pe, h, rhs.dtype, rhs.device, ws=ws)
+    g = make_grid(shape, pe, h)
+    _check("rgp_pcg_solve", load().rgp_pcg_solve(
+        ctypes.byref(g), dtype_code(rhs.dtype), _ptr(hdiag), _ptr(hoff), float(alpha), _ptr(rhs),
+        _ptr(x), int(maxit), float(rtol), _ptr(it), _ptr(rr), _ptr(wsb), wsb.numel(),
+        _stream_ptr(stream)))
+    return x, it, rr
+
+
+def apply_correction(I_plus, I_minus, b, pe, h=(1.0, 1.0, 1.0), *, stream=None):
+    """Jacobian-modulation corrected pair (T+, T-) in the image dtype."""
+    _dev_check(I_plus, I_minus, b)
+    Tp = torch.empty_like(I_plus)
+    Tm = torch.empty_like(I_minus)
+    g = make_grid(tuple(I_plus.shape), pe, h)
+    _check("rgp_apply_correction", load().rgp_apply_correction(
+        ctypes.byref(g), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
+        dtype_code(b.dtype), _ptr(b), _ptr(Tp), _ptr(Tm), _stream_ptr(stream)))
+    return Tp, Tm
+
+
+@dataclasses.dataclass
+class Options:
+    """Solver options (defaults: the paper's alpha, beta, PCG 10 iterations / rtol 0.1)."""
+
+    alpha: float = 300.0
+    beta: float = 1e-4
+    levels: int = 1
+    gn_iters: int = 5
+    pcg_iters: int = 10
+    ls_max_trials: int = 10
+    pcg_rtol: float = 0.1
+    armijo_c: float = 1e-4
+    ot_eps: float = 1e-3
+    ot_guard: bool = True
+
+    def to_c(self, use_b_init: bool = False) -> SolverOpts:
+        o = SolverOpts()
+        o.alpha, o.beta = float(self.alpha), float(self.beta)
+        o.levels, o.gn_iters, o.pcg_iters = int(self.levels), int(self.gn_iters), int(self.pcg_iters)
+        o.ls_max_trials = int(self.ls_max_trials)
+        o.pcg_rtol, o.armijo_c, o.ot_eps = float(self.pcg_rtol), float(self.armijo_c), float(self.ot_eps)
+        o.ot_guard = int(bool(self.ot_guard))
+        o.use_b_init = int(bool(use_b_init))
+        return o
+
+
+def coarsest_shape(shape, levels):
+    s = tuple(int(x) for x in shape)
+    for _ in range(levels - 1):
+        s = tuple((x + 1) // 2 for x in s)
+    return s
+
+
+def correct(I_plus, I_minus, pe, h=(1.0, 1.0, 1.0), opts: Optional[Options] = None, *,
+            real_dtype=None, b_init=None, want_images=True, want_stats=True, out=None, ws=None,
+            stream=None):
+    """The whole hot path (rgp_correct).  Returns dict(b, T_plus, T_minus, stats)."""
+    _dev_check(I_plus, I_minus, b_init)
+    opts = opts or Options()
+    real_dtype = real_dtype or (torch.float64 if I_plus.dtype == torch.float64 else torch.float32)
+    shape = tuple(I_plus.shape)
+    dev = I_plus.device
+    copts = opts.to_c(use_b_init=b_init is not None)
+    b = out if out is not None else torch.empty(field_shape(shape, pe), dtype=real_dtype, device=dev)
+    Tp = torch.empty_like(I_plus) if want_images else None
+    Tm = torch.empty_like(I_minus) if want_images else None
+    stats = (torch.empty(STAT_HEADER + opts.levels * opts.gn_iters * STAT_FIELDS,
+                         dtype=torch.float64, device=dev) if want_stats else None)
+    wsb, _ = _ws(OP_CORRECT, shape, pe, h, real_dtype, dev, opts=copts, ws=ws)
+    g = make_grid(shape, pe, h)
+    _check("rgp_correct", load().rgp_correct(
+        ctypes.byref(g), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
+        dtype_code(real_dtype), ctypes.byref(copts), _ptr(b_init), _ptr(b), _ptr(Tp), _ptr(Tm),
+        _ptr(stats), _ptr(wsb), wsb.numel(), _stream_ptr(stream)))
+    return dict(b=b, T_plus=Tp, T_minus=Tm, stats=stats)
+
+
+def parse_stats(stats: torch.Tensor, levels: int, gn_iters: int):
+    """Host view of a stats buffer: (header dict, list of per-level lists of record dicts)."""
+    s = stats.detach().double().cpu().numpy()
+    head = dict(ot_guarded=int(s[0]) if math.isfinite(s[0]) else -1, ot_shift=float(s[1]))
+    recs = s[STAT_HEADER:].reshape(levels, gn_iters, STAT_FIELDS)
+    out = []
+    for lv in range(levels):
+        out.append([dict(zip(STAT_NAMES, map(float, recs[lv, it]))) for it in range(gn_iters)])
+    return head, out

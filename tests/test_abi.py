@@ -1,0 +1,114 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point that
+``include/rgp.h`` declares, and rejects bad arguments synchronously without touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rgp.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:[a-z_]+\s*\*?\s+)+\**(rgp_[a-z_]+)\s*\(", src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2403_10706_amd import rgp
+    return rgp.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve", "rgp_correct"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for n in _declared():
+        assert hasattr(lib, n), n
+    from paper_2403_10706_amd import rgp
+    assert set(_declared()) == set(rgp.EXPORTS)
+
+
+def test_status_strings_and_defaults(lib):
+    from paper_2403_10706_amd import rgp
+    assert lib.rgp_status_string(0) == b"ok"
+    assert lib.rgp_status_string(-8).startswith(b"workspace")
+    o = rgp.SolverOpts()
+    lib.rgp_default_opts(ctypes.byref(o))
+    assert o.alpha == 300.0 and o.beta == 1e-4 and o.pcg_iters == 10 and o.pcg_rtol == 0.1
+    assert o.ls_max_trials == 10 and o.ot_guard == 1
+
+
+def test_workspace_size_and_validation(lib):
+    from paper_2403_10706_amd import rgp
+    g = rgp.make_grid((144, 168, 111), 1)
+    n = ctypes.c_size_t(0)
+    for op in range(6):
+        o = rgp.SolverOpts()
+        lib.rgp_default_opts(ctypes.byref(o))
+        o.levels = 3
+        assert lib.rgp_workspace_size(op, ctypes.byref(g), rgp.F32, ctypes.byref(o),
+                                      ctypes.byref(n)) == 0
+        assert n.value > 0 and n.value % 256 == 0
+    # the full solve needs the pyramid and ~12 field arrays
+    o.levels = 3
+    lib.rgp_workspace_size(rgp.OP_CORRECT, ctypes.byref(g), rgp.F32, ctypes.byref(o),
+                           ctypes.byref(n))
+    nb = 144 * 169 * 111 * 4
+    assert n.value >= 12 * nb
+    # bad grids / dtypes / options are rejected before any device work
+    bad = rgp.make_grid((144, 1, 111), 1)
+    assert lib.rgp_workspace_size(1, ctypes.byref(bad), rgp.F32, None, ctypes.byref(n)) == -2
+    bad = rgp.make_grid((4, 4, 4), 3)
+    assert lib.rgp_workspace_size(1, ctypes.byref(bad), rgp.F32, None, ctypes.byref(n)) == -1
+    bad = rgp.make_grid((4, 4, 4), 1, h=(1.0, 0.0, 1.0))
+    assert lib.rgp_workspace_size(1, ctypes.byref(bad), rgp.F32, None, ctypes.byref(n)) == -1
+    assert lib.rgp_workspace_size(1, ctypes.byref(g), rgp.BF16, None, ctypes.byref(n)) == -3
+    o.levels = 0
+    assert lib.rgp_workspace_size(rgp.OP_CORRECT, ctypes.byref(g), rgp.F32, ctypes.byref(o),
+                                  ctypes.byref(n)) == -1
+    o.levels = 9   # 168 cells along PE halve to 1 cell on the ninth level
+    assert lib.rgp_workspace_size(rgp.OP_CORRECT, ctypes.byref(g), rgp.F32, ctypes.byref(o),
+                                  ctypes.byref(n)) == -2
+
+
+def test_entry_points_reject_bad_arguments_without_device(lib):
+    from paper_2403_10706_amd import rgp
+    g = rgp.make_grid((8, 9, 10), 1)
+    fake = ctypes.c_void_p(0x1000)
+    # missing workspace
+    assert lib.rgp_loss_grad(ctypes.byref(g), rgp.F32, fake, fake, rgp.F32, fake, 300.0, 1e-4,
+                             fake, None, None, None, None, 0, None) == -8
+    # hdiag without hoff
+    assert lib.rgp_loss_grad(ctypes.byref(g), rgp.F32, fake, fake, rgp.F32, fake, 300.0, 1e-4,
+                             fake, None, fake, None, fake, 1 << 30, None) == -1
+    # FP64 images with FP32 arithmetic is not offered
+    assert lib.rgp_loss_grad(ctypes.byref(g), rgp.F64, fake, fake, rgp.F32, fake, 300.0, 1e-4,
+                             fake, None, None, None, fake, 1 << 30, None) == -3
+    # negative weight
+    assert lib.rgp_loss_grad(ctypes.byref(g), rgp.F32, fake, fake, rgp.F32, fake, -1.0, 1e-4,
+                             fake, None, None, None, fake, 1 << 30, None) == -1
+    assert lib.rgp_pcg_solve(ctypes.byref(g), rgp.F32, fake, fake, 300.0, fake, fake, 0, 0.1,
+                             None, None, fake, 1 << 30, None) == -1
+    assert lib.rgp_ot_init(ctypes.byref(g), rgp.BF16, fake, fake, rgp.BF16, fake, 1e-3, 1, None,
+                           fake, 1 << 30, None) == -3
+    assert lib.rgp_ot_init(None, rgp.F32, fake, fake, rgp.F32, fake, 1e-3, 1, None, fake,
+                           1 << 30, None) == -1
+    o = rgp.SolverOpts()
+    lib.rgp_default_opts(ctypes.byref(o))
+    o.use_b_init = 1
+    assert lib.rgp_correct(ctypes.byref(g), rgp.F32, fake, fake, rgp.F32, ctypes.byref(o), None,
+                           fake, None, None, None, fake, 1 << 30, None) == -1
+    o.use_b_init = 0
+    o.ls_max_trials = 11
+    assert lib.rgp_correct(ctypes.byref(g), rgp.F32, fake, fake, rgp.F32, ctypes.byref(o), None,
+                           fake, None, None, None, fake, 1 << 30, None) == -1
+    # misaligned workspace
+    o.ls_max_trials = 10
+    assert lib.rgp_correct(ctypes.byref(g), rgp.F32, fake, fake, rgp.F32, ctypes.byref(o), None,
+                           fake, None, None, None, ctypes.c_void_p(0x1004), 1 << 30, None) == -8
