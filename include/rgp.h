@@ -18,8 +18,10 @@
  *  - Scalars produced on the device (J, iteration counts, ...) are written to caller-owned
  *    DEVICE memory; no call synchronises the host.  Every call is enqueued on `stream` (a
  *    hipStream_t; NULL is the default stream) and returns as soon as the work is enqueued.
- *  - `ws`/`ws_bytes` is a caller-owned device workspace of at least rgp_workspace_size() bytes.
- *    The library never allocates device memory.  Calls that share a workspace must not overlap.
+ *  - `ws`/`ws_bytes` is a caller-owned device workspace of at least rgp_workspace_size() bytes,
+ *    256-byte aligned and ZERO-FILLED before its first use; the library keeps the parts it relies
+ *    on at zero between calls, so a workspace can be reused by any entry point afterwards.  The
+ *    library never allocates device memory.  Calls that share a workspace must not overlap.
  *  - Argument errors are reported synchronously through the return value; nothing is enqueued
  *    then.  A violated barrier (|d b / d v| >= 1 somewhere) is a value, J = +inf, not an error.
  */
@@ -111,7 +113,7 @@ rgp_status rgp_ot_init(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus
 /* Objective J = D + alpha S + beta P of Eq. (6) at b, with D the SSD of the mass-preserving
  * transforms of Eq. (1)-(2), S the smoothness term of Eq. (5) (seven-point negative Laplacian on
  * the staggered field, Neumann boundaries) and P the barrier of Eq. (3); all with weight vol/2.
- * jdsp_dev (device, 4 doubles): J, D, S, P (J = P = +inf when the barrier is violated).
+ * jdsp_dev (device, 4 doubles, nullable): J, D, S, P (J = P = +inf when the barrier is violated).
  * Optional outputs (field arrays, nullable): grad = grad J; hdiag/hoff = the Gauss-Newton
  * Hessian of Sec. 2.3.1 in banded form - hdiag its diagonal (the Jacobi preconditioner) and
  * hoff[k] the coupling of PE nodes k and k+1 (0 at the last node); the cross-axis couplings are

@@ -104,29 +104,24 @@ struct Carver {
   }
 };
 
+// Slots of block sums (kMaxGrid blocks x kPartStride doubles each).
+enum PartSlot { kPartLoss = 0, kPartPcg0, kPartPcg1, kPartTrial0, kPartTrial1, kPartTrial2,
+                kPartHvp, kPartShift, kPartSlots };
+
 struct Control {
   State* st;
-  unsigned* counter;
+  PcgSlot* slots;
   unsigned long long* guarded;
-  double* partials;
+  double* part;
+  double* slot(int k) const { return part + (size_t)k * kMaxGrid * kPartStride; }
 };
 
-size_t partial_doubles(const Geom& g) {
-  size_t n = 0;
-  n = std::max(n, (size_t)5 * loss_grad_blocks(g));
-  n = std::max(n, (size_t)18 * trial_blocks(g));
-  n = std::max(n, (size_t)7 * pcg_blocks(g));
-  n = std::max(n, (size_t)1 * hvp_blocks(g));
-  n = std::max(n, (size_t)2 * shift_blocks(g.ncell));
-  return n;
-}
-
-Control carve_control(Carver& c, const Geom& finest) {
+Control carve_control(Carver& c) {
   Control k;
   k.st = static_cast<State*>(c.take(sizeof(State)));
-  k.counter = static_cast<unsigned*>(c.take(sizeof(unsigned)));
+  k.slots = static_cast<PcgSlot*>(c.take(2 * sizeof(PcgSlot)));
   k.guarded = static_cast<unsigned long long*>(c.take(sizeof(unsigned long long)));
-  k.partials = static_cast<double*>(c.take(partial_doubles(finest) * sizeof(double)));
+  k.part = static_cast<double*>(c.take((size_t)kPartSlots * kMaxGrid * kPartStride * sizeof(double)));
   return k;
 }
 
@@ -167,7 +162,7 @@ struct CorrectWs {
 CorrectWs carve_correct(void* ws, const Level* lv, int levels, DType real) {
   Carver c(ws);
   CorrectWs w;
-  w.ctl = carve_control(c, lv[0].g);
+  w.ctl = carve_control(c);
   const size_t rs = dsize(real);
   for (int l = 0; l < kMaxLevels; ++l) w.img[l][0] = w.img[l][1] = nullptr;
   for (int l = 1; l < levels; ++l) {
@@ -193,7 +188,7 @@ CorrectWs carve_correct(void* ws, const Level* lv, int levels, DType real) {
 
 size_t correct_bytes(const Level* lv, int levels, DType real) {
   Carver c(nullptr);
-  carve_control(c, lv[0].g);
+  carve_control(c);
   const size_t rs = dsize(real);
   for (int l = 1; l < levels; ++l) {
     c.take(lv[l].g.ncell * rs);
@@ -226,13 +221,17 @@ rgp_status check_opts(const rgp_solver_opts* o) {
   return RGP_OK;
 }
 
-// One Gauss-Newton solve of `iters` steps on one level.  b enters in B[cur]; on return the final
-// field is in B[cur].
+// `gn_iters` Gauss-Newton steps on one level.  b enters in B[cur]; on return the final field is
+// in B[cur].
 hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const void* Im, DType img,
                      DType real, const rgp_solver_opts* o, int& cur, double* records,
                      hipStream_t s) {
   hipError_t e;
+  const Control& k = w.ctl;
+  const Launch Llg = plan_loss_grad(g, real);
+  const Launch Lpcg = plan_pcg(g, real);
   for (int it = 0; it < o->gn_iters; ++it) {
+    double* rec = records ? records + (size_t)it * kStatFields : nullptr;
     LossGradArgs la{};
     la.g = g;
     la.Ip = Ip;
@@ -240,17 +239,15 @@ hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const vo
     la.b_in = w.B[cur];
     la.q = w.X;
     la.step = it > 0;
+    la.level_start = it == 0;
     la.b_out = it > 0 ? w.B[1 - cur] : nullptr;
     la.grad = w.G;
     la.diag = w.Dg;
     la.off = w.Of;
     la.alpha = o->alpha;
     la.beta = o->beta;
-    la.st = w.ctl.st;
-    la.partials = w.ctl.partials;
-    la.counter = w.ctl.counter;
-    la.record = records ? records + (size_t)it * kStatFields : nullptr;
-    la.gn_mode = 1;
+    la.st = k.st;
+    la.part = k.slot(kPartLoss);
     if ((e = launch_loss_grad(la, img, real, s)) != hipSuccess) return e;
     if (it > 0) cur = 1 - cur;
 
@@ -270,13 +267,17 @@ hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const vo
       pa.p_out = w.P[out];
       pa.w_out = w.W[out];
       pa.alpha = o->alpha;
-      pa.st = w.ctl.st;
-      pa.partials = w.ctl.partials;
-      pa.counter = w.ctl.counter;
+      pa.st = k.st;
+      pa.slots = k.slots;
+      pa.part_prev = k.slot(kPartPcg0 + in);
+      pa.part = k.slot(kPartPcg0 + out);
+      pa.nprod = Lpcg.grid;
       pa.iter = i;
       pa.maxit = o->pcg_iters;
       pa.rtol = o->pcg_rtol;
       pa.gn_mode = 1;
+      pa.lf = LossFinalArgs{k.slot(kPartLoss), Llg.grid, g.vol, o->alpha, o->beta, k.st,
+                            nullptr, rec, 1};
       if ((e = launch_pcg_step(pa, real, s)) != hipSuccess) return e;
     }
 
@@ -294,13 +295,24 @@ hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const vo
       ta.alpha = o->alpha;
       ta.beta = o->beta;
       ta.armijo_c = o->armijo_c;
-      ta.st = w.ctl.st;
-      ta.partials = w.ctl.partials;
-      ta.counter = w.ctl.counter;
-      ta.record = records ? records + (size_t)it * kStatFields : nullptr;
+      ta.st = k.st;
+      ta.part = k.slot(kPartTrial0 + p);
       ta.first = first;
-      ta.last_pass = (first + nc >= o->ls_max_trials) ? 1 : 0;
-      if ((e = launch_trial(ta, nc, img, real, s)) != hipSuccess) return e;
+      ta.nc = nc;
+      if ((e = launch_trial(ta, img, real, s)) != hipSuccess) return e;
+      DecideArgs da{};
+      da.part_prev = ta.part;
+      da.nprod_prev = plan_trial(g, real, nc).grid;
+      da.prev_first = first;
+      da.prev_nc = nc;
+      da.total = o->ls_max_trials;
+      da.vol = g.vol;
+      da.alpha = o->alpha;
+      da.beta = o->beta;
+      da.armijo_c = o->armijo_c;
+      da.st = k.st;
+      da.record = rec;
+      if ((e = launch_decide(da, s)) != hipSuccess) return e;
       first += nc;
     }
   }
@@ -308,7 +320,7 @@ hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const vo
     ApplyArgs aa{};
     aa.b = w.B[cur];
     aa.q = w.X;
-    aa.st = w.ctl.st;
+    aa.st = k.st;
     aa.n = g.nnode;
     if ((e = launch_apply_step(aa, real, s)) != hipSuccess) return e;
   }
@@ -363,10 +375,10 @@ rgp_status rgp_workspace_size(rgp_op op, const rgp_grid* grid, rgp_dtype real_t,
     case RGP_OP_LOSS_GRAD:
     case RGP_OP_GN_HVP:
     case RGP_OP_APPLY_CORRECTION:
-      carve_control(c, g);
+      carve_control(c);
       break;
     case RGP_OP_PCG_SOLVE:
-      carve_control(c, g);
+      carve_control(c);
       for (int i = 0; i < 6; ++i) c.take(g.nnode * dsize(dr));
       break;
     case RGP_OP_CORRECT: {
@@ -406,18 +418,19 @@ rgp_status rgp_ot_init(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const Geom g = geom_of(grid);
   Carver c(ws);
-  Control k = carve_control(c, g);
+  Control k = carve_control(c);
   unsigned long long* gd = n_guarded_dev ? reinterpret_cast<unsigned long long*>(n_guarded_dev)
                                          : k.guarded;
-  RGP_HIP(launch_reset(SetStateArgs{k.st, k.counter, gd}, s));
-  RGP_HIP(launch_shift(ShiftArgs{I_plus, I_minus, g.ncell, ot_eps, k.st, k.partials, k.counter},
-                       di, s));
+  RGP_HIP(launch_shift(ShiftArgs{I_plus, I_minus, g.ncell, k.slot(kPartShift), gd}, di, s));
   OtArgs oa{};
   oa.g = g;
   oa.Ip = I_plus;
   oa.Im = I_minus;
   oa.b0 = b0;
   oa.st = k.st;
+  oa.shift_part = k.slot(kPartShift);
+  oa.shift_nprod = shift_grid(g.ncell);
+  oa.eps = ot_eps;
   oa.guard = guard ? 1 : 0;
   oa.guard_slope = kGuardSlope;
   oa.guarded = gd;
@@ -433,7 +446,7 @@ rgp_status rgp_loss_grad(const rgp_grid* grid, rgp_dtype img_t, const void* I_pl
   if (st != RGP_OK) return st;
   DType di, dr;
   if ((st = check_types(img_t, real_t, &di, &dr)) != RGP_OK) return st;
-  if (!I_plus || !I_minus || !b || !jdsp_dev) return RGP_EINVAL;
+  if (!I_plus || !I_minus || !b) return RGP_EINVAL;
   if ((hdiag == nullptr) != (hoff == nullptr)) return RGP_EINVAL;
   if (!(alpha >= 0.0) || !(beta >= 0.0) || !std::isfinite(alpha) || !std::isfinite(beta))
     return RGP_EINVAL;
@@ -441,8 +454,7 @@ rgp_status rgp_loss_grad(const rgp_grid* grid, rgp_dtype img_t, const void* I_pl
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const Geom g = geom_of(grid);
   Carver c(ws);
-  Control k = carve_control(c, g);
-  RGP_HIP(launch_reset(SetStateArgs{k.st, k.counter, nullptr}, s));
+  Control k = carve_control(c);
   LossGradArgs la{};
   la.g = g;
   la.Ip = I_plus;
@@ -454,10 +466,14 @@ rgp_status rgp_loss_grad(const rgp_grid* grid, rgp_dtype img_t, const void* I_pl
   la.alpha = alpha;
   la.beta = beta;
   la.st = k.st;
-  la.partials = k.partials;
-  la.counter = k.counter;
-  la.jdsp = jdsp_dev;
+  la.part = k.slot(kPartLoss);
   RGP_HIP(launch_loss_grad(la, di, dr, s));
+  if (jdsp_dev) {
+    const Launch L = plan_loss_grad(g, dr);
+    RGP_HIP(launch_loss_final(
+        LossFinalArgs{k.slot(kPartLoss), L.grid, g.vol, alpha, beta, k.st, jdsp_dev, nullptr, 0},
+        s));
+  }
   return RGP_OK;
 }
 
@@ -474,8 +490,7 @@ rgp_status rgp_gn_hvp(const rgp_grid* grid, rgp_dtype real_t, const void* hdiag,
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const Geom g = geom_of(grid);
   Carver c(ws);
-  Control k = carve_control(c, g);
-  RGP_HIP(launch_reset(SetStateArgs{k.st, k.counter, nullptr}, s));
+  Control k = carve_control(c);
   HvpArgs ha{};
   ha.g = g;
   ha.diag = hdiag;
@@ -483,10 +498,9 @@ rgp_status rgp_gn_hvp(const rgp_grid* grid, rgp_dtype real_t, const void* hdiag,
   ha.v = v;
   ha.Hv = Hv;
   ha.alpha = alpha;
-  ha.partials = k.partials;
-  ha.counter = k.counter;
-  ha.vHv = vHv_dev;
+  ha.part = vHv_dev ? k.slot(kPartHvp) : nullptr;
   RGP_HIP(launch_hvp(ha, dr, s));
+  if (vHv_dev) RGP_HIP(launch_sum_final(k.slot(kPartHvp), plan_hvp(g, dr).grid, vHv_dev, s));
   return RGP_OK;
 }
 
@@ -506,10 +520,10 @@ rgp_status rgp_pcg_solve(const rgp_grid* grid, rgp_dtype real_t, const void* hdi
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const Geom g = geom_of(grid);
   Carver c(ws);
-  Control k = carve_control(c, g);
+  Control k = carve_control(c);
   void* vec[6];
   for (int i = 0; i < 6; ++i) vec[i] = c.take(g.nnode * dsize(dr));
-  RGP_HIP(launch_reset(SetStateArgs{k.st, k.counter, nullptr}, s));
+  const Launch L = plan_pcg(g, dr);
   for (int i = 0; i <= maxit; ++i) {
     PcgArgs pa{};
     pa.g = g;
@@ -527,8 +541,10 @@ rgp_status rgp_pcg_solve(const rgp_grid* grid, rgp_dtype real_t, const void* hdi
     pa.w_out = vec[3 * out + 2];
     pa.alpha = alpha;
     pa.st = k.st;
-    pa.partials = k.partials;
-    pa.counter = k.counter;
+    pa.slots = k.slots;
+    pa.part_prev = k.slot(kPartPcg0 + in);
+    pa.part = k.slot(kPartPcg0 + out);
+    pa.nprod = L.grid;
     pa.iter = i;
     pa.maxit = maxit;
     pa.rtol = rtol;
@@ -579,7 +595,7 @@ rgp_status rgp_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus
   CorrectWs w = carve_correct(ws, lv, L, dr);
   const size_t rs = dsize(dr);
 
-  RGP_HIP(launch_reset(SetStateArgs{w.ctl.st, w.ctl.counter, w.ctl.guarded}, s));
+  RGP_HIP(launch_reset(SetStateArgs{w.ctl.st, w.ctl.guarded}, s));
   const int64_t nrec = (int64_t)L * opts->gn_iters;
   if (stats_dev)
     RGP_HIP(launch_fill(stats_dev, RGP_STAT_HEADER + nrec * kStatFields, std::nan(""), s));
@@ -610,8 +626,8 @@ rgp_status rgp_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus
   if (opts->use_b_init) {
     RGP_HIP(hipMemcpyAsync(w.B[0], b_init, top.g.nnode * rs, hipMemcpyDeviceToDevice, s));
   } else {
-    RGP_HIP(launch_shift(ShiftArgs{imgs[L - 1][0], imgs[L - 1][1], top.g.ncell, opts->ot_eps,
-                                   w.ctl.st, w.ctl.partials, w.ctl.counter},
+    RGP_HIP(launch_shift(ShiftArgs{imgs[L - 1][0], imgs[L - 1][1], top.g.ncell,
+                                   w.ctl.slot(kPartShift), w.ctl.guarded},
                          ity[L - 1], s));
     OtArgs oa{};
     oa.g = top.g;
@@ -619,6 +635,9 @@ rgp_status rgp_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus
     oa.Im = imgs[L - 1][1];
     oa.b0 = w.B[0];
     oa.st = w.ctl.st;
+    oa.shift_part = w.ctl.slot(kPartShift);
+    oa.shift_nprod = shift_grid(top.g.ncell);
+    oa.eps = opts->ot_eps;
     oa.guard = opts->ot_guard ? 1 : 0;
     oa.guard_slope = kGuardSlope;
     oa.guarded = w.ctl.guarded;

@@ -18,7 +18,7 @@
 namespace rgp {
 
 // ------------------------------------------------------------------------------------------
-// Positivity shift: min and max|.| over both images.
+// Positivity shift: block-wise min and max|.| over both images; the OT kernel combines them.
 // ------------------------------------------------------------------------------------------
 template <typename TI>
 __global__ __launch_bounds__(kBlock) void k_shift(ShiftArgs a) {
@@ -36,8 +36,7 @@ __global__ __launch_bounds__(kBlock) void k_shift(ShiftArgs a) {
     lo = fmin(lo, __shfl_xor(lo, off, kWave));
     hi = fmax(hi, __shfl_xor(hi, off, kWave));
   }
-  __shared__ double sl[kWaves], sh[kWaves];
-  __shared__ int is_last;
+  __shared__ double sl[kBlock / kWave], sh[kBlock / kWave];
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   if (lane == 0) {
     sl[wv] = lo;
@@ -45,31 +44,45 @@ __global__ __launch_bounds__(kBlock) void k_shift(ShiftArgs a) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 1; w < kWaves; ++w) {
+    for (int w = 0; w < kBlock / kWave; ++w) {
       lo = fmin(lo, sl[w]);
       hi = fmax(hi, sh[w]);
     }
-    lo = fmin(lo, sl[0]);
-    hi = fmax(hi, sh[0]);
-    a.partials[2 * blockIdx.x + 0] = lo;
-    a.partials[2 * blockIdx.x + 1] = hi;
-    __threadfence();
-    const unsigned prev = atomicAdd(a.counter, 1u);
-    is_last = prev == gridDim.x - 1u;
+    a.part[(size_t)blockIdx.x * kPartStride + 0] = lo;
+    a.part[(size_t)blockIdx.x * kPartStride + 1] = hi;
+    if (blockIdx.x == 0 && a.guarded) *a.guarded = 0ull;
+  }
+}
+
+// Shift from the block-wise extrema (every thread of the calling block gets it).
+__device__ __forceinline__ double shift_from(const double* part, unsigned nprod, double eps,
+                                             bool empty) {
+  __shared__ double sl[kBlock / kWave], sh[kBlock / kWave];
+  double lo = inf_d(), hi = 0.0;
+  for (unsigned b = threadIdx.x; b < nprod; b += blockDim.x) {
+    lo = fmin(lo, part[(size_t)b * kPartStride + 0]);
+    hi = fmax(hi, part[(size_t)b * kPartStride + 1]);
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, kWave));
+    hi = fmax(hi, __shfl_xor(hi, off, kWave));
+  }
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  if (lane == 0) {
+    sl[wv] = lo;
+    sh[wv] = hi;
   }
   __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  if (threadIdx.x == 0) {
-    double L = inf_d(), H = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b) {
-      L = fmin(L, a.partials[2 * b + 0]);
-      H = fmax(H, a.partials[2 * b + 1]);
-    }
-    if (a.n == 0) L = 0.0;
-    a.st->ot_shift = fmax(0.0, -L) + a.eps * H;
-    *a.counter = 0u;
+  lo = inf_d();
+  hi = 0.0;
+  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+    lo = fmin(lo, sl[w]);
+    hi = fmax(hi, sh[w]);
   }
+  __syncthreads();
+  if (empty) lo = 0.0;
+  return fmax(0.0, -lo) + eps * hi;
 }
 
 // Largest i in [-1, m] with C[i] < r (C[-1] = -inf), i.e. lower_bound - 1.
@@ -110,7 +123,8 @@ __global__ __launch_bounds__(kBlock) void k_ot(OtArgs a, int nc) {
   const TI* __restrict__ Ip = static_cast<const TI*>(a.Ip);
   const TI* __restrict__ Im = static_cast<const TI*>(a.Im);
   TR* __restrict__ b0 = static_cast<TR*>(a.b0);
-  const double s = a.st->ot_shift;
+  const double s = shift_from(a.shift_part, a.shift_nprod, a.eps, g.ncell == 0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.st->ot_shift = s;
   const double hp = g.hp;
 
   const int c = threadIdx.x % nc;
@@ -226,15 +240,15 @@ __global__ __launch_bounds__(kBlock) void k_ot(OtArgs a, int nc) {
   }
 }
 
-unsigned shift_blocks(int64_t n) {
-  int64_t nb = (n + kBlock * 8 - 1) / (kBlock * 8);
+unsigned shift_grid(int64_t n) {
+  int64_t nb = (n + kBlock * 16 - 1) / (kBlock * 16);
   if (nb < 1) nb = 1;
-  if (nb > 2048) nb = 2048;
+  if (nb > kMaxGrid) nb = kMaxGrid;
   return (unsigned)nb;
 }
 
 hipError_t launch_shift(const ShiftArgs& a, DType img, hipStream_t s) {
-  const unsigned nb = shift_blocks(a.n);
+  const unsigned nb = shift_grid(a.n);
   if (img == DType::F64)
     hipLaunchKernelGGL(k_shift<double>, dim3(nb), dim3(kBlock), 0, s, a);
   else if (img == DType::F32)

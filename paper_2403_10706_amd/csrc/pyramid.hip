@@ -106,7 +106,6 @@ __global__ void k_reset(SetStateArgs a) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     State z = {};
     *a.st = z;
-    if (a.counter) *a.counter = 0u;
     if (a.guarded) *a.guarded = 0ull;
   }
 }

@@ -17,8 +17,7 @@
 namespace rgp {
 
 constexpr int kWave = 64;         // CDNA wavefront width
-constexpr int kBlock = 256;       // threads per workgroup (4 wavefronts)
-constexpr int kWaves = kBlock / kWave;
+constexpr int kBlock = 256;       // threads per workgroup of the small kernels
 
 // bfloat16 image storage: upper 16 bits of an IEEE binary32.
 struct bf16_t {
@@ -57,33 +56,73 @@ __host__ __device__ inline int64_t node_base(const Geom& g, int64_t col) {
   return ix * g.nxs + iy * g.nys;
 }
 
-// Per-pair device scalars of the solver.  All reductions are accumulated in FP64 in a fixed
-// order, so results are bitwise reproducible run to run.
+// Per-pair device scalars of the solver (written by one designated block of a kernel and read by
+// later kernels only, so kernel boundaries order every access).
 struct State {
   // objective at the current iterate
   double J, D, S, P, gnorm2;
   // line search
   double gq, sbq, sqq;      // grad.q, sum dB.dQ / h^2, sum dQ.dQ / h^2 (S is quadratic in gamma)
   double gamma;
-  int32_t accepted, trials, gn_stop, ls_done;
-  // PCG (Chronopoulos-Gear recurrences for r^T z and r^T r)
-  double alpha, beta, rz, rr, bnorm2, relres;
-  int32_t pcg_status, pcg_iters;
+  int32_t accepted, trials, gn_stop, pad0;
+  // PCG summary of the current GN step
+  double relres;
+  int32_t pcg_iters, pad1;
   // OT
   double ot_shift;
-  int64_t ot_guarded;
   double pad[4];
 };
 
-enum PcgStatus : int32_t { kPcgRunning = 0, kPcgFinish = 1, kPcgDone = 2 };
+// PCG recurrence scalars, double-buffered by iteration parity: kernel i reads slot (i-1)&1 and its
+// block 0 writes slot i&1.
+struct PcgSlot {
+  double rz, rr, bnorm2, relres;
+  int32_t status, iters;
+  double pad[2];
+};
+
+enum PcgStatus : int32_t { kPcgRunning = 0, kPcgDone = 2 };
 
 // Stats record written once per Gauss-Newton step.
 constexpr int kStatFields = 12;
 
+// Partial sums: every reducing kernel writes kPartStride doubles per block (plain stores); the
+// consumer (a later kernel) reduces them in block order.  Grids are capped at kMaxGrid blocks.
+constexpr int kPartStride = 24;
+constexpr int kMaxGrid = 256;
+
+// Column-run tiling: a tile is 64 consecutive columns x S consecutive PE nodes, owned by one
+// wavefront.  Tiles are split into 8 contiguous ranges, one per XCD (blocks are dealt to the XCDs
+// round-robin), and the wavefronts of an XCD stride through its range.
+struct WaveIter {
+  int64_t t, end, stride;
+};
+
+__device__ __forceinline__ WaveIter wave_iter(int64_t ntiles) {
+  const unsigned G = gridDim.x, wpb = blockDim.x / 64u, w = threadIdx.x / 64u;
+  unsigned nxcd = 1, xcd = 0, lb = blockIdx.x, gl = G;
+  if (G >= 8u && G % 8u == 0u) {
+    nxcd = 8u;
+    xcd = blockIdx.x % 8u;
+    lb = blockIdx.x / 8u;
+    gl = G / 8u;
+  }
+  WaveIter it;
+  const int64_t lo = ntiles * xcd / nxcd, hi = ntiles * (xcd + 1) / nxcd;
+  it.t = lo + (int64_t)lb * wpb + w;
+  it.end = hi;
+  it.stride = (int64_t)gl * wpb;
+  return it;
+}
+
 // ----------------------------------------------------------------------------------------
-// Reductions: wavefront shuffles, then LDS across the 4 wavefronts, then per-block partials in
-// global memory; the last block to arrive reduces the partials in block order.
+// Reductions: wavefront shuffles, then LDS across the wavefronts of the block.  A producer kernel
+// stores its block sums with plain stores; a consumer kernel reduces all blocks in block order.
+// No atomics and no fences: visibility comes from the kernel boundary, and the fixed order makes
+// every result bitwise reproducible.
 // ----------------------------------------------------------------------------------------
+
+constexpr int kMaxWaves = 16;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -92,8 +131,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double (*sh)[kWaves]) {
+__device__ __forceinline__ void block_sum(double (&v)[K]) {
+  __shared__ double sh[K > 0 ? K : 1][kMaxWaves];
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const double s = wave_sum(v[k]);
@@ -103,55 +144,33 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double (*sh)[kWaves]) 
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) s += sh[k][w];
+    for (int w = 0; w < nw; ++w) s += sh[k][w];
     v[k] = s;
   }
   __syncthreads();
 }
 
-// Writes this block's K partial sums and returns true in the last block to arrive (all threads of
-// that block see true).  The last block then calls reduce_partials and must reset the counter.
+// Block sums of v stored at part[blockIdx.x * kPartStride + k].
 template <int K>
-__device__ bool publish_partials(double (&v)[K], double* partials, unsigned* counter,
-                                 unsigned block_id, unsigned nblocks) {
-  __shared__ double sh[K > 0 ? K : 1][kWaves];
-  __shared__ int is_last;
-  block_sum<K>(v, sh);
+__device__ __forceinline__ void store_partials(double (&v)[K], double* part) {
+  block_sum<K>(v);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) partials[(size_t)block_id * K + k] = v[k];
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    is_last = (prev == nblocks - 1u);
+    for (int k = 0; k < K; ++k) part[(size_t)blockIdx.x * kPartStride + k] = v[k];
   }
-  __syncthreads();
-  const bool last = is_last != 0;
-  if (last) __threadfence();
-  return last;
 }
 
-// Fixed-order reduction of the partials (called by every thread of the last block).
+// Every thread of the calling block obtains the sums over nprod producer blocks.
 template <int K>
-__device__ void reduce_partials(double (&out)[K], const double* partials, unsigned nblocks) {
-  __shared__ double sh[K > 0 ? K : 1][kWaves];
+__device__ __forceinline__ void reduce_partials(double (&out)[K], const double* part,
+                                                unsigned nprod) {
 #pragma unroll
   for (int k = 0; k < K; ++k) out[k] = 0.0;
-  for (unsigned b = threadIdx.x; b < nblocks; b += kBlock) {
+  for (unsigned b = threadIdx.x; b < nprod; b += blockDim.x) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) out[k] += partials[(size_t)b * K + k];
+    for (int k = 0; k < K; ++k) out[k] += part[(size_t)b * kPartStride + k];
   }
-  block_sum<K>(out, sh);
-}
-
-// Block id remapped so that each XCD (blocks are dealt round-robin to the 8 XCDs) works on a
-// contiguous range of tiles, which keeps stencil neighbours in the same L2.
-__device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned nblocks) {
-  constexpr unsigned kXcd = 8;
-  const unsigned per = nblocks / kXcd;
-  const unsigned full = per * kXcd;
-  if (bid >= full) return bid;
-  return (bid % kXcd) * per + bid / kXcd;
+  block_sum<K>(out);
 }
 
 __device__ __forceinline__ double inf_d() { return __longlong_as_double(0x7ff0000000000000LL); }

@@ -40,24 +40,41 @@ __device__ __forceinline__ bf16_t from_real<bf16_t>(float v) { return f32_to_bf1
 template <>
 __device__ __forceinline__ bf16_t from_real<bf16_t>(double v) { return f32_to_bf16((float)v); }
 
+// Launch shape of a tiled kernel: grid of `grid` blocks of `block` threads over `ntiles` tiles of
+// 64 columns x S nodes.
+struct Launch {
+  unsigned grid, block;
+  int S;
+  int64_t ntiles;
+};
+
 struct LossGradArgs {
   Geom g;
   const void* Ip;
   const void* Im;
   const void* b_in;
   const void* q;      // step direction (used when step != 0)
-  void* b_out;        // receives b_in + gamma q (or b_in); may be null when step == 0
+  void* b_out;        // receives b_in + gamma q (step != 0)
   void* grad;         // nullable
   void* diag;         // nullable (then off is ignored)
   void* off;
   double alpha, beta;
   State* st;
-  double* partials;
-  unsigned* counter;
-  double* jdsp;       // nullable: J, D, S, P
-  double* record;     // nullable: stats record of this GN step
-  int step;           // apply the pending line-search step first
-  int gn_mode;        // maintain gn_stop
+  double* part;       // block sums: sum r^2, sum S terms, sum phi, violations, sum g^2
+  int step;           // apply the accepted line-search step first
+  int level_start;    // first GN step of a level: block 0 clears gn_stop / accepted
+};
+
+// Reduction of loss_grad's block sums into J, D, S, P (one block, or every PCG block of
+// iteration 0 when gn_mode).
+struct LossFinalArgs {
+  const double* part;
+  unsigned nprod;
+  double vol, alpha, beta;
+  State* st;
+  double* jdsp;       // nullable
+  double* record;     // nullable (written when the barrier is violated in gn_mode)
+  int gn_mode;
 };
 
 struct TrialArgs {
@@ -69,11 +86,17 @@ struct TrialArgs {
   const void* grad;
   double alpha, beta, armijo_c;
   State* st;
-  double* partials;
-  unsigned* counter;
+  double* part;             // block sums: [gq, sbq, sqq, then (sum r^2, sum phi, violations) per candidate]
+  int first, nc;            // gamma_c = 2^-(first + c), c < nc
+};
+
+struct DecideArgs {
+  const double* part_prev;
+  unsigned nprod_prev;
+  int prev_first, prev_nc, total;
+  double vol, alpha, beta, armijo_c;
+  State* st;
   double* record;
-  int first;       // index of the first candidate (gamma = 2^-first)
-  int last_pass;   // no candidate accepted after this pass -> stop
 };
 
 struct ApplyArgs {
@@ -99,9 +122,7 @@ struct HvpArgs {
   const void* v;
   void* Hv;
   double alpha;
-  double* partials;
-  unsigned* counter;
-  double* vHv;   // nullable
+  double* part;   // nullable: block sums of v.Hv
 };
 
 struct PcgArgs {
@@ -117,25 +138,27 @@ struct PcgArgs {
   void* r_out;
   void* p_out;
   void* w_out;
-  double alpha;       // smoothness weight (cross-axis couplings)
+  double alpha;             // smoothness weight (cross-axis couplings)
   State* st;
-  double* partials;
-  unsigned* counter;
+  PcgSlot* slots;           // [2]
+  const double* part_prev;  // block sums of iteration iter-1
+  double* part;             // block sums of this iteration
+  unsigned nprod;           // grid size of every PCG kernel of this solve
   int iter, maxit;
   double rtol;
   int gn_mode;
-  int32_t* iters_out;   // nullable
-  double* relres_out;   // nullable
+  int32_t* iters_out;       // nullable
+  double* relres_out;       // nullable
+  // gn_mode, iteration 0: finalise loss_grad's sums
+  LossFinalArgs lf;
 };
 
 struct ShiftArgs {
   const void* Ip;
   const void* Im;
   int64_t n;
-  double eps;
-  State* st;
-  double* partials;
-  unsigned* counter;
+  double* part;                  // block min / max|.|
+  unsigned long long* guarded;   // zeroed by block 0 (the OT kernel counts into it)
 };
 
 struct OtArgs {
@@ -143,10 +166,13 @@ struct OtArgs {
   const void* Ip;
   const void* Im;
   void* b0;
-  const State* st;      // ot_shift
+  State* st;                     // block 0 stores the shift
+  const double* shift_part;
+  unsigned shift_nprod;
+  double eps;
   int guard;
   double guard_slope;
-  unsigned long long* guarded;   // nullable counter (zeroed by the host sequence)
+  unsigned long long* guarded;   // nullable counter (zeroed by the shift kernel)
 };
 
 struct RestrictArgs {
@@ -164,26 +190,32 @@ struct ProlongArgs {
 
 struct SetStateArgs {
   State* st;
-  unsigned* counter;
   unsigned long long* guarded;
 };
 
-unsigned loss_grad_blocks(const Geom& g);
-unsigned trial_blocks(const Geom& g);
-unsigned hvp_blocks(const Geom& g);
-unsigned pcg_blocks(const Geom& g);
-unsigned shift_blocks(int64_t n);
+Launch plan_tiles(const Geom& g, int S, int block);
+Launch plan_loss_grad(const Geom& g, DType real);
+Launch plan_trial(const Geom& g, DType real, int nc);
+Launch plan_pcg(const Geom& g, DType real);
+Launch plan_hvp(const Geom& g, DType real);
+unsigned shift_grid(int64_t n);
 
 hipError_t launch_loss_grad(const LossGradArgs& a, DType img, DType real, hipStream_t s);
-hipError_t launch_trial(const TrialArgs& a, int ncand, DType img, DType real, hipStream_t s);
+hipError_t launch_loss_final(const LossFinalArgs& a, hipStream_t s);
+hipError_t launch_trial(const TrialArgs& a, DType img, DType real, hipStream_t s);
+hipError_t launch_decide(const DecideArgs& a, hipStream_t s);
 hipError_t launch_apply_step(const ApplyArgs& a, DType real, hipStream_t s);
 hipError_t launch_correct(const CorrectArgs& a, DType img, DType real, hipStream_t s);
 hipError_t launch_hvp(const HvpArgs& a, DType real, hipStream_t s);
+hipError_t launch_sum_final(const double* part, unsigned nprod, double* out, hipStream_t s);
 hipError_t launch_pcg_step(const PcgArgs& a, DType real, hipStream_t s);
 hipError_t launch_shift(const ShiftArgs& a, DType img, hipStream_t s);
 hipError_t launch_ot(const OtArgs& a, DType img, DType real, hipStream_t s);
 hipError_t launch_restrict(const RestrictArgs& a, DType src, DType dst, hipStream_t s);
 hipError_t launch_prolong(const ProlongArgs& a, DType real, hipStream_t s);
 hipError_t launch_reset(const SetStateArgs& a, hipStream_t s);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_stats_header(double* stats, const State* st, const unsigned long long* guarded,
+                               hipStream_t s);
 
 }  // namespace rgp

@@ -160,7 +160,8 @@ class Workspace:
         dev = torch.device(device)
         buf = self._buf.get(dev)
         if buf is None or buf.numel() < nbytes:
-            buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
+            # zero-filled once: the library keeps its counters at zero afterwards
+            buf = torch.zeros(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
             self._buf[dev] = buf
         return buf
 
@@ -323,3 +324,53 @@ def parse_stats(stats: torch.Tensor, levels: int, gn_iters: int):
     for lv in range(levels):
         out.append([dict(zip(STAT_NAMES, map(float, recs[lv, it]))) for it in range(gn_iters)])
     return head, out
+
+
+# ---------------------------------------------------------------------------------------------
+# Allocation-free variants for timed loops: every output and the (zero-filled) workspace are
+# passed in; nothing is checked beyond what the library itself validates.
+# ---------------------------------------------------------------------------------------------
+
+def correct_into(I_plus, I_minus, pe, opts: Options, b_out, T_plus, T_minus, ws, *, h=(1.0, 1.0, 1.0),
+                 stats=None, b_init=None, stream=None):
+    g = make_grid(tuple(I_plus.shape), pe, h)
+    copts = opts.to_c(use_b_init=b_init is not None)
+    _check("rgp_correct", load().rgp_correct(
+        ctypes.byref(g), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
+        dtype_code(b_out.dtype), ctypes.byref(copts), _ptr(b_init), _ptr(b_out), _ptr(T_plus),
+        _ptr(T_minus), _ptr(stats), _ptr(ws), ws.numel(), _stream_ptr(stream)))
+
+
+def loss_grad_into(I_plus, I_minus, b, pe, jdsp, grad, hdiag, hoff, ws, *, h=(1.0, 1.0, 1.0),
+                   alpha=300.0, beta=1e-4, stream=None):
+    g = make_grid(tuple(I_plus.shape), pe, h)
+    _check("rgp_loss_grad", load().rgp_loss_grad(
+        ctypes.byref(g), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
+        dtype_code(b.dtype), _ptr(b), float(alpha), float(beta), _ptr(jdsp), _ptr(grad),
+        _ptr(hdiag), _ptr(hoff), _ptr(ws), ws.numel(), _stream_ptr(stream)))
+
+
+def gn_hvp_into(hdiag, hoff, v, Hv, vHv, shape, pe, ws, *, h=(1.0, 1.0, 1.0), alpha=300.0,
+                stream=None):
+    g = make_grid(shape, pe, h)
+    _check("rgp_gn_hvp", load().rgp_gn_hvp(
+        ctypes.byref(g), dtype_code(v.dtype), _ptr(hdiag), _ptr(hoff), float(alpha), _ptr(v),
+        _ptr(Hv), _ptr(vHv), _ptr(ws), ws.numel(), _stream_ptr(stream)))
+
+
+def pcg_solve_into(hdiag, hoff, rhs, x, shape, pe, maxit, ws, *, rtol=0.0, h=(1.0, 1.0, 1.0),
+                   alpha=300.0, iters=None, relres=None, stream=None):
+    g = make_grid(shape, pe, h)
+    _check("rgp_pcg_solve", load().rgp_pcg_solve(
+        ctypes.byref(g), dtype_code(rhs.dtype), _ptr(hdiag), _ptr(hoff), float(alpha), _ptr(rhs),
+        _ptr(x), int(maxit), float(rtol), _ptr(iters), _ptr(relres), _ptr(ws), ws.numel(),
+        _stream_ptr(stream)))
+
+
+def ot_init_into(I_plus, I_minus, pe, b0, ws, *, h=(1.0, 1.0, 1.0), eps=1e-3, guard=True,
+                 n_guarded=None, stream=None):
+    g = make_grid(tuple(I_plus.shape), pe, h)
+    _check("rgp_ot_init", load().rgp_ot_init(
+        ctypes.byref(g), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
+        dtype_code(b0.dtype), _ptr(b0), float(eps), int(bool(guard)), _ptr(n_guarded), _ptr(ws),
+        ws.numel(), _stream_ptr(stream)))

@@ -84,6 +84,9 @@ def test_entry_points_reject_bad_arguments_without_device(lib):
     # missing workspace
     assert lib.rgp_loss_grad(ctypes.byref(g), rgp.F32, fake, fake, rgp.F32, fake, 300.0, 1e-4,
                              fake, None, None, None, None, 0, None) == -8
+    # missing field
+    assert lib.rgp_loss_grad(ctypes.byref(g), rgp.F32, fake, fake, rgp.F32, None, 300.0, 1e-4,
+                             fake, None, None, None, fake, 1 << 30, None) == -1
     # hdiag without hoff
     assert lib.rgp_loss_grad(ctypes.byref(g), rgp.F32, fake, fake, rgp.F32, fake, 300.0, 1e-4,
                              fake, None, fake, None, fake, 1 << 30, None) == -1
