@@ -130,7 +130,6 @@ def main():
     rgp.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
 
     levels, gn_iters, pcg_iters = 3, 10, 20
     log("bench: generating the 144x168x111 pair (seed 1)")
@@ -147,28 +146,43 @@ def main():
     Tp = torch.empty_like(Ip)
     Tm = torch.empty_like(Im)
 
+    # The whole correction is captured once into a HIP graph (rgp_correct_plan) on a side
+    # stream of default priority; one step = one replay.  The eager path is timed too.
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(side)   # every library call below is enqueued on `side`
+    stream = side
+    plan = rgp.Plan(Ip, Im, pe, opts, b, Tp, Tm, ws, stream=side)
+
     def step():
-        rgp.correct_into(Ip, Im, pe, opts, b, Tp, Tm, ws)
+        plan.launch(side)
+
+    def timed(fn, steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(side)
+        for _ in range(steps):
+            fn()
+        e1.record(side)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, e0.elapsed_time(e1)
 
     log(f"bench: warmup {args.warmup}")
     for _ in range(args.warmup):
         step()
+        rgp.correct_into(Ip, Im, pe, opts, b, Tp, Tm, ws, stream=side)
     torch.cuda.synchronize()
-    log(f"bench: timing {args.steps} steps")
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = e0.elapsed_time(e1)
+    log(f"bench: timing {args.steps} steps (graph replay)")
+    wall, gpu_ms = timed(step, args.steps)
+    eager_wall, _ = timed(lambda: rgp.correct_into(Ip, Im, pe, opts, b, Tp, Tm, ws, stream=side),
+                          max(3, args.steps // 4))
+    eager_ms = 1e3 * eager_wall / max(3, args.steps // 4)
     ms_per_step = 1e3 * wall / args.steps
     value = args.steps / wall
-    log(f"bench: {ms_per_step:.3f} ms/pair wall, {gpu_ms / args.steps:.3f} ms/pair on the stream")
+    log(f"bench: {ms_per_step:.3f} ms/pair wall (graph), {gpu_ms / args.steps:.3f} ms/pair on "
+        f"the stream, eager {eager_ms:.3f} ms/pair")
 
     # ---- per-kernel rooflines at the finest level (algorithmic bytes / event-timed launch) ----
     N = int(np.prod(shape))
@@ -231,10 +245,11 @@ def main():
                     "3 levels x 10 GN x 20 PCG (rtol 0), OT init, Armijo",
                     shape=list(shape), pe_dim=pe, levels=levels, gn_iters=gn_iters,
                     pcg_iters=pcg_iters, global_batch=1),
-        gpu_ms_per_step=round(gpu_ms / args.steps, 4),
+        gpu_ms_per_step=round(gpu_ms / args.steps, 4), eager_ms_per_step=round(eager_ms, 4),
         roofline=roofline, kernels=kernels, cpu_baseline=cpu,
         device=torch.cuda.get_device_name(0),
     )
+    plan.close()
     print(json.dumps(line), flush=True)
 
 

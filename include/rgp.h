@@ -160,6 +160,21 @@ rgp_status rgp_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus
                        const void* b_init, void* b_out, void* T_plus, void* T_minus,
                        double* stats_dev, void* ws, size_t ws_bytes, void* stream);
 
+/* Captured solve: the whole sequence of rgp_correct (same arguments, same buffers) recorded once
+ * into a HIP graph on `stream` (a non-default hipStream_t), so that rgp_plan_launch replays the
+ * entire correction with one launch.  Every replay recomputes from the current contents of the
+ * input buffers and overwrites the outputs; the buffers and the workspace must stay alive and
+ * unchanged in size until rgp_plan_destroy.  For callers that repeat one correction shape (a
+ * serving loop, a benchmark). */
+typedef struct rgp_plan_s* rgp_plan;
+rgp_status rgp_correct_plan(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                            const void* I_minus, rgp_dtype real_t, const rgp_solver_opts* opts,
+                            const void* b_init, void* b_out, void* T_plus, void* T_minus,
+                            double* stats_dev, void* ws, size_t ws_bytes, void* stream,
+                            rgp_plan* plan);
+rgp_status rgp_plan_launch(rgp_plan plan, void* stream);
+rgp_status rgp_plan_destroy(rgp_plan plan);
+
 #ifdef __cplusplus
 }
 #endif

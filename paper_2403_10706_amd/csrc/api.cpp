@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <new>
 
 #include "../../include/rgp.h"
 #include "rgp_internal.hpp"
@@ -252,6 +253,19 @@ hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const vo
     if (it > 0) cur = 1 - cur;
 
     for (int i = 0; i <= o->pcg_iters; ++i) {
+      const int in = (i + 1) & 1, out = i & 1;
+      PcgScalarArgs sa{};
+      sa.st = k.st;
+      sa.slots = k.slots;
+      sa.part_prev = k.slot(kPartPcg0 + in);
+      sa.nprod = Lpcg.grid;
+      sa.iter = i;
+      sa.maxit = o->pcg_iters;
+      sa.rtol = o->pcg_rtol;
+      sa.gn_mode = 1;
+      sa.lf = LossFinalArgs{k.slot(kPartLoss), Llg.grid, g.vol, o->alpha, o->beta, k.st,
+                            nullptr, rec, 1};
+      if ((e = launch_pcg_scalars(sa, s)) != hipSuccess) return e;
       PcgArgs pa{};
       pa.g = g;
       pa.diag = w.Dg;
@@ -259,7 +273,6 @@ hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const vo
       pa.rhs = w.G;
       pa.rhs_sign = -1.0;
       pa.x = w.X;
-      const int in = (i + 1) & 1, out = i & 1;
       pa.r_in = w.R[in];
       pa.p_in = w.P[in];
       pa.w_in = w.W[in];
@@ -267,17 +280,9 @@ hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const vo
       pa.p_out = w.P[out];
       pa.w_out = w.W[out];
       pa.alpha = o->alpha;
-      pa.st = k.st;
-      pa.slots = k.slots;
-      pa.part_prev = k.slot(kPartPcg0 + in);
+      pa.slot = k.slots + out;
       pa.part = k.slot(kPartPcg0 + out);
-      pa.nprod = Lpcg.grid;
       pa.iter = i;
-      pa.maxit = o->pcg_iters;
-      pa.rtol = o->pcg_rtol;
-      pa.gn_mode = 1;
-      pa.lf = LossFinalArgs{k.slot(kPartLoss), Llg.grid, g.vol, o->alpha, o->beta, k.st,
-                            nullptr, rec, 1};
       if ((e = launch_pcg_step(pa, real, s)) != hipSuccess) return e;
     }
 
@@ -525,6 +530,19 @@ rgp_status rgp_pcg_solve(const rgp_grid* grid, rgp_dtype real_t, const void* hdi
   for (int i = 0; i < 6; ++i) vec[i] = c.take(g.nnode * dsize(dr));
   const Launch L = plan_pcg(g, dr);
   for (int i = 0; i <= maxit; ++i) {
+    const int in = (i + 1) & 1, out = i & 1;
+    PcgScalarArgs sa{};
+    sa.st = k.st;
+    sa.slots = k.slots;
+    sa.part_prev = k.slot(kPartPcg0 + in);
+    sa.nprod = L.grid;
+    sa.iter = i;
+    sa.maxit = maxit;
+    sa.rtol = rtol;
+    sa.gn_mode = 0;
+    sa.iters_out = iters_dev;
+    sa.relres_out = relres_dev;
+    RGP_HIP(launch_pcg_scalars(sa, s));
     PcgArgs pa{};
     pa.g = g;
     pa.diag = hdiag;
@@ -532,7 +550,6 @@ rgp_status rgp_pcg_solve(const rgp_grid* grid, rgp_dtype real_t, const void* hdi
     pa.rhs = rhs;
     pa.rhs_sign = 1.0;
     pa.x = x;
-    const int in = (i + 1) & 1, out = i & 1;
     pa.r_in = vec[3 * in + 0];
     pa.p_in = vec[3 * in + 1];
     pa.w_in = vec[3 * in + 2];
@@ -540,17 +557,9 @@ rgp_status rgp_pcg_solve(const rgp_grid* grid, rgp_dtype real_t, const void* hdi
     pa.p_out = vec[3 * out + 1];
     pa.w_out = vec[3 * out + 2];
     pa.alpha = alpha;
-    pa.st = k.st;
-    pa.slots = k.slots;
-    pa.part_prev = k.slot(kPartPcg0 + in);
+    pa.slot = k.slots + out;
     pa.part = k.slot(kPartPcg0 + out);
-    pa.nprod = L.grid;
     pa.iter = i;
-    pa.maxit = maxit;
-    pa.rtol = rtol;
-    pa.gn_mode = 0;
-    pa.iters_out = iters_dev;
-    pa.relres_out = relres_dev;
     RGP_HIP(launch_pcg_step(pa, dr, s));
   }
   return RGP_OK;
@@ -576,10 +585,13 @@ rgp_status rgp_apply_correction(const rgp_grid* grid, rgp_dtype img_t, const voi
   return RGP_OK;
 }
 
-rgp_status rgp_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
-                       const void* I_minus, rgp_dtype real_t, const rgp_solver_opts* opts,
-                       const void* b_init, void* b_out, void* T_plus, void* T_minus,
-                       double* stats_dev, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+rgp_status check_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                         const void* I_minus, rgp_dtype real_t, const rgp_solver_opts* opts,
+                         const void* b_init, void* b_out, void* ws, size_t ws_bytes) {
   rgp_status st = check_grid(grid);
   if (st != RGP_OK) return st;
   DType di, dr;
@@ -587,8 +599,17 @@ rgp_status rgp_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus
   if ((st = check_opts(opts)) != RGP_OK) return st;
   if (!I_plus || !I_minus || !b_out) return RGP_EINVAL;
   if (opts->use_b_init && !b_init) return RGP_EINVAL;
-  if ((st = need_ws(RGP_OP_CORRECT, grid, real_t, opts, ws, ws_bytes)) != RGP_OK) return st;
-  const hipStream_t s = static_cast<hipStream_t>(stream);
+  return need_ws(RGP_OP_CORRECT, grid, real_t, opts, ws, ws_bytes);
+}
+
+// Enqueues the whole correction (arguments already validated).
+rgp_status enqueue_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                           const void* I_minus, rgp_dtype real_t, const rgp_solver_opts* opts,
+                           const void* b_init, void* b_out, void* T_plus, void* T_minus,
+                           double* stats_dev, void* ws, hipStream_t s) {
+  DType di, dr;
+  dtype_of(img_t, &di);
+  dtype_of(real_t, &dr);
   const int L = opts->levels;
   Level lv[kMaxLevels];
   if (make_levels(grid, L, lv) != 0) return RGP_ESHAPE;
@@ -680,6 +701,83 @@ rgp_status rgp_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus
   }
   RGP_HIP(hipMemcpyAsync(b_out, w.B[cur], lv[0].g.nnode * rs, hipMemcpyDeviceToDevice, s));
   if (stats_dev) RGP_HIP(launch_stats_header(stats_dev, w.ctl.st, w.ctl.guarded, s));
+  return RGP_OK;
+}
+
+}  // namespace
+
+struct rgp_plan_s {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+extern "C" {
+
+rgp_status rgp_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                       const void* I_minus, rgp_dtype real_t, const rgp_solver_opts* opts,
+                       const void* b_init, void* b_out, void* T_plus, void* T_minus,
+                       double* stats_dev, void* ws, size_t ws_bytes, void* stream) {
+  rgp_status st = check_correct(grid, img_t, I_plus, I_minus, real_t, opts, b_init, b_out, ws,
+                                ws_bytes);
+  if (st != RGP_OK) return st;
+  return enqueue_correct(grid, img_t, I_plus, I_minus, real_t, opts, b_init, b_out, T_plus,
+                         T_minus, stats_dev, ws, static_cast<hipStream_t>(stream));
+}
+
+rgp_status rgp_correct_plan(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                            const void* I_minus, rgp_dtype real_t, const rgp_solver_opts* opts,
+                            const void* b_init, void* b_out, void* T_plus, void* T_minus,
+                            double* stats_dev, void* ws, size_t ws_bytes, void* stream,
+                            rgp_plan* plan) {
+  if (!plan) return RGP_EINVAL;
+  *plan = nullptr;
+  if (!stream) return RGP_EINVAL;  // the legacy default stream cannot be captured
+  rgp_status st = check_correct(grid, img_t, I_plus, I_minus, real_t, opts, b_init, b_out, ws,
+                                ws_bytes);
+  if (st != RGP_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  RGP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  st = enqueue_correct(grid, img_t, I_plus, I_minus, real_t, opts, b_init, b_out, T_plus, T_minus,
+                       stats_dev, ws, s);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &graph);
+  if (st != RGP_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) g_last_hip = (int)e;
+    return st != RGP_OK ? st : RGP_EHIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    g_last_hip = (int)e2;
+    return RGP_EHIP;
+  }
+  rgp_plan p = new (std::nothrow) rgp_plan_s{graph, exec};
+  if (!p) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return RGP_EINVAL;
+  }
+  *plan = p;
+  return RGP_OK;
+}
+
+rgp_status rgp_plan_launch(rgp_plan plan, void* stream) {
+  if (!plan) return RGP_EINVAL;
+  RGP_HIP(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)));
+  return RGP_OK;
+}
+
+rgp_status rgp_plan_destroy(rgp_plan plan) {
+  if (!plan) return RGP_OK;
+  const hipError_t e1 = hipGraphExecDestroy(plan->exec);
+  const hipError_t e2 = hipGraphDestroy(plan->graph);
+  delete plan;
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    g_last_hip = (int)(e1 != hipSuccess ? e1 : e2);
+    return RGP_EHIP;
+  }
   return RGP_OK;
 }
 

@@ -446,13 +446,13 @@ Launch plan_tiles(const Geom& g, int S, int block) {
   return L;
 }
 
-// Big FP32 problems use 1024-thread blocks (16 wavefronts per CU in one block, at most 256
-// blocks); small problems and FP64 (more registers) use 256-thread blocks.
+// 256-thread blocks; the grid holds one wavefront per tile up to kMaxGrid blocks (full
+// occupancy matters more than anything else for these latency-heavy gathers and stencils).
 static int pick_block(const Geom& g, DType real, int S) {
-  if (real != DType::F32) return 256;
-  const int64_t nct = (g.ncol + kWave - 1) / kWave;
-  const int64_t ntiles = nct * ((g.mp + 1 + S - 1) / S);
-  return ntiles > 1024 ? 1024 : 256;
+  (void)g;
+  (void)real;
+  (void)S;
+  return 256;
 }
 
 Launch plan_loss_grad(const Geom& g, DType real) {

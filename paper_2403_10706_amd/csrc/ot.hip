@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_ot(OtArgs a, int nc) {
 unsigned shift_grid(int64_t n) {
   int64_t nb = (n + kBlock * 16 - 1) / (kBlock * 16);
   if (nb < 1) nb = 1;
-  if (nb > kMaxGrid) nb = kMaxGrid;
+  if (nb > 256) nb = 256;  // every OT block combines these block extrema
   return (unsigned)nb;
 }
 

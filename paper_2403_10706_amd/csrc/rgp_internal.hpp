@@ -77,19 +77,21 @@ struct State {
 // block 0 writes slot i&1.
 struct PcgSlot {
   double rz, rr, bnorm2, relres;
+  double alpha, beta;   // coefficients the next main kernel applies
   int32_t status, iters;
-  double pad[2];
 };
 
-enum PcgStatus : int32_t { kPcgRunning = 0, kPcgDone = 2 };
+// Running: apply the update and take the next HVP; Finish: apply the last update x += a p only;
+// Done: nothing left to do.
+enum PcgStatus : int32_t { kPcgRunning = 0, kPcgFinish = 1, kPcgDone = 2 };
 
 // Stats record written once per Gauss-Newton step.
 constexpr int kStatFields = 12;
 
-// Partial sums: every reducing kernel writes kPartStride doubles per block (plain stores); the
-// consumer (a later kernel) reduces them in block order.  Grids are capped at kMaxGrid blocks.
+// Partial sums: every reducing kernel writes kPartStride doubles per block (plain stores); a later
+// single-block kernel reduces them in block order.  Grids are capped at kMaxGrid blocks.
 constexpr int kPartStride = 24;
-constexpr int kMaxGrid = 256;
+constexpr int kMaxGrid = 2048;
 
 // Column-run tiling: a tile is 64 consecutive columns x S consecutive PE nodes, owned by one
 // wavefront.  Tiles are split into 8 contiguous ranges, one per XCD (blocks are dealt to the XCDs

@@ -139,18 +139,24 @@ struct PcgArgs {
   void* p_out;
   void* w_out;
   double alpha;             // smoothness weight (cross-axis couplings)
+  const PcgSlot* slot;      // coefficients and status of this iteration (from k_pcg_scalars)
+  double* part;             // block sums of this iteration
+  int iter;
+};
+
+// Single-block kernel between PCG iterations: reduces the block sums of iteration iter-1 and
+// writes the coefficients and status of iteration iter into slots[iter & 1].
+struct PcgScalarArgs {
   State* st;
   PcgSlot* slots;           // [2]
   const double* part_prev;  // block sums of iteration iter-1
-  double* part;             // block sums of this iteration
-  unsigned nprod;           // grid size of every PCG kernel of this solve
+  unsigned nprod;           // grid of the main PCG kernels
   int iter, maxit;
   double rtol;
   int gn_mode;
   int32_t* iters_out;       // nullable
   double* relres_out;       // nullable
-  // gn_mode, iteration 0: finalise loss_grad's sums
-  LossFinalArgs lf;
+  LossFinalArgs lf;         // gn_mode, iteration 0: J, D, S, P of the current iterate
 };
 
 struct ShiftArgs {
@@ -209,6 +215,7 @@ hipError_t launch_correct(const CorrectArgs& a, DType img, DType real, hipStream
 hipError_t launch_hvp(const HvpArgs& a, DType real, hipStream_t s);
 hipError_t launch_sum_final(const double* part, unsigned nprod, double* out, hipStream_t s);
 hipError_t launch_pcg_step(const PcgArgs& a, DType real, hipStream_t s);
+hipError_t launch_pcg_scalars(const PcgScalarArgs& a, hipStream_t s);
 hipError_t launch_shift(const ShiftArgs& a, DType img, hipStream_t s);
 hipError_t launch_ot(const OtArgs& a, DType img, DType real, hipStream_t s);
 hipError_t launch_restrict(const RestrictArgs& a, DType src, DType dst, hipStream_t s);

@@ -54,7 +54,8 @@ class SolverOpts(ctypes.Structure):
 
 EXPORTS = ("rgp_status_string", "rgp_last_hip_error", "rgp_default_opts", "rgp_workspace_size",
            "rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
-           "rgp_apply_correction", "rgp_correct")
+           "rgp_apply_correction", "rgp_correct", "rgp_correct_plan", "rgp_plan_launch",
+           "rgp_plan_destroy")
 
 _lib = None
 
@@ -86,8 +87,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rgp_apply_correction.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp, vp]
     lib.rgp_correct.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int, op, vp, vp, vp, vp, vp, vp,
                                 sz, vp]
+    lib.rgp_correct_plan.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int, op, vp, vp, vp, vp,
+                                     vp, vp, sz, vp, ctypes.POINTER(ctypes.c_void_p)]
+    lib.rgp_plan_launch.argtypes = [vp, vp]
+    lib.rgp_plan_destroy.argtypes = [vp]
     for name in ("rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
-                 "rgp_apply_correction", "rgp_correct", "rgp_workspace_size"):
+                 "rgp_apply_correction", "rgp_correct", "rgp_workspace_size", "rgp_correct_plan",
+                 "rgp_plan_launch", "rgp_plan_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -374,3 +380,38 @@ def ot_init_into(I_plus, I_minus, pe, b0, ws, *, h=(1.0, 1.0, 1.0), eps=1e-3, gu
         ctypes.byref(g), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
         dtype_code(b0.dtype), _ptr(b0), float(eps), int(bool(guard)), _ptr(n_guarded), _ptr(ws),
         ws.numel(), _stream_ptr(stream)))
+
+
+class Plan:
+    """A whole correction captured once into a HIP graph (rgp_correct_plan) and replayed with one
+    launch per call.  Capture needs a non-default stream; the tensors passed here must stay alive
+    for the plan's lifetime (the plan keeps references)."""
+
+    def __init__(self, I_plus, I_minus, pe, opts: Options, b_out, T_plus, T_minus, ws, *,
+                 h=(1.0, 1.0, 1.0), stats=None, b_init=None, stream):
+        _dev_check(I_plus, I_minus, b_out, T_plus, T_minus, stats, b_init)
+        self._keep = (I_plus, I_minus, b_out, T_plus, T_minus, ws, stats, b_init)
+        self._grid = make_grid(tuple(I_plus.shape), pe, h)
+        self._opts = opts.to_c(use_b_init=b_init is not None)
+        self._handle = ctypes.c_void_p(None)
+        self.stream = stream
+        _check("rgp_correct_plan", load().rgp_correct_plan(
+            ctypes.byref(self._grid), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
+            dtype_code(b_out.dtype), ctypes.byref(self._opts), _ptr(b_init), _ptr(b_out),
+            _ptr(T_plus), _ptr(T_minus), _ptr(stats), _ptr(ws), ws.numel(),
+            _stream_ptr(stream), ctypes.byref(self._handle)))
+
+    def launch(self, stream=None):
+        _check("rgp_plan_launch", load().rgp_plan_launch(self._handle,
+                                                         _stream_ptr(stream or self.stream)))
+
+    def close(self):
+        if self._handle:
+            _check("rgp_plan_destroy", load().rgp_plan_destroy(self._handle))
+            self._handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -86,7 +86,10 @@ def test_pcg_parity(shape, pe, real):
         ref = orc.pcg_solve(lin, rhs, pe, maxit, rtol)
         its = int(to_host(it)[0])
         assert its == ref.iters, (its, ref.iters)
-        assert rel2(to_host(x), ref.x) <= _tol(real, 1e-9, VEC_RTOL)
+        # FP32 CG drifts from FP64 CG as rounding differences are amplified iteration by
+        # iteration (loss of orthogonality): the bar grows linearly beyond 10 iterations
+        # (FP64 on the device matches to 1e-9).
+        assert rel2(to_host(x), ref.x) <= _tol(real, 1e-9, VEC_RTOL * max(1.0, its / 10.0))
         # the device tracks |r| by the FP64 recurrence over FP32 vectors: compare the normalised
         # residual absolutely in FP32
         got = float(to_host(rr)[0])
@@ -264,3 +267,48 @@ def test_correct_c2_full_schedule():
     assert err <= BFINAL_ATOL
     _, recs = rgp.parse_stats(out["stats"], 3, 10)
     assert recs[-1][-1]["J"] == pytest.approx(ref.levels[-1][2][-1].J, rel=J_RTOL)
+
+
+def test_correct_plan_replays_match_eager():
+    """The captured graph replays the whole correction; every replay equals the eager result
+    bitwise (deterministic reductions), with eager work and synchronisation in between, and a
+    replay after the inputs changed in place follows the new inputs."""
+    rgp = _rgp()
+    shape, pe = (40, 48, 36), 1
+    p = _pair(shape, pe, seed=19, scale=30.0)
+    dt = torch.float32
+    Ip, Im = to_dev(p.I_plus, dt), to_dev(p.I_minus, dt)
+    opts = rgp.Options(levels=2, gn_iters=3, pcg_iters=6, pcg_rtol=0.0)
+    eager = rgp.correct(Ip, Im, pe, opts=opts)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    nbytes = rgp.workspace_size(rgp.OP_CORRECT, shape, pe, (1.0, 1.0, 1.0), dt, opts.to_c())
+    ws = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(rgp.field_shape(shape, pe), dtype=dt, device="cuda")
+    Tp, Tm = torch.empty_like(Ip), torch.empty_like(Im)
+    stats = torch.empty(rgp.STAT_HEADER + 2 * 3 * rgp.STAT_FIELDS, dtype=torch.float64,
+                        device="cuda")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        plan = rgp.Plan(Ip, Im, pe, opts, b, Tp, Tm, ws, stats=stats, stream=s)
+        for rep in range(3):
+            b.fill_(7.0)
+            plan.launch(s)
+            s.synchronize()
+            assert torch.equal(b, eager["b"]), rep
+            assert torch.equal(Tp, eager["T_plus"]) and torch.equal(Tm, eager["T_minus"])
+            assert torch.equal(stats, eager["stats"]) or np.allclose(
+                to_host(stats), to_host(eager["stats"]), equal_nan=True)
+            again = rgp.correct(Ip, Im, pe, opts=opts)   # eager work between replays
+            s.synchronize()
+            assert torch.equal(again["b"], eager["b"])
+        Ip.mul_(1.05)
+        Im.mul_(0.97)
+        s.synchronize()
+        plan.launch(s)
+        s.synchronize()
+        fresh = rgp.correct(Ip, Im, pe, opts=opts)
+        s.synchronize()
+        assert torch.equal(b, fresh["b"])
+        assert not torch.equal(b, eager["b"])
+        plan.close()
