@@ -54,9 +54,11 @@ rgp_status check_grid(const rgp_grid* g) {
     if (!(g->h[d] > 0.0) || !std::isfinite(g->h[d])) return RGP_EINVAL;
     cells *= g->m[d];
     nodes *= g->m[d] + (d == g->pe ? 1 : 0);
-    if (nodes >= (int64_t(1) << 31)) return RGP_ESHAPE;
+    if (nodes > (int64_t(1) << 28)) return RGP_ESHAPE;
   }
   if (g->m[g->pe] < 2) return RGP_ESHAPE;
+  // the contiguous axis of the field (its two halo rows are held by at most 1024 lanes)
+  if (g->m[2] + (g->pe == 2 ? 1 : 0) > 512) return RGP_ESHAPE;
   (void)cells;
   return RGP_OK;
 }
@@ -230,7 +232,7 @@ hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const vo
   hipError_t e;
   const Control& k = w.ctl;
   const Launch Llg = plan_loss_grad(g, real);
-  const Launch Lpcg = plan_pcg(g, real);
+  const PcgPlan Lpcg = plan_pcg(g, real);
   for (int it = 0; it < o->gn_iters; ++it) {
     double* rec = records ? records + (size_t)it * kStatFields : nullptr;
     LossGradArgs la{};
@@ -263,9 +265,10 @@ hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const vo
       sa.maxit = o->pcg_iters;
       sa.rtol = o->pcg_rtol;
       sa.gn_mode = 1;
+      sa.fused = Lpcg.fused;
       sa.lf = LossFinalArgs{k.slot(kPartLoss), Llg.grid, g.vol, o->alpha, o->beta, k.st,
                             nullptr, rec, 1};
-      if ((e = launch_pcg_scalars(sa, s)) != hipSuccess) return e;
+      if ((i == 0 || !sa.fused) && (e = launch_pcg_scalars(sa, s)) != hipSuccess) return e;
       PcgArgs pa{};
       pa.g = g;
       pa.diag = w.Dg;
@@ -280,9 +283,8 @@ hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const vo
       pa.p_out = w.P[out];
       pa.w_out = w.W[out];
       pa.alpha = o->alpha;
-      pa.slot = k.slots + out;
       pa.part = k.slot(kPartPcg0 + out);
-      pa.iter = i;
+      pa.sc = sa;
       if ((e = launch_pcg_step(pa, real, s)) != hipSuccess) return e;
     }
 
@@ -528,7 +530,7 @@ rgp_status rgp_pcg_solve(const rgp_grid* grid, rgp_dtype real_t, const void* hdi
   Control k = carve_control(c);
   void* vec[6];
   for (int i = 0; i < 6; ++i) vec[i] = c.take(g.nnode * dsize(dr));
-  const Launch L = plan_pcg(g, dr);
+  const PcgPlan L = plan_pcg(g, dr);
   for (int i = 0; i <= maxit; ++i) {
     const int in = (i + 1) & 1, out = i & 1;
     PcgScalarArgs sa{};
@@ -540,9 +542,10 @@ rgp_status rgp_pcg_solve(const rgp_grid* grid, rgp_dtype real_t, const void* hdi
     sa.maxit = maxit;
     sa.rtol = rtol;
     sa.gn_mode = 0;
+    sa.fused = L.fused;
     sa.iters_out = iters_dev;
     sa.relres_out = relres_dev;
-    RGP_HIP(launch_pcg_scalars(sa, s));
+    if (i == 0 || !sa.fused) RGP_HIP(launch_pcg_scalars(sa, s));
     PcgArgs pa{};
     pa.g = g;
     pa.diag = hdiag;
@@ -557,9 +560,8 @@ rgp_status rgp_pcg_solve(const rgp_grid* grid, rgp_dtype real_t, const void* hdi
     pa.p_out = vec[3 * out + 1];
     pa.w_out = vec[3 * out + 2];
     pa.alpha = alpha;
-    pa.slot = k.slots + out;
     pa.part = k.slot(kPartPcg0 + out);
-    pa.iter = i;
+    pa.sc = sa;
     RGP_HIP(launch_pcg_step(pa, dr, s));
   }
   return RGP_OK;

@@ -243,7 +243,7 @@ __global__ __launch_bounds__(BLK) void k_loss_grad(LossGradArgs a) {
 }
 
 // J, D, S, P from loss_grad's block sums (standalone entry point; one block).
-__global__ __launch_bounds__(kBlock) void k_loss_final(LossFinalArgs a) { finalize_loss(a, true); }
+__global__ __launch_bounds__(kReduceBlock) void k_loss_final(LossFinalArgs a) { finalize_loss(a, true); }
 
 // --------------------------------------------------------------------------------------------
 // Armijo trials: block sums of D and P at b + gamma_c q for NC step sizes gamma_c = 2^-(first+c)
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(BLK) void k_trial(TrialArgs a) {
 }
 
 // Armijo decision on the pass just evaluated (one block).
-__global__ __launch_bounds__(kBlock) void k_decide(DecideArgs a) {
+__global__ __launch_bounds__(kReduceBlock) void k_decide(DecideArgs a) {
   const State* st = a.st;
   if (load_flag(&st->gn_stop) || st->accepted) return;
   decide_pass(a);
@@ -492,7 +492,7 @@ hipError_t launch_loss_grad(const LossGradArgs& a, DType img, DType real, hipStr
 }
 
 hipError_t launch_loss_final(const LossFinalArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kReduceBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -517,7 +517,7 @@ hipError_t launch_trial(const TrialArgs& a, DType img, DType real, hipStream_t s
 }
 
 hipError_t launch_decide(const DecideArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(kReduceBlock), 0, s, a);
   return hipGetLastError();
 }
 

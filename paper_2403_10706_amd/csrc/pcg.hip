@@ -84,77 +84,29 @@ __global__ __launch_bounds__(BLK) void k_hvp(HvpArgs a) {
 }
 
 // out = sum of one slot of block sums (one block).
-__global__ __launch_bounds__(kBlock) void k_sum_final(const double* part, unsigned nprod,
+__global__ __launch_bounds__(kReduceBlock) void k_sum_final(const double* part, unsigned nprod,
                                                       double* out) {
   double t[1];
   reduce_partials<1>(t, part, nprod);
   if (threadIdx.x == 0) *out = t[0];
 }
 
-// Tiling of the PCG step: a wavefront owns a slab of X consecutive x-rows, a chunk of 64
-// consecutive y columns (one per lane) and a run of S consecutive PE nodes, and marches along x:
-// the p values of the rows x-1, x and x+1 stay in registers, y neighbours come from lane
-// shuffles, and only the slab's outer rows (and the PE run ends) are recomputed from the previous
-// vectors.
-struct SlabTiles {
-  int nslab, nchunk, nrun;
-  int64_t ntiles;
-};
-__host__ __device__ inline SlabTiles slab_tiles(const Geom& g, int S, int X) {
-  SlabTiles T;
-  T.nslab = (g.nx + X - 1) / X;
-  T.nchunk = (g.ny + kWave - 1) / kWave;
-  T.nrun = (g.mp + 1 + S - 1) / S;
-  T.ntiles = (int64_t)T.nslab * T.nchunk * T.nrun;
-  return T;
+// ---- scalar phase ---------------------------------------------------------------------------
+__device__ __forceinline__ void pcg_outputs(const PcgScalarArgs& a, const PcgSlot& c) {
+  a.st->pcg_iters = c.iters;
+  a.st->relres = c.relres;
+  if (a.iters_out) *a.iters_out = c.iters;
+  if (a.relres_out) *a.relres_out = c.relres;
 }
 
-// ---- scalar phase of iteration `iter` (one block) ------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_pcg_scalars(PcgScalarArgs a) {
-  State* st = a.st;
-  const int it_ = a.iter;
-  const bool lead = threadIdx.x == 0;
-  auto finish_outputs = [&](const PcgSlot& c) {
-    st->pcg_iters = c.iters;
-    st->relres = c.relres;
-    if (a.iters_out) *a.iters_out = c.iters;
-    if (a.relres_out) *a.relres_out = c.relres;
-  };
-  if (a.gn_mode && load_flag(&st->gn_stop)) {
-    if (lead) {
-      PcgSlot d{};
-      d.status = kPcgDone;
-      a.slots[it_ & 1] = d;
-    }
-    return;
-  }
-  if (it_ == 0) {
-    bool viol = false;
-    // J, D, S, P of the current iterate; a violated barrier stops the GN solve on this level.
-    if (a.gn_mode) viol = finalize_loss(a.lf, true);
-    if (lead) {
-      PcgSlot s0{};
-      s0.status = viol ? kPcgDone : kPcgRunning;
-      a.slots[0] = s0;
-    }
-    return;
-  }
-  const PcgSlot prev = a.slots[(it_ - 1) & 1];
-  if (prev.status != kPcgRunning) {  // the solve has ended: carry the final slot forward
-    if (lead) {
-      PcgSlot c = prev;
-      c.status = kPcgDone;
-      a.slots[it_ & 1] = c;
-      if (it_ == a.maxit) finish_outputs(c);
-    }
-    return;
-  }
-  double t[7];
-  reduce_partials<7>(t, a.part_prev, a.nprod);
-  if (!lead) return;
+// Slot of iteration it >= 1 from the running slot of iteration it-1 and the block sums t of
+// iteration it-1: [0] p.w, [1] r.w/d, [2] w.w/d, [3] r.w, [4] w.w, and at it == 1 [5] r.r/d and
+// [6] r.r of the initial residual.  `fin` is set when the solve ends here.
+__device__ __forceinline__ PcgSlot pcg_advance(const PcgSlot& prev, const double (&t)[7], int it,
+                                               int maxit, double rtol, bool& fin) {
   PcgSlot cur = prev;
   double rz = prev.rz, rr = prev.rr, bn = prev.bnorm2;
-  if (it_ == 1) {
+  if (it == 1) {
     rz = t[5];
     rr = t[6];
     bn = t[6];
@@ -163,232 +115,395 @@ __global__ __launch_bounds__(kBlock) void k_pcg_scalars(PcgScalarArgs a) {
   cur.bnorm2 = bn;
   if (!(bn > 0.0) || !(pw > 0.0)) {  // zero right-hand side or p^T H p <= 0: keep x
     cur.status = kPcgDone;
-    cur.iters = it_ - 1;
-    cur.relres = it_ == 1 ? (bn > 0.0 ? 1.0 : 0.0) : prev.relres;
-    finish_outputs(cur);
-  } else {
-    const double a2 = rz / pw;
-    const double rzn = rz - 2.0 * a2 * t[1] + a2 * a2 * t[2];
-    const double rrn = rr - 2.0 * a2 * t[3] + a2 * a2 * t[4];
-    cur.alpha = a2;
-    cur.beta = rzn / rz;
-    cur.rz = rzn;
-    cur.rr = rrn;
-    cur.iters = it_;
-    cur.relres = sqrt(fmax(rrn, 0.0) / bn);
-    const bool finish = cur.relres < a.rtol || it_ >= a.maxit;
-    cur.status = finish ? kPcgFinish : kPcgRunning;
-    if (finish) finish_outputs(cur);
+    cur.iters = it - 1;
+    cur.relres = it == 1 ? (bn > 0.0 ? 1.0 : 0.0) : prev.relres;
+    fin = true;
+    return cur;
   }
-  a.slots[it_ & 1] = cur;
+  const double a2 = rz / pw;
+  const double rzn = rz - 2.0 * a2 * t[1] + a2 * a2 * t[2];
+  const double rrn = rr - 2.0 * a2 * t[3] + a2 * a2 * t[4];
+  cur.alpha = a2;
+  cur.beta = rzn / rz;
+  cur.rz = rzn;
+  cur.rr = rrn;
+  cur.iters = it;
+  cur.relres = sqrt(fmax(rrn, 0.0) / bn);
+  fin = cur.relres < rtol || it >= maxit;
+  cur.status = fin ? kPcgFinish : kPcgRunning;
+  return cur;
 }
 
-// ---- main phase of iteration `iter`: update, w = H p, block sums ---------------------------
-template <typename TR, int S, int X, int BLK>
-__global__ __launch_bounds__(BLK) void k_pcg_step(PcgArgs a) {
-  const PcgSlot sl = *a.slot;
-  if (sl.status == kPcgDone) return;
-  const int it_ = a.iter;
-  const bool first = it_ == 0;
-  const TR al = (TR)sl.alpha, be = (TR)sl.beta;
+// Slot of iteration a.iter >= 1 from the previous slot and this thread's partial sums t of the
+// previous block sums (load_partials_cm); identical in every block, since the block sums are
+// reduced in a fixed order.  Block 0 stores it and, when the solve ends, the iteration count and
+// residual.
+__device__ __forceinline__ PcgSlot pcg_scalar_phase(const PcgScalarArgs& a, const PcgSlot& prev,
+                                                    double (&t)[7]) {
+  const int it = a.iter;
+  PcgSlot cur;
+  bool fin = false;
+  if (prev.status != kPcgRunning) {  // the solve has ended: carry the final slot forward
+    cur = prev;
+    cur.status = kPcgDone;
+    fin = it == a.maxit;
+  } else {
+    block_sum<7>(t);
+    cur = pcg_advance(prev, t, it, a.maxit, a.rtol, fin);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.slots[it & 1] = cur;
+    if (fin) pcg_outputs(a, cur);
+  }
+  return cur;
+}
 
+// One block.  Iteration 0: in Gauss-Newton mode, a stopped solve or a violated barrier at the
+// current iterate (J = +inf, finalised here from loss_grad's block sums) gives status Done.
+// Later iterations (when not fused into k_pcg_step): the scalar phase.
+__global__ __launch_bounds__(kReduceBlock) void k_pcg_scalars(PcgScalarArgs a) {
+  State* st = a.st;
+  if (a.iter > 0) {
+    const PcgSlot prev = a.slots[(a.iter - 1) & 1];
+    double t[7];
+    load_partials_cm<7>(t, a.part_prev, a.nprod, a.iter == 1 ? 7 : 5);
+    pcg_scalar_phase(a, prev, t);
+    return;
+  }
+  if (a.gn_mode && load_flag(&st->gn_stop)) {
+    if (threadIdx.x == 0) {
+      PcgSlot d{};
+      d.status = kPcgDone;
+      a.slots[0] = d;
+    }
+    return;
+  }
+  bool viol = false;
+  if (a.gn_mode) viol = finalize_loss(a.lf, true);
+  if (threadIdx.x == 0) {
+    PcgSlot s0{};
+    s0.status = viol ? kPcgDone : kPcgRunning;
+    a.slots[0] = s0;
+  }
+}
+
+// ---- main phase: plane-march PCG step -------------------------------------------------------
+// Raw values of one node read by the update (x only on owned planes).
+template <typename TR>
+struct NodeRaw {
+  TR d, r, w, p, x;
+};
+
+// One PCG iteration over the units of a plane march (see MarchGeo).  Per plane o of a unit every
+// thread owns npt plane positions: it applies the update (x += a p, r -= a w, p = r/d + b p,
+// stored) one plane ahead (o+1) so that the o-neighbours of p stay in registers, writes p of plane
+// o into an LDS plane buffer together with the two halo rows (nb positions on each side of the
+// unit's flat run, recomputed from the previous vectors), and forms w = H p at plane o from LDS
+// (a and b neighbours) and registers (o neighbours).  Raw values of plane o+2 and the halo rows of
+// plane o+1 are loaded while plane o is computed.  The LDS plane buffer is double-buffered so that
+// one barrier per plane suffices.  Planes just outside the unit contribute p only (recomputed).
+template <typename TR, int ROLE, int BLK, int NPT, int HMAX>
+__global__ __launch_bounds__(BLK) void k_pcg_step(PcgArgs a, MarchGeo m) {
+  extern __shared__ unsigned char lds_raw[];
+  TR* lds = reinterpret_cast<TR*>(lds_raw);
+  const int it = a.sc.iter;
+  const bool first = it == 0;
   const Geom g = a.g;
-  const TR* __restrict__ dg = static_cast<const TR*>(a.diag);
-  const TR* __restrict__ of = static_cast<const TR*>(a.off);
-  const TR* __restrict__ rhs = static_cast<const TR*>(a.rhs);
-  TR* __restrict__ x = static_cast<TR*>(a.x);
-  const TR* __restrict__ ri = static_cast<const TR*>(a.r_in);
-  const TR* __restrict__ pi = static_cast<const TR*>(a.p_in);
-  const TR* __restrict__ wi = static_cast<const TR*>(a.w_in);
-  TR* __restrict__ ro = static_cast<TR*>(a.r_out);
-  TR* __restrict__ po = static_cast<TR*>(a.p_out);
-  TR* __restrict__ wo = static_cast<TR*>(a.w_out);
-  const TR sgn = (TR)a.rhs_sign;
-  const int mp = g.mp;
+  const uint32_t nbytes = (uint32_t)(g.nnode * (int64_t)sizeof(TR));
+  const BRes rD = bres(a.diag, nbytes), rO = bres(a.off, nbytes), rB = bres(a.rhs, nbytes);
+  const BRes rX = bres(a.x, nbytes), rRi = bres(a.r_in, nbytes), rPi = bres(a.p_in, nbytes);
+  const BRes rWi = bres(a.w_in, nbytes), rRo = bres(a.r_out, nbytes);
+  const BRes rPo = bres(a.p_out, nbytes), rWo = bres(a.w_out, nbytes);
+  const int no = m.no, na = m.na, nb = m.nb;
+  const int64_t P = m.P;
+  const int T = m.T;
+  const int t = threadIdx.x;
+  constexpr uint32_t kSz = sizeof(TR);
 
+  auto load_raw = [&](int64_t n, bool with_x) -> NodeRaw<TR> {
+    NodeRaw<TR> v;
+    const uint32_t bo = (uint32_t)n * kSz;
+    v.d = bld<TR>(rD, bo);
+    if (first) {
+      v.r = bld<TR>(rB, bo);
+      v.w = v.p = v.x = TR(0);
+    } else {
+      v.r = bld<TR>(rRi, bo);
+      v.w = bld<TR>(rWi, bo);
+      v.p = bld<TR>(rPi, bo);
+      v.x = with_x ? bld<TR>(rX, bo) : TR(0);
+    }
+    return v;
+  };
+
+  // units: 8 contiguous ranges, one per XCD (blocks are dealt to the XCDs round-robin), with the
+  // o-chunk fastest so that units sharing halo planes run together on one XCD
+  const unsigned G = gridDim.x;
+  unsigned nxcd = 1, xcd = 0, lb = blockIdx.x, gl = G;
+  if (G >= 8u && G % 8u == 0u) {
+    nxcd = 8u;
+    xcd = blockIdx.x % 8u;
+    lb = blockIdx.x / 8u;
+    gl = G / 8u;
+  }
+  const int64_t ulo = m.units * xcd / nxcd, uhi = m.units * (xcd + 1) / nxcd;
+
+  // state of the current unit and the loads of its first planes
+  int64_t f0 = 0;
+  int Teff = 0, o0 = 0, oe = 0;
+  int fl[NPT], ia[NPT], ib[NPT];
+  bool own[NPT];
+  int64_t hpos[HMAX];
+  NodeRaw<TR> A0[NPT], M0[NPT], B[NPT], C[NPT], Hc[HMAX], Hn[HMAX];
+  TR Om[NPT], Oc[NPT], On[NPT], Ob[NPT], Obn[NPT];
+  // PE-lower coupling of a node when the PE axis is a or b
+  auto off_lower = [&](int64_t n, int i) -> TR {
+    if (ROLE == 1) return ia[i] > 0 ? bld<TR>(rO, (uint32_t)(n - nb) * kSz) : TR(0);
+    if (ROLE == 2) return ib[i] > 0 ? bld<TR>(rO, (uint32_t)(n - 1) * kSz) : TR(0);
+    return TR(0);
+  };
+  // geometry of unit uu and the loads of planes o0-1 .. o0+1 and the halo rows of o0
+  auto begin_unit = [&](int64_t uu) {
+    const int ti = (int)(uu / m.noc), oc = (int)(uu - (int64_t)ti * m.noc);
+    f0 = (int64_t)ti * T;
+    Teff = (int)min<int64_t>(T, P - f0);
+    o0 = oc * m.XL;
+    oe = min(o0 + m.XL, no);
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int l = t + i * BLK;
+      own[i] = l < Teff;
+      fl[i] = own[i] ? l : Teff - 1;
+      const int64_t f = f0 + fl[i];
+      ia[i] = (int)(f / nb);
+      ib[i] = (int)(f - (int64_t)ia[i] * nb);
+    }
+#pragma unroll
+    for (int j = 0; j < HMAX; ++j) {
+      const int h = t + j * BLK;
+      int64_t hp = -1;
+      if (h < 2 * nb) {
+        hp = h < nb ? f0 - nb + h : f0 + Teff + (h - nb);
+        if (hp < 0 || hp >= P) hp = -1;
+      }
+      hpos[j] = hp;
+    }
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int64_t n = (int64_t)o0 * P + f0 + fl[i];
+      A0[i] = load_raw(n, true);
+      if (o0 + 1 < no) B[i] = load_raw(n + P, o0 + 1 < oe);
+      Oc[i] = bld<TR>(rO, (uint32_t)n * kSz);
+      Ob[i] = off_lower(n, i);
+      Om[i] = TR(0);
+      if (o0 > 0) {
+        M0[i] = load_raw(n - P, false);
+        if (ROLE == 0) Om[i] = bld<TR>(rO, (uint32_t)(n - P) * kSz);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < HMAX; ++j)
+      if (hpos[j] >= 0) Hc[j] = load_raw((int64_t)o0 * P + hpos[j], false);
+  };
+
+  // Fused: the previous iteration's block sums are loaded first, then the first unit's planes,
+  // so that the reduction waits for the former only and the latter arrive meanwhile.
+  const bool fused = !first && a.sc.fused;
+  const PcgSlot prev = a.sc.slots[fused ? (it - 1) & 1 : it & 1];
+  double tsum[7];
+  if (fused) load_partials_cm<7>(tsum, a.sc.part_prev, a.sc.nprod, it == 1 ? 7 : 5);
+  int64_t u = ulo + lb;
+  if (u < uhi) begin_unit(u);
+  const PcgSlot sl = fused ? pcg_scalar_phase(a.sc, prev, tsum) : prev;
+  if (sl.status == kPcgDone) return;
+  const TR al = (TR)sl.alpha, be = (TR)sl.beta;
   if (sl.status == kPcgFinish) {  // last update x += a p of the previous iteration (pointwise)
+    TR* __restrict__ x = static_cast<TR*>(a.x);
+    const TR* __restrict__ pi = static_cast<const TR*>(a.p_in);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.nnode; i += stride)
       x[i] = x[i] + al * pi[i];
     return;
   }
-
-  // Updated search direction at an arbitrary node (same arithmetic as for owned nodes).
-  auto pnew = [&](int64_t n) -> TR {
-    if (first) return sgn * rhs[n] / dg[n];
-    const TR r = ri[n] - al * wi[n];
-    return r / dg[n] + be * pi[n];
-  };
+  const TR sgn = (TR)a.rhs_sign;
   const TR cx = (TR)(a.alpha * g.vol / (g.hx * g.hx));
   const TR cy = (TR)(a.alpha * g.vol / (g.hy * g.hy));
-  const int lane = threadIdx.x & (kWave - 1);
-  const SlabTiles T = slab_tiles(g, S, X);
+  // constant couplings along the non-PE directions of the march
+  const TR c_o = ROLE == 0 ? TR(0) : cx;
+  const TR c_a = ROLE == 0 ? cx : (ROLE == 1 ? TR(0) : cy);
+  const TR c_b = ROLE == 2 ? TR(0) : cy;
+  auto p_of = [&](const NodeRaw<TR>& v) -> TR {
+    if (first) return sgn * v.r / v.d;
+    return (v.r - al * v.w) / v.d + be * v.p;
+  };
+  TR Pm[NPT], Pc[NPT], Pn[NPT], Dc[NPT], Rc[NPT], Dn[NPT], Rn[NPT];
+  auto own_update = [&](int o, const NodeRaw<TR> (&R)[NPT], TR (&Pq)[NPT], TR (&Dq)[NPT],
+                        TR (&Rq)[NPT]) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const TR d = R[i].d;
+      TR r, xn, p;
+      if (first) {
+        r = sgn * R[i].r;
+        xn = TR(0);
+        p = r / d;
+      } else {
+        r = R[i].r - al * R[i].w;
+        xn = R[i].x + al * R[i].p;
+        p = r / d + be * R[i].p;
+      }
+      Pq[i] = p;
+      Dq[i] = d;
+      Rq[i] = r;
+      if (own[i]) {
+        const uint32_t bo = (uint32_t)((int64_t)o * P + f0 + fl[i]) * kSz;
+        bst<TR>(rX, bo, xn);
+        bst<TR>(rRo, bo, r);
+        bst<TR>(rPo, bo, p);
+      }
+    }
+  };
 
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (WaveIter it = wave_iter(T.ntiles); it.t < it.end; it.t += it.stride) {
-    const int chunk = (int)(it.t % T.nchunk);
-    const int64_t rest = it.t / T.nchunk;
-    const int run = (int)(rest % T.nrun);
-    const int slab = (int)(rest / T.nrun);
-    const int iy = chunk * kWave + lane;
-    const bool yok = iy < g.ny;
-    const int64_t iyc = yok ? iy : g.ny - 1;
-    const bool hasym = iyc > 0, hasyp = iyc < g.ny - 1;
-    const int k0 = run * S;
-    const int ix0 = slab * X;
-    const int nrow = min(X, g.nx - ix0);
-    const int64_t ybase = iyc * g.nys;
-
-    // Own update of row ix: x, r, p at the S owned nodes (stored), p at the two PE halo nodes.
-    auto own_row = [&](int ix, TR (&P)[S + 2], TR (&D)[S], TR (&R)[S]) {
-      const int64_t base = (int64_t)ix * g.nxs + ybase;
+  for (; u < uhi; u += gl) {
+    if (u != ulo + lb) begin_unit(u);
 #pragma unroll
-      for (int i = 0; i < S + 2; ++i) {
-        int k = k0 - 1 + i;
-        const bool own = i >= 1 && i <= S;
-        const bool nodeok = k >= 0 && k <= mp;
-        k = k < 0 ? 0 : (k > mp ? mp : k);
-        const int64_t n = base + (int64_t)k * g.nps;
-        if (!own) {
-          P[i] = pnew(n);
-          continue;
+    for (int i = 0; i < NPT; ++i) {
+      Pm[i] = o0 > 0 ? p_of(M0[i]) : TR(0);
+      Pn[i] = TR(0);
+      Dn[i] = TR(1);
+      Rn[i] = TR(0);
+    }
+    own_update(o0, A0, Pc, Dc, Rc);
+    for (int o = o0; o < oe; ++o) {
+      // loads for later planes: raw plane o+2 (owned or the halo plane), halo rows and couplings
+      // of plane o+1
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) {
+        const int64_t n1 = (int64_t)(o + 1) * P + f0 + fl[i];
+        if (o + 2 < no && o + 2 <= oe) C[i] = load_raw(n1 + P, o + 2 < oe);
+        if (o + 1 < oe) {
+          On[i] = bld<TR>(rO, (uint32_t)n1 * kSz);
+          Obn[i] = off_lower(n1, i);
         }
-        const TR d = dg[n];
-        TR r, xn, p;
-        if (first) {
-          r = sgn * rhs[n];
-          xn = TR(0);
-          p = r / d;
+      }
+      if (o + 1 < oe) {
+#pragma unroll
+        for (int j = 0; j < HMAX; ++j)
+          if (hpos[j] >= 0) Hn[j] = load_raw((int64_t)(o + 1) * P + hpos[j], false);
+      }
+      // plane o+1 from the raw values loaded one plane earlier
+      if (o + 1 < oe) {
+        own_update(o + 1, B, Pn, Dn, Rn);
+      } else if (o + 1 < no) {
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) Pn[i] = p_of(B[i]);
+      }
+      TR* buf = lds + (o & 1) * (T + 2 * nb);
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) buf[fl[i] + nb] = Pc[i];
+#pragma unroll
+      for (int j = 0; j < HMAX; ++j)
+        if (hpos[j] >= 0) buf[hpos[j] - f0 + nb] = p_of(Hc[j]);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) {
+        const int li = fl[i] + nb;
+        const TR pk = Pc[i];
+        const bool am = ia[i] > 0, ap = ia[i] < na - 1, bm = ib[i] > 0, bp = ib[i] < nb - 1;
+        const TR pam = am ? buf[li - nb] : TR(0), pap = ap ? buf[li + nb] : TR(0);
+        const TR pbm = bm ? buf[li - 1] : TR(0), pbp = bp ? buf[li + 1] : TR(0);
+        const TR pom = o > 0 ? Pm[i] : TR(0), pop = o < no - 1 ? Pn[i] : TR(0);
+        TR w = Dc[i] * pk;
+        if (ROLE == 0) {
+          w += Om[i] * pom + Oc[i] * pop;
+          w -= c_a * (pam + pap) + c_b * (pbm + pbp);
+        } else if (ROLE == 1) {
+          w += Ob[i] * pam + Oc[i] * pap;
+          w -= c_o * (pom + pop) + c_b * (pbm + pbp);
         } else {
-          const TR pold = pi[n];
-          r = ri[n] - al * wi[n];
-          xn = x[n] + al * pold;
-          p = r / d + be * pold;
+          w += Ob[i] * pbm + Oc[i] * pbp;
+          w -= c_o * (pom + pop) + c_a * (pam + pap);
         }
-        P[i] = p;
-        D[i - 1] = d;
-        R[i - 1] = r;
-        if (nodeok && yok) {
-          x[n] = xn;
-          ro[n] = r;
-          po[n] = p;
-        }
-      }
-    };
-    // p of a neighbouring row outside the slab (owned nodes only).
-    auto halo_row = [&](int ix, TR (&P)[S + 2]) {
-      const int64_t base = (int64_t)ix * g.nxs + ybase;
-#pragma unroll
-      for (int i = 1; i <= S; ++i) {
-        int k = k0 - 1 + i;
-        k = k > mp ? mp : k;
-        P[i] = pnew(base + (int64_t)k * g.nps);
-      }
-    };
-
-    TR Pm[S + 2], Pc[S + 2], Pn[S + 2];
-    TR Dc[S], Rc[S], Dn[S], Rn[S];
-#pragma unroll
-    for (int i = 0; i < S + 2; ++i) Pm[i] = Pc[i] = Pn[i] = TR(0);
-#pragma unroll
-    for (int i = 0; i < S; ++i) Dn[i] = Rn[i] = TR(1);
-    if (ix0 > 0) halo_row(ix0 - 1, Pm);
-    own_row(ix0, Pc, Dc, Rc);
-#pragma unroll
-    for (int j = 0; j < X; ++j) {
-      if (j >= nrow) break;
-      const int ix = ix0 + j;
-      const bool hasxm = ix > 0, hasxp = ix + 1 < g.nx;
-      if (j + 1 < nrow) {
-        own_row(ix + 1, Pn, Dn, Rn);
-      } else if (hasxp) {
-        halo_row(ix + 1, Pn);
-      }
-      const int64_t base = (int64_t)ix * g.nxs + ybase;
-      // off at nodes k0-1 .. k0+S-1
-      TR oo[S + 1];
-#pragma unroll
-      for (int i = 0; i < S + 1; ++i) {
-        int k = k0 - 1 + i;
-        k = k < 0 ? 0 : (k > mp ? mp : k);
-        oo[i] = of[base + (int64_t)k * g.nps];
-      }
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int k = k0 + s;
-        const bool nodeok = k <= mp;
-        const int kc = nodeok ? k : mp;
-        const int64_t n = base + (int64_t)kc * g.nps;
-        const TR pk = Pc[s + 1];
-        TR pym = __shfl_up(pk, 1, kWave);
-        TR pyp = __shfl_down(pk, 1, kWave);
-        if (lane == 0 && hasym) pym = pnew(n - g.nys);
-        if (lane == kWave - 1 && hasyp) pyp = pnew(n + g.nys);
-        const TR d = Dc[s];
-        TR w = d * pk;
-        if (k > 0) w += oo[s] * Pc[s];
-        if (k < mp) w += oo[s + 1] * Pc[s + 2];
-        TR crx = TR(0), cry = TR(0);
-        if (hasxm) crx += Pm[s + 1];
-        if (hasxp) crx += Pn[s + 1];
-        if (hasym) cry += pym;
-        if (hasyp) cry += pyp;
-        w -= cx * crx + cy * cry;
-        if (nodeok && yok) {
-          wo[n] = w;
-          // FP64 products and sums; one reciprocal of the diagonal per node
-          const double r = (double)Rc[s], ww = (double)w, id = (double)(TR(1) / d);
-          const double wd = ww * id;
+        if (own[i]) {
+          bst<TR>(rWo, (uint32_t)((int64_t)o * P + f0 + fl[i]) * kSz, w);
+          // FP64 products and sums
+          const double r = (double)Rc[i], ww = (double)w, dd = (double)Dc[i];
           acc[0] += (double)pk * ww;
-          acc[1] += r * wd;
-          acc[2] += ww * wd;
+          acc[1] += r * ww / dd;
+          acc[2] += ww * ww / dd;
           acc[3] += r * ww;
           acc[4] += ww * ww;
           if (first) {
-            acc[5] += r * r * id;
+            acc[5] += r * r / dd;
             acc[6] += r * r;
           }
         }
       }
 #pragma unroll
-      for (int i = 0; i < S + 2; ++i) {
+      for (int i = 0; i < NPT; ++i) {
         Pm[i] = Pc[i];
         Pc[i] = Pn[i];
-      }
-#pragma unroll
-      for (int i = 0; i < S; ++i) {
         Dc[i] = Dn[i];
         Rc[i] = Rn[i];
+        if (ROLE == 0) Om[i] = Oc[i];
+        B[i] = C[i];
+        if (o + 1 < oe) {
+          Oc[i] = On[i];
+          Ob[i] = Obn[i];
+        }
       }
+#pragma unroll
+      for (int j = 0; j < HMAX; ++j) Hc[j] = Hn[j];
     }
+    __syncthreads();  // the next unit reuses the LDS buffers
   }
-  store_partials<7>(acc, a.part);
+  store_partials_cm<7>(acc, a.part);
 }
 
 Launch plan_hvp(const Geom& g, DType real) {
   return plan_tiles(g, kRun, (real == DType::F32 && plan_tiles(g, kRun, 256).ntiles > 1024) ? 1024 : 256);
 }
 
-// PCG launch shape: slab depth X = 2, run length S = 4, 256-thread blocks, one wavefront per
-// tile up to kMaxGrid blocks (measured best on 144x168x111; full occupancy needs the large grid,
-// which the single-block scalar kernel makes affordable).
-namespace {
-constexpr int kPcgS = 4;
-constexpr int kPcgX = 2;
-constexpr int kPcgBlock = 256;
-}
-Launch plan_pcg(const Geom& g, DType real) {
-  (void)real;
-  Launch L;
-  L.S = kPcgS;
-  L.block = kPcgBlock;
-  L.ntiles = slab_tiles(g, kPcgS, kPcgX).ntiles;
-  const int64_t wpb = kPcgBlock / kWave;
-  int64_t grid = (L.ntiles + wpb - 1) / wpb;
-  if (grid > kMaxGrid) grid = kMaxGrid;
+// PCG launch shape.  256-thread blocks with one plane position per thread (two above 4 M nodes);
+// 512-thread blocks when the contiguous axis is longer than 256 nodes, so that the two halo rows
+// fit in two slots per thread.  XL is the shortest march that keeps every unit resident at once
+// (at most 16 wavefronts per CU over 256 CUs): the halo planes cost less than a second wave of
+// workgroups (measured on 144x168x111 and 200x200x132).
+PcgPlan plan_pcg(const Geom& g, DType real) {
+  PcgPlan L{};
+  const int nb = march_geo(g, 1, 1).nb;
+  if (real == DType::F64) {
+    L.block = 2 * nb <= 512 ? 256 : 512;
+    L.npt = 1;
+    L.hmax = 2;
+  } else if (2 * nb <= 512) {
+    L.block = 256;
+    L.npt = g.nnode > (int64_t(4) << 20) ? 2 : 1;
+    L.hmax = 2 * nb <= 256 ? 1 : 2;
+  } else {
+    L.block = 512;
+    L.npt = 1;
+    L.hmax = 2;
+  }
+  const int T = (int)L.block * L.npt;
+  static const int kXL[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+  const int64_t max_units = 4096 / ((int64_t)L.block / kWave);
+  MarchGeo m = march_geo(g, T, 64);
+  for (int xl : kXL) {
+    const MarchGeo c = march_geo(g, T, xl);
+    if (c.units <= max_units) {
+      m = c;
+      break;
+    }
+  }
+  L.m = m;
+  int64_t grid = m.units < kMaxGrid ? m.units : kMaxGrid;
   if (grid > 8) grid = (grid + 7) / 8 * 8;
   if (grid > kMaxGrid) grid = kMaxGrid;
   L.grid = (unsigned)(grid < 1 ? 1 : grid);
+  L.lds = 2 * (size_t)(T + 2 * nb) * (real == DType::F64 ? 8 : 4);
+  L.fused = 1;
   return L;
 }
 
@@ -404,25 +519,51 @@ hipError_t launch_hvp(const HvpArgs& a, DType real, hipStream_t s) {
 }
 
 hipError_t launch_sum_final(const double* part, unsigned nprod, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, part, nprod, out);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kReduceBlock), 0, s, part, nprod, out);
   return hipGetLastError();
 }
 
-hipError_t launch_pcg_step(const PcgArgs& a, DType real, hipStream_t s) {
-  const Launch L = plan_pcg(a.g, real);
-  if (real == DType::F64)
-    hipLaunchKernelGGL((k_pcg_step<double, kPcgS, kPcgX, kPcgBlock>), dim3(L.grid),
-                       dim3(kPcgBlock), 0, s, a);
-  else if (real == DType::F32)
-    hipLaunchKernelGGL((k_pcg_step<float, kPcgS, kPcgX, kPcgBlock>), dim3(L.grid),
-                       dim3(kPcgBlock), 0, s, a);
+template <typename TR, int BLK, int NPT, int HMAX>
+static void launch_step_cfg(const PcgArgs& a, const PcgPlan& L, hipStream_t s) {
+  const int role = L.m.role;
+  if (role == 0)
+    hipLaunchKernelGGL((k_pcg_step<TR, 0, BLK, NPT, HMAX>), dim3(L.grid), dim3(BLK), L.lds, s, a,
+                       L.m);
+  else if (role == 1)
+    hipLaunchKernelGGL((k_pcg_step<TR, 1, BLK, NPT, HMAX>), dim3(L.grid), dim3(BLK), L.lds, s, a,
+                       L.m);
   else
+    hipLaunchKernelGGL((k_pcg_step<TR, 2, BLK, NPT, HMAX>), dim3(L.grid), dim3(BLK), L.lds, s, a,
+                       L.m);
+}
+
+hipError_t launch_pcg_step(const PcgArgs& a, DType real, hipStream_t s) {
+  const PcgPlan L = plan_pcg(a.g, real);
+  if (2 * L.m.nb > L.hmax * (int)L.block) return hipErrorInvalidValue;
+  if (real == DType::F64) {
+    if (L.block == 256)
+      launch_step_cfg<double, 256, 1, 2>(a, L, s);
+    else
+      launch_step_cfg<double, 512, 1, 2>(a, L, s);
+  } else if (real == DType::F32) {
+    if (L.block == 512)
+      launch_step_cfg<float, 512, 1, 2>(a, L, s);
+    else if (L.npt == 1 && L.hmax == 1)
+      launch_step_cfg<float, 256, 1, 1>(a, L, s);
+    else if (L.npt == 1)
+      launch_step_cfg<float, 256, 1, 2>(a, L, s);
+    else if (L.hmax == 1)
+      launch_step_cfg<float, 256, 2, 1>(a, L, s);
+    else
+      launch_step_cfg<float, 256, 2, 2>(a, L, s);
+  } else {
     return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_pcg_scalars(const PcgScalarArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kReduceBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@ namespace rgp {
 
 constexpr int kWave = 64;         // CDNA wavefront width
 constexpr int kBlock = 256;       // threads per workgroup of the small kernels
+constexpr int kReduceBlock = 512;   // threads of the single-block reducing kernels
 
 // bfloat16 image storage: upper 16 bits of an IEEE binary32.
 struct bf16_t {
@@ -162,17 +163,136 @@ __device__ __forceinline__ void store_partials(double (&v)[K], double* part) {
   }
 }
 
-// Every thread of the calling block obtains the sums over nprod producer blocks.
+// Every thread of the calling block obtains the sums over nprod producer blocks.  The loads are
+// issued in batches of 4 (2 for K > 8) blocks per thread, all independent, so that one batch costs
+// one memory round trip; the summation order is fixed.
 template <int K>
 __device__ __forceinline__ void reduce_partials(double (&out)[K], const double* part,
                                                 unsigned nprod) {
 #pragma unroll
   for (int k = 0; k < K; ++k) out[k] = 0.0;
-  for (unsigned b = threadIdx.x; b < nprod; b += blockDim.x) {
+  constexpr int kB = K <= 8 ? 4 : 2;
+  for (unsigned b0 = 0; b0 < nprod; b0 += kB * blockDim.x) {
+    double v[kB][K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) out[k] += part[(size_t)b * kPartStride + k];
+    for (int j = 0; j < kB; ++j) {
+      const unsigned b = b0 + j * blockDim.x + threadIdx.x;
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[j][k] = b < nprod ? part[(size_t)b * kPartStride + k] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kB; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k) out[k] += v[j][k];
   }
   block_sum<K>(out);
+}
+
+// ----------------------------------------------------------------------------------------
+// Buffer-resource memory access: one 128-bit descriptor per array (in scalar registers) and one
+// 32-bit byte offset per lane shared by every array indexed at the same node, which keeps the
+// per-lane address state of kernels that stream many arrays small.  Accesses outside the
+// descriptor's range read 0 and are dropped on store.
+// ----------------------------------------------------------------------------------------
+typedef __amdgpu_buffer_rsrc_t BRes;
+
+__device__ __forceinline__ BRes bres(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bld(BRes r, uint32_t off);
+template <>
+__device__ __forceinline__ float bld<float>(BRes r, uint32_t off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double bld<double>(BRes r, uint32_t off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+  return __hiloint2double((int)v[1], (int)v[0]);
+}
+template <typename T>
+__device__ __forceinline__ void bst(BRes r, uint32_t off, T v);
+template <>
+__device__ __forceinline__ void bst<float>(BRes r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)off, 0, 0);
+}
+template <>
+__device__ __forceinline__ void bst<double>(BRes r, uint32_t off, double v) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  u32x2 w;
+  w[0] = (unsigned)u;
+  w[1] = (unsigned)(u >> 32);
+  __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)off, 0, 0);
+}
+
+// ----------------------------------------------------------------------------------------
+// Plane march over the node grid.  The field array is viewed as (o, a, b) with b contiguous, the
+// (a, b) plane contiguous and o the outermost axis, whichever of x, y and PE they are:
+//   PE axis 0: o = PE, a = x, b = y;   PE axis 1: o = x, a = PE, b = y;   PE axis 2: o = x, a = y,
+//   b = PE.
+// A work unit is a flat run of T consecutive plane positions (so any plane shape tiles without
+// waste) times XL consecutive planes; a workgroup marches through its unit plane by plane.
+// ----------------------------------------------------------------------------------------
+struct MarchGeo {
+  int32_t no, na, nb;    // extents of o, a, b
+  int32_t role;          // which of o (0), a (1), b (2) is the PE axis
+  int64_t P;             // plane size na * nb (also the o stride)
+  int32_t T, XL;         // unit: T plane positions x XL planes
+  int32_t ntile, noc;    // units per plane, units along o
+  int64_t units;
+};
+
+__host__ __device__ inline MarchGeo march_geo(const Geom& g, int T, int XL) {
+  MarchGeo m{};
+  if (g.pe == 0) {
+    m.no = g.mp + 1; m.na = g.nx; m.nb = g.ny; m.role = 0;
+  } else if (g.pe == 1) {
+    m.no = g.nx; m.na = g.mp + 1; m.nb = g.ny; m.role = 1;
+  } else {
+    m.no = g.nx; m.na = g.ny; m.nb = g.mp + 1; m.role = 2;
+  }
+  m.P = (int64_t)m.na * m.nb;
+  m.T = T;
+  m.XL = XL;
+  m.ntile = (int32_t)((m.P + T - 1) / T);
+  m.noc = (m.no + XL - 1) / XL;
+  m.units = (int64_t)m.ntile * m.noc;
+  return m;
+}
+
+// Column-major variant for consumers that reduce in every block: sum k of block b is stored at
+// part[k * kMaxGrid + b], so the consumer's loads of one sum over all blocks are coalesced.
+template <int K>
+__device__ __forceinline__ void store_partials_cm(double (&v)[K], double* part) {
+  block_sum<K>(v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) part[(size_t)k * kMaxGrid + blockIdx.x] = v[k];
+  }
+}
+
+// Per-thread partial sums of the first `kuse` column-major sums over nprod blocks (loads only,
+// in batches of 4 independent loads per sum; block_sum completes the reduction in a fixed order).
+template <int K>
+__device__ __forceinline__ void load_partials_cm(double (&out)[K], const double* part,
+                                                 unsigned nprod, int kuse) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) out[k] = 0.0;
+  for (unsigned b0 = 0; b0 < nprod; b0 += 4u * blockDim.x) {
+    double v[K][4];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const unsigned b = b0 + j * blockDim.x + threadIdx.x;
+        v[k][j] = (k < kuse && b < nprod) ? part[(size_t)k * kMaxGrid + b] : 0.0;
+      }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) out[k] += v[k][j];
+  }
 }
 
 __device__ __forceinline__ double inf_d() { return __longlong_as_double(0x7ff0000000000000LL); }

@@ -125,6 +125,25 @@ struct HvpArgs {
   double* part;   // nullable: block sums of v.Hv
 };
 
+// Scalar phase of a PCG iteration: reduces the block sums of iteration iter-1 and derives the
+// coefficients and status of iteration iter (slots[iter & 1]).  Iteration 0 runs it in the
+// single-block k_pcg_scalars (which also finalises the objective in Gauss-Newton mode); later
+// iterations run it either there too or (fused) at the start of every block of k_pcg_step,
+// block 0 writing the slot.
+struct PcgScalarArgs {
+  State* st;
+  PcgSlot* slots;           // [2]
+  const double* part_prev;  // block sums of iteration iter-1
+  unsigned nprod;           // grid of the main PCG kernels
+  int iter, maxit;
+  double rtol;
+  int gn_mode;
+  int fused;                // iter >= 1: 1 = k_pcg_step derives the slot, 0 = k_pcg_scalars does
+  int32_t* iters_out;       // nullable
+  double* relres_out;       // nullable
+  LossFinalArgs lf;         // gn_mode, iteration 0: J, D, S, P of the current iterate
+};
+
 struct PcgArgs {
   Geom g;
   const void* diag;
@@ -139,24 +158,18 @@ struct PcgArgs {
   void* p_out;
   void* w_out;
   double alpha;             // smoothness weight (cross-axis couplings)
-  const PcgSlot* slot;      // coefficients and status of this iteration (from k_pcg_scalars)
   double* part;             // block sums of this iteration
-  int iter;
+  PcgScalarArgs sc;         // iteration index, slots and the previous block sums
 };
 
-// Single-block kernel between PCG iterations: reduces the block sums of iteration iter-1 and
-// writes the coefficients and status of iteration iter into slots[iter & 1].
-struct PcgScalarArgs {
-  State* st;
-  PcgSlot* slots;           // [2]
-  const double* part_prev;  // block sums of iteration iter-1
-  unsigned nprod;           // grid of the main PCG kernels
-  int iter, maxit;
-  double rtol;
-  int gn_mode;
-  int32_t* iters_out;       // nullable
-  double* relres_out;       // nullable
-  LossFinalArgs lf;         // gn_mode, iteration 0: J, D, S, P of the current iterate
+// Launch shape of the PCG step: `block` threads, npt plane positions per thread, hmax halo slots
+// per thread, units of XL planes (m), `lds` bytes of dynamic LDS.
+struct PcgPlan {
+  unsigned grid, block;
+  int npt, hmax;
+  MarchGeo m;
+  size_t lds;
+  int fused;               // scalar phase inside k_pcg_step (else one k_pcg_scalars per iteration)
 };
 
 struct ShiftArgs {
@@ -202,7 +215,7 @@ struct SetStateArgs {
 Launch plan_tiles(const Geom& g, int S, int block);
 Launch plan_loss_grad(const Geom& g, DType real);
 Launch plan_trial(const Geom& g, DType real, int nc);
-Launch plan_pcg(const Geom& g, DType real);
+PcgPlan plan_pcg(const Geom& g, DType real);
 Launch plan_hvp(const Geom& g, DType real);
 unsigned shift_grid(int64_t n);
 

@@ -72,7 +72,9 @@ constexpr int kTrialSlots = 18;
 __device__ __forceinline__ int armijo_pick(const double* t, int first, int nc, const State& st,
                                            double gq, double sbq, double sqq, double vol,
                                            double alpha, double beta, double c, double& gamma) {
-  for (int k = 0; k < nc; ++k) {
+#pragma unroll
+  for (int k = 0; k < (kTrialSlots - 3) / 3; ++k) {  // unrolled: t stays in registers
+    if (k >= nc) break;
     const double gm = ldexp(1.0, -(first + k));
     const double D = 0.5 * vol * t[3 + 3 * k];
     const double P = t[5 + 3 * k] > 0.0 ? inf_d() : 0.5 * vol * t[4 + 3 * k];
