@@ -4,16 +4,28 @@
 One step = one whole correction of one synthetic 3T-brain-shaped pair, 144x168x111, phase
 encoding along dim 1, FP32: image pyramid (3 levels), OT initialisation on the coarsest level,
 10 Gauss-Newton steps per level with 20 PCG iterations each (rtol 0) and Armijo line search,
-prolongation between levels, and the Jacobian-modulation correction - all through rgp_correct.
-Inputs are resident in HBM before the timed region.  The per-kernel lines time back-to-back
-launches of each hot kernel at the finest level with HIP events on the stream they run on.
+prolongation between levels, and the Jacobian-modulation correction - all through the C ABI.
+Inputs are resident in HBM before the timed region.  The correction is captured once into a HIP
+graph (rgp_correct_plan) and one step is one replay; an eager pass of the same correction follows
+with the library's kernel timing on (HIP events recorded at the start and end of every hot
+kernel, rgp_timing_*), from which the per-kernel rooflines are computed.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
+
+Other modes (profiling helpers; their output goes under profiles/):
+  --pmc-probe                 a plain 256 MiB elementwise copy, then one PCG solve on the finest
+                              level (the workload for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)
+  --traffic-summary F W       HBM traffic of the finest-level PCG step from the two --pmc runs
+                              (directories F and W), scaled by the copy kernel's counters
+  --profile-summary D         text summary of a rocprofv3 --kernel-trace --stats run in D
 """
 import argparse
+import csv
+import glob
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -23,8 +35,11 @@ if ROOT not in sys.path:
 
 METRIC = "volume pairs corrected/s at 144×168×111; loss_grad+gn_hvp HBM GB/s vs peak"
 HBM_PEAK_GBPS = 8000.0
+SHAPE, PE, LEVELS, GN_ITERS, PCG_ITERS = (144, 168, 111), 1, 3, 10, 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pcg_step_c2_traffic.json")
-KERNEL_SOURCES = ("paper_2403_10706_amd/csrc/pcg.hip", "paper_2403_10706_amd/csrc/rgp_internal.hpp")
+KERNEL_SOURCES = ("paper_2403_10706_amd/csrc/pcg.hip", "paper_2403_10706_amd/csrc/rgp_internal.hpp",
+                  "paper_2403_10706_amd/csrc/rgp_launch.hpp")
+COPY_MIB = 256
 
 
 def log(*a):
@@ -40,7 +55,8 @@ def kernel_source_hash():
 
 
 def measured_traffic():
-    """HBM bytes per launch of the PCG step from committed rocprofv3 counters, if still valid."""
+    """HBM bytes per launch of the finest-level PCG step from committed rocprofv3 counters, if
+    they were taken on the current kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
@@ -50,25 +66,77 @@ def measured_traffic():
     return rec.get("bytes_per_launch")
 
 
-def event_time_ms(fn, stream, reps):
-    import torch
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(reps):
-        fn()
-    e1.record(stream)
-    e1.synchronize()
-    return e0.elapsed_time(e1)
+# ---------------------------------------------------------------------------------------------
+# algorithmic bytes per launch (FP32 field f, image element size fi)
+
+def algorithmic_bytes(rec, f=4, fi=4, maxit=PCG_ITERS):
+    k, n, c, tag = rec["kernel"], rec["nodes"], rec["cells"], rec["tag"]
+    if k == "pcg_step":
+        if tag == 0:           # first iteration: reads rhs, diag, off; writes x, r, p, w
+            return 7 * f * n
+        if tag >= maxit:       # last update x += a p
+            return 3 * f * n
+        return 10 * f * n      # reads x, r, p, w, diag, off; writes x, r, p, w
+    if k == "loss_grad":       # reads I+, I-, b (and q); writes grad, diag, off (and b + g q)
+        return 2 * fi * c + (6 if tag else 4) * f * n
+    if k == "trial":           # reads I+, I-, b, q
+        return 2 * fi * c + 2 * f * n
+    if k == "hvp":             # reads v, diag, off; writes Hv
+        return 4 * f * n
+    if k == "ot":              # reads I+, I-; writes b0
+        return 2 * fi * c + f * n
+    if k == "shift":           # reads I+, I-
+        return 2 * fi * c
+    return 0
 
 
-def cpu_baseline(pair, levels, gn_iters, pcg_iters):
+BYTES_RULE = {
+    "pcg_step": "full iteration: reads x,r,p,w,diag,off, writes x,r,p,w (40 B/node)",
+    "loss_grad": "reads I+,I-,b[,q], writes grad,diag,off[,b+gq] (8 B/cell + 16 or 24 B/node)",
+    "trial": "reads I+,I-,b,q (8 B/cell + 8 B/node)",
+    "hvp": "reads v,diag,off, writes Hv (16 B/node)",
+    "ot": "reads I+,I-, writes b0 (8 B/cell + 4 B/node)",
+    "shift": "reads I+,I- (8 B/cell)",
+}
+
+
+def summarize_records(recs, maxit=PCG_ITERS):
+    """Group timed launches by kernel and volume; the PCG step keeps full iterations only and
+    trial passes keep first passes (later passes exit early once a step is accepted)."""
+    groups = {}
+    for r in recs:
+        if r["kernel"] == "pcg_step" and not (1 <= r["tag"] < maxit):
+            continue
+        if r["kernel"] == "trial" and r["tag"] != 1:
+            continue
+        key = (r["kernel"], r["nodes"], r["tag"] if r["kernel"] == "loss_grad" else 0)
+        groups.setdefault(key, []).append(r)
+    out = {}
+    for (k, nodes, tag), rs in sorted(groups.items(),
+                                      key=lambda kv: (kv[0][0], -kv[0][1], kv[0][2])):
+        ms = [r["ms"] for r in rs]
+        mean = sum(ms) / len(ms)
+        med = statistics.median(ms)
+        b = algorithmic_bytes(rs[0], maxit=maxit)
+        gbps = b / (mean * 1e-3) / 1e9 if mean > 0 else 0.0
+        name = f"{k}@{nodes}n" + ("+step" if (k == "loss_grad" and tag) else "")
+        out[name] = dict(kernel=k, cells=rs[0]["cells"], nodes=nodes, grid=rs[0]["grid"],
+                         launches=len(rs), us_mean=round(mean * 1e3, 3),
+                         us_median=round(med * 1e3, 3), bytes_per_launch=b,
+                         achieved_GBps=round(gbps, 1), frac=round(gbps / HBM_PEAK_GBPS, 4),
+                         bytes_rule=BYTES_RULE[k])
+    return out
+
+
+# ---------------------------------------------------------------------------------------------
+
+def cpu_baseline(pair, levels, gn_iters, pcg_iters, sample_gn=5):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload.
 
-    Sample: the pyramid, OT on the coarsest level, ONE Gauss-Newton step (with the full PCG
-    iteration count) on every level, the prolongations and the final correction.  The per-pair
-    time is extrapolated by counting each level's measured GN step gn_iters times.
+    Sample: the pyramid, OT on the coarsest level, `sample_gn` of the gn_iters Gauss-Newton steps
+    (each with the full PCG iteration count) on every level, the prolongations and the final
+    correction (about 12 s on one core).  The per-pair time counts the measured GN steps
+    gn_iters / sample_gn times.
     """
     import numpy as np
     from threadpoolctl import threadpool_limits
@@ -92,34 +160,189 @@ def cpu_baseline(pair, levels, gn_iters, pcg_iters):
                 b = orc.prolong_field(b, P.shape, pe)
                 t_fixed += time.perf_counter() - t1
             t1 = time.perf_counter()
-            b, _ = orc.gauss_newton(P, M, b, pe, hh, gn_iters=1, pcg_iters=pcg_iters, pcg_rtol=0.0)
+            b, _ = orc.gauss_newton(P, M, b, pe, hh, gn_iters=sample_gn, pcg_iters=pcg_iters,
+                                    pcg_rtol=0.0)
             t_gn += time.perf_counter() - t1
         t1 = time.perf_counter()
         orc.transform(Ip, b, pe, pair.h, 1.0)
         orc.transform(Im, b, pe, pair.h, -1.0)
         t_fixed += time.perf_counter() - t1
     sample_s = t_fixed + t_gn
-    per_pair = t_fixed + gn_iters * t_gn
+    per_pair = t_fixed + t_gn * gn_iters / sample_gn
     return dict(value=1.0 / per_pair, unit="pairs/s", cores=1, kind="oracle",
-                sample=(f"pyramid + OT + 1 of {gn_iters} GN steps (PCG {pcg_iters}) per level + "
-                        f"prolongations + correction, {sample_s:.1f} s measured; per-pair time "
-                        f"{per_pair:.1f} s extrapolated (GN step x {gn_iters}); FP64 NumPy, "
-                        "1 thread"))
+                sample=(f"pyramid + OT + {sample_gn} of {gn_iters} GN steps (PCG {pcg_iters}) per "
+                        f"level + prolongations + correction, {sample_s:.1f} s measured; per-pair "
+                        f"time {per_pair:.1f} s extrapolated (GN steps x {gn_iters / sample_gn:g}); "
+                        "FP64 NumPy, 1 thread"))
 
+
+# ---------------------------------------------------------------------------------------------
+# profiling helpers
+
+def pmc_probe():
+    """Workload of the rocprofv3 --pmc runs: a plain elementwise copy of known size (256 MiB read,
+    256 MiB written), then one 20-iteration PCG solve on the finest level of the bench pair."""
+    import torch
+
+    import synth
+    from paper_2403_10706_amd import rgp
+
+    rgp.load()
+    dev = torch.device("cuda:0")
+    src = torch.ones(COPY_MIB << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 2.0, out=dst)
+    torch.cuda.synchronize()
+    pair = synth.make_workload("c2")
+    Ip = torch.as_tensor(pair.I_plus).to(dev, torch.float32).contiguous()
+    Im = torch.as_tensor(pair.I_minus).to(dev, torch.float32).contiguous()
+    b = torch.zeros(rgp.field_shape(pair.shape, pair.pe), dtype=torch.float32, device=dev)
+    _, g, hd, ho = rgp.loss_grad(Ip, Im, b, pair.pe)
+    x, its, rel = rgp.pcg_solve(hd, ho, -g, pair.shape, pair.pe, maxit=PCG_ITERS, rtol=0.0)
+    torch.cuda.synchronize()
+    log(f"pmc probe: PCG {int(its.item())} iterations, relres {float(rel.item()):.3e}")
+
+
+def _csv_rows(d, pattern):
+    files = glob.glob(os.path.join(d, "**", pattern), recursive=True)
+    if not files:
+        raise SystemExit(f"no {pattern} under {d}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def _counter(rows, counter):
+    """(kernel name, grid size, value) per dispatch for one counter, in dispatch order."""
+    out = []
+    for r in sorted(rows, key=lambda r: int(r.get("Dispatch_Id", 0))):
+        if r.get("Counter_Name") != counter:
+            continue
+        out.append((r["Kernel_Name"], int(r.get("Grid_Size", 0)), float(r["Counter_Value"])))
+    return out
+
+
+def traffic_summary(fetch_dir, write_dir):
+    nb = SHAPE[0] * (SHAPE[1] + 1) * SHAPE[2]
+    vals = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _counter(_csv_rows(d, "*counter_collection.csv"), counter)
+        # the copy: the elementwise kernels over the largest grid that are not fills
+        ew = [(g, v) for name, g, v in rows if "elementwise" in name and "Fill" not in name]
+        gmax = max((g for g, _ in ew), default=0)
+        copy = [v for g, v in ew if g == gmax]
+        pcg = [(g, v) for name, g, v in rows if "k_pcg_step" in name]
+        if not copy or not pcg:
+            raise SystemExit(f"{counter}: copy or PCG dispatches missing in {d}")
+        # the solve's launches in order: iteration 0, full iterations, last update; keep the full
+        # ones (all on the finest grid)
+        full = [v for _, v in pcg[1:-1]]
+        vals[counter] = dict(copy_kib=statistics.median(copy),
+                             pcg_kib=statistics.median(full), pcg_launches=len(full))
+    expect_kib = COPY_MIB * 1024.0
+    sf = expect_kib / vals["FETCH_SIZE"]["copy_kib"]
+    sw = expect_kib / vals["WRITE_SIZE"]["copy_kib"]
+    fetch_b = vals["FETCH_SIZE"]["pcg_kib"] * sf * 1024.0
+    write_b = vals["WRITE_SIZE"]["pcg_kib"] * sw * 1024.0
+    algo = 40 * nb
+    rec = dict(kernel="k_pcg_step",
+               workload="144x168x111 PE dim 1 FP32, finest level, full PCG iteration",
+               bytes_per_launch=int(round(fetch_b + write_b)), fetch_bytes=int(round(fetch_b)),
+               write_bytes=int(round(write_b)), algorithmic_bytes=algo,
+               traffic_over_algorithmic=round((fetch_b + write_b) / algo, 4),
+               fetch_kib_raw=vals["FETCH_SIZE"]["pcg_kib"],
+               write_kib_raw=vals["WRITE_SIZE"]["pcg_kib"],
+               copy_fetch_kib_raw=vals["FETCH_SIZE"]["copy_kib"],
+               copy_write_kib_raw=vals["WRITE_SIZE"]["copy_kib"],
+               copy_expected_kib=expect_kib, scale_fetch=round(sf, 6), scale_write=round(sw, 6),
+               launches=vals["FETCH_SIZE"]["pcg_launches"], source_sha256=kernel_source_hash(),
+               commands=["rocprofv3 --pmc FETCH_SIZE --output-format csv -d <F> -o run -- "
+                         "python3 bench.py --pmc-probe",
+                         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <W> -o run -- "
+                         "python3 bench.py --pmc-probe",
+                         "python3 bench.py --traffic-summary <F> <W>"])
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def profile_summary(d):
+    """Text summary of a rocprofv3 --kernel-trace --stats run: the per-kernel statistics table,
+    then every kernel split by grid size (mean and median duration per launch)."""
+    stats = _csv_rows(d, "*kernel_stats.csv")
+    trace = _csv_rows(d, "*kernel_trace.csv")
+    print("== rocprofv3 kernel statistics (per kernel name) ==")
+    print(f"{'kernel':70s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}")
+    for r in stats[:30]:
+        name = r["Name"][:70]
+        print(f"{name:70s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.2f} "
+              f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}")
+    groups = {}
+    for r in trace:
+        name = r["Kernel_Name"].split("(")[0]
+        key = (name, int(r["Grid_Size_X"]), int(r["Workgroup_Size_X"]))
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        groups.setdefault(key, []).append(dur)
+    # PCG solves: runs of consecutive k_pcg_step launches on one grid (iteration 0, the full
+    # iterations, the last update); the interior launches are the full iterations
+    trace_sorted = sorted(trace, key=lambda r: int(r["Start_Timestamp"]))
+    runs, cur, cur_grid = [], [], None
+    for r in trace_sorted:
+        name = r["Kernel_Name"]
+        g = int(r["Grid_Size_X"])
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        if "k_pcg_step" in name and (cur_grid is None or g == cur_grid):
+            cur.append(dur)
+            cur_grid = g
+            continue
+        if cur:
+            runs.append((cur_grid, cur))
+        cur, cur_grid = ([dur], g) if "k_pcg_step" in name else ([], None)
+    if cur:
+        runs.append((cur_grid, cur))
+    interior = {}
+    for g, v in runs:
+        interior.setdefault(g, []).extend(v[1:-1])
+    print()
+    print("== k_pcg_step, full iterations only (interior launches of each solve) ==")
+    print(f"{'grid_threads':>12s} {'n':>6s} {'mean_us':>9s} {'median_us':>9s}")
+    for g, v in sorted(interior.items(), key=lambda kv: -kv[0]):
+        if v:
+            print(f"{g:12d} {len(v):6d} {sum(v) / len(v):9.2f} {statistics.median(v):9.2f}")
+    print()
+    print("== per kernel and grid (from the kernel trace) ==")
+    print(f"{'kernel':62s} {'grid_threads':>12s} {'wg':>5s} {'n':>6s} {'mean_us':>9s} "
+          f"{'median_us':>9s} {'total_ms':>9s}")
+    for (name, gx, wg), v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:40]:
+        print(f"{name[-62:]:62s} {gx:12d} {wg:5d} {len(v):6d} {sum(v) / len(v):9.2f} "
+              f"{statistics.median(v):9.2f} {sum(v) / 1e3:9.3f}")
+
+
+# ---------------------------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--eager-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--pmc-probe", action="store_true")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--profile-summary", metavar="DIR")
     args = ap.parse_args()
+    if args.traffic_summary:
+        return traffic_summary(*args.traffic_summary)
+    if args.profile_summary:
+        return profile_summary(args.profile_summary)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
               "per-pair work is independent, so pairs shard across GPUs with no communication.",
               file=sys.stderr)
         sys.exit(2)
+    if args.pmc_probe:
+        return pmc_probe()
 
     import numpy as np
     import torch
@@ -131,14 +354,14 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    levels, gn_iters, pcg_iters = 3, 10, 20
     log("bench: generating the 144x168x111 pair (seed 1)")
     pair = synth.make_workload("c2")
     shape, pe = pair.shape, pair.pe
+    assert tuple(shape) == SHAPE and pe == PE
     dt = torch.float32
     Ip = torch.as_tensor(pair.I_plus).to(dev, dt).contiguous()
     Im = torch.as_tensor(pair.I_minus).to(dev, dt).contiguous()
-    opts = rgp.Options(levels=levels, gn_iters=gn_iters, pcg_iters=pcg_iters, pcg_rtol=0.0)
+    opts = rgp.Options(levels=LEVELS, gn_iters=GN_ITERS, pcg_iters=PCG_ITERS, pcg_rtol=0.0)
     copts = opts.to_c()
     nbytes = rgp.workspace_size(rgp.OP_CORRECT, shape, pe, (1.0, 1.0, 1.0), dt, copts)
     ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
@@ -147,15 +370,14 @@ def main():
     Tm = torch.empty_like(Im)
 
     # The whole correction is captured once into a HIP graph (rgp_correct_plan) on a side
-    # stream of default priority; one step = one replay.  The eager path is timed too.
+    # stream of default priority; one step = one replay.
     side = torch.cuda.Stream()
     torch.cuda.synchronize()
     torch.cuda.set_stream(side)   # every library call below is enqueued on `side`
-    stream = side
     plan = rgp.Plan(Ip, Im, pe, opts, b, Tp, Tm, ws, stream=side)
 
-    def step():
-        plan.launch(side)
+    def eager():
+        rgp.correct_into(Ip, Im, pe, opts, b, Tp, Tm, ws, stream=side)
 
     def timed(fn, steps):
         e0 = torch.cuda.Event(enable_timing=True)
@@ -171,70 +393,68 @@ def main():
 
     log(f"bench: warmup {args.warmup}")
     for _ in range(args.warmup):
-        step()
-        rgp.correct_into(Ip, Im, pe, opts, b, Tp, Tm, ws, stream=side)
+        plan.launch(side)
+        eager()
     torch.cuda.synchronize()
     log(f"bench: timing {args.steps} steps (graph replay)")
-    wall, gpu_ms = timed(step, args.steps)
-    eager_wall, _ = timed(lambda: rgp.correct_into(Ip, Im, pe, opts, b, Tp, Tm, ws, stream=side),
-                          max(3, args.steps // 4))
-    eager_ms = 1e3 * eager_wall / max(3, args.steps // 4)
+    wall, gpu_ms = timed(lambda: plan.launch(side), args.steps)
     ms_per_step = 1e3 * wall / args.steps
     value = args.steps / wall
-    log(f"bench: {ms_per_step:.3f} ms/pair wall (graph), {gpu_ms / args.steps:.3f} ms/pair on "
-        f"the stream, eager {eager_ms:.3f} ms/pair")
+    log(f"bench: {ms_per_step:.3f} ms/pair wall, {gpu_ms / args.steps:.3f} ms/pair on the stream")
 
-    # ---- per-kernel rooflines at the finest level (algorithmic bytes / event-timed launch) ----
-    N = int(np.prod(shape))
-    Nb = int(np.prod(rgp.field_shape(shape, pe)))
-    f = 4
-    reps = args.kernel_reps
-    jdsp, g, hd, ho = rgp.loss_grad(Ip, Im, b, pe)
-    lg_ws = torch.zeros(rgp.workspace_size(rgp.OP_LOSS_GRAD, shape, pe, (1, 1, 1), dt), dtype=torch.uint8, device=dev)
-    t_lg = event_time_ms(lambda: rgp.loss_grad_into(Ip, Im, b, pe, None, g, hd, ho, lg_ws),
-                         stream, reps) / reps
-    v = torch.randn_like(b)
+    # ---- eager pass with kernel timing: per-kernel durations from HIP events ----
+    ne = max(1, args.eager_steps)
+    rgp.timing_start(1 << 16)
+    eager_wall, _ = timed(eager, ne)
+    recs = rgp.timing_stop(1 << 16)
+    eager_ms = 1e3 * eager_wall / ne
+    log(f"bench: eager with kernel timing {eager_ms:.3f} ms/pair ({len(recs)} timed launches)")
+    kernels = summarize_records(recs)
+
+    # stand-alone calls at full resolution: loss_grad, gn_hvp, ot_init (R launches each)
+    R = 20
+    lg_ws = torch.zeros(rgp.workspace_size(rgp.OP_LOSS_GRAD, shape, pe, (1, 1, 1), dt),
+                        dtype=torch.uint8, device=dev)
+    ot_ws = torch.zeros(rgp.workspace_size(rgp.OP_OT_INIT, shape, pe, (1, 1, 1), dt),
+                        dtype=torch.uint8, device=dev)
+    g = torch.empty_like(b)
+    hd = torch.empty_like(b)
+    ho = torch.empty_like(b)
+    v = torch.randn(b.shape, device=dev, dtype=dt)
     Hv = torch.empty_like(b)
     vhv = torch.empty(1, dtype=torch.float64, device=dev)
-    t_hv = event_time_ms(lambda: rgp.gn_hvp_into(hd, ho, v, Hv, vhv, shape, pe, lg_ws),
-                         stream, reps) / reps
-    pcg_ws = torch.zeros(rgp.workspace_size(rgp.OP_PCG_SOLVE, shape, pe, (1, 1, 1), dt), dtype=torch.uint8, device=dev)
-    x = torch.empty_like(b)
-    rhs = -g
-    m1, m2 = 20, 20 + reps
-    t_p1 = event_time_ms(lambda: rgp.pcg_solve_into(hd, ho, rhs, x, shape, pe, m1, pcg_ws),
-                         stream, 5) / 5
-    t_p2 = event_time_ms(lambda: rgp.pcg_solve_into(hd, ho, rhs, x, shape, pe, m2, pcg_ws),
-                         stream, 5) / 5
-    t_pcg = (t_p2 - t_p1) / (m2 - m1)
     b0 = torch.empty_like(b)
-    ot_ws = torch.zeros(rgp.workspace_size(rgp.OP_OT_INIT, shape, pe, (1, 1, 1), dt), dtype=torch.uint8, device=dev)
-    t_ot = event_time_ms(lambda: rgp.ot_init_into(Ip, Im, pe, b0, ot_ws), stream, reps) / reps
+    bz = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    rgp.timing_start(1 << 12)
+    for _ in range(R):
+        rgp.loss_grad_into(Ip, Im, bz, pe, None, g, hd, ho, lg_ws, stream=side)
+    for _ in range(R):
+        rgp.gn_hvp_into(hd, ho, v, Hv, vhv, shape, pe, lg_ws, stream=side)
+    for _ in range(R):
+        rgp.ot_init_into(Ip, Im, pe, b0, ot_ws, stream=side)
+    torch.cuda.synchronize()
+    solo = rgp.timing_stop(1 << 12)
+    for name, rec in summarize_records(solo).items():
+        kernels["standalone:" + name] = rec
+    for name, rec in kernels.items():
+        log(f"bench: {name:34s} n={rec['launches']:4d} {rec['us_mean']:8.2f} us "
+            f"(median {rec['us_median']:7.2f})  {rec['achieved_GBps']:7.1f} GB/s  "
+            f"frac {rec['frac']:.3f}")
 
-    kernels = {}
-
-    def add(name, bytes_per_launch, ms, note):
-        gbps = bytes_per_launch / (ms * 1e-3) / 1e9
-        kernels[name] = dict(bytes_per_launch=bytes_per_launch, us_per_launch=round(ms * 1e3, 3),
-                             achieved_GBps=round(gbps, 1), frac=round(gbps / HBM_PEAK_GBPS, 4),
-                             bytes_rule=note)
-        log(f"bench: {name:10s} {ms * 1e3:8.2f} us  {gbps:8.1f} GB/s  ({gbps / HBM_PEAK_GBPS:.3f} of peak)")
-
-    add("pcg_step", 10 * Nb * f, t_pcg, "reads x,r,p,w,diag,off; writes x,r,p,w (40 B/node)")
-    add("loss_grad", 2 * N * f + 4 * Nb * f, t_lg, "reads I+,I-,b; writes grad,diag,off")
-    add("gn_hvp", 4 * Nb * f, t_hv, "reads v,diag,off; writes Hv (16 B/node)")
-    add("ot_init", 2 * N * f + Nb * f, t_ot, "reads I+,I- once; writes b0 (shift pass included in time)")
-
-    dom = kernels["pcg_step"]
+    nb = int(np.prod(rgp.field_shape(shape, pe)))
+    dom = next(r for r in kernels.values() if r["kernel"] == "pcg_step" and r["nodes"] == nb)
     traffic = measured_traffic()
     roofline = dict(bound="hbm", achieved=dom["achieved_GBps"], peak=HBM_PEAK_GBPS, unit="GB/s",
-                    frac=dom["frac"], traffic=traffic, kernel="k_pcg_step<float,8>",
-                    bytes_per_launch=dom["bytes_per_launch"], us_per_launch=dom["us_per_launch"])
+                    frac=dom["frac"], traffic=traffic,
+                    kernel="k_pcg_step (finest level, 144x169x111 nodes, full PCG iterations)",
+                    bytes_per_launch=dom["bytes_per_launch"], us_per_launch=dom["us_mean"],
+                    us_median=dom["us_median"], launches=dom["launches"], grid=dom["grid"])
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("bench: timing the FP64 oracle on a bounded sample (about 10 s)")
-        cpu = cpu_baseline(pair, levels, gn_iters, pcg_iters)
+        log("bench: timing the FP64 oracle on a bounded sample (about 12 s)")
+        cpu = cpu_baseline(pair, LEVELS, GN_ITERS, PCG_ITERS)
         log(f"bench: oracle {1.0 / cpu['value']:.1f} s/pair extrapolated")
 
     line = dict(
@@ -243,8 +463,8 @@ def main():
         scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(workload="3T-brain-shaped pair 144x168x111, PE dim 1, FP32 images and field, "
                     "3 levels x 10 GN x 20 PCG (rtol 0), OT init, Armijo",
-                    shape=list(shape), pe_dim=pe, levels=levels, gn_iters=gn_iters,
-                    pcg_iters=pcg_iters, global_batch=1),
+                    shape=list(shape), pe_dim=pe, levels=LEVELS, gn_iters=GN_ITERS,
+                    pcg_iters=PCG_ITERS, global_batch=1),
         gpu_ms_per_step=round(gpu_ms / args.steps, 4), eager_ms_per_step=round(eager_ms, 4),
         roofline=roofline, kernels=kernels, cpu_baseline=cpu,
         device=torch.cuda.get_device_name(0),

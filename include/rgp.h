@@ -46,8 +46,10 @@ typedef enum {
 
 typedef enum { RGP_F64 = 0, RGP_F32 = 1, RGP_BF16 = 2 } rgp_dtype;
 
-/* Grid of one volume.  m: cells per axis (caller order, each >= 1, product < 2^31, m[pe] >= 2);
- * pe: phase-encoding axis 0..2; h: voxel sizes (> 0).  b is measured in the units of h. */
+/* Grid of one volume.  m: cells per axis (caller order, each >= 1, m[pe] >= 2, at most 2^28
+ * field nodes, and at most 512 field nodes along the contiguous axis m[2], i.e. m[2] <= 512, or
+ * m[2] <= 511 when pe == 2; other grids give RGP_ESHAPE); pe: phase-encoding axis 0..2; h: voxel
+ * sizes (> 0).  b is measured in the units of h. */
 typedef struct {
   int64_t m[3];
   int32_t pe;
@@ -174,6 +176,36 @@ rgp_status rgp_correct_plan(const rgp_grid* grid, rgp_dtype img_t, const void* I
                             rgp_plan* plan);
 rgp_status rgp_plan_launch(rgp_plan plan, void* stream);
 rgp_status rgp_plan_destroy(rgp_plan plan);
+
+/* Kernel timing (instrumentation; not part of the method).  rgp_timing_start(capacity) creates
+ * `capacity` pairs of HIP events (host API objects, no device memory) and from then on every
+ * launch of a hot kernel that is not being captured into a graph records one pair at the start
+ * and the end of the kernel itself (hipExtLaunchKernelGGL), until the pairs run out.
+ * rgp_timing_stop() ends the recording, waits for the recorded events, writes up to `max`
+ * records (in launch order) to the HOST array `out`, stores their number in *n and releases the
+ * events.  `kernel` is an rgp_kernel_kind; `cells`/`nodes` give the volume the launch covered
+ * (cells of the images, nodes of the field; 0 when not applicable).  Not thread-safe against
+ * concurrent launches from other threads' timing sessions: one session per process at a time.
+ * Errors: RGP_EINVAL (capacity < 1 or > 1<<20; out or n null), RGP_EHIP (event calls). */
+typedef enum {
+  RGP_KERNEL_PCG_STEP = 0,   /* one Jacobi-PCG iteration (Sec. 2.3.1) incl. w = H p */
+  RGP_KERNEL_LOSS_GRAD = 1,  /* objective, gradient and GN Hessian diagonals (Sec. 2.3) */
+  RGP_KERNEL_TRIAL = 2,      /* Armijo trial objectives */
+  RGP_KERNEL_HVP = 3,        /* stand-alone GN Hessian-vector product */
+  RGP_KERNEL_OT = 4,         /* column-wise optimal-transport initialisation (Sec. 2.2) */
+  RGP_KERNEL_SHIFT = 5       /* positivity shift of the OT initialisation */
+} rgp_kernel_kind;
+typedef struct {
+  int32_t kernel;
+  int32_t tag;       /* PCG step: the PCG iteration (0 = first); trial: candidates; else 0 */
+  uint32_t grid;     /* workgroups */
+  uint32_t pad;
+  int64_t cells;
+  int64_t nodes;
+  double ms;         /* kernel duration */
+} rgp_timing_record;
+rgp_status rgp_timing_start(int32_t capacity);
+rgp_status rgp_timing_stop(rgp_timing_record* out, int32_t max, int32_t* n);
 
 #ifdef __cplusplus
 }

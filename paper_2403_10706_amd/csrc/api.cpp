@@ -2,9 +2,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "../../include/rgp.h"
 #include "rgp_internal.hpp"
@@ -21,6 +24,18 @@ using namespace rgp;
 namespace {
 
 thread_local int g_last_hip = 0;
+
+// ---- kernel timing registry -------------------------------------------------------------
+struct TimingRec {
+  int kind, tag;
+  unsigned grid;
+  int64_t cells, nodes;
+  hipEvent_t e0, e1;
+};
+std::mutex g_timing_mu;
+std::atomic<bool> g_timing_on{false};
+std::vector<TimingRec> g_timing;
+size_t g_timing_used = 0;
 
 constexpr size_t kAlign = 256;
 constexpr double kGuardSlope = 0.99;
@@ -784,3 +799,77 @@ rgp_status rgp_plan_destroy(rgp_plan plan) {
 }
 
 }  // extern "C"
+
+// ---- kernel timing ----------------------------------------------------------------------
+
+bool rgp::timing_slot(int kind, int tag, unsigned grid, int64_t cells, int64_t nodes,
+                      hipStream_t s, hipEvent_t* e0, hipEvent_t* e1) {
+  if (!g_timing_on.load(std::memory_order_relaxed)) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  if (!g_timing_on.load(std::memory_order_relaxed) || g_timing_used >= g_timing.size())
+    return false;
+  TimingRec& r = g_timing[g_timing_used++];
+  r.kind = kind;
+  r.tag = tag;
+  r.grid = grid;
+  r.cells = cells;
+  r.nodes = nodes;
+  *e0 = r.e0;
+  *e1 = r.e1;
+  return true;
+}
+
+namespace {
+void timing_release_locked() {
+  for (TimingRec& r : g_timing) {
+    if (r.e0) (void)hipEventDestroy(r.e0);
+    if (r.e1) (void)hipEventDestroy(r.e1);
+  }
+  g_timing.clear();
+  g_timing_used = 0;
+}
+}  // namespace
+
+rgp_status rgp_timing_start(int32_t capacity) {
+  if (capacity < 1 || capacity > (1 << 20)) return RGP_EINVAL;
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  g_timing_on.store(false);
+  timing_release_locked();
+  g_timing.resize((size_t)capacity, TimingRec{0, 0, 0, 0, 0, nullptr, nullptr});
+  for (TimingRec& r : g_timing) {
+    hipError_t e = hipEventCreate(&r.e0);
+    if (e == hipSuccess) e = hipEventCreate(&r.e1);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      timing_release_locked();
+      return RGP_EHIP;
+    }
+  }
+  g_timing_on.store(true);
+  return RGP_OK;
+}
+
+rgp_status rgp_timing_stop(rgp_timing_record* out, int32_t max, int32_t* n) {
+  if (!out || !n || max < 0) return RGP_EINVAL;
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  g_timing_on.store(false);
+  rgp_status st = RGP_OK;
+  int32_t k = 0;
+  for (size_t i = 0; i < g_timing_used && k < max; ++i) {
+    const TimingRec& r = g_timing[i];
+    float ms = 0.0f;
+    hipError_t e = hipEventSynchronize(r.e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.e0, r.e1);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      st = RGP_EHIP;
+      break;
+    }
+    out[k++] = rgp_timing_record{r.kind, r.tag, r.grid, 0u, r.cells, r.nodes, (double)ms};
+  }
+  *n = k;
+  timing_release_locked();
+  return st;
+}

@@ -482,11 +482,11 @@ Launch plan_trial(const Geom& g, DType real, int nc) {
 hipError_t launch_loss_grad(const LossGradArgs& a, DType img, DType real, hipStream_t s) {
   const Launch L = plan_loss_grad(a.g, real);
   if (L.block == 1024) {
-    RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_loss_grad<TI, TR, kRun, 1024>),
-                                                     dim3(L.grid), dim3(1024), 0, s, a));
+    RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH(kKindLossGrad, a.g, (k_loss_grad<TI, TR, kRun, 1024>),
+                                             L.grid, 1024, 0, s, a));
   } else {
-    RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_loss_grad<TI, TR, kRun, 256>),
-                                                     dim3(L.grid), dim3(256), 0, s, a));
+    RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH(kKindLossGrad, a.g, (k_loss_grad<TI, TR, kRun, 256>),
+                                             L.grid, 256, 0, s, a));
   }
   return hipGetLastError();
 }
@@ -499,8 +499,8 @@ hipError_t launch_loss_final(const LossFinalArgs& a, hipStream_t s) {
 hipError_t launch_trial(const TrialArgs& a, DType img, DType real, hipStream_t s) {
   const Launch L = plan_trial(a.g, real, a.nc);
 #define RGP_TRIAL(NC, B)                                                                   \
-  RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_trial<TI, TR, kRun, NC, B>),          \
-                                                   dim3(L.grid), dim3(B), 0, s, a))
+  RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH_T(kKindTrial, NC, a.g,                          \
+                                             (k_trial<TI, TR, kRun, NC, B>), L.grid, B, 0, s, a))
   switch (a.nc) {
     case 1:
       if (L.block == 1024) RGP_TRIAL(1, 1024);

@@ -250,11 +250,11 @@ unsigned shift_grid(int64_t n) {
 hipError_t launch_shift(const ShiftArgs& a, DType img, hipStream_t s) {
   const unsigned nb = shift_grid(a.n);
   if (img == DType::F64)
-    hipLaunchKernelGGL(k_shift<double>, dim3(nb), dim3(kBlock), 0, s, a);
+    RGP_LAUNCH_N(kKindShift, a.n, 0, k_shift<double>, nb, kBlock, 0, s, a);
   else if (img == DType::F32)
-    hipLaunchKernelGGL(k_shift<float>, dim3(nb), dim3(kBlock), 0, s, a);
+    RGP_LAUNCH_N(kKindShift, a.n, 0, k_shift<float>, nb, kBlock, 0, s, a);
   else
-    hipLaunchKernelGGL(k_shift<bf16_t>, dim3(nb), dim3(kBlock), 0, s, a);
+    RGP_LAUNCH_N(kKindShift, a.n, 0, k_shift<bf16_t>, nb, kBlock, 0, s, a);
   return hipGetLastError();
 }
 
@@ -280,7 +280,7 @@ hipError_t launch_ot(const OtArgs& a, DType img, DType real, hipStream_t s) {
   do {                                                                                \
     hipFuncSetAttribute((const void*)k_ot<TI, TR>,                                   \
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);        \
-    hipLaunchKernelGGL((k_ot<TI, TR>), dim3(nb), dim3(kBlock), lds, s, a, nc);        \
+    RGP_LAUNCH(kKindOt, a.g, (k_ot<TI, TR>), nb, kBlock, lds, s, a, nc);              \
   } while (0)
   if (real == DType::F64 && img == DType::F64) RGP_OT_LAUNCH(double, double);
   else if (real == DType::F32 && img == DType::F32) RGP_OT_LAUNCH(float, float);

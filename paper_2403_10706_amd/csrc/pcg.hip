@@ -510,11 +510,11 @@ PcgPlan plan_pcg(const Geom& g, DType real) {
 hipError_t launch_hvp(const HvpArgs& a, DType real, hipStream_t s) {
   const Launch L = plan_hvp(a.g, real);
   if (real == DType::F64)
-    hipLaunchKernelGGL((k_hvp<double, kRun, 256>), dim3(L.grid), dim3(256), 0, s, a);
+    RGP_LAUNCH(kKindHvp, a.g, (k_hvp<double, kRun, 256>), L.grid, 256, 0, s, a);
   else if (L.block == 1024)
-    hipLaunchKernelGGL((k_hvp<float, kRun, 1024>), dim3(L.grid), dim3(1024), 0, s, a);
+    RGP_LAUNCH(kKindHvp, a.g, (k_hvp<float, kRun, 1024>), L.grid, 1024, 0, s, a);
   else
-    hipLaunchKernelGGL((k_hvp<float, kRun, 256>), dim3(L.grid), dim3(256), 0, s, a);
+    RGP_LAUNCH(kKindHvp, a.g, (k_hvp<float, kRun, 256>), L.grid, 256, 0, s, a);
   return hipGetLastError();
 }
 
@@ -527,14 +527,14 @@ template <typename TR, int BLK, int NPT, int HMAX>
 static void launch_step_cfg(const PcgArgs& a, const PcgPlan& L, hipStream_t s) {
   const int role = L.m.role;
   if (role == 0)
-    hipLaunchKernelGGL((k_pcg_step<TR, 0, BLK, NPT, HMAX>), dim3(L.grid), dim3(BLK), L.lds, s, a,
-                       L.m);
+    RGP_LAUNCH_T(kKindPcgStep, a.sc.iter, a.g, (k_pcg_step<TR, 0, BLK, NPT, HMAX>), L.grid, BLK,
+                 L.lds, s, a, L.m);
   else if (role == 1)
-    hipLaunchKernelGGL((k_pcg_step<TR, 1, BLK, NPT, HMAX>), dim3(L.grid), dim3(BLK), L.lds, s, a,
-                       L.m);
+    RGP_LAUNCH_T(kKindPcgStep, a.sc.iter, a.g, (k_pcg_step<TR, 1, BLK, NPT, HMAX>), L.grid, BLK,
+                 L.lds, s, a, L.m);
   else
-    hipLaunchKernelGGL((k_pcg_step<TR, 2, BLK, NPT, HMAX>), dim3(L.grid), dim3(BLK), L.lds, s, a,
-                       L.m);
+    RGP_LAUNCH_T(kKindPcgStep, a.sc.iter, a.g, (k_pcg_step<TR, 2, BLK, NPT, HMAX>), L.grid, BLK,
+                 L.lds, s, a, L.m);
 }
 
 hipError_t launch_pcg_step(const PcgArgs& a, DType real, hipStream_t s) {

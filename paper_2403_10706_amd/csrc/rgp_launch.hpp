@@ -1,6 +1,7 @@
 // Kernel argument blocks and host launchers of librgp (internal; not part of the C-ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -218,6 +219,38 @@ Launch plan_trial(const Geom& g, DType real, int nc);
 PcgPlan plan_pcg(const Geom& g, DType real);
 Launch plan_hvp(const Geom& g, DType real);
 unsigned shift_grid(int64_t n);
+
+// Kernel timing (instrumentation behind rgp_timing_start/stop): when it is enabled and the stream
+// is not being captured, timing_slot hands out a pair of HIP events that hipExtLaunchKernelGGL
+// records at the start and the end of the kernel itself, and notes the launch (tag: the PCG
+// iteration of a PCG step, the candidate count of a trial pass, else 0).
+enum KernelKind : int {
+  kKindPcgStep = 0,
+  kKindLossGrad = 1,
+  kKindTrial = 2,
+  kKindHvp = 3,
+  kKindOt = 4,
+  kKindShift = 5,
+  kKindCount = 6
+};
+bool timing_slot(int kind, int tag, unsigned grid, int64_t cells, int64_t nodes, hipStream_t s,
+                 hipEvent_t* e0, hipEvent_t* e1);
+
+#define RGP_LAUNCH_TN(KIND, TAG, CELLS, NODES, KERNEL, GRID, BLOCK, LDS, S, ...)             \
+  do {                                                                                       \
+    hipEvent_t rgp_e0_, rgp_e1_;                                                              \
+    if (::rgp::timing_slot((KIND), (TAG), (GRID), (CELLS), (NODES), (S), &rgp_e0_, &rgp_e1_)) \
+      hipExtLaunchKernelGGL(KERNEL, dim3(GRID), dim3(BLOCK), (LDS), (S), rgp_e0_, rgp_e1_, 0, \
+                            __VA_ARGS__);                                                     \
+    else                                                                                      \
+      hipLaunchKernelGGL(KERNEL, dim3(GRID), dim3(BLOCK), (LDS), (S), __VA_ARGS__);           \
+  } while (0)
+#define RGP_LAUNCH_N(KIND, CELLS, NODES, KERNEL, GRID, BLOCK, LDS, S, ...) \
+  RGP_LAUNCH_TN(KIND, 0, CELLS, NODES, KERNEL, GRID, BLOCK, LDS, S, __VA_ARGS__)
+#define RGP_LAUNCH_T(KIND, TAG, G, KERNEL, GRID, BLOCK, LDS, S, ...) \
+  RGP_LAUNCH_TN(KIND, TAG, (G).ncell, (G).nnode, KERNEL, GRID, BLOCK, LDS, S, __VA_ARGS__)
+#define RGP_LAUNCH(KIND, G, KERNEL, GRID, BLOCK, LDS, S, ...) \
+  RGP_LAUNCH_TN(KIND, 0, (G).ncell, (G).nnode, KERNEL, GRID, BLOCK, LDS, S, __VA_ARGS__)
 
 hipError_t launch_loss_grad(const LossGradArgs& a, DType img, DType real, hipStream_t s);
 hipError_t launch_loss_final(const LossFinalArgs& a, hipStream_t s);

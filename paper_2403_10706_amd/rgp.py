@@ -55,7 +55,17 @@ class SolverOpts(ctypes.Structure):
 EXPORTS = ("rgp_status_string", "rgp_last_hip_error", "rgp_default_opts", "rgp_workspace_size",
            "rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
            "rgp_apply_correction", "rgp_correct", "rgp_correct_plan", "rgp_plan_launch",
-           "rgp_plan_destroy")
+           "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop")
+
+# rgp_kernel_kind
+KERNEL_PCG_STEP, KERNEL_LOSS_GRAD, KERNEL_TRIAL, KERNEL_HVP, KERNEL_OT, KERNEL_SHIFT = range(6)
+KERNEL_NAMES = ("pcg_step", "loss_grad", "trial", "hvp", "ot", "shift")
+
+
+class TimingRecord(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("tag", ctypes.c_int32), ("grid", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("cells", ctypes.c_int64), ("nodes", ctypes.c_int64),
+                ("ms", ctypes.c_double)]
 
 _lib = None
 
@@ -91,9 +101,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                      vp, vp, sz, vp, ctypes.POINTER(ctypes.c_void_p)]
     lib.rgp_plan_launch.argtypes = [vp, vp]
     lib.rgp_plan_destroy.argtypes = [vp]
+    lib.rgp_timing_start.argtypes = [i32]
+    lib.rgp_timing_stop.argtypes = [ctypes.POINTER(TimingRecord), i32, ctypes.POINTER(i32)]
     for name in ("rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
                  "rgp_apply_correction", "rgp_correct", "rgp_workspace_size", "rgp_correct_plan",
-                 "rgp_plan_launch", "rgp_plan_destroy"):
+                 "rgp_plan_launch", "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -415,3 +427,17 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def timing_start(capacity: int = 65536):
+    """Start recording the duration of every eager hot-kernel launch (rgp_timing_start)."""
+    _check("rgp_timing_start", load().rgp_timing_start(int(capacity)))
+
+
+def timing_stop(max_records: int = 65536):
+    """Stop recording; returns one dict per timed launch (kernel, tag, grid, cells, nodes, ms)."""
+    recs = (TimingRecord * max_records)()
+    n = ctypes.c_int32(0)
+    _check("rgp_timing_stop", load().rgp_timing_stop(recs, int(max_records), ctypes.byref(n)))
+    return [dict(kernel=KERNEL_NAMES[r.kernel], tag=r.tag, grid=r.grid, cells=r.cells,
+                 nodes=r.nodes, ms=r.ms) for r in recs[:n.value]]

@@ -69,6 +69,17 @@ def test_workspace_size_and_validation(lib):
     bad = rgp.make_grid((4, 4, 4), 1, h=(1.0, 0.0, 1.0))
     assert lib.rgp_workspace_size(1, ctypes.byref(bad), rgp.F32, None, ctypes.byref(n)) == -1
     assert lib.rgp_workspace_size(1, ctypes.byref(g), rgp.BF16, None, ctypes.byref(n)) == -3
+    # the contiguous field axis holds at most 512 nodes; at most 2^28 field nodes
+    ok = rgp.make_grid((16, 16, 512), 1)
+    assert lib.rgp_workspace_size(1, ctypes.byref(ok), rgp.F32, None, ctypes.byref(n)) == 0
+    bad = rgp.make_grid((16, 16, 513), 1)
+    assert lib.rgp_workspace_size(1, ctypes.byref(bad), rgp.F32, None, ctypes.byref(n)) == -2
+    ok = rgp.make_grid((16, 16, 511), 2)
+    assert lib.rgp_workspace_size(1, ctypes.byref(ok), rgp.F32, None, ctypes.byref(n)) == 0
+    bad = rgp.make_grid((16, 16, 512), 2)
+    assert lib.rgp_workspace_size(1, ctypes.byref(bad), rgp.F32, None, ctypes.byref(n)) == -2
+    bad = rgp.make_grid((2048, 2048, 128), 0)
+    assert lib.rgp_workspace_size(1, ctypes.byref(bad), rgp.F32, None, ctypes.byref(n)) == -2
     o.levels = 0
     assert lib.rgp_workspace_size(rgp.OP_CORRECT, ctypes.byref(g), rgp.F32, ctypes.byref(o),
                                   ctypes.byref(n)) == -1
