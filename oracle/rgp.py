@@ -282,6 +282,38 @@ def objective_gradient_cols(Ip, Im, b, hc, alpha=ALPHA, beta=BETA):
     return obj, g, lin
 
 
+def interp_lin_T(u: np.ndarray, xi: np.ndarray, m: int) -> np.ndarray:
+    """Adjoint of the value part of ``interp_lin``: G[..., k] = sum_j u_j ((1 - w_j) [k0_j = k]
+    + w_j [k0_j + 1 = k]) over k = 0..m-1, with k0 = floor(xi), w = xi - k0 (R1, R2; samples
+    outside 0..m-1 receive nothing)."""
+    k0f = np.floor(xi)
+    w = xi - k0f
+    k0 = k0f.astype(np.int64)
+    G = np.zeros(u.shape[:-1] + (m,))
+    lead = np.indices(u.shape[:-1])
+    for k, wt in ((k0, 1.0 - w), (k0 + 1, w)):
+        ok = (k >= 0) & (k < m)
+        idx = tuple(np.broadcast_to(ax[..., None], u.shape)[ok] for ax in lead) + (k[ok],)
+        np.add.at(G, idx, (u * wt)[ok])
+    return G
+
+
+def image_gradient_cols(Ip, Im, b, hc):
+    """Gradient of J with respect to the two images (only D depends on them, Eq. 2):
+    dJ/dI+ = vol A+^T (r (1 + Db)), dJ/dI- = -vol A-^T (r (1 - Db)), with A+- the linear
+    interpolation at xi+- = j +- (A b)/h and r = T+ - T-."""
+    hp = hc[2]
+    vol = hc[0] * hc[1] * hc[2]
+    m = Ip.shape[-1]
+    Tp, _, _, Db = transform_cols(Ip, b, hp, +1.0)
+    Tm, _, _, _ = transform_cols(Im, b, hp, -1.0)
+    r = Tp - Tm
+    Ab = avg(b)
+    gp = vol * interp_lin_T(r * (1.0 + Db), _positions(m, Ab, hp, +1.0), m)
+    gm = -vol * interp_lin_T(r * (1.0 - Db), _positions(m, Ab, hp, -1.0), m)
+    return gp, gm
+
+
 def gn_matvec_cols(lin: Linearization, v: np.ndarray) -> np.ndarray:
     """H_J v = vol [A^T(c1 w) + D^T(c2 w)] + alpha vol L v + (beta vol/2) D^T(phi'' D v),
     w = c1 A v + c2 D v: the Gauss-Newton approximation of Sec. 2.3.1 (drops sum r nabla^2 r)."""
@@ -580,6 +612,13 @@ def objective_gradient(Ip, Im, b, pe, h, alpha=ALPHA, beta=BETA):
     obj, g, lin = objective_gradient_cols(to_cols(Ip, pe), to_cols(Im, pe), to_cols(b, pe), hc,
                                           alpha, beta)
     return obj, (None if g is None else from_cols(g, pe)), lin
+
+
+def image_gradient(Ip, Im, b, pe, h):
+    """(dJ/dI+, dJ/dI-) in caller layout (cells)."""
+    hc = col_spacing(h, pe)
+    gp, gm = image_gradient_cols(to_cols(Ip, pe), to_cols(Im, pe), to_cols(b, pe), hc)
+    return from_cols(gp, pe), from_cols(gm, pe)
 
 
 def gn_matvec(lin: Linearization, v, pe):

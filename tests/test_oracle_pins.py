@@ -509,3 +509,56 @@ def test_known_field_recovery():
     assert rms <= 0.25
     ri = rgp.relative_improvement(p.I_plus, p.I_minus, res.T_plus, res.T_minus)
     assert ri > 90.0
+
+
+# ------------------------------------------------------------------------------------------
+# Gradient with respect to the images (the adjoint of the interpolation and modulation)
+# ------------------------------------------------------------------------------------------
+
+def test_interpolation_adjoint_identity():
+    """<A(I), u> = <I, A^T(u)> for the linear interpolation at shifted positions, samples outside
+    the column dropped on both sides."""
+    rng = np.random.default_rng(70)
+    na, nb, m = 3, 4, 9
+    I = rng.standard_normal((na, nb, m))
+    xi = np.arange(m) + rng.uniform(-2.5, 2.5, (na, nb, m))
+    u = rng.standard_normal((na, nb, m))
+    val, _ = rgp.interp_lin(I, xi, 1.0)
+    G = rgp.interp_lin_T(u, xi, m)
+    assert float(np.sum(val * u)) == pytest.approx(float(np.sum(I * G)), rel=1e-13)
+
+
+def test_image_gradient_is_the_exact_derivative_of_D():
+    """D is a quadratic form in each image (the sample positions depend on b only), so central
+    differences of the plain-loop objective are exact up to rounding, for every entry."""
+    Ip, Im, b, hc = _tiny(71, shape=(2, 3, 6), base=0.8, amp=0.2)
+    gp, gm = rgp.image_gradient_cols(Ip, Im, b, hc)
+    e = 1e-3
+    for which, I, g in (("+", Ip, gp), ("-", Im, gm)):
+        fd = np.zeros_like(I)
+        for idx in np.ndindex(I.shape):
+            Iu, Id = I.copy(), I.copy()
+            Iu[idx] += e
+            Id[idx] -= e
+            args_u = (Iu, Im) if which == "+" else (Ip, Iu)
+            args_d = (Id, Im) if which == "+" else (Ip, Id)
+            Ju = loops.objective(*args_u, b, hc, ALPHA, BETA)[0]
+            Jd = loops.objective(*args_d, b, hc, ALPHA, BETA)[0]
+            fd[idx] = (Ju - Jd) / (2 * e)
+        np.testing.assert_allclose(g, fd, rtol=1e-8, atol=1e-10 * np.max(np.abs(fd)))
+
+
+def test_image_gradient_random_directions_and_polarity_swap():
+    Ip, Im, b, hc = _tiny(72, shape=(4, 5, 11), base=1.7, amp=0.4)
+    gp, gm = rgp.image_gradient_cols(Ip, Im, b, hc)
+    rng = np.random.default_rng(73)
+    for _ in range(4):
+        dp, dm = rng.standard_normal(Ip.shape), rng.standard_normal(Im.shape)
+        e = 0.5   # exact for a quadratic
+        Ju = rgp.objective_cols(Ip + e * dp, Im + e * dm, b, hc).D   # only D holds the images
+        Jd = rgp.objective_cols(Ip - e * dp, Im - e * dm, b, hc).D
+        assert (Ju - Jd) / (2 * e) == pytest.approx(float(np.sum(gp * dp + gm * dm)), rel=1e-10)
+    # swapping the acquisitions and negating b leaves J unchanged and swaps the gradients
+    sp, sm = rgp.image_gradient_cols(Im, Ip, -b, hc)
+    np.testing.assert_allclose(sp, gm, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(sm, gp, rtol=1e-13, atol=1e-15)
