@@ -141,6 +141,18 @@ rgp_status rgp_pcg_solve(const rgp_grid* grid, rgp_dtype real_t, const void* hdi
                          double rtol, int32_t* iters_dev, double* relres_dev, void* ws,
                          size_t ws_bytes, void* stream);
 
+/* Gradient of the objective with respect to the two images (only the distance term of Eq. 2
+ * depends on them): dJ/dI+ = vol A+^T (r (1 + d_v b)) and dJ/dI- = -vol A-^T (r (1 - d_v b)),
+ * where A+- is the 1D linear interpolation at x +- b v (zero outside the column) and
+ * r = T+ - T- the residual of Eq. 1.  The backward of the objective with respect to I+-
+ * (differentiation extension).  gI_plus/gI_minus: cell arrays of real_t (both required), written
+ * in full.  Needs |d_v b| < 1 everywhere (then the sample positions are monotone along every
+ * column and each output value is accumulated by one thread without atomics); otherwise the
+ * output is unspecified (finite writes only, in bounds). */
+rgp_status rgp_loss_grad_images(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                                const void* I_minus, rgp_dtype real_t, const void* b,
+                                void* gI_plus, void* gI_minus, void* stream);
+
 /* Jacobian-modulation correction (Sec. 2.4.7): T+ = I+(x + b v)(1 + d_v b) and
  * T- = I-(x - b v)(1 - d_v b) at the cell centres, with the 1D linear image model (zero outside
  * the column).  T_plus/T_minus: arrays of img_t (nullable). */

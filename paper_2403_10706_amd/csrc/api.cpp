@@ -582,6 +582,25 @@ rgp_status rgp_pcg_solve(const rgp_grid* grid, rgp_dtype real_t, const void* hdi
   return RGP_OK;
 }
 
+rgp_status rgp_loss_grad_images(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                                const void* I_minus, rgp_dtype real_t, const void* b,
+                                void* gI_plus, void* gI_minus, void* stream) {
+  rgp_status st = check_grid(grid);
+  if (st != RGP_OK) return st;
+  DType di, dr;
+  if ((st = check_types(img_t, real_t, &di, &dr)) != RGP_OK) return st;
+  if (!I_plus || !I_minus || !b || !gI_plus || !gI_minus) return RGP_EINVAL;
+  ImageGradArgs ia{};
+  ia.g = geom_of(grid);
+  ia.Ip = I_plus;
+  ia.Im = I_minus;
+  ia.b = b;
+  ia.gIp = gI_plus;
+  ia.gIm = gI_minus;
+  RGP_HIP(launch_image_grad(ia, di, dr, static_cast<hipStream_t>(stream)));
+  return RGP_OK;
+}
+
 rgp_status rgp_apply_correction(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
                                 const void* I_minus, rgp_dtype real_t, const void* b,
                                 void* T_plus, void* T_minus, void* stream) {

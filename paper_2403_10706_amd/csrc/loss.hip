@@ -455,6 +455,88 @@ static int pick_block(const Geom& g, DType real, int S) {
   return 256;
 }
 
+// --------------------------------------------------------------------------------------------
+// dJ/dI+ and dJ/dI- (only D depends on the images, Eq. 2): per column the residual r_j, weighted
+// by vol (1 + D b_j) for I+ and -vol (1 - D b_j) for I-, is spread back onto the two samples that
+// interpolate the image at xi+-_j (the adjoint of the linear image model, zero outside).  With
+// |D b| < 1 the positions increase strictly along the column, so one thread walks its column once
+// and emits every sample's total in order while holding at most two open samples: no atomics and
+// every output written once.  (With |D b| >= 1 somewhere the output is unspecified.)
+// --------------------------------------------------------------------------------------------
+template <typename TR>
+struct Spread {
+  int kc, kw;     // open samples kc, kc + 1; samples below kw are written
+  TR a0, a1;
+};
+
+template <typename TI, typename TR>
+__global__ __launch_bounds__(kBlock) void k_image_grad(ImageGradArgs a) {
+  const Geom g = a.g;
+  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= g.ncol) return;
+  const TI* __restrict__ Ip = static_cast<const TI*>(a.Ip);
+  const TI* __restrict__ Im = static_cast<const TI*>(a.Im);
+  const TR* __restrict__ b = static_cast<const TR*>(a.b);
+  TR* __restrict__ gp = static_cast<TR*>(a.gIp);
+  TR* __restrict__ gm = static_cast<TR*>(a.gIm);
+  const int mp = g.mp;
+  const int64_t cb = cell_base(g, col), nb = node_base(g, col);
+  const int64_t cps = g.cps, nps = g.nps;
+  const TR inv_hp = TR(1) / (TR)g.hp;
+  const TR vol = (TR)g.vol;
+  constexpr int kNone = -(1 << 30);
+
+  auto emit = [&](TR* out, int& kw, int k, TR v) {
+    if (k < kw || k >= mp) return;  // outside the column (or out of order)
+    for (; kw < k; ++kw) out[cb + (int64_t)kw * cps] = TR(0);
+    out[cb + (int64_t)k * cps] = v;
+    kw = k + 1;
+  };
+  auto push = [&](Spread<TR>& e, TR* out, int k0, TR w, TR u) {
+    if (k0 != e.kc) {
+      if (e.kc != kNone) {
+        emit(out, e.kw, e.kc, e.a0);
+        if (k0 == e.kc + 1) {
+          e.a0 = e.a1;
+        } else {
+          emit(out, e.kw, e.kc + 1, e.a1);
+          e.a0 = TR(0);
+        }
+        e.a1 = TR(0);
+      }
+      e.kc = k0;
+    }
+    e.a0 += (TR(1) - w) * u;
+    e.a1 += w * u;
+  };
+  Spread<TR> sp{kNone, 0, TR(0), TR(0)}, sm{kNone, 0, TR(0), TR(0)};
+  TR b0 = b[nb];
+  for (int j = 0; j < mp; ++j) {
+    const TR b1 = b[nb + (int64_t)(j + 1) * nps];
+    const TR ab = (b0 + b1) * TR(0.5);
+    const TR db = (b1 - b0) * inv_hp;
+    const TR t = ab * inv_hp;
+    TR vp, slp, vm, slm;
+    interp_at(Ip, cb, cps, mp, j, t, inv_hp, vp, slp);
+    interp_at(Im, cb, cps, mp, j, -t, inv_hp, vm, slm);
+    const TR r = vp * (TR(1) + db) - vm * (TR(1) - db);
+    // the same interval as interp_at: k0 = j + floor(+-t), w = +-t - floor(+-t)
+    TR fp = fmin(fmax(floor(t), TR(-mp - 2)), TR(mp + 2));
+    TR fm = fmin(fmax(floor(-t), TR(-mp - 2)), TR(mp + 2));
+    push(sp, gp, j + (int)fp, t - fp, vol * r * (TR(1) + db));
+    push(sm, gm, j + (int)fm, -t - fm, -vol * r * (TR(1) - db));
+    b0 = b1;
+  }
+  for (Spread<TR>* e : {&sp, &sm}) {
+    TR* out = e == &sp ? gp : gm;
+    if (e->kc != kNone) {
+      emit(out, e->kw, e->kc, e->a0);
+      emit(out, e->kw, e->kc + 1, e->a1);
+    }
+    for (; e->kw < mp; ++e->kw) out[cb + (int64_t)e->kw * cps] = TR(0);
+  }
+}
+
 Launch plan_loss_grad(const Geom& g, DType real) {
   return plan_tiles(g, kRun, pick_block(g, real, kRun));
 }
@@ -534,6 +616,13 @@ hipError_t launch_correct(const CorrectArgs& a, DType img, DType real, hipStream
   Launch L = plan_tiles(a.g, kRun, 1024);
   RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_correct<TI, TR, kRun>), dim3(L.grid),
                                                    dim3(1024), 0, s, a));
+  return hipGetLastError();
+}
+
+hipError_t launch_image_grad(const ImageGradArgs& a, DType img, DType real, hipStream_t s) {
+  const unsigned nb = (unsigned)((a.g.ncol + kBlock - 1) / kBlock);
+  RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_image_grad<TI, TR>), dim3(nb),
+                                                   dim3(kBlock), 0, s, a));
   return hipGetLastError();
 }
 

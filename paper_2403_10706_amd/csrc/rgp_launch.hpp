@@ -78,6 +78,15 @@ struct LossFinalArgs {
   int gn_mode;
 };
 
+struct ImageGradArgs {
+  Geom g;
+  const void* Ip;
+  const void* Im;
+  const void* b;
+  void* gIp;          // dJ/dI+ (cells, field type)
+  void* gIm;          // dJ/dI- (cells, field type)
+};
+
 struct TrialArgs {
   Geom g;
   const void* Ip;
@@ -258,6 +267,7 @@ hipError_t launch_trial(const TrialArgs& a, DType img, DType real, hipStream_t s
 hipError_t launch_decide(const DecideArgs& a, hipStream_t s);
 hipError_t launch_apply_step(const ApplyArgs& a, DType real, hipStream_t s);
 hipError_t launch_correct(const CorrectArgs& a, DType img, DType real, hipStream_t s);
+hipError_t launch_image_grad(const ImageGradArgs& a, DType img, DType real, hipStream_t s);
 hipError_t launch_hvp(const HvpArgs& a, DType real, hipStream_t s);
 hipError_t launch_sum_final(const double* part, unsigned nprod, double* out, hipStream_t s);
 hipError_t launch_pcg_step(const PcgArgs& a, DType real, hipStream_t s);

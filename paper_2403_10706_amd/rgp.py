@@ -55,7 +55,7 @@ class SolverOpts(ctypes.Structure):
 EXPORTS = ("rgp_status_string", "rgp_last_hip_error", "rgp_default_opts", "rgp_workspace_size",
            "rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
            "rgp_apply_correction", "rgp_correct", "rgp_correct_plan", "rgp_plan_launch",
-           "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop")
+           "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop", "rgp_loss_grad_images")
 
 # rgp_kernel_kind
 KERNEL_PCG_STEP, KERNEL_LOSS_GRAD, KERNEL_TRIAL, KERNEL_HVP, KERNEL_OT, KERNEL_SHIFT = range(6)
@@ -102,10 +102,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rgp_plan_launch.argtypes = [vp, vp]
     lib.rgp_plan_destroy.argtypes = [vp]
     lib.rgp_timing_start.argtypes = [i32]
+    lib.rgp_loss_grad_images.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp, vp]
     lib.rgp_timing_stop.argtypes = [ctypes.POINTER(TimingRecord), i32, ctypes.POINTER(i32)]
     for name in ("rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
                  "rgp_apply_correction", "rgp_correct", "rgp_workspace_size", "rgp_correct_plan",
-                 "rgp_plan_launch", "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop"):
+                 "rgp_plan_launch", "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop",
+                 "rgp_loss_grad_images"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -246,6 +248,18 @@ def gn_hvp(hdiag, hoff, v, shape, pe, h=(1.0, 1.0, 1.0), alpha=300.0, *, ws=None
         ctypes.byref(g), dtype_code(v.dtype), _ptr(hdiag), _ptr(hoff), float(alpha), _ptr(v),
         _ptr(Hv), _ptr(vhv), _ptr(wsb), wsb.numel(), _stream_ptr(stream)))
     return Hv, vhv
+
+
+def loss_grad_images(I_plus, I_minus, b, pe, h=(1.0, 1.0, 1.0), *, stream=None):
+    """(dJ/dI+, dJ/dI-) as cell arrays of b's dtype (rgp_loss_grad_images)."""
+    _dev_check(I_plus, I_minus, b)
+    gp = torch.empty(tuple(I_plus.shape), dtype=b.dtype, device=b.device)
+    gm = torch.empty_like(gp)
+    g = make_grid(tuple(I_plus.shape), pe, h)
+    _check("rgp_loss_grad_images", load().rgp_loss_grad_images(
+        ctypes.byref(g), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
+        dtype_code(b.dtype), _ptr(b), _ptr(gp), _ptr(gm), _stream_ptr(stream)))
+    return gp, gm
 
 
 def pcg_solve(hdiag, hoff, rhs, shape, pe, h=(1.0, 1.0, 1.0), alpha=300.0, *, maxit=10,

@@ -312,3 +312,184 @@ def test_correct_plan_replays_match_eager():
         assert torch.equal(b, fresh["b"])
         assert not torch.equal(b, eager["b"])
         plan.close()
+
+
+# ---- precision: BF16 image storage, FP32 field and arithmetic, FP64 sums --------------------
+
+@pytest.mark.parametrize("shape,pe", [SHAPES[0], SHAPES[2], SHAPES[4]])
+def test_bf16_images_parity_and_error(shape, pe):
+    """BF16 images: parity with the oracle on the same BF16-rounded images (FP32 bars); against
+    the FP64 oracle on the unrounded images the error is that of the image rounding, stated and
+    bounded (about 2^-9 relative per image value)."""
+    rgp = _rgp()
+    bf, f32 = torch.bfloat16, torch.float32
+    p = _pair(shape, pe, seed=21)
+    h = (1.0, 1.1, 0.9)
+    Ip, Im = rounded(p.I_plus, bf), rounded(p.I_minus, bf)
+    b = rounded(smooth_field(shape, pe, seed=22, amp=min(2.0, shape[pe] / 4)), f32)
+    jdsp, g, hd, ho = rgp.loss_grad(to_dev(Ip, bf), to_dev(Im, bf), to_dev(b, f32), pe, h)
+    obj, gref, lin = orc.objective_gradient(Ip, Im, b, pe, h)
+    j = to_host(jdsp)
+    assert j[0] == pytest.approx(obj.J, rel=J_RTOL)
+    assert rel2(to_host(g), gref) <= VEC_RTOL
+    assert rel2(to_host(hd), orc.gn_diag(lin, pe)) <= VEC_RTOL
+    v = rounded(np.random.default_rng(4).standard_normal(b.shape), f32)
+    Hv, _ = rgp.gn_hvp(hd, ho, to_dev(v, f32), shape, pe, h)
+    assert rel2(to_host(Hv), orc.gn_matvec(lin, v, pe)) <= VEC_RTOL
+    b0, _ = rgp.ot_init(to_dev(Ip, bf), to_dev(Im, bf), pe, h, real_dtype=f32)
+    ot_ref = orc.ot_init(Ip, Im, pe, h)
+    assert float(np.max(np.abs(to_host(b0) - ot_ref.b0))) <= B0_ATOL
+    # against the FP64 oracle on the unrounded images
+    obj64, g64, _ = orc.objective_gradient(p.I_plus, p.I_minus, b, pe, h)
+    ot64 = orc.ot_init(p.I_plus, p.I_minus, pe, h)
+    eJ = abs(j[0] - obj64.J) / abs(obj64.J)
+    eg = rel2(to_host(g), g64)
+    eb0 = float(np.max(np.abs(to_host(b0) - ot64.b0)))
+    say(f"[bf16 images] shape={shape} pe={pe}: vs FP64 oracle on unrounded images: "
+        f"J rel {eJ:.2e}, grad rel {eg:.2e}, b0 max-abs {eb0:.2e} voxel")
+    assert eJ <= 2e-2 and eg <= 5e-2 and eb0 <= 5e-2
+
+
+@pytest.mark.timeout(900)
+def test_correct_c2_bf16_images():
+    """144x168x111 with BF16 images (FP32 field and arithmetic): the full schedule within 0.01
+    voxel of the oracle on the same BF16-rounded images; the distance to the FP64 oracle on the
+    unrounded images is stated."""
+    rgp = _rgp()
+    bf = torch.bfloat16
+    p = synth.make_workload("c2")
+    Ip, Im = rounded(p.I_plus, bf), rounded(p.I_minus, bf)
+    opts = rgp.Options(levels=3, gn_iters=10, pcg_iters=20, pcg_rtol=0.0)
+    out = rgp.correct(to_dev(Ip, bf), to_dev(Im, bf), p.pe, opts=opts, real_dtype=torch.float32)
+    b = to_host(out["b"])
+    say("[correct c2 bf16] oracle on the BF16-rounded images")
+    ref = orc.solve(Ip, Im, p.pe, levels=3, gn_iters=10, pcg_iters=20, pcg_rtol=0.0)
+    err = float(np.max(np.abs(b - ref.b)))
+    say("[correct c2 bf16] FP64 oracle on the unrounded images")
+    ref64 = orc.solve(p.I_plus, p.I_minus, p.pe, levels=3, gn_iters=10, pcg_iters=20,
+                      pcg_rtol=0.0)
+    e64 = float(np.max(np.abs(b - ref64.b)))
+    say(f"[correct c2 bf16] max|b - b_oracle(bf16 images)| = {err:.3e} voxel; "
+        f"max|b - b_oracle(FP64 images)| = {e64:.3e} voxel (max|b| = {np.abs(ref64.b).max():.3f})")
+    assert err <= BFINAL_ATOL
+    assert e64 <= 5 * BFINAL_ATOL
+
+
+# ---- the 7T-brain-shaped workload ------------------------------------------------------------
+
+@pytest.mark.timeout(600)
+def test_correct_c3_full_schedule():
+    """200x200x132 (PE along dim 0), FP32, 4 levels x 10 GN x 20 PCG (rtol 0): the final field
+    at 8192 seeded nodes within 0.01 voxel of the oracle's, the objective after the last GN step
+    within 1e-5 (tests/golden/c3_solve_sample.npz, written by tests/golden/make_c3_golden.py
+    from the oracle)."""
+    import os
+    rgp = _rgp()
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "c3_solve_sample.npz"))
+    p = synth.make_workload("c3")
+    assert tuple(gold["shape"]) == tuple(p.shape) and int(gold["pe"]) == p.pe
+    dt = torch.float32
+    Ip, Im = rounded(p.I_plus, dt), rounded(p.I_minus, dt)
+    opts = rgp.Options(levels=4, gn_iters=10, pcg_iters=20, pcg_rtol=0.0)
+    out = rgp.correct(to_dev(Ip, dt), to_dev(Im, dt), p.pe, opts=opts)
+    b = to_host(out["b"]).ravel()
+    err = float(np.max(np.abs(b[gold["b_index"]] - gold["b"])))
+    say(f"[correct c3 full schedule] max|b - b_oracle| over {gold['b'].size} nodes = "
+        f"{err:.3e} voxel (oracle max|b| = {float(gold['b_absmax']):.3f})")
+    assert err <= BFINAL_ATOL
+    head, recs = rgp.parse_stats(out["stats"], 4, 10)
+    assert recs[-1][-1]["J"] == pytest.approx(float(gold["J"][-1, -1]), rel=J_RTOL)
+    assert head["ot_guarded"] == int(gold["ot_guarded"])
+    Tp = to_host(out["T_plus"]).ravel()[gold["cell_index"]]
+    Tm = to_host(out["T_minus"]).ravel()[gold["cell_index"]]
+    assert rel2(Tp, gold["T_plus"]) <= 1e-3 and rel2(Tm, gold["T_minus"]) <= 1e-3
+
+
+# ---- differentiation: the objective as a torch.autograd.Function -----------------------------
+
+IMG = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
+
+
+@pytest.mark.parametrize("real,img", [("f64", "f64"), ("f32", "f32"), ("f32", "bf16")])
+@pytest.mark.parametrize("shape,pe", [SHAPES[0], SHAPES[1], SHAPES[3], SHAPES[4]])
+def test_autograd_gradients_match_oracle(shape, pe, real, img):
+    """J.backward() gives dJ/db (= loss_grad's gradient) and dJ/dI+- (the adjoint of the
+    interpolation and modulation) equal to the oracle's on the same rounded inputs."""
+    from paper_2403_10706_amd import autograd as ag
+    rgp = _rgp()
+    say(f"[autograd] shape={shape} pe={pe} real={real} img={img}")
+    p = _pair(shape, pe, seed=31)
+    h = (1.0, 1.2, 0.9)
+    it, dt = IMG[img], REAL[real]
+    Ip, Im = rounded(p.I_plus, it), rounded(p.I_minus, it)
+    b = rounded(smooth_field(shape, pe, seed=32, amp=min(2.0, shape[pe] / 4)), dt)
+    tIp = to_dev(Ip, it).requires_grad_()
+    tIm = to_dev(Im, it).requires_grad_()
+    tb = to_dev(b, dt).requires_grad_()
+    J = ag.objective(tIp, tIm, tb, pe, h)
+    J.backward()
+    obj, gref, _ = orc.objective_gradient(Ip, Im, b, pe, h)
+    gp_ref, gm_ref = orc.image_gradient(Ip, Im, b, pe, h)
+    assert float(J.detach()) == pytest.approx(obj.J, rel=_tol(real, 1e-12, J_RTOL))
+    assert rel2(to_host(tb.grad), gref) <= _tol(real, 1e-11, VEC_RTOL)
+    # the kernel's output in the field type, then the gradients in the images' dtype
+    gp, gm = rgp.loss_grad_images(tIp.detach(), tIm.detach(), tb.detach(), pe, h)
+    assert rel2(to_host(gp), gp_ref) <= _tol(real, 1e-11, VEC_RTOL)
+    assert rel2(to_host(gm), gm_ref) <= _tol(real, 1e-11, VEC_RTOL)
+    tol_img = {"f64": 1e-11, "f32": VEC_RTOL, "bf16": 1e-2}[img]   # BF16 rounds the gradient
+    assert tIp.grad.dtype == it and tIm.grad.dtype == it
+    assert rel2(to_host(tIp.grad), gp_ref) <= tol_img
+    assert rel2(to_host(tIm.grad), gm_ref) <= tol_img
+
+
+def test_autograd_gradcheck_fp64():
+    """torch.autograd.gradcheck of the hand-written backward against central differences of the
+    device forward, FP64, a tiny grid, all three inputs."""
+    from paper_2403_10706_amd import autograd as ag
+    _rgp()
+    shape, pe = (4, 6, 5), 1
+    p = _pair(shape, pe, seed=33)
+    b = smooth_field(shape, pe, seed=34, amp=0.6, max_slope=0.3)
+    dt = torch.float64
+    args = (to_dev(p.I_plus, dt).requires_grad_(), to_dev(p.I_minus, dt).requires_grad_(),
+            to_dev(b, dt).requires_grad_())
+    assert torch.autograd.gradcheck(lambda a, c, d: ag.objective(a, c, d, pe, (1.0, 0.9, 1.1)),
+                                    args, eps=1e-6, atol=1e-7, rtol=1e-5)
+
+
+@pytest.mark.timeout(900)
+def test_autograd_c2_bf16_directional_fd():
+    """The 144x168x111 pair with BF16 images and an FP32 field: the device gradient against the
+    oracle's FP64 gradient on the same BF16 images (1e-4), and along 64 seeded random directions
+    (max|d| = 1 voxel) against central differences (h = 1e-3) of the FP64 oracle J: relative
+    1e-3 (the kinks of the linear image model limit the differences) plus the FP32 gradient
+    error bound 1e-4 |g| |d|."""
+    from paper_2403_10706_amd import autograd as ag
+    _rgp()
+    p = synth.make_workload("c2")
+    bf, f32 = torch.bfloat16, torch.float32
+    h = (1.0, 1.0, 1.0)
+    Ip, Im = rounded(p.I_plus, bf), rounded(p.I_minus, bf)
+    b = rounded(smooth_field(p.shape, p.pe, seed=40, amp=4.0), f32)
+    tb = to_dev(b, f32).requires_grad_()
+    J = ag.objective(to_dev(Ip, bf), to_dev(Im, bf), tb, p.pe, h)
+    J.backward()
+    g = to_host(tb.grad)
+    obj, gref, _ = orc.objective_gradient(Ip, Im, b, p.pe, h)
+    assert float(J.detach()) == pytest.approx(obj.J, rel=J_RTOL)
+    assert rel2(g, gref) <= VEC_RTOL
+    rng = np.random.default_rng(1000)
+    gn = float(np.linalg.norm(gref))
+    worst = 0.0
+    say("[autograd c2 bf16] 64 directions against oracle central differences")
+    for k in range(64):
+        d = rng.standard_normal(b.shape)
+        d /= np.abs(d).max()
+        Jp = orc.objective(Ip, Im, b + 1e-3 * d, p.pe, h).J
+        Jm = orc.objective(Ip, Im, b - 1e-3 * d, p.pe, h).J
+        fd = (Jp - Jm) / 2e-3
+        an = float(np.sum(g * d))
+        bound = 1e-3 * abs(fd) + 1e-4 * gn * float(np.linalg.norm(d))
+        worst = max(worst, abs(fd - an) / bound)
+        assert abs(fd - an) <= bound, (k, fd, an)
+    say(f"[autograd c2 bf16] worst |fd - g.d| / bound = {worst:.3f}")
