@@ -189,6 +189,28 @@ rgp_status rgp_correct_plan(const rgp_grid* grid, rgp_dtype img_t, const void* I
 rgp_status rgp_plan_launch(rgp_plan plan, void* stream);
 rgp_status rgp_plan_destroy(rgp_plan plan);
 
+/* Batched correction (batching extension): n volume pairs of their own shapes, PE axes and
+ * buffers corrected by one captured HIP graph (replayed with rgp_plan_launch) in which every
+ * Gauss-Newton kernel - loss_grad, the PCG scalar phase and steps, the Armijo passes and
+ * decisions, the step update - is ONE launch covering all pairs, each pair's workgroups reading
+ * their arguments from a table in the workspace; the pyramid, OT, prolongation and correction
+ * kernels run pair by pair inside the same graph.  Per pair the arithmetic is that of
+ * rgp_correct (same options for all pairs; use_b_init must be 0; at most 1024 pairs; the
+ * contiguous field axis of every pair at most 256 nodes, else RGP_ESHAPE).  I_plus, I_minus,
+ * b_out: host arrays of n device pointers; T_plus, T_minus, stats_dev: NULL or host arrays of n
+ * device pointers (all entries non-NULL).  ws: one zero-filled workspace of at least
+ * rgp_batch_workspace_size bytes holding every pair's workspace and the launch tables, which
+ * this call writes (it synchronises `stream` once, to upload them, then captures on it).
+ * Buffers and workspace must outlive the plan. */
+rgp_status rgp_batch_workspace_size(int32_t n, const rgp_grid* grids, rgp_dtype real_t,
+                                    const rgp_solver_opts* opts, size_t* bytes);
+rgp_status rgp_correct_batch_plan(int32_t n, const rgp_grid* grids, rgp_dtype img_t,
+                                  const void* const* I_plus, const void* const* I_minus,
+                                  rgp_dtype real_t, const rgp_solver_opts* opts,
+                                  void* const* b_out, void* const* T_plus, void* const* T_minus,
+                                  double* const* stats_dev, void* ws, size_t ws_bytes,
+                                  void* stream, rgp_plan* plan);
+
 /* Kernel timing (instrumentation; not part of the method).  rgp_timing_start(capacity) creates
  * `capacity` pairs of HIP events (host API objects, no device memory) and from then on every
  * launch of a hot kernel that is not being captured into a graph records one pair at the start

@@ -12,6 +12,7 @@
 #include "../../include/rgp.h"
 #include "rgp_internal.hpp"
 #include "rgp_launch.hpp"
+#include "batch.hpp"
 
 namespace rgp {
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
@@ -20,6 +21,15 @@ hipError_t launch_stats_header(double* stats, const State* st, const unsigned lo
 }  // namespace rgp
 
 using namespace rgp;
+
+Recorder*& rgp::active_recorder() {
+  thread_local Recorder* r = nullptr;
+  return r;
+}
+bool& rgp::batch_plans() {
+  thread_local bool b = false;
+  return b;
+}
 
 namespace {
 
@@ -638,6 +648,12 @@ rgp_status check_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_pl
   return need_ws(RGP_OP_CORRECT, grid, real_t, opts, ws, ws_bytes);
 }
 
+hipError_t copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (active_recorder())
+    return record_other([dst, src, bytes](hipStream_t s2) { return copy_d2d(dst, src, bytes, s2); });
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+}
+
 // Enqueues the whole correction (arguments already validated).
 rgp_status enqueue_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
                            const void* I_minus, rgp_dtype real_t, const rgp_solver_opts* opts,
@@ -681,7 +697,7 @@ rgp_status enqueue_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_
   // Initial field on the coarsest level.
   const Level& top = lv[L - 1];
   if (opts->use_b_init) {
-    RGP_HIP(hipMemcpyAsync(w.B[0], b_init, top.g.nnode * rs, hipMemcpyDeviceToDevice, s));
+    RGP_HIP(copy_d2d(w.B[0], b_init, top.g.nnode * rs, s));
   } else {
     RGP_HIP(launch_shift(ShiftArgs{imgs[L - 1][0], imgs[L - 1][1], top.g.ncell,
                                    w.ctl.slot(kPartShift), w.ctl.guarded},
@@ -735,7 +751,7 @@ rgp_status enqueue_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_
     ca.Tm = T_minus;
     RGP_HIP(launch_correct(ca, di, dr, s));
   }
-  RGP_HIP(hipMemcpyAsync(b_out, w.B[cur], lv[0].g.nnode * rs, hipMemcpyDeviceToDevice, s));
+  RGP_HIP(copy_d2d(b_out, w.B[cur], lv[0].g.nnode * rs, s));
   if (stats_dev) RGP_HIP(launch_stats_header(stats_dev, w.ctl.st, w.ctl.guarded, s));
   return RGP_OK;
 }
@@ -891,4 +907,253 @@ rgp_status rgp_timing_stop(rgp_timing_record* out, int32_t max, int32_t* n) {
   *n = k;
   timing_release_locked();
   return st;
+}
+
+// ---- batched correction -------------------------------------------------------------------
+
+namespace {
+
+constexpr int kMaxBatch = 1024;
+constexpr int kBatchMaxContig = 256;  // nodes along the contiguous axis (one PCG tile shape)
+
+struct BatchPlansScope {
+  bool saved;
+  BatchPlansScope() : saved(batch_plans()) { batch_plans() = true; }
+  ~BatchPlansScope() { batch_plans() = saved; }
+};
+struct RecorderScope {
+  Recorder* saved;
+  explicit RecorderScope(Recorder* r) : saved(active_recorder()) { active_recorder() = r; }
+  ~RecorderScope() { active_recorder() = saved; }
+};
+
+rgp_status check_batch_grids(int32_t n, const rgp_grid* grids, rgp_dtype real_t,
+                             const rgp_solver_opts* opts) {
+  if (n < 1 || n > kMaxBatch || !grids) return RGP_EINVAL;
+  rgp_status st = check_opts(opts);
+  if (st != RGP_OK) return st;
+  if (opts->use_b_init) return RGP_EINVAL;
+  DType dr;
+  if (!dtype_of(real_t, &dr) || dr == DType::BF16) return RGP_EDTYPE;
+  for (int p = 0; p < n; ++p) {
+    if ((st = check_grid(&grids[p])) != RGP_OK) return st;
+    if (grids[p].m[2] + (grids[p].pe == 2 ? 1 : 0) > kBatchMaxContig) return RGP_ESHAPE;
+    Level lv[kMaxLevels];
+    if (make_levels(&grids[p], opts->levels, lv) != 0) return RGP_ESHAPE;
+  }
+  return RGP_OK;
+}
+
+size_t pair_bytes(const rgp_grid* g, const rgp_solver_opts* o, DType dr) {
+  Level lv[kMaxLevels];
+  make_levels(g, o->levels, lv);
+  return align_up(correct_bytes(lv, o->levels, dr));
+}
+
+// One shared launch of the merged sequence: where its tables sit in the arena.
+struct BatchSlot {
+  bool shared = false;
+  RecKind kind = RecKind::kOther;
+  size_t tab = 0, geo = 0, starts = 0;
+  unsigned grid = 0;
+  size_t lds = 0;
+  int var[4] = {0, 0, 0, 0};
+};
+
+// Records the correction of every pair (their workspaces laid out back to back from ws) and
+// merges the sequences: returns the per-pair launches and the table arena.
+rgp_status record_batch(int32_t n, const rgp_grid* grids, rgp_dtype img_t,
+                        const void* const* I_plus, const void* const* I_minus, rgp_dtype real_t,
+                        const rgp_solver_opts* opts, void* const* b_out, void* const* T_plus,
+                        void* const* T_minus, double* const* stats, unsigned char* ws,
+                        std::vector<Recorder>& recs, std::vector<BatchSlot>& slots,
+                        std::vector<unsigned char>& arena, size_t& pairs_total) {
+  DType dr;
+  dtype_of(real_t, &dr);
+  recs.assign((size_t)n, Recorder{});
+  size_t off = 0;
+  {
+    BatchPlansScope bp;
+    for (int p = 0; p < n; ++p) {
+      RecorderScope rs(&recs[(size_t)p]);
+      rgp_status st = enqueue_correct(&grids[p], img_t, I_plus[p], I_minus[p], real_t, opts,
+                                      nullptr, b_out[p], T_plus ? T_plus[p] : nullptr,
+                                      T_minus ? T_minus[p] : nullptr, stats ? stats[p] : nullptr,
+                                      ws + off, nullptr);
+      if (st != RGP_OK) return st;
+      off += pair_bytes(&grids[p], opts, dr);
+    }
+  }
+  pairs_total = off;
+  const size_t L = recs[0].launches.size();
+  for (int p = 1; p < n; ++p)
+    if (recs[(size_t)p].launches.size() != L) return RGP_EINVAL;
+  slots.assign(L, BatchSlot{});
+  arena.clear();
+  auto put = [&](const void* src, size_t bytes) {
+    const size_t at = align_up(arena.size());
+    arena.resize(at + bytes);
+    std::memcpy(arena.data() + at, src, bytes);
+    return at;
+  };
+  for (size_t i = 0; i < L; ++i) {
+    const RecLaunch& r0 = recs[0].launches[i];
+    BatchSlot& sl = slots[i];
+    sl.kind = r0.kind;
+    bool same = true;
+    for (int p = 1; p < n && same; ++p) {
+      const RecLaunch& r = recs[(size_t)p].launches[i];
+      same = r.kind == r0.kind && r.block == r0.block && r.args.size() == r0.args.size() &&
+             std::equal(r.var, r.var + 4, r0.var);
+    }
+    if (!same) {
+      // the sequences must have the same shape; differing kinds mean they do not
+      for (int p = 1; p < n; ++p)
+        if (recs[(size_t)p].launches[i].kind != r0.kind) return RGP_EINVAL;
+    }
+    if (r0.kind == RecKind::kOther || n == 1 || !same) continue;
+    sl.shared = true;
+    std::copy(r0.var, r0.var + 4, sl.var);
+    std::vector<unsigned char> tab;
+    std::vector<uint32_t> starts((size_t)n + 1, 0);
+    std::vector<MarchGeo> geo;
+    for (int p = 0; p < n; ++p) {
+      const RecLaunch& r = recs[(size_t)p].launches[i];
+      tab.insert(tab.end(), r.args.begin(), r.args.end());
+      starts[(size_t)p + 1] = starts[(size_t)p] + r.grid;
+      sl.lds = std::max(sl.lds, r.lds);
+      geo.push_back(r.geo);
+    }
+    sl.grid = starts[(size_t)n];
+    sl.tab = put(tab.data(), tab.size());
+    sl.starts = put(starts.data(), starts.size() * sizeof(uint32_t));
+    if (r0.kind == RecKind::kPcgStep) sl.geo = put(geo.data(), geo.size() * sizeof(MarchGeo));
+  }
+  arena.resize(align_up(arena.size()));
+  return RGP_OK;
+}
+
+hipError_t issue_batch(int32_t n, const std::vector<Recorder>& recs,
+                       const std::vector<BatchSlot>& slots, const unsigned char* arena_dev,
+                       hipStream_t s) {
+  for (size_t i = 0; i < slots.size(); ++i) {
+    const BatchSlot& sl = slots[i];
+    hipError_t e = hipSuccess;
+    if (!sl.shared) {
+      for (int p = 0; p < n && e == hipSuccess; ++p) e = recs[(size_t)p].launches[i].replay(s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
+    const void* tab = arena_dev + sl.tab;
+    const uint32_t* starts = reinterpret_cast<const uint32_t*>(arena_dev + sl.starts);
+    switch (sl.kind) {
+      case RecKind::kLossGrad:
+        e = launch_loss_grad_batch(tab, starts, n, sl.grid, (DType)sl.var[0], (DType)sl.var[1], s);
+        break;
+      case RecKind::kTrial:
+        e = launch_trial_batch(tab, starts, n, sl.grid, sl.var[2], (DType)sl.var[0],
+                               (DType)sl.var[1], s);
+        break;
+      case RecKind::kDecide:
+        e = launch_decide_batch(tab, n, s);
+        break;
+      case RecKind::kApply:
+        e = launch_apply_step_batch(tab, starts, n, sl.grid, (DType)sl.var[0], s);
+        break;
+      case RecKind::kPcgScalars:
+        e = launch_pcg_scalars_batch(tab, n, s);
+        break;
+      case RecKind::kPcgStep:
+        e = launch_pcg_step_batch(tab, reinterpret_cast<const MarchGeo*>(arena_dev + sl.geo),
+                                  starts, n, sl.grid, sl.lds, (DType)sl.var[0], s);
+        break;
+      default:
+        e = hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+rgp_status rgp_batch_workspace_size(int32_t n, const rgp_grid* grids, rgp_dtype real_t,
+                                    const rgp_solver_opts* opts, size_t* bytes) {
+  if (!bytes) return RGP_EINVAL;
+  rgp_status st = check_batch_grids(n, grids, real_t, opts);
+  if (st != RGP_OK) return st;
+  // a dry recording with placeholder addresses gives the size of the launch tables
+  std::vector<const void*> img((size_t)n, reinterpret_cast<const void*>(kAlign));
+  std::vector<void*> out((size_t)n, reinterpret_cast<void*>(kAlign));
+  std::vector<Recorder> recs;
+  std::vector<BatchSlot> slots;
+  std::vector<unsigned char> arena;
+  size_t pairs = 0;
+  st = record_batch(n, grids, RGP_F32, img.data(), img.data(), real_t, opts, out.data(), nullptr,
+                    nullptr, nullptr, nullptr, recs, slots, arena, pairs);
+  if (st != RGP_OK) return st;
+  *bytes = pairs + arena.size();
+  return RGP_OK;
+}
+
+rgp_status rgp_correct_batch_plan(int32_t n, const rgp_grid* grids, rgp_dtype img_t,
+                                  const void* const* I_plus, const void* const* I_minus,
+                                  rgp_dtype real_t, const rgp_solver_opts* opts,
+                                  void* const* b_out, void* const* T_plus, void* const* T_minus,
+                                  double* const* stats_dev, void* ws, size_t ws_bytes,
+                                  void* stream, rgp_plan* plan) {
+  if (!plan) return RGP_EINVAL;
+  *plan = nullptr;
+  if (!stream) return RGP_EINVAL;  // the legacy default stream cannot be captured
+  rgp_status st = check_batch_grids(n, grids, real_t, opts);
+  if (st != RGP_OK) return st;
+  DType di, dr;
+  if ((st = check_types(img_t, real_t, &di, &dr)) != RGP_OK) return st;
+  if (!I_plus || !I_minus || !b_out) return RGP_EINVAL;
+  for (int p = 0; p < n; ++p) {
+    if (!I_plus[p] || !I_minus[p] || !b_out[p]) return RGP_EINVAL;
+    if ((T_plus && !T_plus[p]) || (T_minus && !T_minus[p]) || (stats_dev && !stats_dev[p]))
+      return RGP_EINVAL;
+  }
+  size_t need = 0;
+  if ((st = rgp_batch_workspace_size(n, grids, real_t, opts, &need)) != RGP_OK) return st;
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+    return RGP_EWORKSPACE;
+  std::vector<Recorder> recs;
+  std::vector<BatchSlot> slots;
+  std::vector<unsigned char> arena;
+  size_t pairs = 0;
+  st = record_batch(n, grids, img_t, I_plus, I_minus, real_t, opts, b_out, T_plus, T_minus,
+                    stats_dev, static_cast<unsigned char*>(ws), recs, slots, arena, pairs);
+  if (st != RGP_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* arena_dev = static_cast<unsigned char*>(ws) + pairs;
+  if (!arena.empty()) {
+    RGP_HIP(hipMemcpyAsync(arena_dev, arena.data(), arena.size(), hipMemcpyHostToDevice, s));
+    RGP_HIP(hipStreamSynchronize(s));  // the host tables are released on return
+  }
+  RGP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  const hipError_t e = issue_batch(n, recs, slots, arena_dev, s);
+  hipGraph_t graph = nullptr;
+  const hipError_t e1 = hipStreamEndCapture(s, &graph);
+  if (e != hipSuccess || e1 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    g_last_hip = (int)(e != hipSuccess ? e : e1);
+    return RGP_EHIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    g_last_hip = (int)e2;
+    return RGP_EHIP;
+  }
+  rgp_plan pl = new (std::nothrow) rgp_plan_s{graph, exec};
+  if (!pl) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return RGP_EINVAL;
+  }
+  *plan = pl;
+  return RGP_OK;
 }

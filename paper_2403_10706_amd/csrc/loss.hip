@@ -13,6 +13,7 @@
 #include "rgp_internal.hpp"
 #include "rgp_launch.hpp"
 #include "rgp_solver.hpp"
+#include "batch.hpp"
 
 namespace rgp {
 
@@ -73,8 +74,8 @@ __device__ __forceinline__ void phi3(TR z, TR& f, TR& f1, TR& f2) {
 // (diag, off).  With step != 0 it first forms b = b_in + gamma q (gamma and the acceptance from
 // the line search) and writes it to b_out, a different buffer since neighbours read b_in.
 // --------------------------------------------------------------------------------------------
-template <typename TI, typename TR, int S, int BLK>
-__global__ __launch_bounds__(BLK) void k_loss_grad(LossGradArgs a) {
+template <typename TI, typename TR, int S>
+__device__ __forceinline__ void loss_grad_body(const LossGradArgs& a, VBlock vb) {
   const Geom g = a.g;
   const TI* __restrict__ Ip = static_cast<const TI*>(a.Ip);
   const TI* __restrict__ Im = static_cast<const TI*>(a.Im);
@@ -90,14 +91,14 @@ __global__ __launch_bounds__(BLK) void k_loss_grad(LossGradArgs a) {
   const int64_t ntiles = nct * ((mp + 1 + S - 1) / S);
   const int lane = threadIdx.x & (kWave - 1);
 
-  if (a.level_start && blockIdx.x == 0 && threadIdx.x == 0) {
+  if (a.level_start && vb.id == 0 && threadIdx.x == 0) {
     st->gn_stop = 0;
     st->accepted = 0;
   }
   TR coef = TR(0);
   if (a.step) {
     if (load_flag(&st->gn_stop)) {  // the solve stopped on this level: carry b over unchanged
-      for (WaveIter it = wave_iter(ntiles); it.t < it.end; it.t += it.stride) {
+      for (WaveIter it = wave_iter(ntiles, vb); it.t < it.end; it.t += it.stride) {
         const int64_t col = (it.t % nct) * kWave + lane;
         const int k0 = (int)(it.t / nct) * S;
         if (col >= g.ncol) continue;
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(BLK) void k_loss_grad(LossGradArgs a) {
 
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // r^2, S terms, phi, violations, g^2
 
-  for (WaveIter it = wave_iter(ntiles); it.t < it.end; it.t += it.stride) {
+  for (WaveIter it = wave_iter(ntiles, vb); it.t < it.end; it.t += it.stride) {
     const int64_t col = (it.t % nct) * kWave + lane;
     const int k0 = (int)(it.t / nct) * S;
     const bool colok = col < g.ncol;
@@ -239,7 +240,22 @@ __global__ __launch_bounds__(BLK) void k_loss_grad(LossGradArgs a) {
       dR = ndR;
     }
   }
-  store_partials<5>(acc, a.part);
+  store_partials<5>(acc, a.part, vb.id);
+}
+
+template <typename TI, typename TR, int S, int BLK>
+__global__ __launch_bounds__(BLK) void k_loss_grad(LossGradArgs a) {
+  loss_grad_body<TI, TR, S>(a, hw_block());
+}
+
+// One launch over several volumes: tab[p] drives the workgroups starts[p] .. starts[p+1]-1.
+template <typename TI, typename TR, int S, int BLK>
+__global__ __launch_bounds__(BLK) void k_loss_grad_batch(const LossGradArgs* __restrict__ tab,
+                                                         const uint32_t* __restrict__ starts,
+                                                         int n) {
+  VBlock vb;
+  const int p = batch_volume(starts, n, vb);
+  loss_grad_body<TI, TR, S>(tab[p], vb);
 }
 
 // J, D, S, P from loss_grad's block sums (standalone entry point; one block).
@@ -252,8 +268,8 @@ __global__ __launch_bounds__(kReduceBlock) void k_loss_final(LossFinalArgs a) { 
 // and the two S sums.  A single-block decide kernel then takes the first (largest) gamma that
 // satisfies the Armijo condition, which is exactly what halving from gamma = 1 selects.
 // --------------------------------------------------------------------------------------------
-template <typename TI, typename TR, int S, int NC, int BLK>
-__global__ __launch_bounds__(BLK) void k_trial(TrialArgs a) {
+template <typename TI, typename TR, int S, int NC>
+__device__ __forceinline__ void trial_body(const TrialArgs& a, VBlock vb) {
   const State* st = a.st;
   if (load_flag(&st->gn_stop) || st->accepted) return;
   const Geom g = a.g;
@@ -281,7 +297,7 @@ __global__ __launch_bounds__(BLK) void k_trial(TrialArgs a) {
 #pragma unroll
   for (int i = 0; i < K; ++i) v[i] = 0.0;
 
-  for (WaveIter it = wave_iter(ntiles); it.t < it.end; it.t += it.stride) {
+  for (WaveIter it = wave_iter(ntiles, vb); it.t < it.end; it.t += it.stride) {
     const int64_t col = (it.t % nct) * kWave + lane;
     const int k0 = (int)(it.t / nct) * S;
     const bool colok = col < g.ncol;
@@ -357,26 +373,55 @@ __global__ __launch_bounds__(BLK) void k_trial(TrialArgs a) {
       }
     }
   }
-  store_partials<K>(v, a.part);
+  store_partials<K>(v, a.part, vb.id);
 }
 
-// Armijo decision on the pass just evaluated (one block).
-__global__ __launch_bounds__(kReduceBlock) void k_decide(DecideArgs a) {
+template <typename TI, typename TR, int S, int NC, int BLK>
+__global__ __launch_bounds__(BLK) void k_trial(TrialArgs a) {
+  trial_body<TI, TR, S, NC>(a, hw_block());
+}
+
+template <typename TI, typename TR, int S, int NC, int BLK>
+__global__ __launch_bounds__(BLK) void k_trial_batch(const TrialArgs* __restrict__ tab,
+                                                     const uint32_t* __restrict__ starts, int n) {
+  VBlock vb;
+  const int p = batch_volume(starts, n, vb);
+  trial_body<TI, TR, S, NC>(tab[p], vb);
+}
+
+// Armijo decision on the pass just evaluated (one block per volume).
+__device__ __forceinline__ void decide_body(const DecideArgs& a) {
   const State* st = a.st;
   if (load_flag(&st->gn_stop) || st->accepted) return;
   decide_pass(a);
 }
+__global__ __launch_bounds__(kReduceBlock) void k_decide(DecideArgs a) { decide_body(a); }
+__global__ __launch_bounds__(kReduceBlock) void k_decide_batch(const DecideArgs* __restrict__ tab) {
+  decide_body(tab[blockIdx.x]);
+}
 
 // b <- b + gamma q (in place, pointwise) with the accepted line-search step.
 template <typename TR>
-__global__ __launch_bounds__(kBlock) void k_apply_step(ApplyArgs a) {
+__device__ __forceinline__ void apply_step_body(const ApplyArgs& a, VBlock vb) {
   const State* st = a.st;
   if (!st->accepted) return;
   const TR gam = (TR)st->gamma;
   TR* __restrict__ b = static_cast<TR*>(a.b);
   const TR* __restrict__ q = static_cast<const TR*>(a.q);
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = (int64_t)vb.id * kBlock + threadIdx.x;
   if (i < a.n) b[i] = b[i] + gam * q[i];
+}
+template <typename TR>
+__global__ __launch_bounds__(kBlock) void k_apply_step(ApplyArgs a) {
+  apply_step_body<TR>(a, hw_block());
+}
+template <typename TR>
+__global__ __launch_bounds__(kBlock) void k_apply_step_batch(const ApplyArgs* __restrict__ tab,
+                                                             const uint32_t* __restrict__ starts,
+                                                             int n) {
+  VBlock vb;
+  const int p = batch_volume(starts, n, vb);
+  apply_step_body<TR>(tab[p], vb);
 }
 
 // Corrected images T[I+, b, v] and T[I-, b, -v] at the cell centres (Sec. 2.4.7).
@@ -393,7 +438,7 @@ __global__ __launch_bounds__(1024) void k_correct(CorrectArgs a) {
   const int64_t ntiles = nct * ((mp + S - 1) / S);
   const int lane = threadIdx.x & (kWave - 1);
   const TR inv_hp = TR(1) / (TR)g.hp;
-  for (WaveIter it = wave_iter(ntiles); it.t < it.end; it.t += it.stride) {
+  for (WaveIter it = wave_iter(ntiles, hw_block()); it.t < it.end; it.t += it.stride) {
     const int64_t col = (it.t % nct) * kWave + lane;
     const int k0 = (int)(it.t / nct) * S;
     if (col >= g.ncol) continue;
@@ -440,7 +485,7 @@ Launch plan_tiles(const Geom& g, int S, int block) {
   const int64_t wpb = block / kWave;
   int64_t grid = (L.ntiles + wpb - 1) / wpb;
   if (grid > kMaxGrid) grid = kMaxGrid;
-  if (grid > 8) grid = (grid + 7) / 8 * 8;  // whole XCD rounds (see wave_iter)
+  if (grid > 8 || batch_plans()) grid = (grid + 7) / 8 * 8;  // whole XCD rounds (see wave_iter)
   if (grid > kMaxGrid) grid = kMaxGrid;
   L.grid = (unsigned)(grid < 1 ? 1 : grid);
   return L;
@@ -563,6 +608,9 @@ Launch plan_trial(const Geom& g, DType real, int nc) {
 
 hipError_t launch_loss_grad(const LossGradArgs& a, DType img, DType real, hipStream_t s) {
   const Launch L = plan_loss_grad(a.g, real);
+  if (active_recorder())
+    return record_launch(RecKind::kLossGrad, a, L.grid, L.block, 0, (int)img, (int)real, 0,
+                         [a, img, real](hipStream_t s2) { return launch_loss_grad(a, img, real, s2); });
   if (L.block == 1024) {
     RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH(kKindLossGrad, a.g, (k_loss_grad<TI, TR, kRun, 1024>),
                                              L.grid, 1024, 0, s, a));
@@ -574,12 +622,17 @@ hipError_t launch_loss_grad(const LossGradArgs& a, DType img, DType real, hipStr
 }
 
 hipError_t launch_loss_final(const LossFinalArgs& a, hipStream_t s) {
+  if (active_recorder())
+    return record_other([a](hipStream_t s2) { return launch_loss_final(a, s2); });
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kReduceBlock), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_trial(const TrialArgs& a, DType img, DType real, hipStream_t s) {
   const Launch L = plan_trial(a.g, real, a.nc);
+  if (active_recorder())
+    return record_launch(RecKind::kTrial, a, L.grid, L.block, 0, (int)img, (int)real, a.nc,
+                         [a, img, real](hipStream_t s2) { return launch_trial(a, img, real, s2); });
 #define RGP_TRIAL(NC, B)                                                                   \
   RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH_T(kKindTrial, NC, a.g,                          \
                                              (k_trial<TI, TR, kRun, NC, B>), L.grid, B, 0, s, a))
@@ -599,12 +652,18 @@ hipError_t launch_trial(const TrialArgs& a, DType img, DType real, hipStream_t s
 }
 
 hipError_t launch_decide(const DecideArgs& a, hipStream_t s) {
+  if (active_recorder())
+    return record_launch(RecKind::kDecide, a, 1, kReduceBlock, 0, 0, 0, 0,
+                         [a](hipStream_t s2) { return launch_decide(a, s2); });
   hipLaunchKernelGGL(k_decide, dim3(1), dim3(kReduceBlock), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_apply_step(const ApplyArgs& a, DType real, hipStream_t s) {
   const unsigned nb = (unsigned)((a.n + kBlock - 1) / kBlock);
+  if (active_recorder())
+    return record_launch(RecKind::kApply, a, nb, kBlock, 0, (int)real, 0, 0,
+                         [a, real](hipStream_t s2) { return launch_apply_step(a, real, s2); });
   if (real == DType::F64)
     hipLaunchKernelGGL(k_apply_step<double>, dim3(nb), dim3(kBlock), 0, s, a);
   else
@@ -613,6 +672,8 @@ hipError_t launch_apply_step(const ApplyArgs& a, DType real, hipStream_t s) {
 }
 
 hipError_t launch_correct(const CorrectArgs& a, DType img, DType real, hipStream_t s) {
+  if (active_recorder())
+    return record_other([a, img, real](hipStream_t s2) { return launch_correct(a, img, real, s2); });
   Launch L = plan_tiles(a.g, kRun, 1024);
   RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_correct<TI, TR, kRun>), dim3(L.grid),
                                                    dim3(1024), 0, s, a));
@@ -620,9 +681,55 @@ hipError_t launch_correct(const CorrectArgs& a, DType img, DType real, hipStream
 }
 
 hipError_t launch_image_grad(const ImageGradArgs& a, DType img, DType real, hipStream_t s) {
+  if (active_recorder())
+    return record_other([a, img, real](hipStream_t s2) { return launch_image_grad(a, img, real, s2); });
   const unsigned nb = (unsigned)((a.g.ncol + kBlock - 1) / kBlock);
   RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_image_grad<TI, TR>), dim3(nb),
                                                    dim3(kBlock), 0, s, a));
+  return hipGetLastError();
+}
+
+// ---- shared launches over several volumes -----------------------------------------------------
+
+hipError_t launch_loss_grad_batch(const void* tab, const uint32_t* starts, int n, unsigned grid,
+                                  DType img, DType real, hipStream_t s) {
+  const LossGradArgs* t = static_cast<const LossGradArgs*>(tab);
+  RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_loss_grad_batch<TI, TR, kRun, 256>),
+                                                   dim3(grid), dim3(256), 0, s, t, starts, n));
+  return hipGetLastError();
+}
+
+hipError_t launch_trial_batch(const void* tab, const uint32_t* starts, int n, unsigned grid,
+                              int nc, DType img, DType real, hipStream_t s) {
+  const TrialArgs* t = static_cast<const TrialArgs*>(tab);
+#define RGP_TRIAL_B(NC)                                                                      \
+  RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_trial_batch<TI, TR, kRun, NC, 256>),    \
+                                                   dim3(grid), dim3(256), 0, s, t, starts, n))
+  switch (nc) {
+    case 1: RGP_TRIAL_B(1); break;
+    case 2: RGP_TRIAL_B(2); break;
+    case 3: RGP_TRIAL_B(3); break;
+    case 4: RGP_TRIAL_B(4); break;
+    case 5: RGP_TRIAL_B(5); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef RGP_TRIAL_B
+  return hipGetLastError();
+}
+
+hipError_t launch_decide_batch(const void* tab, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_decide_batch, dim3(n), dim3(kReduceBlock), 0, s,
+                     static_cast<const DecideArgs*>(tab));
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_step_batch(const void* tab, const uint32_t* starts, int n, unsigned grid,
+                                   DType real, hipStream_t s) {
+  const ApplyArgs* t = static_cast<const ApplyArgs*>(tab);
+  if (real == DType::F64)
+    hipLaunchKernelGGL(k_apply_step_batch<double>, dim3(grid), dim3(kBlock), 0, s, t, starts, n);
+  else
+    hipLaunchKernelGGL(k_apply_step_batch<float>, dim3(grid), dim3(kBlock), 0, s, t, starts, n);
   return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 // first node of a segment is a binary search, later nodes advance monotonically (merge path).
 #include "rgp_internal.hpp"
 #include "rgp_launch.hpp"
+#include "batch.hpp"
 
 namespace rgp {
 
@@ -248,6 +249,8 @@ unsigned shift_grid(int64_t n) {
 }
 
 hipError_t launch_shift(const ShiftArgs& a, DType img, hipStream_t s) {
+  if (active_recorder())
+    return record_other([a, img](hipStream_t s2) { return launch_shift(a, img, s2); });
   const unsigned nb = shift_grid(a.n);
   if (img == DType::F64)
     RGP_LAUNCH_N(kKindShift, a.n, 0, k_shift<double>, nb, kBlock, 0, s, a);
@@ -272,6 +275,8 @@ int ot_cols_per_block(int mp) {
 }
 
 hipError_t launch_ot(const OtArgs& a, DType img, DType real, hipStream_t s) {
+  if (active_recorder())
+    return record_other([a, img, real](hipStream_t s2) { return launch_ot(a, img, real, s2); });
   const int nc = ot_cols_per_block(a.g.mp);
   if (nc == 0) return hipErrorInvalidValue;
   const unsigned nb = (unsigned)((a.g.ncol + nc - 1) / nc);

@@ -17,6 +17,7 @@
 #include "rgp_internal.hpp"
 #include "rgp_launch.hpp"
 #include "rgp_solver.hpp"
+#include "batch.hpp"
 
 namespace rgp {
 
@@ -38,7 +39,7 @@ __global__ __launch_bounds__(BLK) void k_hvp(HvpArgs a) {
   const TR cx = (TR)(a.alpha * g.vol / (g.hx * g.hx));
   const TR cy = (TR)(a.alpha * g.vol / (g.hy * g.hy));
   double acc[1] = {0.0};
-  for (WaveIter it = wave_iter(ntiles); it.t < it.end; it.t += it.stride) {
+  for (WaveIter it = wave_iter(ntiles, hw_block()); it.t < it.end; it.t += it.stride) {
     const int64_t col = (it.t % nct) * kWave + lane;
     const int k0 = (int)(it.t / nct) * S;
     const bool colok = col < g.ncol;
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(BLK) void k_hvp(HvpArgs a) {
       }
     }
   }
-  if (a.part) store_partials<1>(acc, a.part);
+  if (a.part) store_partials<1>(acc, a.part, blockIdx.x);
 }
 
 // out = sum of one slot of block sums (one block).
@@ -139,7 +140,7 @@ __device__ __forceinline__ PcgSlot pcg_advance(const PcgSlot& prev, const double
 // reduced in a fixed order.  Block 0 stores it and, when the solve ends, the iteration count and
 // residual.
 __device__ __forceinline__ PcgSlot pcg_scalar_phase(const PcgScalarArgs& a, const PcgSlot& prev,
-                                                    double (&t)[7]) {
+                                                    double (&t)[7], VBlock vb) {
   const int it = a.iter;
   PcgSlot cur;
   bool fin = false;
@@ -151,7 +152,7 @@ __device__ __forceinline__ PcgSlot pcg_scalar_phase(const PcgScalarArgs& a, cons
     block_sum<7>(t);
     cur = pcg_advance(prev, t, it, a.maxit, a.rtol, fin);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (vb.id == 0 && threadIdx.x == 0) {
     a.slots[it & 1] = cur;
     if (fin) pcg_outputs(a, cur);
   }
@@ -161,13 +162,13 @@ __device__ __forceinline__ PcgSlot pcg_scalar_phase(const PcgScalarArgs& a, cons
 // One block.  Iteration 0: in Gauss-Newton mode, a stopped solve or a violated barrier at the
 // current iterate (J = +inf, finalised here from loss_grad's block sums) gives status Done.
 // Later iterations (when not fused into k_pcg_step): the scalar phase.
-__global__ __launch_bounds__(kReduceBlock) void k_pcg_scalars(PcgScalarArgs a) {
+__device__ __forceinline__ void pcg_scalars_body(const PcgScalarArgs& a) {
   State* st = a.st;
   if (a.iter > 0) {
     const PcgSlot prev = a.slots[(a.iter - 1) & 1];
     double t[7];
     load_partials_cm<7>(t, a.part_prev, a.nprod, a.iter == 1 ? 7 : 5);
-    pcg_scalar_phase(a, prev, t);
+    pcg_scalar_phase(a, prev, t, VBlock{0u, 1u});
     return;
   }
   if (a.gn_mode && load_flag(&st->gn_stop)) {
@@ -186,6 +187,13 @@ __global__ __launch_bounds__(kReduceBlock) void k_pcg_scalars(PcgScalarArgs a) {
     a.slots[0] = s0;
   }
 }
+__global__ __launch_bounds__(kReduceBlock) void k_pcg_scalars(PcgScalarArgs a) {
+  pcg_scalars_body(a);
+}
+__global__ __launch_bounds__(kReduceBlock) void k_pcg_scalars_batch(
+    const PcgScalarArgs* __restrict__ tab) {
+  pcg_scalars_body(tab[blockIdx.x]);
+}
 
 // ---- main phase: plane-march PCG step -------------------------------------------------------
 // Raw values of one node read by the update (x only on owned planes).
@@ -203,7 +211,7 @@ struct NodeRaw {
 // plane o+1 are loaded while plane o is computed.  The LDS plane buffer is double-buffered so that
 // one barrier per plane suffices.  Planes just outside the unit contribute p only (recomputed).
 template <typename TR, int ROLE, int BLK, int NPT, int HMAX>
-__global__ __launch_bounds__(BLK) void k_pcg_step(PcgArgs a, MarchGeo m) {
+__device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& m, VBlock vb) {
   extern __shared__ unsigned char lds_raw[];
   TR* lds = reinterpret_cast<TR*>(lds_raw);
   const int it = a.sc.iter;
@@ -238,12 +246,12 @@ __global__ __launch_bounds__(BLK) void k_pcg_step(PcgArgs a, MarchGeo m) {
 
   // units: 8 contiguous ranges, one per XCD (blocks are dealt to the XCDs round-robin), with the
   // o-chunk fastest so that units sharing halo planes run together on one XCD
-  const unsigned G = gridDim.x;
-  unsigned nxcd = 1, xcd = 0, lb = blockIdx.x, gl = G;
+  const unsigned G = vb.n;
+  unsigned nxcd = 1, xcd = 0, lb = vb.id, gl = G;
   if (G >= 8u && G % 8u == 0u) {
     nxcd = 8u;
-    xcd = blockIdx.x % 8u;
-    lb = blockIdx.x / 8u;
+    xcd = vb.id % 8u;
+    lb = vb.id / 8u;
     gl = G / 8u;
   }
   const int64_t ulo = m.units * xcd / nxcd, uhi = m.units * (xcd + 1) / nxcd;
@@ -314,14 +322,14 @@ __global__ __launch_bounds__(BLK) void k_pcg_step(PcgArgs a, MarchGeo m) {
   if (fused) load_partials_cm<7>(tsum, a.sc.part_prev, a.sc.nprod, it == 1 ? 7 : 5);
   int64_t u = ulo + lb;
   if (u < uhi) begin_unit(u);
-  const PcgSlot sl = fused ? pcg_scalar_phase(a.sc, prev, tsum) : prev;
+  const PcgSlot sl = fused ? pcg_scalar_phase(a.sc, prev, tsum, vb) : prev;
   if (sl.status == kPcgDone) return;
   const TR al = (TR)sl.alpha, be = (TR)sl.beta;
   if (sl.status == kPcgFinish) {  // last update x += a p of the previous iteration (pointwise)
     TR* __restrict__ x = static_cast<TR*>(a.x);
     const TR* __restrict__ pi = static_cast<const TR*>(a.p_in);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.nnode; i += stride)
+    const int64_t stride = (int64_t)vb.n * blockDim.x;
+    for (int64_t i = (int64_t)vb.id * blockDim.x + threadIdx.x; i < g.nnode; i += stride)
       x[i] = x[i] + al * pi[i];
     return;
   }
@@ -458,7 +466,29 @@ __global__ __launch_bounds__(BLK) void k_pcg_step(PcgArgs a, MarchGeo m) {
     }
     __syncthreads();  // the next unit reuses the LDS buffers
   }
-  store_partials_cm<7>(acc, a.part);
+  store_partials_cm<7>(acc, a.part, vb.id);
+}
+
+template <typename TR, int ROLE, int BLK, int NPT, int HMAX>
+__global__ __launch_bounds__(BLK) void k_pcg_step(PcgArgs a, MarchGeo m) {
+  pcg_step_body<TR, ROLE, BLK, NPT, HMAX>(a, m, hw_block());
+}
+
+// One launch over several volumes (their PE axes may differ: the march role is per volume).
+template <typename TR, int BLK, int NPT, int HMAX>
+__global__ __launch_bounds__(BLK) void k_pcg_step_batch(const PcgArgs* __restrict__ tab,
+                                                        const MarchGeo* __restrict__ geo,
+                                                        const uint32_t* __restrict__ starts,
+                                                        int n) {
+  VBlock vb;
+  const int p = batch_volume(starts, n, vb);
+  const MarchGeo m = geo[p];
+  if (m.role == 0)
+    pcg_step_body<TR, 0, BLK, NPT, HMAX>(tab[p], m, vb);
+  else if (m.role == 1)
+    pcg_step_body<TR, 1, BLK, NPT, HMAX>(tab[p], m, vb);
+  else
+    pcg_step_body<TR, 2, BLK, NPT, HMAX>(tab[p], m, vb);
 }
 
 Launch plan_hvp(const Geom& g, DType real) {
@@ -473,6 +503,20 @@ Launch plan_hvp(const Geom& g, DType real) {
 PcgPlan plan_pcg(const Geom& g, DType real) {
   PcgPlan L{};
   const int nb = march_geo(g, 1, 1).nb;
+  if (batch_plans()) {
+    // shared launches: one tile shape for every volume (the batch entry point checks nb <= 256),
+    // a march of 8 planes (the batch supplies the parallelism), every share whole XCD rounds
+    L.block = 256;
+    L.npt = 1;
+    L.hmax = 2;
+    L.m = march_geo(g, 256, 8);
+    int64_t grid = L.m.units < kMaxGrid ? L.m.units : kMaxGrid;
+    grid = (grid + 7) / 8 * 8;
+    L.grid = (unsigned)(grid > kMaxGrid ? kMaxGrid : grid);
+    L.lds = 2 * (size_t)(256 + 2 * nb) * (real == DType::F64 ? 8 : 4);
+    L.fused = 1;
+    return L;
+  }
   if (real == DType::F64) {
     L.block = 2 * nb <= 512 ? 256 : 512;
     L.npt = 1;
@@ -508,6 +552,8 @@ PcgPlan plan_pcg(const Geom& g, DType real) {
 }
 
 hipError_t launch_hvp(const HvpArgs& a, DType real, hipStream_t s) {
+  if (active_recorder())
+    return record_other([a, real](hipStream_t s2) { return launch_hvp(a, real, s2); });
   const Launch L = plan_hvp(a.g, real);
   if (real == DType::F64)
     RGP_LAUNCH(kKindHvp, a.g, (k_hvp<double, kRun, 256>), L.grid, 256, 0, s, a);
@@ -519,6 +565,10 @@ hipError_t launch_hvp(const HvpArgs& a, DType real, hipStream_t s) {
 }
 
 hipError_t launch_sum_final(const double* part, unsigned nprod, double* out, hipStream_t s) {
+  if (active_recorder())
+    return record_other([part, nprod, out](hipStream_t s2) {
+      return launch_sum_final(part, nprod, out, s2);
+    });
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kReduceBlock), 0, s, part, nprod, out);
   return hipGetLastError();
 }
@@ -539,6 +589,9 @@ static void launch_step_cfg(const PcgArgs& a, const PcgPlan& L, hipStream_t s) {
 
 hipError_t launch_pcg_step(const PcgArgs& a, DType real, hipStream_t s) {
   const PcgPlan L = plan_pcg(a.g, real);
+  if (active_recorder())
+    return record_launch(RecKind::kPcgStep, a, L.grid, L.block, L.lds, (int)real, L.npt, L.hmax,
+                         [a, real](hipStream_t s2) { return launch_pcg_step(a, real, s2); }, &L.m);
   if (2 * L.m.nb > L.hmax * (int)L.block) return hipErrorInvalidValue;
   if (real == DType::F64) {
     if (L.block == 256)
@@ -563,7 +616,32 @@ hipError_t launch_pcg_step(const PcgArgs& a, DType real, hipStream_t s) {
 }
 
 hipError_t launch_pcg_scalars(const PcgScalarArgs& a, hipStream_t s) {
+  if (active_recorder())
+    return record_launch(RecKind::kPcgScalars, a, 1, kReduceBlock, 0, 0, 0, 0,
+                         [a](hipStream_t s2) { return launch_pcg_scalars(a, s2); });
   hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kReduceBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---- shared launches over several volumes -----------------------------------------------------
+
+hipError_t launch_pcg_scalars_batch(const void* tab, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_scalars_batch, dim3(n), dim3(kReduceBlock), 0, s,
+                     static_cast<const PcgScalarArgs*>(tab));
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_step_batch(const void* tab, const MarchGeo* geo, const uint32_t* starts,
+                                 int n, unsigned grid, size_t lds, DType real, hipStream_t s) {
+  const PcgArgs* t = static_cast<const PcgArgs*>(tab);
+  if (real == DType::F64)
+    hipLaunchKernelGGL((k_pcg_step_batch<double, 256, 1, 2>), dim3(grid), dim3(256), lds, s, t,
+                       geo, starts, n);
+  else if (real == DType::F32)
+    hipLaunchKernelGGL((k_pcg_step_batch<float, 256, 1, 2>), dim3(grid), dim3(256), lds, s, t,
+                       geo, starts, n);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

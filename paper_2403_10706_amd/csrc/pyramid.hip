@@ -7,6 +7,7 @@
 // to the outer coarse centres (constant extrapolation).  b keeps its physical units.
 #include "rgp_internal.hpp"
 #include "rgp_launch.hpp"
+#include "batch.hpp"
 
 namespace rgp {
 
@@ -125,6 +126,8 @@ __global__ void k_stats_header(double* stats, const State* st, const unsigned lo
 }
 
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
+  if (active_recorder())
+    return record_other([p, n, v](hipStream_t s2) { return launch_fill(p, n, v, s2); });
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
   if (nb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill, dim3(nb), dim3(kBlock), 0, s, p, n, v);
@@ -133,11 +136,17 @@ hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
 
 hipError_t launch_stats_header(double* stats, const State* st, const unsigned long long* guarded,
                                hipStream_t s) {
+  if (active_recorder())
+    return record_other([stats, st, guarded](hipStream_t s2) {
+      return launch_stats_header(stats, st, guarded, s2);
+    });
   hipLaunchKernelGGL(k_stats_header, dim3(1), dim3(64), 0, s, stats, st, guarded);
   return hipGetLastError();
 }
 
 hipError_t launch_restrict(const RestrictArgs& a, DType src, DType dst, hipStream_t s) {
+  if (active_recorder())
+    return record_other([a, src, dst](hipStream_t s2) { return launch_restrict(a, src, dst, s2); });
   const int64_t n = (int64_t)a.mc[0] * a.mc[1] * a.mc[2];
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
   if (nb == 0) return hipSuccess;
@@ -153,6 +162,8 @@ hipError_t launch_restrict(const RestrictArgs& a, DType src, DType dst, hipStrea
 }
 
 hipError_t launch_prolong(const ProlongArgs& a, DType real, hipStream_t s) {
+  if (active_recorder())
+    return record_other([a, real](hipStream_t s2) { return launch_prolong(a, real, s2); });
   int64_t n = 1;
   for (int d = 0; d < 3; ++d) n *= (int64_t)(a.mf[d] + (d == a.pe ? 1 : 0));
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
@@ -165,6 +176,7 @@ hipError_t launch_prolong(const ProlongArgs& a, DType real, hipStream_t s) {
 }
 
 hipError_t launch_reset(const SetStateArgs& a, hipStream_t s) {
+  if (active_recorder()) return record_other([a](hipStream_t s2) { return launch_reset(a, s2); });
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a);
   return hipGetLastError();
 }

@@ -101,13 +101,38 @@ struct WaveIter {
   int64_t t, end, stride;
 };
 
-__device__ __forceinline__ WaveIter wave_iter(int64_t ntiles) {
-  const unsigned G = gridDim.x, wpb = blockDim.x / 64u, w = threadIdx.x / 64u;
-  unsigned nxcd = 1, xcd = 0, lb = blockIdx.x, gl = G;
+// A workgroup's place in the grid of its volume: the hardware block in a plain launch, or its
+// place within one volume's share of a batched launch (each share is a whole number of XCD rounds,
+// so id % 8 is still the hardware XCD).
+struct VBlock {
+  unsigned id, n;
+};
+__device__ __forceinline__ VBlock hw_block() { return VBlock{blockIdx.x, gridDim.x}; }
+
+// Volume of the calling workgroup in a batched launch over n volumes whose shares start at
+// starts[0..n] (starts[n] = grid): the largest p with starts[p] <= blockIdx.x.
+__device__ __forceinline__ int batch_volume(const uint32_t* __restrict__ starts, int n,
+                                            VBlock& vb) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (starts[mid] <= blockIdx.x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  vb.id = blockIdx.x - starts[lo];
+  vb.n = starts[lo + 1] - starts[lo];
+  return lo;
+}
+
+__device__ __forceinline__ WaveIter wave_iter(int64_t ntiles, VBlock vb) {
+  const unsigned G = vb.n, wpb = blockDim.x / 64u, w = threadIdx.x / 64u;
+  unsigned nxcd = 1, xcd = 0, lb = vb.id, gl = G;
   if (G >= 8u && G % 8u == 0u) {
     nxcd = 8u;
-    xcd = blockIdx.x % 8u;
-    lb = blockIdx.x / 8u;
+    xcd = vb.id % 8u;
+    lb = vb.id / 8u;
     gl = G / 8u;
   }
   WaveIter it;
@@ -153,13 +178,13 @@ __device__ __forceinline__ void block_sum(double (&v)[K]) {
   __syncthreads();
 }
 
-// Block sums of v stored at part[blockIdx.x * kPartStride + k].
+// Block sums of v stored at part[blk * kPartStride + k] (blk: the block's VBlock id).
 template <int K>
-__device__ __forceinline__ void store_partials(double (&v)[K], double* part) {
+__device__ __forceinline__ void store_partials(double (&v)[K], double* part, unsigned blk) {
   block_sum<K>(v);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) part[(size_t)blockIdx.x * kPartStride + k] = v[k];
+    for (int k = 0; k < K; ++k) part[(size_t)blk * kPartStride + k] = v[k];
   }
 }
 
@@ -264,11 +289,11 @@ __host__ __device__ inline MarchGeo march_geo(const Geom& g, int T, int XL) {
 // Column-major variant for consumers that reduce in every block: sum k of block b is stored at
 // part[k * kMaxGrid + b], so the consumer's loads of one sum over all blocks are coalesced.
 template <int K>
-__device__ __forceinline__ void store_partials_cm(double (&v)[K], double* part) {
+__device__ __forceinline__ void store_partials_cm(double (&v)[K], double* part, unsigned blk) {
   block_sum<K>(v);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) part[(size_t)k * kMaxGrid + blockIdx.x] = v[k];
+    for (int k = 0; k < K; ++k) part[(size_t)k * kMaxGrid + blk] = v[k];
   }
 }
 

@@ -55,7 +55,8 @@ class SolverOpts(ctypes.Structure):
 EXPORTS = ("rgp_status_string", "rgp_last_hip_error", "rgp_default_opts", "rgp_workspace_size",
            "rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
            "rgp_apply_correction", "rgp_correct", "rgp_correct_plan", "rgp_plan_launch",
-           "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop", "rgp_loss_grad_images")
+           "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop", "rgp_loss_grad_images",
+           "rgp_batch_workspace_size", "rgp_correct_batch_plan")
 
 # rgp_kernel_kind
 KERNEL_PCG_STEP, KERNEL_LOSS_GRAD, KERNEL_TRIAL, KERNEL_HVP, KERNEL_OT, KERNEL_SHIFT = range(6)
@@ -103,11 +104,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rgp_plan_destroy.argtypes = [vp]
     lib.rgp_timing_start.argtypes = [i32]
     lib.rgp_loss_grad_images.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp, vp]
+    lib.rgp_batch_workspace_size.argtypes = [i32, gp, ctypes.c_int, op, ctypes.POINTER(sz)]
+    lib.rgp_correct_batch_plan.argtypes = [i32, gp, ctypes.c_int, vp, vp, ctypes.c_int, op, vp, vp,
+                                           vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_void_p)]
     lib.rgp_timing_stop.argtypes = [ctypes.POINTER(TimingRecord), i32, ctypes.POINTER(i32)]
     for name in ("rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
                  "rgp_apply_correction", "rgp_correct", "rgp_workspace_size", "rgp_correct_plan",
                  "rgp_plan_launch", "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop",
-                 "rgp_loss_grad_images"):
+                 "rgp_loss_grad_images", "rgp_batch_workspace_size", "rgp_correct_batch_plan"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -425,6 +429,79 @@ class Plan:
             ctypes.byref(self._grid), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
             dtype_code(b_out.dtype), ctypes.byref(self._opts), _ptr(b_init), _ptr(b_out),
             _ptr(T_plus), _ptr(T_minus), _ptr(stats), _ptr(ws), ws.numel(),
+            _stream_ptr(stream), ctypes.byref(self._handle)))
+
+    def launch(self, stream=None):
+        _check("rgp_plan_launch", load().rgp_plan_launch(self._handle,
+                                                         _stream_ptr(stream or self.stream)))
+
+    def close(self):
+        if self._handle:
+            _check("rgp_plan_destroy", load().rgp_plan_destroy(self._handle))
+            self._handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr_array(ts):
+    if ts is None:
+        return None
+    arr = (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+    return ctypes.cast(arr, ctypes.c_void_p), arr
+
+
+def batch_workspace_size(shapes, pes, real_dtype, opts: "Options", hs=None) -> int:
+    n = len(shapes)
+    hs = hs or [(1.0, 1.0, 1.0)] * n
+    grids = (Grid * n)(*[make_grid(tuple(sh), pe, h) for sh, pe, h in zip(shapes, pes, hs)])
+    c = opts.to_c()
+    out = ctypes.c_size_t(0)
+    _check("rgp_batch_workspace_size", load().rgp_batch_workspace_size(
+        n, grids, dtype_code(real_dtype), ctypes.byref(c), ctypes.byref(out)))
+    return out.value
+
+
+class BatchPlan:
+    """n pairs of their own shapes and PE axes corrected by one captured graph in which every
+    Gauss-Newton kernel is one launch over all pairs (rgp_correct_batch_plan).  Allocates the
+    outputs (b, and the corrected images when want_images) and the workspace; `launch` replays."""
+
+    def __init__(self, I_plus, I_minus, pes, opts: "Options", *, hs=None,
+                 real_dtype=torch.float32, want_images=True, want_stats=False, stream):
+        n = len(I_plus)
+        assert len(I_minus) == n and len(pes) == n and n >= 1
+        _dev_check(*I_plus, *I_minus)
+        dev = I_plus[0].device
+        hs = hs or [(1.0, 1.0, 1.0)] * n
+        shapes = [tuple(t.shape) for t in I_plus]
+        self.n = n
+        self.pes = list(pes)
+        self._grids = (Grid * n)(*[make_grid(sh, pe, h) for sh, pe, h in zip(shapes, pes, hs)])
+        self._opts = opts.to_c()
+        nbytes = batch_workspace_size(shapes, pes, real_dtype, opts, hs)
+        self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+        self.b = [torch.empty(field_shape(sh, pe), dtype=real_dtype, device=dev)
+                  for sh, pe in zip(shapes, pes)]
+        self.T_plus = [torch.empty_like(t) for t in I_plus] if want_images else None
+        self.T_minus = [torch.empty_like(t) for t in I_minus] if want_images else None
+        self.stats = ([torch.empty(STAT_HEADER + opts.levels * opts.gn_iters * STAT_FIELDS,
+                                   dtype=torch.float64, device=dev) for _ in range(n)]
+                      if want_stats else None)
+        self._keep = (list(I_plus), list(I_minus))
+        arrs = [_ptr_array(x) for x in (I_plus, I_minus, self.b, self.T_plus, self.T_minus,
+                                        self.stats)]
+        self._arrs = arrs
+        vp = [a[0] if a is not None else None for a in arrs]
+        self.stream = stream
+        self._handle = ctypes.c_void_p(None)
+        torch.cuda.synchronize()
+        _check("rgp_correct_batch_plan", load().rgp_correct_batch_plan(
+            n, self._grids, dtype_code(I_plus[0].dtype), vp[0], vp[1], dtype_code(real_dtype),
+            ctypes.byref(self._opts), vp[2], vp[3], vp[4], vp[5], _ptr(self.ws), self.ws.numel(),
             _stream_ptr(stream), ctypes.byref(self._handle)))
 
     def launch(self, stream=None):

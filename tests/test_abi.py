@@ -126,3 +126,24 @@ def test_entry_points_reject_bad_arguments_without_device(lib):
     o.ls_max_trials = 10
     assert lib.rgp_correct(ctypes.byref(g), rgp.F32, fake, fake, rgp.F32, ctypes.byref(o), None,
                            fake, None, None, None, ctypes.c_void_p(0x1004), 1 << 30, None) == -8
+
+
+def test_batch_workspace_size_and_limits(lib):
+    from paper_2403_10706_amd import rgp
+    opts = rgp.Options(levels=2, gn_iters=2, pcg_iters=3)
+    shapes = [(20, 24, 16), (18, 30, 22), (26, 17, 19)]
+    pes = [1, 0, 1]
+    n_all = rgp.batch_workspace_size(shapes, pes, __import__("torch").float32, opts)
+    single = 0
+    for sh, pe in zip(shapes, pes):
+        single += rgp.workspace_size(rgp.OP_CORRECT, sh, pe, (1.0, 1.0, 1.0),
+                                     __import__("torch").float32, opts.to_c())
+    assert n_all > single                      # every pair's workspace plus the launch tables
+    n = ctypes.c_size_t(0)
+    g = (rgp.Grid * 1)(rgp.make_grid((16, 16, 300), 1))   # contiguous axis above 256 nodes
+    c = opts.to_c()
+    assert lib.rgp_batch_workspace_size(1, g, rgp.F32, ctypes.byref(c), ctypes.byref(n)) == -2
+    assert lib.rgp_batch_workspace_size(0, g, rgp.F32, ctypes.byref(c), ctypes.byref(n)) == -1
+    c.use_b_init = 1
+    g = (rgp.Grid * 1)(rgp.make_grid((16, 16, 20), 1))
+    assert lib.rgp_batch_workspace_size(1, g, rgp.F32, ctypes.byref(c), ctypes.byref(n)) == -1
