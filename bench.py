@@ -18,6 +18,8 @@ Other modes (profiling helpers; their output goes under profiles/):
   --traffic-summary F W       HBM traffic of the finest-level PCG step from the two --pmc runs
                               (directories F and W), scaled by the copy kernel's counters
   --profile-summary D         text summary of a rocprofv3 --kernel-trace --stats run in D
+  --batch N                   the batching benchmark: N uneven pairs, plain per-pair graphs
+                              against one batched graph (its own JSON line)
 """
 import argparse
 import csv
@@ -320,6 +322,88 @@ def profile_summary(d):
 
 
 # ---------------------------------------------------------------------------------------------
+# batching: the uneven batch of pairs, plain per-pair graphs against one batched graph
+
+def batch_bench(n, steps, scale):
+    """n synthetic pairs of uneven sizes (dims 96..200 x 96..200 x 60..132), PE along dim 0 or 1,
+    BF16 images, FP32 field, 3 levels x 10 GN x 20 PCG.  Plain: one captured graph per pair
+    (rgp_correct_plan) replayed pair after pair on one stream; batched: one captured graph for
+    all pairs (rgp_correct_batch_plan).  Both use the same images; the final fields are compared
+    with each other and with the true fields the pairs were synthesised from."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2403_10706_amd import rgp
+
+    rgp.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"bench --batch: generating {n} uneven pairs")
+    pairs = synth.make_batch(n, scale=scale)
+    bf = torch.bfloat16
+    Ip = [torch.as_tensor(p.I_plus).to(dev, bf).contiguous() for p in pairs]
+    Im = [torch.as_tensor(p.I_minus).to(dev, bf).contiguous() for p in pairs]
+    pes = [p.pe for p in pairs]
+    opts = rgp.Options(levels=LEVELS, gn_iters=GN_ITERS, pcg_iters=PCG_ITERS, pcg_rtol=0.0)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(side)
+    # plain: one graph per pair, one shared workspace (the pairs run one after another)
+    wsz = max(rgp.workspace_size(rgp.OP_CORRECT, tuple(p.shape), p.pe, (1.0, 1.0, 1.0),
+                                 torch.float32, opts.to_c()) for p in pairs)
+    ws = torch.zeros(wsz, dtype=torch.uint8, device=dev)
+    bp_out = [torch.empty(rgp.field_shape(tuple(p.shape), p.pe), dtype=torch.float32,
+                          device=dev) for p in pairs]
+    Tp = [torch.empty_like(t) for t in Ip]
+    Tm = [torch.empty_like(t) for t in Im]
+    plans = [rgp.Plan(Ip[i], Im[i], pes[i], opts, bp_out[i], Tp[i], Tm[i], ws, stream=side)
+             for i in range(n)]
+    batch = rgp.BatchPlan(Ip, Im, pes, opts, stream=side)
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    def plain():
+        for pl in plans:
+            pl.launch(side)
+
+    plain()
+    batch.launch(side)
+    t_plain = timed(plain, steps)
+    t_batch = timed(lambda: batch.launch(side), steps)
+    d_bp, e_plain, e_batch = [], [], []
+    for i, p in enumerate(pairs):
+        bb = batch.b[i].double().cpu().numpy()
+        bq = bp_out[i].double().cpu().numpy()
+        d_bp.append(float(np.max(np.abs(bb - bq))))
+        e_plain.append(float(np.sqrt(np.mean((bq - p.b_true) ** 2))))
+        e_batch.append(float(np.sqrt(np.mean((bb - p.b_true) ** 2))))
+    for pl in plans:
+        pl.close()
+    batch.close()
+    cells = int(sum(np.prod(p.shape) for p in pairs))
+    line = dict(metric=f"pairs corrected/s, {n} uneven pairs (BF16 images, FP32 field)",
+                unit="pairs/s", batched=round(n / t_batch, 3), plain=round(n / t_plain, 3),
+                speedup=round(t_plain / t_batch, 3), ms_batched=round(1e3 * t_batch, 3),
+                ms_plain=round(1e3 * t_plain, 3), steps=steps, cells=cells, image_scale=scale,
+                max_abs_b_batched_vs_plain=max(d_bp),
+                rms_error_vs_true_plain=round(float(np.mean(e_plain)), 6),
+                rms_error_vs_true_batched=round(float(np.mean(e_batch)), 6),
+                config=dict(levels=LEVELS, gn_iters=GN_ITERS, pcg_iters=PCG_ITERS,
+                            shapes=[list(p.shape) for p in pairs], pe=pes),
+                device=torch.cuda.get_device_name(0))
+    log(f"bench --batch: plain {n / t_plain:.2f} pairs/s, batched {n / t_batch:.2f} pairs/s "
+        f"(x{t_plain / t_batch:.2f}); max|b_batched - b_plain| = {max(d_bp):.2e}")
+    print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
@@ -331,6 +415,9 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--profile-summary", metavar="DIR")
+    ap.add_argument("--batch", type=int, metavar="N", default=0,
+                    help="the batching benchmark over N uneven pairs instead of the headline")
+    ap.add_argument("--batch-scale", type=float, default=1000.0)
     args = ap.parse_args()
     if args.traffic_summary:
         return traffic_summary(*args.traffic_summary)
@@ -343,6 +430,8 @@ def main():
         sys.exit(2)
     if args.pmc_probe:
         return pmc_probe()
+    if args.batch:
+        return batch_bench(args.batch, max(1, args.steps // 4), args.batch_scale)
 
     import numpy as np
     import torch

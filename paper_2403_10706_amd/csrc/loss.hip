@@ -485,7 +485,7 @@ Launch plan_tiles(const Geom& g, int S, int block) {
   const int64_t wpb = block / kWave;
   int64_t grid = (L.ntiles + wpb - 1) / wpb;
   if (grid > kMaxGrid) grid = kMaxGrid;
-  if (grid > 8 || batch_plans()) grid = (grid + 7) / 8 * 8;  // whole XCD rounds (see wave_iter)
+  grid = (grid + 7) / 8 * 8;  // whole XCD rounds (see wave_iter); spare blocks add zero sums
   if (grid > kMaxGrid) grid = kMaxGrid;
   L.grid = (unsigned)(grid < 1 ? 1 : grid);
   return L;

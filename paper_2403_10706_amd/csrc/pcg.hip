@@ -495,42 +495,19 @@ Launch plan_hvp(const Geom& g, DType real) {
   return plan_tiles(g, kRun, (real == DType::F32 && plan_tiles(g, kRun, 256).ntiles > 1024) ? 1024 : 256);
 }
 
-// PCG launch shape.  256-thread blocks with one plane position per thread (two above 4 M nodes);
-// 512-thread blocks when the contiguous axis is longer than 256 nodes, so that the two halo rows
-// fit in two slots per thread.  XL is the shortest march that keeps every unit resident at once
-// (at most 16 wavefronts per CU over 256 CUs): the halo planes cost less than a second wave of
-// workgroups (measured on 144x168x111 and 200x200x132).
+// PCG launch shape: one plane position per thread; 256-thread workgroups, 512 when the
+// contiguous axis is longer than 256 nodes, so that its two halo rows fit in at most two slots
+// per thread.  XL is the shortest march that keeps every unit resident at once (at most 16
+// wavefronts per CU over 256 CUs): the halo planes cost less than a second wave of workgroups
+// (measured on 144x168x111 and 200x200x132).  Batched launches use the same shapes (so a batched
+// pair computes exactly what it computes alone) with two halo slots for every pair.
 PcgPlan plan_pcg(const Geom& g, DType real) {
   PcgPlan L{};
   const int nb = march_geo(g, 1, 1).nb;
-  if (batch_plans()) {
-    // shared launches: one tile shape for every volume (the batch entry point checks nb <= 256),
-    // a march of 8 planes (the batch supplies the parallelism), every share whole XCD rounds
-    L.block = 256;
-    L.npt = 1;
-    L.hmax = 2;
-    L.m = march_geo(g, 256, 8);
-    int64_t grid = L.m.units < kMaxGrid ? L.m.units : kMaxGrid;
-    grid = (grid + 7) / 8 * 8;
-    L.grid = (unsigned)(grid > kMaxGrid ? kMaxGrid : grid);
-    L.lds = 2 * (size_t)(256 + 2 * nb) * (real == DType::F64 ? 8 : 4);
-    L.fused = 1;
-    return L;
-  }
-  if (real == DType::F64) {
-    L.block = 2 * nb <= 512 ? 256 : 512;
-    L.npt = 1;
-    L.hmax = 2;
-  } else if (2 * nb <= 512) {
-    L.block = 256;
-    L.npt = g.nnode > (int64_t(4) << 20) ? 2 : 1;
-    L.hmax = 2 * nb <= 256 ? 1 : 2;
-  } else {
-    L.block = 512;
-    L.npt = 1;
-    L.hmax = 2;
-  }
-  const int T = (int)L.block * L.npt;
+  L.block = 2 * nb <= 512 ? 256 : 512;
+  L.npt = 1;
+  L.hmax = (2 * nb <= (int)L.block && !batch_plans()) ? 1 : 2;
+  const int T = (int)L.block;
   static const int kXL[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
   const int64_t max_units = 4096 / ((int64_t)L.block / kWave);
   MarchGeo m = march_geo(g, T, 64);
@@ -543,9 +520,9 @@ PcgPlan plan_pcg(const Geom& g, DType real) {
   }
   L.m = m;
   int64_t grid = m.units < kMaxGrid ? m.units : kMaxGrid;
-  if (grid > 8) grid = (grid + 7) / 8 * 8;
+  grid = (grid + 7) / 8 * 8;  // whole XCD rounds
   if (grid > kMaxGrid) grid = kMaxGrid;
-  L.grid = (unsigned)(grid < 1 ? 1 : grid);
+  L.grid = (unsigned)grid;
   L.lds = 2 * (size_t)(T + 2 * nb) * (real == DType::F64 ? 8 : 4);
   L.fused = 1;
   return L;
@@ -593,24 +570,23 @@ hipError_t launch_pcg_step(const PcgArgs& a, DType real, hipStream_t s) {
     return record_launch(RecKind::kPcgStep, a, L.grid, L.block, L.lds, (int)real, L.npt, L.hmax,
                          [a, real](hipStream_t s2) { return launch_pcg_step(a, real, s2); }, &L.m);
   if (2 * L.m.nb > L.hmax * (int)L.block) return hipErrorInvalidValue;
-  if (real == DType::F64) {
-    if (L.block == 256)
+  if (real != DType::F64 && real != DType::F32) return hipErrorInvalidValue;
+  const bool f64 = real == DType::F64;
+  if (L.block == 512) {
+    if (f64)
+      launch_step_cfg<double, 512, 1, 2>(a, L, s);
+    else
+      launch_step_cfg<float, 512, 1, 2>(a, L, s);
+  } else if (L.hmax == 1) {
+    if (f64)
+      launch_step_cfg<double, 256, 1, 1>(a, L, s);
+    else
+      launch_step_cfg<float, 256, 1, 1>(a, L, s);
+  } else {
+    if (f64)
       launch_step_cfg<double, 256, 1, 2>(a, L, s);
     else
-      launch_step_cfg<double, 512, 1, 2>(a, L, s);
-  } else if (real == DType::F32) {
-    if (L.block == 512)
-      launch_step_cfg<float, 512, 1, 2>(a, L, s);
-    else if (L.npt == 1 && L.hmax == 1)
-      launch_step_cfg<float, 256, 1, 1>(a, L, s);
-    else if (L.npt == 1)
       launch_step_cfg<float, 256, 1, 2>(a, L, s);
-    else if (L.hmax == 1)
-      launch_step_cfg<float, 256, 2, 1>(a, L, s);
-    else
-      launch_step_cfg<float, 256, 2, 2>(a, L, s);
-  } else {
-    return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
