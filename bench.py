@@ -357,6 +357,8 @@ def batch_bench(n, steps, scale):
                           device=dev) for p in pairs]
     Tp = [torch.empty_like(t) for t in Ip]
     Tm = [torch.empty_like(t) for t in Im]
+    for i in range(n):
+        rgp.autotune(tuple(pairs[i].shape), pes[i], torch.float32, opts, ws=ws, stream=side)
     plans = [rgp.Plan(Ip[i], Im[i], pes[i], opts, bp_out[i], Tp[i], Tm[i], ws, stream=side)
              for i in range(n)]
     batch = rgp.BatchPlan(Ip, Im, pes, opts, stream=side)
@@ -459,10 +461,13 @@ def main():
     Tm = torch.empty_like(Im)
 
     # The whole correction is captured once into a HIP graph (rgp_correct_plan) on a side
-    # stream of default priority; one step = one replay.
+    # stream of default priority; one step = one replay.  The PCG march of every level is tuned
+    # first (rgp_autotune, part of the setup like the capture).
     side = torch.cuda.Stream()
     torch.cuda.synchronize()
     torch.cuda.set_stream(side)   # every library call below is enqueued on `side`
+    tuned_xl = rgp.autotune(shape, pe, dt, opts, ws=ws, stream=side)
+    log(f"bench: tuned PCG march lengths per level (finest first): {tuned_xl}")
     plan = rgp.Plan(Ip, Im, pe, opts, b, Tp, Tm, ws, stream=side)
 
     def eager():
@@ -553,7 +558,7 @@ def main():
         config=dict(workload="3T-brain-shaped pair 144x168x111, PE dim 1, FP32 images and field, "
                     "3 levels x 10 GN x 20 PCG (rtol 0), OT init, Armijo",
                     shape=list(shape), pe_dim=pe, levels=LEVELS, gn_iters=GN_ITERS,
-                    pcg_iters=PCG_ITERS, global_batch=1),
+                    pcg_iters=PCG_ITERS, global_batch=1, pcg_march_lengths=tuned_xl),
         gpu_ms_per_step=round(gpu_ms / args.steps, 4), eager_ms_per_step=round(eager_ms, 4),
         roofline=roofline, kernels=kernels, cpu_baseline=cpu,
         device=torch.cuda.get_device_name(0),

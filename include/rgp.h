@@ -211,6 +211,17 @@ rgp_status rgp_correct_batch_plan(int32_t n, const rgp_grid* grids, rgp_dtype im
                                   double* const* stats_dev, void* ws, size_t ws_bytes,
                                   void* stream, rgp_plan* plan);
 
+/* Autotuner of the PCG tile shape (batching extension): for every pyramid level of `grid` under
+ * `opts` (one level when opts is NULL) it times the candidate march lengths of the PCG step - a
+ * work unit is 256 consecutive positions of the contiguous node plane times XL planes - on the
+ * workspace's own vectors (a correction workspace; their contents are overwritten, the parts the
+ * library relies on are left as rgp_correct needs them) and records the fastest in a
+ * process-wide table that every later plain or batched launch on that geometry and field type
+ * uses.  Synchronises `stream`; RGP_EINVAL while the stream is being captured.  xl_out: host
+ * array of opts->levels int32 (nullable) receiving the chosen XL per level, finest first. */
+rgp_status rgp_autotune(const rgp_grid* grid, rgp_dtype real_t, const rgp_solver_opts* opts,
+                        void* ws, size_t ws_bytes, void* stream, int32_t* xl_out);
+
 /* Kernel timing (instrumentation; not part of the method).  rgp_timing_start(capacity) creates
  * `capacity` pairs of HIP events (host API objects, no device memory) and from then on every
  * launch of a hot kernel that is not being captured into a graph records one pair at the start

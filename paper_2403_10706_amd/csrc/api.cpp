@@ -1157,3 +1157,93 @@ rgp_status rgp_correct_batch_plan(int32_t n, const rgp_grid* grids, rgp_dtype im
   *plan = pl;
   return RGP_OK;
 }
+
+// ---- autotuner of the PCG march ----------------------------------------------------------
+
+rgp_status rgp_autotune(const rgp_grid* grid, rgp_dtype real_t, const rgp_solver_opts* opts,
+                        void* ws, size_t ws_bytes, void* stream, int32_t* xl_out) {
+  rgp_status st = check_grid(grid);
+  if (st != RGP_OK) return st;
+  DType dr;
+  if (!dtype_of(real_t, &dr) || dr == DType::BF16) return RGP_EDTYPE;
+  rgp_solver_opts o;
+  rgp_default_opts(&o);
+  if (opts) o = *opts;
+  if (!opts) o.levels = 1;
+  if ((st = check_opts(&o)) != RGP_OK) return st;
+  if ((st = need_ws(RGP_OP_CORRECT, grid, real_t, &o, ws, ws_bytes)) != RGP_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  RGP_HIP(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) return RGP_EINVAL;  // timing needs eager launches
+  Level lv[kMaxLevels];
+  if (make_levels(grid, o.levels, lv) != 0) return RGP_ESHAPE;
+  const CorrectWs w = carve_correct(ws, lv, o.levels, dr);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  RGP_HIP(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  for (int l = 0; l < o.levels && e == hipSuccess; ++l) {
+    const Geom& g = lv[l].g;
+    // a running PCG state: both slots and the previous block sums set to ones
+    e = launch_fill(reinterpret_cast<double*>(w.ctl.slots), 2 * sizeof(PcgSlot) / sizeof(double),
+                    1.0, s);
+    if (e == hipSuccess)
+      e = launch_fill(w.ctl.slot(kPartPcg0), 2 * (int64_t)kMaxGrid * kPartStride, 1.0, s);
+    const PcgPlan H = plan_pcg_xl(g, dr, -1);  // the untuned choice
+    set_tuned_march(g, dr, 0);
+    const int64_t cap = 4096 / ((int64_t)H.block / kWave);
+    int best_xl = H.m.XL;
+    float best_ms = 1e30f;
+    for (int xl : kMarchLengths) {
+      if (e != hipSuccess) break;
+      const PcgPlan L = plan_pcg_xl(g, dr, xl);
+      if (xl > L.m.no || L.m.units > 4 * cap || (L.m.units < cap / 16 && xl != H.m.XL)) continue;
+      PcgArgs pa{};
+      pa.g = g;
+      pa.diag = w.Dg;
+      pa.off = w.Of;
+      pa.rhs = w.G;
+      pa.rhs_sign = -1.0;
+      pa.x = w.X;
+      pa.r_in = w.R[1];
+      pa.p_in = w.P[1];
+      pa.w_in = w.W[1];
+      pa.r_out = w.R[0];
+      pa.p_out = w.P[0];
+      pa.w_out = w.W[0];
+      pa.alpha = o.alpha;
+      pa.part = w.ctl.slot(kPartPcg0);
+      pa.sc.st = w.ctl.st;
+      pa.sc.slots = w.ctl.slots;
+      pa.sc.part_prev = w.ctl.slot(kPartPcg1);
+      pa.sc.nprod = L.grid;
+      pa.sc.iter = 2;              // reads slot 1 and the sums above, writes slot 0
+      pa.sc.maxit = 1 << 30;
+      pa.sc.rtol = 0.0;
+      pa.sc.fused = 1;
+      constexpr int kReps = 8;
+      for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_pcg_step_plan(pa, dr, L, s);
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int r = 0; r < kReps && e == hipSuccess; ++r) e = launch_pcg_step_plan(pa, dr, L, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && ms < best_ms) {
+        best_ms = ms;
+        best_xl = xl;
+      }
+    }
+    if (e == hipSuccess) {
+      set_tuned_march(g, dr, best_xl);
+      if (xl_out) xl_out[l] = best_xl;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    return RGP_EHIP;
+  }
+  return RGP_OK;
+}

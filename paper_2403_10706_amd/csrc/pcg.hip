@@ -19,6 +19,10 @@
 #include "rgp_solver.hpp"
 #include "batch.hpp"
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace rgp {
 
 namespace {
@@ -501,21 +505,52 @@ Launch plan_hvp(const Geom& g, DType real) {
 // wavefronts per CU over 256 CUs): the halo planes cost less than a second wave of workgroups
 // (measured on 144x168x111 and 200x200x132).  Batched launches use the same shapes (so a batched
 // pair computes exactly what it computes alone) with two halo slots for every pair.
-PcgPlan plan_pcg(const Geom& g, DType real) {
+// Marches chosen by the autotuner (rgp_autotune), per volume geometry and field type.
+namespace {
+struct TuneKey {
+  int32_t mp, nx, ny, pe, real;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(mp, nx, ny, pe, real) < std::tie(o.mp, o.nx, o.ny, o.pe, o.real);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned_xl;
+TuneKey tune_key(const Geom& g, DType real) { return TuneKey{g.mp, g.nx, g.ny, g.pe, (int)real}; }
+}  // namespace
+
+void set_tuned_march(const Geom& g, DType real, int xl) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (xl > 0)
+    g_tuned_xl[tune_key(g, real)] = xl;
+  else
+    g_tuned_xl.erase(tune_key(g, real));
+}
+
+int tuned_march(const Geom& g, DType real) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const auto it = g_tuned_xl.find(tune_key(g, real));
+  return it == g_tuned_xl.end() ? 0 : it->second;
+}
+
+PcgPlan plan_pcg_xl(const Geom& g, DType real, int xl_force) {
   PcgPlan L{};
   const int nb = march_geo(g, 1, 1).nb;
   L.block = 2 * nb <= 512 ? 256 : 512;
   L.npt = 1;
   L.hmax = (2 * nb <= (int)L.block && !batch_plans()) ? 1 : 2;
   const int T = (int)L.block;
-  static const int kXL[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
-  const int64_t max_units = 4096 / ((int64_t)L.block / kWave);
   MarchGeo m = march_geo(g, T, 64);
-  for (int xl : kXL) {
-    const MarchGeo c = march_geo(g, T, xl);
-    if (c.units <= max_units) {
-      m = c;
-      break;
+  const int xl_t = xl_force > 0 ? xl_force : tuned_march(g, real);
+  if (xl_t > 0) {
+    m = march_geo(g, T, xl_t);
+  } else {
+    const int64_t max_units = 4096 / ((int64_t)L.block / kWave);
+    for (int xl : kMarchLengths) {
+      const MarchGeo c = march_geo(g, T, xl);
+      if (c.units <= max_units) {
+        m = c;
+        break;
+      }
     }
   }
   L.m = m;
@@ -527,6 +562,8 @@ PcgPlan plan_pcg(const Geom& g, DType real) {
   L.fused = 1;
   return L;
 }
+
+PcgPlan plan_pcg(const Geom& g, DType real) { return plan_pcg_xl(g, real, 0); }
 
 hipError_t launch_hvp(const HvpArgs& a, DType real, hipStream_t s) {
   if (active_recorder())
@@ -565,7 +602,10 @@ static void launch_step_cfg(const PcgArgs& a, const PcgPlan& L, hipStream_t s) {
 }
 
 hipError_t launch_pcg_step(const PcgArgs& a, DType real, hipStream_t s) {
-  const PcgPlan L = plan_pcg(a.g, real);
+  return launch_pcg_step_plan(a, real, plan_pcg(a.g, real), s);
+}
+
+hipError_t launch_pcg_step_plan(const PcgArgs& a, DType real, const PcgPlan& L, hipStream_t s) {
   if (active_recorder())
     return record_launch(RecKind::kPcgStep, a, L.grid, L.block, L.lds, (int)real, L.npt, L.hmax,
                          [a, real](hipStream_t s2) { return launch_pcg_step(a, real, s2); }, &L.m);

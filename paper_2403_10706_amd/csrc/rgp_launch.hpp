@@ -226,6 +226,11 @@ Launch plan_tiles(const Geom& g, int S, int block);
 Launch plan_loss_grad(const Geom& g, DType real);
 Launch plan_trial(const Geom& g, DType real, int nc);
 PcgPlan plan_pcg(const Geom& g, DType real);
+// Candidate march lengths (planes per work unit) of the PCG step.
+constexpr int kMarchLengths[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+PcgPlan plan_pcg_xl(const Geom& g, DType real, int xl);  // xl <= 0: tuned or heuristic
+void set_tuned_march(const Geom& g, DType real, int xl);  // xl <= 0 forgets the entry
+int tuned_march(const Geom& g, DType real);               // 0 when not tuned
 Launch plan_hvp(const Geom& g, DType real);
 unsigned shift_grid(int64_t n);
 
@@ -271,6 +276,7 @@ hipError_t launch_image_grad(const ImageGradArgs& a, DType img, DType real, hipS
 hipError_t launch_hvp(const HvpArgs& a, DType real, hipStream_t s);
 hipError_t launch_sum_final(const double* part, unsigned nprod, double* out, hipStream_t s);
 hipError_t launch_pcg_step(const PcgArgs& a, DType real, hipStream_t s);
+hipError_t launch_pcg_step_plan(const PcgArgs& a, DType real, const PcgPlan& L, hipStream_t s);
 hipError_t launch_pcg_scalars(const PcgScalarArgs& a, hipStream_t s);
 hipError_t launch_shift(const ShiftArgs& a, DType img, hipStream_t s);
 hipError_t launch_ot(const OtArgs& a, DType img, DType real, hipStream_t s);

@@ -56,7 +56,7 @@ EXPORTS = ("rgp_status_string", "rgp_last_hip_error", "rgp_default_opts", "rgp_w
            "rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
            "rgp_apply_correction", "rgp_correct", "rgp_correct_plan", "rgp_plan_launch",
            "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop", "rgp_loss_grad_images",
-           "rgp_batch_workspace_size", "rgp_correct_batch_plan")
+           "rgp_batch_workspace_size", "rgp_correct_batch_plan", "rgp_autotune")
 
 # rgp_kernel_kind
 KERNEL_PCG_STEP, KERNEL_LOSS_GRAD, KERNEL_TRIAL, KERNEL_HVP, KERNEL_OT, KERNEL_SHIFT = range(6)
@@ -105,13 +105,15 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rgp_timing_start.argtypes = [i32]
     lib.rgp_loss_grad_images.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp, vp]
     lib.rgp_batch_workspace_size.argtypes = [i32, gp, ctypes.c_int, op, ctypes.POINTER(sz)]
+    lib.rgp_autotune.argtypes = [gp, ctypes.c_int, op, vp, sz, vp, ctypes.POINTER(i32)]
     lib.rgp_correct_batch_plan.argtypes = [i32, gp, ctypes.c_int, vp, vp, ctypes.c_int, op, vp, vp,
                                            vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_void_p)]
     lib.rgp_timing_stop.argtypes = [ctypes.POINTER(TimingRecord), i32, ctypes.POINTER(i32)]
     for name in ("rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
                  "rgp_apply_correction", "rgp_correct", "rgp_workspace_size", "rgp_correct_plan",
                  "rgp_plan_launch", "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop",
-                 "rgp_loss_grad_images", "rgp_batch_workspace_size", "rgp_correct_batch_plan"):
+                 "rgp_loss_grad_images", "rgp_batch_workspace_size", "rgp_correct_batch_plan",
+                 "rgp_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -518,6 +520,20 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def autotune(shape, pe, real_dtype, opts: "Options", *, h=(1.0, 1.0, 1.0), ws=None,
+             stream=None):
+    """Tune the PCG march of every pyramid level (rgp_autotune); returns the chosen XL per level."""
+    g = make_grid(tuple(shape), pe, h)
+    c = opts.to_c()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    wsb, _ = _ws(OP_CORRECT, tuple(shape), pe, h, real_dtype, dev, opts=c, ws=ws)
+    out = (ctypes.c_int32 * opts.levels)()
+    _check("rgp_autotune", load().rgp_autotune(ctypes.byref(g), dtype_code(real_dtype),
+                                               ctypes.byref(c), _ptr(wsb), wsb.numel(),
+                                               _stream_ptr(stream), out))
+    return list(out)
 
 
 def timing_start(capacity: int = 65536):

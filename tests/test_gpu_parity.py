@@ -541,3 +541,28 @@ def test_batch_plan_matches_per_pair(img):
     a, c = host[0]
     ora = orc.solve(a, c, pes[0], levels=2, gn_iters=4, pcg_iters=8, pcg_rtol=0.0)
     assert float(np.max(np.abs(to_host(bp.b[0]) - ora.b))) <= BFINAL_ATOL
+
+
+def test_autotune_then_correct():
+    """The autotuner picks one march length per level from the candidates; afterwards the
+    correction (plain and batched) still matches the untuned result up to the order of the block
+    sums, and a captured plan replays the tuned shapes."""
+    rgp = _rgp()
+    shape, pe = (42, 46, 38), 1      # a geometry no other test tunes
+    p = _pair(shape, pe, seed=60, scale=30.0)
+    dt = torch.float32
+    Ip, Im = to_dev(p.I_plus, dt), to_dev(p.I_minus, dt)
+    opts = rgp.Options(levels=2, gn_iters=4, pcg_iters=8, pcg_rtol=0.0)
+    before = rgp.correct(Ip, Im, pe, opts=opts)
+    xls = rgp.autotune(shape, pe, dt, opts)
+    say(f"[autotune] march lengths per level: {xls}")
+    assert len(xls) == 2 and all(x in (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64) for x in xls)
+    after = rgp.correct(Ip, Im, pe, opts=opts)
+    assert float(torch.max(torch.abs(after["b"] - before["b"]))) <= 1e-3
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        bp = rgp.BatchPlan([Ip], [Im], [pe], opts, stream=s)
+        bp.launch(s)
+        s.synchronize()
+    assert torch.equal(bp.b[0], after["b"])
