@@ -74,7 +74,7 @@ __device__ __forceinline__ void phi3(TR z, TR& f, TR& f1, TR& f2) {
 // (diag, off).  With step != 0 it first forms b = b_in + gamma q (gamma and the acceptance from
 // the line search) and writes it to b_out, a different buffer since neighbours read b_in.
 // --------------------------------------------------------------------------------------------
-template <typename TI, typename TR, int S>
+template <typename TI, typename TR, int S, int BLK>
 __device__ __forceinline__ void loss_grad_body(const LossGradArgs& a, VBlock vb) {
   const Geom g = a.g;
   const TI* __restrict__ Ip = static_cast<const TI*>(a.Ip);
@@ -240,12 +240,12 @@ __device__ __forceinline__ void loss_grad_body(const LossGradArgs& a, VBlock vb)
       dR = ndR;
     }
   }
-  store_partials<5>(acc, a.part, vb.id);
+  store_partials<5, BLK>(acc, a.part, vb.id);
 }
 
 template <typename TI, typename TR, int S, int BLK>
 __global__ __launch_bounds__(BLK) void k_loss_grad(LossGradArgs a) {
-  loss_grad_body<TI, TR, S>(a, hw_block());
+  loss_grad_body<TI, TR, S, BLK>(a, hw_block());
 }
 
 // One launch over several volumes: tab[p] drives the workgroups starts[p] .. starts[p+1]-1.
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(BLK) void k_loss_grad_batch(const LossGradArgs* __r
                                                          int n) {
   VBlock vb;
   const int p = batch_volume(starts, n, vb);
-  loss_grad_body<TI, TR, S>(tab[p], vb);
+  loss_grad_body<TI, TR, S, BLK>(tab[p], vb);
 }
 
 // J, D, S, P from loss_grad's block sums (standalone entry point; one block).
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_loss_final(LossFinalArgs a) { 
 // and the two S sums.  A single-block decide kernel then takes the first (largest) gamma that
 // satisfies the Armijo condition, which is exactly what halving from gamma = 1 selects.
 // --------------------------------------------------------------------------------------------
-template <typename TI, typename TR, int S, int NC>
+template <typename TI, typename TR, int S, int NC, int BLK>
 __device__ __forceinline__ void trial_body(const TrialArgs& a, VBlock vb) {
   const State* st = a.st;
   if (load_flag(&st->gn_stop) || st->accepted) return;
@@ -373,12 +373,12 @@ __device__ __forceinline__ void trial_body(const TrialArgs& a, VBlock vb) {
       }
     }
   }
-  store_partials<K>(v, a.part, vb.id);
+  store_partials<K, BLK>(v, a.part, vb.id);
 }
 
 template <typename TI, typename TR, int S, int NC, int BLK>
 __global__ __launch_bounds__(BLK) void k_trial(TrialArgs a) {
-  trial_body<TI, TR, S, NC>(a, hw_block());
+  trial_body<TI, TR, S, NC, BLK>(a, hw_block());
 }
 
 template <typename TI, typename TR, int S, int NC, int BLK>
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(BLK) void k_trial_batch(const TrialArgs* __restrict
                                                      const uint32_t* __restrict__ starts, int n) {
   VBlock vb;
   const int p = batch_volume(starts, n, vb);
-  trial_body<TI, TR, S, NC>(tab[p], vb);
+  trial_body<TI, TR, S, NC, BLK>(tab[p], vb);
 }
 
 // Armijo decision on the pass just evaluated (one block per volume).

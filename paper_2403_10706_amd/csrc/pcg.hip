@@ -85,14 +85,14 @@ __global__ __launch_bounds__(BLK) void k_hvp(HvpArgs a) {
       }
     }
   }
-  if (a.part) store_partials<1>(acc, a.part, blockIdx.x);
+  if (a.part) store_partials<1, BLK>(acc, a.part, blockIdx.x);
 }
 
 // out = sum of one slot of block sums (one block).
 __global__ __launch_bounds__(kReduceBlock) void k_sum_final(const double* part, unsigned nprod,
                                                       double* out) {
   double t[1];
-  reduce_partials<1>(t, part, nprod);
+  reduce_partials<1, kReduceBlock>(t, part, nprod);
   if (threadIdx.x == 0) *out = t[0];
 }
 
@@ -143,6 +143,7 @@ __device__ __forceinline__ PcgSlot pcg_advance(const PcgSlot& prev, const double
 // previous block sums (load_partials_cm); identical in every block, since the block sums are
 // reduced in a fixed order.  Block 0 stores it and, when the solve ends, the iteration count and
 // residual.
+template <int BLK>
 __device__ __forceinline__ PcgSlot pcg_scalar_phase(const PcgScalarArgs& a, const PcgSlot& prev,
                                                     double (&t)[7], VBlock vb) {
   const int it = a.iter;
@@ -153,7 +154,7 @@ __device__ __forceinline__ PcgSlot pcg_scalar_phase(const PcgScalarArgs& a, cons
     cur.status = kPcgDone;
     fin = it == a.maxit;
   } else {
-    block_sum<7>(t);
+    block_sum<7, BLK>(t);
     cur = pcg_advance(prev, t, it, a.maxit, a.rtol, fin);
   }
   if (vb.id == 0 && threadIdx.x == 0) {
@@ -172,7 +173,7 @@ __device__ __forceinline__ void pcg_scalars_body(const PcgScalarArgs& a) {
     const PcgSlot prev = a.slots[(a.iter - 1) & 1];
     double t[7];
     load_partials_cm<7>(t, a.part_prev, a.nprod, a.iter == 1 ? 7 : 5);
-    pcg_scalar_phase(a, prev, t, VBlock{0u, 1u});
+    pcg_scalar_phase<kReduceBlock>(a, prev, t, VBlock{0u, 1u});
     return;
   }
   if (a.gn_mode && load_flag(&st->gn_stop)) {
@@ -326,7 +327,7 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
   if (fused) load_partials_cm<7>(tsum, a.sc.part_prev, a.sc.nprod, it == 1 ? 7 : 5);
   int64_t u = ulo + lb;
   if (u < uhi) begin_unit(u);
-  const PcgSlot sl = fused ? pcg_scalar_phase(a.sc, prev, tsum, vb) : prev;
+  const PcgSlot sl = fused ? pcg_scalar_phase<BLK>(a.sc, prev, tsum, vb) : prev;
   if (sl.status == kPcgDone) return;
   const TR al = (TR)sl.alpha, be = (TR)sl.beta;
   if (sl.status == kPcgFinish) {  // last update x += a p of the previous iteration (pointwise)
@@ -470,7 +471,7 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
     }
     __syncthreads();  // the next unit reuses the LDS buffers
   }
-  store_partials_cm<7>(acc, a.part, vb.id);
+  store_partials_cm<7, BLK>(acc, a.part, vb.id);
 }
 
 template <typename TR, int ROLE, int BLK, int NPT, int HMAX>

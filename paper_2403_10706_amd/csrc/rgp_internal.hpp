@@ -150,38 +150,52 @@ __device__ __forceinline__ WaveIter wave_iter(int64_t ntiles, VBlock vb) {
 // every result bitwise reproducible.
 // ----------------------------------------------------------------------------------------
 
-constexpr int kMaxWaves = 16;
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
   return v;
 }
 
-template <int K>
+// Block sums in a fixed order (BLK = blockDim.x): every thread stores its K values in LDS, the
+// first wavefront adds the BLK/64 values of each lane position and reduces across its lanes with
+// shuffles, and publishes the totals through LDS.  Only one wavefront does cross-lane work, which
+// matters when every workgroup of a large grid reduces at the same time: the shuffles of all
+// wavefronts would compete for the CU's LDS crossbar (measured ~3-4 us per launch for 7 sums).
+template <int K, int BLK>
 __device__ __forceinline__ void block_sum(double (&v)[K]) {
-  __shared__ double sh[K > 0 ? K : 1][kMaxWaves];
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  const int nw = blockDim.x / kWave;
+  constexpr int KC = K < 8 ? K : 8;  // sums per LDS round
+  __shared__ double sh[KC > 0 ? KC : 1][BLK];
+  __shared__ double tot[K > 0 ? K : 1];
+  const int t = threadIdx.x, lane = t & (kWave - 1);
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const double s = wave_sum(v[k]);
-    if (lane == 0) sh[k][wv] = s;
-  }
-  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += KC) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += sh[k][w];
-    v[k] = s;
+    for (int c = 0; c < KC; ++c)
+      if (k0 + c < K) sh[c][t] = v[k0 + c];
+    __syncthreads();
+    if (t < kWave) {
+#pragma unroll
+      for (int c = 0; c < KC; ++c) {
+        if (k0 + c < K) {
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < BLK / kWave; ++j) s += sh[c][lane + kWave * j];
+          s = wave_sum(s);
+          if (lane == 0) tot[k0 + c] = s;
+        }
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = tot[k];
+  __syncthreads();  // the buffers may be reused by the next call
 }
 
 // Block sums of v stored at part[blk * kPartStride + k] (blk: the block's VBlock id).
-template <int K>
+template <int K, int BLK>
 __device__ __forceinline__ void store_partials(double (&v)[K], double* part, unsigned blk) {
-  block_sum<K>(v);
+  block_sum<K, BLK>(v);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) part[(size_t)blk * kPartStride + k] = v[k];
@@ -191,7 +205,7 @@ __device__ __forceinline__ void store_partials(double (&v)[K], double* part, uns
 // Every thread of the calling block obtains the sums over nprod producer blocks.  The loads are
 // issued in batches of 4 (2 for K > 8) blocks per thread, all independent, so that one batch costs
 // one memory round trip; the summation order is fixed.
-template <int K>
+template <int K, int BLK>
 __device__ __forceinline__ void reduce_partials(double (&out)[K], const double* part,
                                                 unsigned nprod) {
 #pragma unroll
@@ -210,7 +224,7 @@ __device__ __forceinline__ void reduce_partials(double (&out)[K], const double* 
 #pragma unroll
       for (int k = 0; k < K; ++k) out[k] += v[j][k];
   }
-  block_sum<K>(out);
+  block_sum<K, BLK>(out);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -288,9 +302,9 @@ __host__ __device__ inline MarchGeo march_geo(const Geom& g, int T, int XL) {
 
 // Column-major variant for consumers that reduce in every block: sum k of block b is stored at
 // part[k * kMaxGrid + b], so the consumer's loads of one sum over all blocks are coalesced.
-template <int K>
+template <int K, int BLK>
 __device__ __forceinline__ void store_partials_cm(double (&v)[K], double* part, unsigned blk) {
-  block_sum<K>(v);
+  block_sum<K, BLK>(v);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) part[(size_t)k * kMaxGrid + blk] = v[k];

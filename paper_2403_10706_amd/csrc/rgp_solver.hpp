@@ -30,7 +30,7 @@ __device__ __forceinline__ int load_flag(const int32_t* f) {
 
 __device__ __forceinline__ bool finalize_loss(const LossFinalArgs& a, bool write) {
   double t[5];
-  reduce_partials<5>(t, a.part, a.nprod);
+  reduce_partials<5, kReduceBlock>(t, a.part, a.nprod);
   const bool viol = t[3] > 0.0;
   if (write && threadIdx.x == 0) {
     State* st = a.st;
@@ -95,7 +95,7 @@ __device__ __forceinline__ int decide_pass(const DecideArgs& a) {
   State* st = a.st;
   const State s = *st;
   double t[kTrialSlots];
-  reduce_partials<kTrialSlots>(t, a.part_prev, a.nprod_prev);  // synchronises the block
+  reduce_partials<kTrialSlots, kReduceBlock>(t, a.part_prev, a.nprod_prev);  // synchronises
   double gq = s.gq, sbq = s.sbq, sqq = s.sqq;
   if (a.prev_first == 0) {
     gq = t[0];
