@@ -249,13 +249,16 @@ __global__ __launch_bounds__(BLK) void k_loss_grad(LossGradArgs a) {
 }
 
 // One launch over several volumes: tab[p] drives the workgroups starts[p] .. starts[p+1]-1.
-template <typename TI, typename TR, int S, int BLK>
+template <typename TI, typename TR, int BLK>
 __global__ __launch_bounds__(BLK) void k_loss_grad_batch(const LossGradArgs* __restrict__ tab,
                                                          const uint32_t* __restrict__ starts,
                                                          int n) {
   VBlock vb;
   const int p = batch_volume(starts, n, vb);
-  loss_grad_body<TI, TR, S, BLK>(tab[p], vb);
+  if (tab[p].run == 4)
+    loss_grad_body<TI, TR, 4, BLK>(tab[p], vb);
+  else
+    loss_grad_body<TI, TR, 2, BLK>(tab[p], vb);
 }
 
 // J, D, S, P from loss_grad's block sums (standalone entry point; one block).
@@ -473,7 +476,12 @@ __global__ __launch_bounds__(1024) void k_correct(CorrectArgs a) {
 // ------------------------------------------------------------------------------------------
 
 namespace {
-constexpr int kRun = 8;  // nodes per thread along the PE axis
+// PE nodes per thread: short runs give more wavefronts and shorter dependent chains (measured on
+// 144x168x111 and its coarser levels: loss_grad 4 on volumes above 1 M nodes, 2 below; the trial
+// passes 2 everywhere; the correction 4).
+constexpr int kRunTrial = 2;
+constexpr int kRunCorrect = 4;
+inline int loss_run(const Geom& g) { return g.nnode > (int64_t(1) << 20) ? 4 : 2; }
 }
 
 Launch plan_tiles(const Geom& g, int S, int block) {
@@ -583,10 +591,10 @@ __global__ __launch_bounds__(kBlock) void k_image_grad(ImageGradArgs a) {
 }
 
 Launch plan_loss_grad(const Geom& g, DType real) {
-  return plan_tiles(g, kRun, pick_block(g, real, kRun));
+  return plan_tiles(g, loss_run(g), pick_block(g, real, loss_run(g)));
 }
 Launch plan_trial(const Geom& g, DType real, int nc) {
-  return plan_tiles(g, kRun, nc == 1 ? pick_block(g, real, kRun) : 256);
+  return plan_tiles(g, kRunTrial, nc == 1 ? pick_block(g, real, kRunTrial) : 256);
 }
 
 #define RGP_DISPATCH_TYPES(IMG, REAL, ...)                                              \
@@ -606,16 +614,18 @@ Launch plan_trial(const Geom& g, DType real, int nc) {
     }                                                                                   \
   } while (0)
 
-hipError_t launch_loss_grad(const LossGradArgs& a, DType img, DType real, hipStream_t s) {
-  const Launch L = plan_loss_grad(a.g, real);
+hipError_t launch_loss_grad(const LossGradArgs& a0, DType img, DType real, hipStream_t s) {
+  const Launch L = plan_loss_grad(a0.g, real);
+  LossGradArgs a = a0;
+  a.run = L.S;
   if (active_recorder())
     return record_launch(RecKind::kLossGrad, a, L.grid, L.block, 0, (int)img, (int)real, 0,
                          [a, img, real](hipStream_t s2) { return launch_loss_grad(a, img, real, s2); });
-  if (L.block == 1024) {
-    RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH(kKindLossGrad, a.g, (k_loss_grad<TI, TR, kRun, 1024>),
-                                             L.grid, 1024, 0, s, a));
+  if (L.S == 4) {
+    RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH(kKindLossGrad, a.g, (k_loss_grad<TI, TR, 4, 256>),
+                                             L.grid, 256, 0, s, a));
   } else {
-    RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH(kKindLossGrad, a.g, (k_loss_grad<TI, TR, kRun, 256>),
+    RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH(kKindLossGrad, a.g, (k_loss_grad<TI, TR, 2, 256>),
                                              L.grid, 256, 0, s, a));
   }
   return hipGetLastError();
@@ -635,7 +645,7 @@ hipError_t launch_trial(const TrialArgs& a, DType img, DType real, hipStream_t s
                          [a, img, real](hipStream_t s2) { return launch_trial(a, img, real, s2); });
 #define RGP_TRIAL(NC, B)                                                                   \
   RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH_T(kKindTrial, NC, a.g,                          \
-                                             (k_trial<TI, TR, kRun, NC, B>), L.grid, B, 0, s, a))
+                                             (k_trial<TI, TR, kRunTrial, NC, B>), L.grid, B, 0, s, a))
   switch (a.nc) {
     case 1:
       if (L.block == 1024) RGP_TRIAL(1, 1024);
@@ -674,8 +684,8 @@ hipError_t launch_apply_step(const ApplyArgs& a, DType real, hipStream_t s) {
 hipError_t launch_correct(const CorrectArgs& a, DType img, DType real, hipStream_t s) {
   if (active_recorder())
     return record_other([a, img, real](hipStream_t s2) { return launch_correct(a, img, real, s2); });
-  Launch L = plan_tiles(a.g, kRun, 1024);
-  RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_correct<TI, TR, kRun>), dim3(L.grid),
+  Launch L = plan_tiles(a.g, kRunCorrect, 1024);
+  RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_correct<TI, TR, kRunCorrect>), dim3(L.grid),
                                                    dim3(1024), 0, s, a));
   return hipGetLastError();
 }
@@ -694,7 +704,7 @@ hipError_t launch_image_grad(const ImageGradArgs& a, DType img, DType real, hipS
 hipError_t launch_loss_grad_batch(const void* tab, const uint32_t* starts, int n, unsigned grid,
                                   DType img, DType real, hipStream_t s) {
   const LossGradArgs* t = static_cast<const LossGradArgs*>(tab);
-  RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_loss_grad_batch<TI, TR, kRun, 256>),
+  RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_loss_grad_batch<TI, TR, 256>),
                                                    dim3(grid), dim3(256), 0, s, t, starts, n));
   return hipGetLastError();
 }
@@ -703,7 +713,7 @@ hipError_t launch_trial_batch(const void* tab, const uint32_t* starts, int n, un
                               int nc, DType img, DType real, hipStream_t s) {
   const TrialArgs* t = static_cast<const TrialArgs*>(tab);
 #define RGP_TRIAL_B(NC)                                                                      \
-  RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_trial_batch<TI, TR, kRun, NC, 256>),    \
+  RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_trial_batch<TI, TR, kRunTrial, NC, 256>), \
                                                    dim3(grid), dim3(256), 0, s, t, starts, n))
   switch (nc) {
     case 1: RGP_TRIAL_B(1); break;

@@ -26,7 +26,7 @@
 namespace rgp {
 
 namespace {
-constexpr int kRun = 8;
+constexpr int kRun = 4;
 }
 
 template <typename TR, int S, int BLK>

@@ -64,6 +64,7 @@ struct LossGradArgs {
   double* part;       // block sums: sum r^2, sum S terms, sum phi, violations, sum g^2
   int step;           // apply the accepted line-search step first
   int level_start;    // first GN step of a level: block 0 clears gn_stop / accepted
+  int run;            // PE nodes per thread of the launch (set by the launcher)
 };
 
 // Reduction of loss_grad's block sums into J, D, S, P (one block, or every PCG block of
