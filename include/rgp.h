@@ -242,7 +242,8 @@ typedef enum {
 } rgp_kernel_kind;
 typedef struct {
   int32_t kernel;
-  int32_t tag;       /* PCG step: the PCG iteration (0 = first); trial: candidates; else 0 */
+  int32_t tag;       /* PCG step: the PCG iteration (0 = first); trial: candidates; loss_grad:
+                        1 when it also applies the previous step; else 0 */
   uint32_t grid;     /* workgroups */
   uint32_t pad;
   int64_t cells;

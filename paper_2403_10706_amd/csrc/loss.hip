@@ -621,12 +621,14 @@ hipError_t launch_loss_grad(const LossGradArgs& a0, DType img, DType real, hipSt
   if (active_recorder())
     return record_launch(RecKind::kLossGrad, a, L.grid, L.block, 0, (int)img, (int)real, 0,
                          [a, img, real](hipStream_t s2) { return launch_loss_grad(a, img, real, s2); });
+  // timing tag 1: the launch also applies the previous step (reads q, writes b + gamma q)
+  const int tag = a.step ? 1 : 0;
   if (L.S == 4) {
-    RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH(kKindLossGrad, a.g, (k_loss_grad<TI, TR, 4, 256>),
-                                             L.grid, 256, 0, s, a));
+    RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH_T(kKindLossGrad, tag, a.g,
+                                               (k_loss_grad<TI, TR, 4, 256>), L.grid, 256, 0, s, a));
   } else {
-    RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH(kKindLossGrad, a.g, (k_loss_grad<TI, TR, 2, 256>),
-                                             L.grid, 256, 0, s, a));
+    RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH_T(kKindLossGrad, tag, a.g,
+                                               (k_loss_grad<TI, TR, 2, 256>), L.grid, 256, 0, s, a));
   }
   return hipGetLastError();
 }
