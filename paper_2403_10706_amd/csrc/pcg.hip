@@ -206,15 +206,27 @@ template <typename TR>
 struct NodeRaw {
   TR d, r, w, p, x;
 };
+// The loads of one march step that stay in flight while the current plane is computed: the raw
+// values of the plane after next, and the couplings and halo rows of the next plane.  Two sets
+// alternate between the steps, so that no register with a pending load is ever copied.
+template <typename TR, int NPT, int HMAX>
+struct Ahead {
+  NodeRaw<TR> raw[NPT];
+  TR oc[NPT], ob[NPT];
+  NodeRaw<TR> halo[HMAX];
+};
 
 // One PCG iteration over the units of a plane march (see MarchGeo).  Per plane o of a unit every
 // thread owns npt plane positions: it applies the update (x += a p, r -= a w, p = r/d + b p,
 // stored) one plane ahead (o+1) so that the o-neighbours of p stay in registers, writes p of plane
 // o into an LDS plane buffer together with the two halo rows (nb positions on each side of the
 // unit's flat run, recomputed from the previous vectors), and forms w = H p at plane o from LDS
-// (a and b neighbours) and registers (o neighbours).  Raw values of plane o+2 and the halo rows of
-// plane o+1 are loaded while plane o is computed.  The LDS plane buffer is double-buffered so that
-// one barrier per plane suffices.  Planes just outside the unit contribute p only (recomputed).
+// (a and b neighbours) and registers (o neighbours).  The raw values of plane o+2 and the halo
+// rows and couplings of plane o+1 are loaded while plane o is computed.  Every step issues the
+// same loads and stores whether or not a lane or plane needs them (unneeded ones go to kNullOff),
+// so each wait covers only the loads of the previous step.  The LDS plane buffer is
+// double-buffered so that one barrier per plane suffices.  Planes just outside the unit
+// contribute p only (recomputed).
 template <typename TR, int ROLE, int BLK, int NPT, int HMAX>
 __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& m, VBlock vb) {
   extern __shared__ unsigned char lds_raw[];
@@ -223,29 +235,27 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
   const bool first = it == 0;
   const Geom g = a.g;
   const uint32_t nbytes = (uint32_t)(g.nnode * (int64_t)sizeof(TR));
-  const BRes rD = bres(a.diag, nbytes), rO = bres(a.off, nbytes), rB = bres(a.rhs, nbytes);
-  const BRes rX = bres(a.x, nbytes), rRi = bres(a.r_in, nbytes), rPi = bres(a.p_in, nbytes);
-  const BRes rWi = bres(a.w_in, nbytes), rRo = bres(a.r_out, nbytes);
-  const BRes rPo = bres(a.p_out, nbytes), rWo = bres(a.w_out, nbytes);
+  const BRes rD = bres(a.diag, nbytes), rO = bres(a.off, nbytes);
+  // iteration 0 reads the right-hand side where later iterations read r (and no w, p, x)
+  const BRes rR = bres(first ? a.rhs : a.r_in, nbytes);
+  const BRes rX = bres(a.x, nbytes), rPi = bres(a.p_in, nbytes), rWi = bres(a.w_in, nbytes);
+  const BRes rRo = bres(a.r_out, nbytes), rPo = bres(a.p_out, nbytes);
+  const BRes rWo = bres(a.w_out, nbytes);
   const int no = m.no, na = m.na, nb = m.nb;
   const int64_t P = m.P;
   const int T = m.T;
   const int t = threadIdx.x;
   constexpr uint32_t kSz = sizeof(TR);
+  auto off_at = [&](bool ok, int64_t n) -> uint32_t { return ok ? (uint32_t)n * kSz : kNullOff; };
 
-  auto load_raw = [&](int64_t n, bool with_x) -> NodeRaw<TR> {
+  auto load_raw = [&](uint32_t bo, bool with_x) -> NodeRaw<TR> {
     NodeRaw<TR> v;
-    const uint32_t bo = (uint32_t)n * kSz;
+    const uint32_t bv = first ? kNullOff : bo;
     v.d = bld<TR>(rD, bo);
-    if (first) {
-      v.r = bld<TR>(rB, bo);
-      v.w = v.p = v.x = TR(0);
-    } else {
-      v.r = bld<TR>(rRi, bo);
-      v.w = bld<TR>(rWi, bo);
-      v.p = bld<TR>(rPi, bo);
-      v.x = with_x ? bld<TR>(rX, bo) : TR(0);
-    }
+    v.r = bld<TR>(rR, bo);
+    v.w = bld<TR>(rWi, bv);
+    v.p = bld<TR>(rPi, bv);
+    v.x = bld<TR>(rX, with_x ? bv : kNullOff);
     return v;
   };
 
@@ -267,15 +277,32 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
   int fl[NPT], ia[NPT], ib[NPT];
   bool own[NPT];
   int64_t hpos[HMAX];
-  NodeRaw<TR> A0[NPT], M0[NPT], B[NPT], C[NPT], Hc[HMAX], Hn[HMAX];
-  TR Om[NPT], Oc[NPT], On[NPT], Ob[NPT], Obn[NPT];
-  // PE-lower coupling of a node when the PE axis is a or b
-  auto off_lower = [&](int64_t n, int i) -> TR {
-    if (ROLE == 1) return ia[i] > 0 ? bld<TR>(rO, (uint32_t)(n - nb) * kSz) : TR(0);
-    if (ROLE == 2) return ib[i] > 0 ? bld<TR>(rO, (uint32_t)(n - 1) * kSz) : TR(0);
+  NodeRaw<TR> A0[NPT], M0[NPT];
+  Ahead<TR, NPT, HMAX> S0, S1;
+  TR Om[NPT];
+  auto node = [&](int o, int i) -> int64_t { return (int64_t)o * P + f0 + fl[i]; };
+  // PE-lower coupling of node n when the PE axis is a or b (0 at the lower boundary)
+  auto off_lower = [&](bool ok, int64_t n, int i) -> TR {
+    if (ROLE == 1) return bld<TR>(rO, off_at(ok && ia[i] > 0, n - nb));
+    if (ROLE == 2) return bld<TR>(rO, off_at(ok && ib[i] > 0, n - 1));
     return TR(0);
   };
-  // geometry of unit uu and the loads of planes o0-1 .. o0+1 and the halo rows of o0
+  // loads of plane q into a set: raw values of q (owned planes and the halo plane after the
+  // unit), couplings and halo rows of q - 1 (owned planes)
+  auto issue = [&](int q, Ahead<TR, NPT, HMAX>& s) {
+    const bool raw_ok = q < no && q <= oe, cpl_ok = q - 1 < oe;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      s.raw[i] = load_raw(off_at(raw_ok, node(q, i)), q < oe);
+      const int64_t n = node(q - 1, i);
+      s.oc[i] = bld<TR>(rO, off_at(cpl_ok, n));
+      s.ob[i] = off_lower(cpl_ok, n, i);
+    }
+#pragma unroll
+    for (int j = 0; j < HMAX; ++j)
+      s.halo[j] = load_raw(off_at(cpl_ok && hpos[j] >= 0, (int64_t)(q - 1) * P + hpos[j]), false);
+  };
+  // geometry of unit uu and the loads of planes o0-1, o0 and (set S0) o0+1
   auto begin_unit = [&](int64_t uu) {
     const int ti = (int)(uu / m.noc), oc = (int)(uu - (int64_t)ti * m.noc);
     f0 = (int64_t)ti * T;
@@ -303,20 +330,11 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
     }
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
-      const int64_t n = (int64_t)o0 * P + f0 + fl[i];
-      A0[i] = load_raw(n, true);
-      if (o0 + 1 < no) B[i] = load_raw(n + P, o0 + 1 < oe);
-      Oc[i] = bld<TR>(rO, (uint32_t)n * kSz);
-      Ob[i] = off_lower(n, i);
-      Om[i] = TR(0);
-      if (o0 > 0) {
-        M0[i] = load_raw(n - P, false);
-        if (ROLE == 0) Om[i] = bld<TR>(rO, (uint32_t)(n - P) * kSz);
-      }
+      A0[i] = load_raw(off_at(true, node(o0, i)), true);
+      M0[i] = load_raw(off_at(o0 > 0, node(o0 - 1, i)), false);
+      Om[i] = ROLE == 0 ? bld<TR>(rO, off_at(o0 > 0, node(o0 - 1, i))) : TR(0);
     }
-#pragma unroll
-    for (int j = 0; j < HMAX; ++j)
-      if (hpos[j] >= 0) Hc[j] = load_raw((int64_t)o0 * P + hpos[j], false);
+    issue(o0 + 1, S0);
   };
 
   // Fused: the previous iteration's block sums are loaded first, then the first unit's planes,
@@ -329,7 +347,7 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
   if (u < uhi) begin_unit(u);
   const PcgSlot sl = fused ? pcg_scalar_phase<BLK>(a.sc, prev, tsum, vb) : prev;
   if (sl.status == kPcgDone) return;
-  const TR al = (TR)sl.alpha, be = (TR)sl.beta;
+  const TR al = first ? TR(0) : (TR)sl.alpha, be = first ? TR(0) : (TR)sl.beta;
   if (sl.status == kPcgFinish) {  // last update x += a p of the previous iteration (pointwise)
     TR* __restrict__ x = static_cast<TR*>(a.x);
     const TR* __restrict__ pi = static_cast<const TR*>(a.p_in);
@@ -350,8 +368,9 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
     return (v.r - al * v.w) / v.d + be * v.p;
   };
   TR Pm[NPT], Pc[NPT], Pn[NPT], Dc[NPT], Rc[NPT], Dn[NPT], Rn[NPT];
-  auto own_update = [&](int o, const NodeRaw<TR> (&R)[NPT], TR (&Pq)[NPT], TR (&Dq)[NPT],
-                        TR (&Rq)[NPT]) {
+  // update of plane o (stored where `store` holds for an owned position)
+  auto update = [&](int o, bool store, const NodeRaw<TR> (&R)[NPT], TR (&Pq)[NPT], TR (&Dq)[NPT],
+                    TR (&Rq)[NPT]) {
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
       const TR d = R[i].d;
@@ -368,106 +387,78 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
       Pq[i] = p;
       Dq[i] = d;
       Rq[i] = r;
-      if (own[i]) {
-        const uint32_t bo = (uint32_t)((int64_t)o * P + f0 + fl[i]) * kSz;
-        bst<TR>(rX, bo, xn);
-        bst<TR>(rRo, bo, r);
-        bst<TR>(rPo, bo, p);
-      }
+      const uint32_t bo = off_at(store && own[i], node(o, i));
+      bst<TR>(rX, bo, xn);
+      bst<TR>(rRo, bo, r);
+      bst<TR>(rPo, bo, p);
     }
   };
 
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  // plane o: `cur` holds the raw values of o+1 and the couplings and halo rows of o; `nxt`
+  // receives those of o+2 and o+1
+  auto step = [&](int o, Ahead<TR, NPT, HMAX>& cur, Ahead<TR, NPT, HMAX>& nxt) {
+    issue(o + 2, nxt);
+    update(o + 1, o + 1 < oe, cur.raw, Pn, Dn, Rn);
+    TR* buf = lds + (o & 1) * (T + 2 * nb);
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) buf[fl[i] + nb] = Pc[i];
+#pragma unroll
+    for (int j = 0; j < HMAX; ++j)
+      if (hpos[j] >= 0) buf[hpos[j] - f0 + nb] = p_of(cur.halo[j]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int li = fl[i] + nb;
+      const TR pk = Pc[i];
+      const bool am = ia[i] > 0, ap = ia[i] < na - 1, bm = ib[i] > 0, bp = ib[i] < nb - 1;
+      const TR pam = am ? buf[li - nb] : TR(0), pap = ap ? buf[li + nb] : TR(0);
+      const TR pbm = bm ? buf[li - 1] : TR(0), pbp = bp ? buf[li + 1] : TR(0);
+      const TR pom = o > 0 ? Pm[i] : TR(0), pop = o < no - 1 ? Pn[i] : TR(0);
+      TR w = Dc[i] * pk;
+      if (ROLE == 0) {
+        w += Om[i] * pom + cur.oc[i] * pop;
+        w -= c_a * (pam + pap) + c_b * (pbm + pbp);
+      } else if (ROLE == 1) {
+        w += cur.ob[i] * pam + cur.oc[i] * pap;
+        w -= c_o * (pom + pop) + c_b * (pbm + pbp);
+      } else {
+        w += cur.ob[i] * pbm + cur.oc[i] * pbp;
+        w -= c_o * (pom + pop) + c_a * (pam + pap);
+      }
+      bst<TR>(rWo, off_at(own[i], node(o, i)), w);
+      if (own[i]) {
+        // FP64 products and sums
+        const double r = (double)Rc[i], ww = (double)w, dd = (double)Dc[i];
+        acc[0] += (double)pk * ww;
+        acc[1] += r * ww / dd;
+        acc[2] += ww * ww / dd;
+        acc[3] += r * ww;
+        acc[4] += ww * ww;
+        if (first) {
+          acc[5] += r * r / dd;
+          acc[6] += r * r;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      Pm[i] = Pc[i];
+      Pc[i] = Pn[i];
+      Dc[i] = Dn[i];
+      Rc[i] = Rn[i];
+      if (ROLE == 0) Om[i] = cur.oc[i];
+    }
+  };
+
   for (; u < uhi; u += gl) {
     if (u != ulo + lb) begin_unit(u);
 #pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-      Pm[i] = o0 > 0 ? p_of(M0[i]) : TR(0);
-      Pn[i] = TR(0);
-      Dn[i] = TR(1);
-      Rn[i] = TR(0);
-    }
-    own_update(o0, A0, Pc, Dc, Rc);
-    for (int o = o0; o < oe; ++o) {
-      // loads for later planes: raw plane o+2 (owned or the halo plane), halo rows and couplings
-      // of plane o+1
-#pragma unroll
-      for (int i = 0; i < NPT; ++i) {
-        const int64_t n1 = (int64_t)(o + 1) * P + f0 + fl[i];
-        if (o + 2 < no && o + 2 <= oe) C[i] = load_raw(n1 + P, o + 2 < oe);
-        if (o + 1 < oe) {
-          On[i] = bld<TR>(rO, (uint32_t)n1 * kSz);
-          Obn[i] = off_lower(n1, i);
-        }
-      }
-      if (o + 1 < oe) {
-#pragma unroll
-        for (int j = 0; j < HMAX; ++j)
-          if (hpos[j] >= 0) Hn[j] = load_raw((int64_t)(o + 1) * P + hpos[j], false);
-      }
-      // plane o+1 from the raw values loaded one plane earlier
-      if (o + 1 < oe) {
-        own_update(o + 1, B, Pn, Dn, Rn);
-      } else if (o + 1 < no) {
-#pragma unroll
-        for (int i = 0; i < NPT; ++i) Pn[i] = p_of(B[i]);
-      }
-      TR* buf = lds + (o & 1) * (T + 2 * nb);
-#pragma unroll
-      for (int i = 0; i < NPT; ++i) buf[fl[i] + nb] = Pc[i];
-#pragma unroll
-      for (int j = 0; j < HMAX; ++j)
-        if (hpos[j] >= 0) buf[hpos[j] - f0 + nb] = p_of(Hc[j]);
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < NPT; ++i) {
-        const int li = fl[i] + nb;
-        const TR pk = Pc[i];
-        const bool am = ia[i] > 0, ap = ia[i] < na - 1, bm = ib[i] > 0, bp = ib[i] < nb - 1;
-        const TR pam = am ? buf[li - nb] : TR(0), pap = ap ? buf[li + nb] : TR(0);
-        const TR pbm = bm ? buf[li - 1] : TR(0), pbp = bp ? buf[li + 1] : TR(0);
-        const TR pom = o > 0 ? Pm[i] : TR(0), pop = o < no - 1 ? Pn[i] : TR(0);
-        TR w = Dc[i] * pk;
-        if (ROLE == 0) {
-          w += Om[i] * pom + Oc[i] * pop;
-          w -= c_a * (pam + pap) + c_b * (pbm + pbp);
-        } else if (ROLE == 1) {
-          w += Ob[i] * pam + Oc[i] * pap;
-          w -= c_o * (pom + pop) + c_b * (pbm + pbp);
-        } else {
-          w += Ob[i] * pbm + Oc[i] * pbp;
-          w -= c_o * (pom + pop) + c_a * (pam + pap);
-        }
-        if (own[i]) {
-          bst<TR>(rWo, (uint32_t)((int64_t)o * P + f0 + fl[i]) * kSz, w);
-          // FP64 products and sums
-          const double r = (double)Rc[i], ww = (double)w, dd = (double)Dc[i];
-          acc[0] += (double)pk * ww;
-          acc[1] += r * ww / dd;
-          acc[2] += ww * ww / dd;
-          acc[3] += r * ww;
-          acc[4] += ww * ww;
-          if (first) {
-            acc[5] += r * r / dd;
-            acc[6] += r * r;
-          }
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < NPT; ++i) {
-        Pm[i] = Pc[i];
-        Pc[i] = Pn[i];
-        Dc[i] = Dn[i];
-        Rc[i] = Rn[i];
-        if (ROLE == 0) Om[i] = Oc[i];
-        B[i] = C[i];
-        if (o + 1 < oe) {
-          Oc[i] = On[i];
-          Ob[i] = Obn[i];
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < HMAX; ++j) Hc[j] = Hn[j];
+    for (int i = 0; i < NPT; ++i) Pm[i] = o0 > 0 ? p_of(M0[i]) : TR(0);
+    update(o0, true, A0, Pc, Dc, Rc);
+    for (int o = o0; o < oe; o += 2) {
+      step(o, S0, S1);
+      if (o + 1 < oe) step(o + 1, S1, S0);
     }
     __syncthreads();  // the next unit reuses the LDS buffers
   }

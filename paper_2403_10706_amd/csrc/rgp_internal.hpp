@@ -144,52 +144,61 @@ __device__ __forceinline__ WaveIter wave_iter(int64_t ntiles, VBlock vb) {
 }
 
 // ----------------------------------------------------------------------------------------
-// Reductions: wavefront shuffles, then LDS across the wavefronts of the block.  A producer kernel
+// Reductions: DPP moves within a wavefront, then LDS across the wavefronts of the block.  A producer kernel
 // stores its block sums with plain stores; a consumer kernel reduces all blocks in block order.
 // No atomics and no fences: visibility comes from the kernel boundary, and the fixed order makes
 // every result bitwise reproducible.
 // ----------------------------------------------------------------------------------------
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+// Cross-lane moves of a double within the 16-lane rows of a wavefront (DPP, no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
 }
 
-// Block sums in a fixed order (BLK = blockDim.x): every thread stores its K values in LDS, the
-// first wavefront adds the BLK/64 values of each lane position and reduces across its lanes with
-// shuffles, and publishes the totals through LDS.  Only one wavefront does cross-lane work, which
-// matters when every workgroup of a large grid reduces at the same time: the shuffles of all
-// wavefronts would compete for the CU's LDS crossbar (measured ~3-4 us per launch for 7 sums).
+// Sum over the 64 lanes of a wavefront (all lanes active), returned to every lane: pairs of
+// lanes, then quads (quad permutations), halves of a row (lane i with 7 - i) and rows (lane i
+// with 15 - i) by DPP, which leaves each 16-lane row holding its total in every lane; the four
+// row totals are then added in a fixed order.  IEEE addition is commutative, so both lanes of a
+// pair hold bitwise the same value at every stage and the result is the same in every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_row<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_row<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_row<0x141>(v);  // row_half_mirror
+  v += dpp_row<0x140>(v);  // row_mirror
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// Block sums in a fixed order (BLK = blockDim.x, every lane active): each wavefront reduces its
+// K values across its lanes (wave_sum), its first lane publishes them in LDS, and every thread
+// adds the BLK/64 wavefront totals in wavefront order.
 template <int K, int BLK>
 __device__ __forceinline__ void block_sum(double (&v)[K]) {
-  constexpr int KC = K < 8 ? K : 8;  // sums per LDS round
-  __shared__ double sh[KC > 0 ? KC : 1][BLK];
-  __shared__ double tot[K > 0 ? K : 1];
-  const int t = threadIdx.x, lane = t & (kWave - 1);
+  constexpr int NW = BLK / kWave;
+  __shared__ double sh[NW][K > 0 ? K : 1];
+  const int w = threadIdx.x / kWave;
 #pragma unroll
-  for (int k0 = 0; k0 < K; k0 += KC) {
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
 #pragma unroll
-    for (int c = 0; c < KC; ++c)
-      if (k0 + c < K) sh[c][t] = v[k0 + c];
-    __syncthreads();
-    if (t < kWave) {
-#pragma unroll
-      for (int c = 0; c < KC; ++c) {
-        if (k0 + c < K) {
-          double s = 0.0;
-#pragma unroll
-          for (int j = 0; j < BLK / kWave; ++j) s += sh[c][lane + kWave * j];
-          s = wave_sum(s);
-          if (lane == 0) tot[k0 + c] = s;
-        }
-      }
-    }
-    __syncthreads();
+    for (int k = 0; k < K; ++k) sh[w][k] = v[k];
   }
+  __syncthreads();
 #pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = tot[k];
-  __syncthreads();  // the buffers may be reused by the next call
+  for (int k = 0; k < K; ++k) {
+    double s = sh[0][k];
+#pragma unroll
+    for (int j = 1; j < NW; ++j) s += sh[j][k];
+    v[k] = s;
+  }
+  __syncthreads();  // the buffer may be reused by the next call
 }
 
 // Block sums of v stored at part[blk * kPartStride + k] (blk: the block's VBlock id).
@@ -234,6 +243,12 @@ __device__ __forceinline__ void reduce_partials(double (&out)[K], const double* 
 // descriptor's range read 0 and are dropped on store.
 // ----------------------------------------------------------------------------------------
 typedef __amdgpu_buffer_rsrc_t BRes;
+
+// A byte offset outside the range of every descriptor made here (they cover at most 2^31 bytes):
+// a load there reads 0 and a store there is dropped.  Kernels use it to issue a fixed sequence of
+// memory operations and mask the ones a lane or a step does not need, so that the compiler can
+// count the operations in flight and wait for exactly the ones an instruction depends on.
+constexpr uint32_t kNullOff = 0x80000000u;
 
 __device__ __forceinline__ BRes bres(const void* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
