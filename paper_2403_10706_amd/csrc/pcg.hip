@@ -363,30 +363,39 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
   const TR c_o = ROLE == 0 ? TR(0) : cx;
   const TR c_a = ROLE == 0 ? cx : (ROLE == 1 ? TR(0) : cy);
   const TR c_b = ROLE == 2 ? TR(0) : cy;
-  auto p_of = [&](const NodeRaw<TR>& v) -> TR {
-    if (first) return sgn * v.r / v.d;
-    return (v.r - al * v.w) / v.d + be * v.p;
+  // The update of one node from its raw values: r -= a w (iteration 0: r = sign * rhs), the
+  // Jacobi step z = r / d (as r times 1/d, which the sums reuse) and p = z + b p.  Owned nodes
+  // and recomputed halo nodes go through this same arithmetic, so both give bitwise the same p.
+  // Iteration 0 loads w = p = x = 0 and runs with a = b = 0.
+  const TR sg = first ? sgn : TR(1);
+  auto upd_of = [&](const NodeRaw<TR>& v, TR& r, TR& z, TR& rd) -> TR {
+    r = sg * v.r - al * v.w;
+    rd = TR(1) / v.d;
+    z = r * rd;
+    return z + be * v.p;
   };
-  TR Pm[NPT], Pc[NPT], Pn[NPT], Dc[NPT], Rc[NPT], Dn[NPT], Rn[NPT];
+  auto p_of = [&](const NodeRaw<TR>& v) -> TR {
+    TR r, z, rd;
+    return upd_of(v, r, z, rd);
+  };
+  // per plane position: p, d, r, z and 1/d of the previous (m), current (c) and next (n) plane
+  TR Pm[NPT], Pc[NPT], Pn[NPT], Dc[NPT], Rc[NPT], Zc[NPT], Ic[NPT];
+  TR Dn[NPT], Rn[NPT], Zn[NPT], In[NPT];
   // update of plane o (stored where `store` holds for an owned position)
   auto update = [&](int o, bool store, const NodeRaw<TR> (&R)[NPT], TR (&Pq)[NPT], TR (&Dq)[NPT],
-                    TR (&Rq)[NPT]) {
+                    TR (&Rq)[NPT], TR (&Zq)[NPT], TR (&Iq)[NPT]) {
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
-      const TR d = R[i].d;
-      TR r, xn, p;
-      if (first) {
-        r = sgn * R[i].r;
-        xn = TR(0);
-        p = r / d;
-      } else {
-        r = R[i].r - al * R[i].w;
-        xn = R[i].x + al * R[i].p;
-        p = r / d + be * R[i].p;
-      }
+      TR r, z, rd;
+      const TR p = upd_of(R[i], r, z, rd);
+      const TR xn = R[i].x + al * R[i].p;
       Pq[i] = p;
-      Dq[i] = d;
+      // d is carried into the next step, which reloads this register set: adding +0 (kept under
+      // IEEE rules) gives it a register of its own, so the reload never waits on a copy
+      Dq[i] = R[i].d + TR(0);
       Rq[i] = r;
+      Zq[i] = z;
+      Iq[i] = rd;
       const uint32_t bo = off_at(store && own[i], node(o, i));
       bst<TR>(rX, bo, xn);
       bst<TR>(rRo, bo, r);
@@ -399,13 +408,18 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
   // receives those of o+2 and o+1
   auto step = [&](int o, Ahead<TR, NPT, HMAX>& cur, Ahead<TR, NPT, HMAX>& nxt) {
     issue(o + 2, nxt);
-    update(o + 1, o + 1 < oe, cur.raw, Pn, Dn, Rn);
-    TR* buf = lds + (o & 1) * (T + 2 * nb);
+    // keep the scheduler from moving these loads behind the wait for the current set
+    __builtin_amdgcn_sched_barrier(0);
+    update(o + 1, o + 1 < oe, cur.raw, Pn, Dn, Rn, Zn, In);
+    // plane buffers of T + 2 nb positions and one spare slot that takes the halo writes of
+    // lanes without a halo position (every lane consumes its halo loads, so that no load of
+    // this set is left pending on some lanes only)
+    TR* buf = lds + (o & 1) * (T + 2 * nb + 1);
 #pragma unroll
     for (int i = 0; i < NPT; ++i) buf[fl[i] + nb] = Pc[i];
 #pragma unroll
     for (int j = 0; j < HMAX; ++j)
-      if (hpos[j] >= 0) buf[hpos[j] - f0 + nb] = p_of(cur.halo[j]);
+      buf[hpos[j] >= 0 ? (int)(hpos[j] - f0) + nb : T + 2 * nb] = p_of(cur.halo[j]);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
@@ -428,15 +442,15 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
       }
       bst<TR>(rWo, off_at(own[i], node(o, i)), w);
       if (own[i]) {
-        // FP64 products and sums
-        const double r = (double)Rc[i], ww = (double)w, dd = (double)Dc[i];
+        // FP64 products and sums (r.w/d as z.w, w.w/d and r.r/d with the stored 1/d)
+        const double r = (double)Rc[i], ww = (double)w, z = (double)Zc[i], id = (double)Ic[i];
         acc[0] += (double)pk * ww;
-        acc[1] += r * ww / dd;
-        acc[2] += ww * ww / dd;
+        acc[1] += z * ww;
+        acc[2] += ww * ww * id;
         acc[3] += r * ww;
         acc[4] += ww * ww;
         if (first) {
-          acc[5] += r * r / dd;
+          acc[5] += r * z;
           acc[6] += r * r;
         }
       }
@@ -447,15 +461,37 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
       Pc[i] = Pn[i];
       Dc[i] = Dn[i];
       Rc[i] = Rn[i];
-      if (ROLE == 0) Om[i] = cur.oc[i];
+      Zc[i] = Zn[i];
+      Ic[i] = In[i];
+      if (ROLE == 0) Om[i] = cur.oc[i] + TR(0);  // own register, as for d above
     }
+  };
+
+  // Completes every load of begin_unit (an empty asm that reads the registers).  The march loop
+  // then starts with exactly the loads of set S0 in flight, as after each of its own iterations;
+  // otherwise the wait counts at the loop head would have to allow for the unit's first loads on
+  // every iteration.
+  auto settle = [&]() {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      __asm__ volatile("" ::"v"(A0[i].d), "v"(A0[i].r), "v"(A0[i].w), "v"(A0[i].p), "v"(A0[i].x));
+      __asm__ volatile("" ::"v"(M0[i].d), "v"(M0[i].r), "v"(M0[i].w), "v"(M0[i].p));
+      __asm__ volatile("" ::"v"(S0.raw[i].d), "v"(S0.raw[i].r), "v"(S0.raw[i].w),
+                       "v"(S0.raw[i].p), "v"(S0.raw[i].x));
+      __asm__ volatile("" ::"v"(S0.oc[i]), "v"(S0.ob[i]), "v"(Om[i]));
+    }
+#pragma unroll
+    for (int j = 0; j < HMAX; ++j)
+      __asm__ volatile("" ::"v"(S0.halo[j].d), "v"(S0.halo[j].r), "v"(S0.halo[j].w),
+                       "v"(S0.halo[j].p));
   };
 
   for (; u < uhi; u += gl) {
     if (u != ulo + lb) begin_unit(u);
+    settle();
 #pragma unroll
     for (int i = 0; i < NPT; ++i) Pm[i] = o0 > 0 ? p_of(M0[i]) : TR(0);
-    update(o0, true, A0, Pc, Dc, Rc);
+    update(o0, true, A0, Pc, Dc, Rc, Zc, Ic);
     for (int o = o0; o < oe; o += 2) {
       step(o, S0, S1);
       if (o + 1 < oe) step(o + 1, S1, S0);
@@ -550,7 +586,7 @@ PcgPlan plan_pcg_xl(const Geom& g, DType real, int xl_force) {
   grid = (grid + 7) / 8 * 8;  // whole XCD rounds
   if (grid > kMaxGrid) grid = kMaxGrid;
   L.grid = (unsigned)grid;
-  L.lds = 2 * (size_t)(T + 2 * nb) * (real == DType::F64 ? 8 : 4);
+  L.lds = 2 * (size_t)(T + 2 * nb + 1) * (real == DType::F64 ? 8 : 4);
   L.fused = 1;
   return L;
 }
