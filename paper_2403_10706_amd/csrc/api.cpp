@@ -1023,6 +1023,7 @@ rgp_status record_batch(int32_t n, const rgp_grid* grids, rgp_dtype img_t,
       starts[(size_t)p + 1] = starts[(size_t)p] + r.grid;
       sl.lds = std::max(sl.lds, r.lds);
       geo.push_back(r.geo);
+      if (r0.kind == RecKind::kPcgStep) sl.var[3] = std::max(sl.var[3], r.geo.XL);
     }
     sl.grid = starts[(size_t)n];
     sl.tab = put(tab.data(), tab.size());
@@ -1065,7 +1066,7 @@ hipError_t issue_batch(int32_t n, const std::vector<Recorder>& recs,
         break;
       case RecKind::kPcgStep:
         e = launch_pcg_step_batch(tab, reinterpret_cast<const MarchGeo*>(arena_dev + sl.geo),
-                                  starts, n, sl.grid, sl.lds, (DType)sl.var[0], s);
+                                  starts, n, sl.grid, sl.lds, (DType)sl.var[0], sl.var[3], s);
         break;
       default:
         e = hipErrorInvalidValue;

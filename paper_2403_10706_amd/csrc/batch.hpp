@@ -81,7 +81,9 @@ hipError_t launch_decide_batch(const void* tab, int n, hipStream_t s);
 hipError_t launch_apply_step_batch(const void* tab, const uint32_t* starts, int n, unsigned grid,
                                    DType real, hipStream_t s);
 hipError_t launch_pcg_scalars_batch(const void* tab, int n, hipStream_t s);
+// max_xl: the longest march of the volumes (units of at most 3 planes load them all up front)
 hipError_t launch_pcg_step_batch(const void* tab, const MarchGeo* geo, const uint32_t* starts,
-                                 int n, unsigned grid, size_t lds, DType real, hipStream_t s);
+                                 int n, unsigned grid, size_t lds, DType real, int max_xl,
+                                 hipStream_t s);
 
 }  // namespace rgp

@@ -5,15 +5,19 @@
 // (existing neighbours only).  diag/off come from loss_grad; diag is also the Jacobi
 // preconditioner.
 //
-// One PCG iteration is two kernels.  A single-block scalar kernel reduces the block sums of
-// iteration i-1 in block order (bitwise reproducible) to a_{i-1} = r.z / p.w and the next r^T z
-// and r^T r from the recurrences r'.z' = r.z - 2a r.w/d + a^2 w.w/d and
-// r'.r' = r.r - 2a r.w + a^2 w.w (Chronopoulos-Gear), so one grid-wide reduction per iteration
-// suffices and nothing needs atomics or fences.  The main kernel then applies the update
-// pointwise (x += a p, r -= a w, p = r/d + b p), recomputing p at the stencil halo from the
-// previous vectors (which therefore live in ping-pong buffers), forms w = H p and stores its
-// block sums of p.w, r.w/d, w.w/d, r.w and w.w.  In exact arithmetic the iterates are those of
-// textbook PCG.
+// One PCG iteration is one kernel.  Every block first reduces the block sums of iteration i-1
+// in block order (bitwise reproducible) to a_{i-1} = r.z / p.w and the next r^T z and r^T r
+// from the recurrences r'.z' = r.z - 2a r.w/d + a^2 w.w/d and r'.r' = r.r - 2a r.w + a^2 w.w
+// (Chronopoulos-Gear), so one grid-wide reduction per iteration suffices and nothing needs
+// atomics or fences.  It then applies the update (x += a p, r -= a w, p = r/d + b p), recomputing
+// p at the stencil halo from the previous vectors (which therefore live in ping-pong buffers),
+// forms w = H p and stores its block sums of p.w, r.w/d, w.w/d, r.w and w.w.  In exact
+// arithmetic the iterates are those of textbook PCG.
+//
+// The compiler does not fuse multiplies and adds in this file (contraction off below); the
+// arithmetic spells out every fused multiply-add.  Each kernel variant (march shape, prefetch
+// depth, plain or batched launch) therefore rounds exactly alike and a volume gets bitwise the
+// same result whichever variant runs it.
 #include "rgp_internal.hpp"
 #include "rgp_launch.hpp"
 #include "rgp_solver.hpp"
@@ -23,7 +27,12 @@
 #include <mutex>
 #include <tuple>
 
+#pragma clang fp contract(off)
+
 namespace rgp {
+
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 namespace {
 constexpr int kRun = 4;
@@ -71,17 +80,18 @@ __global__ __launch_bounds__(BLK) void k_hvp(HvpArgs a) {
       if (lane == 0 && hasym) vym = v[n - g.nys];
       if (lane == kWave - 1 && hasyp) vyp = v[n + g.nys];
       TR h = dg[n] * vk;
-      if (k > 0) h += oo[s] * vv[s];
-      if (k < mp) h += oo[s + 1] * vv[s + 2];
+      if (k > 0) h = fmad(oo[s], vv[s], h);
+      if (k < mp) h = fmad(oo[s + 1], vv[s + 2], h);
       TR crx = TR(0), cry = TR(0);
       if (hasxm) crx += v[n - g.nxs];
       if (hasxp) crx += v[n + g.nxs];
       if (hasym) cry += vym;
       if (hasyp) cry += vyp;
-      h -= cx * crx + cy * cry;
+      h = fmad(-cx, crx, h);
+      h = fmad(-cy, cry, h);
       if (nodeok && colok) {
         Hv[n] = h;
-        acc[0] += (double)vk * (double)h;
+        acc[0] = fmad((double)vk, (double)h, acc[0]);
       }
     }
   }
@@ -221,14 +231,17 @@ struct Ahead {
 // stored) one plane ahead (o+1) so that the o-neighbours of p stay in registers, writes p of plane
 // o into an LDS plane buffer together with the two halo rows (nb positions on each side of the
 // unit's flat run, recomputed from the previous vectors), and forms w = H p at plane o from LDS
-// (a and b neighbours) and registers (o neighbours).  The raw values of plane o+2 and the halo
-// rows and couplings of plane o+1 are loaded while plane o is computed.  Every step issues the
-// same loads and stores whether or not a lane or plane needs them (unneeded ones go to kNullOff),
-// so each wait covers only the loads of the previous step.  The LDS plane buffer is
+// (a and b neighbours) and registers (o neighbours).  PF = 1: the raw values of plane o+2 and the
+// halo rows and couplings of plane o+1 are loaded while plane o is computed (two register sets
+// in turn).  PF = 3, for marches of at most 3 planes: every plane of the unit is loaded before
+// the first is computed, together with the previous iteration's block sums.  Every step issues
+// the same loads and stores whether or not a lane or plane needs them (unneeded ones go to
+// kNullOff), so each wait covers only the loads the step consumes.  The LDS plane buffer is
 // double-buffered so that one barrier per plane suffices.  Planes just outside the unit
 // contribute p only (recomputed).
-template <typename TR, int ROLE, int BLK, int NPT, int HMAX>
+template <typename TR, int ROLE, int BLK, int NPT, int HMAX, int PF>
 __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& m, VBlock vb) {
+  static_assert(PF == 1 || PF == 3, "prefetch: one plane ahead, or whole units of <= 3 planes");
   extern __shared__ unsigned char lds_raw[];
   TR* lds = reinterpret_cast<TR*>(lds_raw);
   const int it = a.sc.iter;
@@ -278,7 +291,7 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
   bool own[NPT];
   int64_t hpos[HMAX];
   NodeRaw<TR> A0[NPT], M0[NPT];
-  Ahead<TR, NPT, HMAX> S0, S1;
+  Ahead<TR, NPT, HMAX> S0, S1, S2;
   TR Om[NPT];
   auto node = [&](int o, int i) -> int64_t { return (int64_t)o * P + f0 + fl[i]; };
   // PE-lower coupling of node n when the PE axis is a or b (0 at the lower boundary)
@@ -302,7 +315,7 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
     for (int j = 0; j < HMAX; ++j)
       s.halo[j] = load_raw(off_at(cpl_ok && hpos[j] >= 0, (int64_t)(q - 1) * P + hpos[j]), false);
   };
-  // geometry of unit uu and the loads of planes o0-1, o0 and (set S0) o0+1
+  // geometry of unit uu and the loads of planes o0-1, o0 and (sets S0.. ) o0+1 .. o0+PF
   auto begin_unit = [&](int64_t uu) {
     const int ti = (int)(uu / m.noc), oc = (int)(uu - (int64_t)ti * m.noc);
     f0 = (int64_t)ti * T;
@@ -335,6 +348,10 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
       Om[i] = ROLE == 0 ? bld<TR>(rO, off_at(o0 > 0, node(o0 - 1, i))) : TR(0);
     }
     issue(o0 + 1, S0);
+    if (PF == 3) {
+      issue(o0 + 2, S1);
+      issue(o0 + 3, S2);
+    }
   };
 
   // Fused: the previous iteration's block sums are loaded first, then the first unit's planes,
@@ -369,10 +386,10 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
   // Iteration 0 loads w = p = x = 0 and runs with a = b = 0.
   const TR sg = first ? sgn : TR(1);
   auto upd_of = [&](const NodeRaw<TR>& v, TR& r, TR& z, TR& rd) -> TR {
-    r = sg * v.r - al * v.w;
+    r = fmad(-al, v.w, sg * v.r);
     rd = TR(1) / v.d;
     z = r * rd;
-    return z + be * v.p;
+    return fmad(be, v.p, z);
   };
   auto p_of = [&](const NodeRaw<TR>& v) -> TR {
     TR r, z, rd;
@@ -388,7 +405,7 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
     for (int i = 0; i < NPT; ++i) {
       TR r, z, rd;
       const TR p = upd_of(R[i], r, z, rd);
-      const TR xn = R[i].x + al * R[i].p;
+      const TR xn = fmad(al, R[i].p, R[i].x);
       Pq[i] = p;
       // d is carried into the next step, which reloads this register set: adding +0 (kept under
       // IEEE rules) gives it a register of its own, so the reload never waits on a copy
@@ -407,7 +424,7 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
   // plane o: `cur` holds the raw values of o+1 and the couplings and halo rows of o; `nxt`
   // receives those of o+2 and o+1
   auto step = [&](int o, Ahead<TR, NPT, HMAX>& cur, Ahead<TR, NPT, HMAX>& nxt) {
-    issue(o + 2, nxt);
+    if (PF == 1) issue(o + 2, nxt);
     // keep the scheduler from moving these loads behind the wait for the current set
     __builtin_amdgcn_sched_barrier(0);
     update(o + 1, o + 1 < oe, cur.raw, Pn, Dn, Rn, Zn, In);
@@ -431,27 +448,33 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
       const TR pom = o > 0 ? Pm[i] : TR(0), pop = o < no - 1 ? Pn[i] : TR(0);
       TR w = Dc[i] * pk;
       if (ROLE == 0) {
-        w += Om[i] * pom + cur.oc[i] * pop;
-        w -= c_a * (pam + pap) + c_b * (pbm + pbp);
+        w = fmad(Om[i], pom, w);
+        w = fmad(cur.oc[i], pop, w);
+        w = fmad(-c_a, pam + pap, w);
+        w = fmad(-c_b, pbm + pbp, w);
       } else if (ROLE == 1) {
-        w += cur.ob[i] * pam + cur.oc[i] * pap;
-        w -= c_o * (pom + pop) + c_b * (pbm + pbp);
+        w = fmad(cur.ob[i], pam, w);
+        w = fmad(cur.oc[i], pap, w);
+        w = fmad(-c_o, pom + pop, w);
+        w = fmad(-c_b, pbm + pbp, w);
       } else {
-        w += cur.ob[i] * pbm + cur.oc[i] * pbp;
-        w -= c_o * (pom + pop) + c_a * (pam + pap);
+        w = fmad(cur.ob[i], pbm, w);
+        w = fmad(cur.oc[i], pbp, w);
+        w = fmad(-c_o, pom + pop, w);
+        w = fmad(-c_a, pam + pap, w);
       }
       bst<TR>(rWo, off_at(own[i], node(o, i)), w);
       if (own[i]) {
         // FP64 products and sums (r.w/d as z.w, w.w/d and r.r/d with the stored 1/d)
         const double r = (double)Rc[i], ww = (double)w, z = (double)Zc[i], id = (double)Ic[i];
-        acc[0] += (double)pk * ww;
-        acc[1] += z * ww;
-        acc[2] += ww * ww * id;
-        acc[3] += r * ww;
-        acc[4] += ww * ww;
+        acc[0] = fmad((double)pk, ww, acc[0]);
+        acc[1] = fmad(z, ww, acc[1]);
+        acc[2] = fmad(ww * ww, id, acc[2]);
+        acc[3] = fmad(r, ww, acc[3]);
+        acc[4] = fmad(ww, ww, acc[4]);
         if (first) {
-          acc[5] += r * z;
-          acc[6] += r * r;
+          acc[5] = fmad(r, z, acc[5]);
+          acc[6] = fmad(r, r, acc[6]);
         }
       }
     }
@@ -492,22 +515,28 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
 #pragma unroll
     for (int i = 0; i < NPT; ++i) Pm[i] = o0 > 0 ? p_of(M0[i]) : TR(0);
     update(o0, true, A0, Pc, Dc, Rc, Zc, Ic);
-    for (int o = o0; o < oe; o += 2) {
-      step(o, S0, S1);
-      if (o + 1 < oe) step(o + 1, S1, S0);
+    if (PF == 1) {
+      for (int o = o0; o < oe; o += 2) {
+        step(o, S0, S1);
+        if (o + 1 < oe) step(o + 1, S1, S0);
+      }
+    } else {  // oe - o0 <= 3 (the planner's guarantee for PF = 3)
+      step(o0, S0, S0);
+      if (o0 + 1 < oe) step(o0 + 1, S1, S1);
+      if (o0 + 2 < oe) step(o0 + 2, S2, S2);
     }
     __syncthreads();  // the next unit reuses the LDS buffers
   }
   store_partials_cm<7, BLK>(acc, a.part, vb.id);
 }
 
-template <typename TR, int ROLE, int BLK, int NPT, int HMAX>
+template <typename TR, int ROLE, int BLK, int NPT, int HMAX, int PF>
 __global__ __launch_bounds__(BLK) void k_pcg_step(PcgArgs a, MarchGeo m) {
-  pcg_step_body<TR, ROLE, BLK, NPT, HMAX>(a, m, hw_block());
+  pcg_step_body<TR, ROLE, BLK, NPT, HMAX, PF>(a, m, hw_block());
 }
 
 // One launch over several volumes (their PE axes may differ: the march role is per volume).
-template <typename TR, int BLK, int NPT, int HMAX>
+template <typename TR, int BLK, int NPT, int HMAX, int PF>
 __global__ __launch_bounds__(BLK) void k_pcg_step_batch(const PcgArgs* __restrict__ tab,
                                                         const MarchGeo* __restrict__ geo,
                                                         const uint32_t* __restrict__ starts,
@@ -516,11 +545,11 @@ __global__ __launch_bounds__(BLK) void k_pcg_step_batch(const PcgArgs* __restric
   const int p = batch_volume(starts, n, vb);
   const MarchGeo m = geo[p];
   if (m.role == 0)
-    pcg_step_body<TR, 0, BLK, NPT, HMAX>(tab[p], m, vb);
+    pcg_step_body<TR, 0, BLK, NPT, HMAX, PF>(tab[p], m, vb);
   else if (m.role == 1)
-    pcg_step_body<TR, 1, BLK, NPT, HMAX>(tab[p], m, vb);
+    pcg_step_body<TR, 1, BLK, NPT, HMAX, PF>(tab[p], m, vb);
   else
-    pcg_step_body<TR, 2, BLK, NPT, HMAX>(tab[p], m, vb);
+    pcg_step_body<TR, 2, BLK, NPT, HMAX, PF>(tab[p], m, vb);
 }
 
 Launch plan_hvp(const Geom& g, DType real) {
@@ -615,18 +644,26 @@ hipError_t launch_sum_final(const double* part, unsigned nprod, double* out, hip
   return hipGetLastError();
 }
 
-template <typename TR, int BLK, int NPT, int HMAX>
-static void launch_step_cfg(const PcgArgs& a, const PcgPlan& L, hipStream_t s) {
+template <typename TR, int BLK, int NPT, int HMAX, int PF>
+static void launch_step_pf(const PcgArgs& a, const PcgPlan& L, hipStream_t s) {
   const int role = L.m.role;
   if (role == 0)
-    RGP_LAUNCH_T(kKindPcgStep, a.sc.iter, a.g, (k_pcg_step<TR, 0, BLK, NPT, HMAX>), L.grid, BLK,
-                 L.lds, s, a, L.m);
+    RGP_LAUNCH_T(kKindPcgStep, a.sc.iter, a.g, (k_pcg_step<TR, 0, BLK, NPT, HMAX, PF>), L.grid,
+                 BLK, L.lds, s, a, L.m);
   else if (role == 1)
-    RGP_LAUNCH_T(kKindPcgStep, a.sc.iter, a.g, (k_pcg_step<TR, 1, BLK, NPT, HMAX>), L.grid, BLK,
-                 L.lds, s, a, L.m);
+    RGP_LAUNCH_T(kKindPcgStep, a.sc.iter, a.g, (k_pcg_step<TR, 1, BLK, NPT, HMAX, PF>), L.grid,
+                 BLK, L.lds, s, a, L.m);
   else
-    RGP_LAUNCH_T(kKindPcgStep, a.sc.iter, a.g, (k_pcg_step<TR, 2, BLK, NPT, HMAX>), L.grid, BLK,
-                 L.lds, s, a, L.m);
+    RGP_LAUNCH_T(kKindPcgStep, a.sc.iter, a.g, (k_pcg_step<TR, 2, BLK, NPT, HMAX, PF>), L.grid,
+                 BLK, L.lds, s, a, L.m);
+}
+// units of at most 3 planes load all of them up front
+template <typename TR, int BLK, int NPT, int HMAX>
+static void launch_step_cfg(const PcgArgs& a, const PcgPlan& L, hipStream_t s) {
+  if (L.m.XL <= 3)
+    launch_step_pf<TR, BLK, NPT, HMAX, 3>(a, L, s);
+  else
+    launch_step_pf<TR, BLK, NPT, HMAX, 1>(a, L, s);
 }
 
 hipError_t launch_pcg_step(const PcgArgs& a, DType real, hipStream_t s) {
@@ -676,16 +713,27 @@ hipError_t launch_pcg_scalars_batch(const void* tab, int n, hipStream_t s) {
 }
 
 hipError_t launch_pcg_step_batch(const void* tab, const MarchGeo* geo, const uint32_t* starts,
-                                 int n, unsigned grid, size_t lds, DType real, hipStream_t s) {
+                                 int n, unsigned grid, size_t lds, DType real, int max_xl,
+                                 hipStream_t s) {
   const PcgArgs* t = static_cast<const PcgArgs*>(tab);
-  if (real == DType::F64)
-    hipLaunchKernelGGL((k_pcg_step_batch<double, 256, 1, 2>), dim3(grid), dim3(256), lds, s, t,
-                       geo, starts, n);
-  else if (real == DType::F32)
-    hipLaunchKernelGGL((k_pcg_step_batch<float, 256, 1, 2>), dim3(grid), dim3(256), lds, s, t,
-                       geo, starts, n);
-  else
+  const bool whole = max_xl <= 3;
+  if (real == DType::F64) {
+    if (whole)
+      hipLaunchKernelGGL((k_pcg_step_batch<double, 256, 1, 2, 3>), dim3(grid), dim3(256), lds, s,
+                         t, geo, starts, n);
+    else
+      hipLaunchKernelGGL((k_pcg_step_batch<double, 256, 1, 2, 1>), dim3(grid), dim3(256), lds, s,
+                         t, geo, starts, n);
+  } else if (real == DType::F32) {
+    if (whole)
+      hipLaunchKernelGGL((k_pcg_step_batch<float, 256, 1, 2, 3>), dim3(grid), dim3(256), lds, s,
+                         t, geo, starts, n);
+    else
+      hipLaunchKernelGGL((k_pcg_step_batch<float, 256, 1, 2, 1>), dim3(grid), dim3(256), lds, s,
+                         t, geo, starts, n);
+  } else {
     return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

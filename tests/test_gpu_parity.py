@@ -543,6 +543,33 @@ def test_batch_plan_matches_per_pair(img):
     assert float(np.max(np.abs(to_host(bp.b[0]) - ora.b))) <= BFINAL_ATOL
 
 
+def test_batch_mixed_marches_bitwise():
+    """A batched launch uses one kernel variant for all pairs: here the middle level of the first
+    pair marches 2 planes per unit (alone it loads whole units up front) while the second pair's
+    marches 4, so the shared launch runs the pipelined variant for both.  The variants spell out
+    the same arithmetic, so the first pair's field must be bitwise the one it gets alone."""
+    rgp = _rgp()
+    specs = [((188, 144, 80), 0), ((200, 200, 160), 0)]
+    pairs = [_pair(sh, pe, seed=70 + i, scale=30.0) for i, (sh, pe) in enumerate(specs)]
+    pes = [pe for _, pe in specs]
+    opts = rgp.Options(levels=2, gn_iters=2, pcg_iters=6, pcg_rtol=0.0)
+    dt = torch.float32
+    Ip = [to_dev(p.I_plus, dt) for p in pairs]
+    Im = [to_dev(p.I_minus, dt) for p in pairs]
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        bp = rgp.BatchPlan(Ip, Im, pes, opts, stream=s)
+        bp.launch(s)
+        s.synchronize()
+    for i, (sh, pe) in enumerate(specs):
+        ref = rgp.correct(Ip[i], Im[i], pe, opts=opts, real_dtype=dt)
+        d = float(torch.max(torch.abs(bp.b[i] - ref["b"])))
+        say(f"[batch mixed marches] pair {i} {sh}: max|b_batch - b_pair| = {d:.3e}")
+        assert torch.equal(bp.b[i], ref["b"]), (i, d)
+    bp.close()
+
+
 def test_autotune_then_correct():
     """The autotuner picks one march length per level from the candidates; afterwards the
     correction (plain and batched) still matches the untuned result up to the order of the block
