@@ -114,6 +114,8 @@ Geom make_geom(const int64_t m[3], int pe, const double h[3]) {
   g.hy = h[ax[1]];
   g.hp = h[pe];
   g.vol = h[0] * h[1] * h[2];
+  g.by_ny = make_fastdiv((uint32_t)g.ny);
+  g.by_nct = make_fastdiv((uint32_t)((g.ncol + kWave - 1) / kWave));
   return g;
 }
 

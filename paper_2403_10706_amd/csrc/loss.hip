@@ -58,37 +58,43 @@ __device__ __forceinline__ CellOut<TR> eval_cell(const TI* __restrict__ Ip, cons
   return o;
 }
 
+// t clamped to [-lim, lim] (one median-of-three).
+__device__ __forceinline__ float clamp_abs(float t, float lim) {
+  return __builtin_amdgcn_fmed3f(t, -lim, lim);
+}
+__device__ __forceinline__ double clamp_abs(double t, double lim) { return fmin(fmax(t, -lim), lim); }
+
+// 1/q: the hardware reciprocal in FP32 (1 ulp), a division in FP64.
+__device__ __forceinline__ float recip(float q) { return __builtin_amdgcn_rcpf(q); }
+__device__ __forceinline__ double recip(double q) { return 1.0 / q; }
+
 // phi(z) = z^4/(1-z^2), phi', phi'' (Eq. 3); valid for |z| < 1.
 template <typename TR>
 __device__ __forceinline__ void phi3(TR z, TR& f, TR& f1, TR& f2) {
   const TR z2 = z * z;
-  const TR q = TR(1) - z2;
-  const TR iq = TR(1) / q;
+  const TR iq = recip(TR(1) - z2);
+  const TR iq2 = iq * iq;
   f = z2 * z2 * iq;
-  f1 = TR(2) * z2 * z * (TR(2) - z2) * iq * iq;
-  f2 = TR(2) * z2 * (TR(6) - TR(3) * z2 + z2 * z2) * iq * iq * iq;
+  f1 = TR(2) * z2 * z * (TR(2) - z2) * iq2;
+  f2 = TR(2) * z2 * (TR(6) - TR(3) * z2 + z2 * z2) * iq2 * iq;
 }
 
 // --------------------------------------------------------------------------------------------
 // loss_grad: block sums of D, S, P (and |grad J|^2); optionally grad J and the GN tridiagonal
-// (diag, off).  With step != 0 it first forms b = b_in + gamma q (gamma and the acceptance from
-// the line search) and writes it to b_out, a different buffer since neighbours read b_in.
+// (diag, off).  With STEP it first forms b = b_in + gamma q (gamma and the acceptance from the
+// line search) and writes it to b_out, a different buffer since neighbours read b_in.
+// Per tile every lane first issues all loads of its run (b, and q with STEP, at nodes k0-1 ..
+// k0+S, the x neighbours, and on the first / last lane of the wavefront the y neighbours, which
+// the other lanes take from the adjacent lane), then the image taps of its S+1 cells, then
+// computes.  Every load and store is unconditional: unneeded ones use kNullOff, and a missing
+// output array is a descriptor of size 0.
 // --------------------------------------------------------------------------------------------
-template <typename TI, typename TR, int S, int BLK>
+template <typename TI, typename TR, int S, int BLK, bool STEP>
 __device__ __forceinline__ void loss_grad_body(const LossGradArgs& a, VBlock vb) {
   const Geom g = a.g;
-  const TI* __restrict__ Ip = static_cast<const TI*>(a.Ip);
-  const TI* __restrict__ Im = static_cast<const TI*>(a.Im);
-  const TR* __restrict__ bin = static_cast<const TR*>(a.b_in);
-  const TR* __restrict__ q = static_cast<const TR*>(a.q);
-  TR* __restrict__ bout = static_cast<TR*>(a.b_out);
-  TR* __restrict__ grad = static_cast<TR*>(a.grad);
-  TR* __restrict__ diag = static_cast<TR*>(a.diag);
-  TR* __restrict__ off = static_cast<TR*>(a.off);
   State* st = a.st;
   const int mp = g.mp;
-  const int64_t nct = (g.ncol + kWave - 1) / kWave;
-  const int64_t ntiles = nct * ((mp + 1 + S - 1) / S);
+  const int64_t ntiles = (int64_t)g.by_nct.d * ((mp + 1 + S - 1) / S);
   const int lane = threadIdx.x & (kWave - 1);
 
   if (a.level_start && vb.id == 0 && threadIdx.x == 0) {
@@ -96,28 +102,28 @@ __device__ __forceinline__ void loss_grad_body(const LossGradArgs& a, VBlock vb)
     st->accepted = 0;
   }
   TR coef = TR(0);
-  if (a.step) {
+  if (STEP) {
     if (load_flag(&st->gn_stop)) {  // the solve stopped on this level: carry b over unchanged
-      for (WaveIter it = wave_iter(ntiles, vb); it.t < it.end; it.t += it.stride) {
-        const int64_t col = (it.t % nct) * kWave + lane;
-        const int k0 = (int)(it.t / nct) * S;
-        if (col >= g.ncol) continue;
-        const int64_t nb = node_base(g, col);
-        for (int s = 0; s < S; ++s) {
-          const int k = k0 + s;
-          if (k <= mp) bout[nb + (int64_t)k * g.nps] = bin[nb + (int64_t)k * g.nps];
-        }
-      }
+      const TR* __restrict__ bin = static_cast<const TR*>(a.b_in);
+      TR* __restrict__ bout = static_cast<TR*>(a.b_out);
+      const int64_t stride = (int64_t)vb.n * blockDim.x;
+      for (int64_t i = (int64_t)vb.id * blockDim.x + threadIdx.x; i < g.nnode; i += stride)
+        bout[i] = bin[i];
       return;
     }
     coef = st->accepted ? (TR)st->gamma : TR(0);
   }
 
-  auto ldb = [&](int64_t n) -> TR {
-    TR v = bin[n];
-    if (a.step) v += coef * q[n];
-    return v;
-  };
+  constexpr uint32_t kSr = sizeof(TR), kSi = sizeof(TI);
+  const uint32_t nbytes = (uint32_t)(g.nnode * (int64_t)kSr);
+  const uint32_t cbytes = (uint32_t)(g.ncell * (int64_t)kSi);
+  const BRes rIp = bres(a.Ip, cbytes), rIm = bres(a.Im, cbytes);
+  const BRes rB = bres(a.b_in, nbytes), rQ = bres(STEP ? a.q : nullptr, STEP ? nbytes : 0u);
+  const BRes rBo = bres(a.b_out, STEP && a.b_out ? nbytes : 0u);
+  const BRes rG = bres(a.grad, a.grad ? nbytes : 0u);
+  const BRes rD = bres(a.diag, a.diag ? nbytes : 0u), rO = bres(a.off, a.diag ? nbytes : 0u);
+  const uint32_t nps = (uint32_t)g.nps, nxs = (uint32_t)g.nxs, nys = (uint32_t)g.nys;
+  const uint32_t cps = (uint32_t)g.cps;
 
   const TR inv_hp = TR(1) / (TR)g.hp;
   const TR wp2 = TR(1) / ((TR)g.hp * (TR)g.hp);
@@ -126,126 +132,155 @@ __device__ __forceinline__ void loss_grad_body(const LossGradArgs& a, VBlock vb)
   const TR vol = (TR)g.vol;
   const TR avol = (TR)(a.alpha * g.vol);
   const TR bh = (TR)(0.5 * a.beta * g.vol);
+  const TR hih = TR(0.5) * inv_hp, bhi = bh * inv_hp, bhw = bh * wp2, avw = avol * wp2;
+  const TR lim = TR(mp + 2);
 
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // r^2, S terms, phi, violations, g^2
 
   for (WaveIter it = wave_iter(ntiles, vb); it.t < it.end; it.t += it.stride) {
-    const int64_t col = (it.t % nct) * kWave + lane;
-    const int k0 = (int)(it.t / nct) * S;
-    const bool colok = col < g.ncol;
-    const int64_t colc = colok ? col : g.ncol - 1;
-    const int64_t ix = colc / g.ny, iy = colc - (colc / g.ny) * g.ny;
-    const int64_t nb = ix * g.nxs + iy * g.nys;
-    const int64_t cb = ix * g.cxs + iy * g.cys;
-    const bool hasym = iy > 0, hasyp = iy < g.ny - 1;
-    const bool hasxm = ix > 0, hasxp = ix < g.nx - 1;
+    const ColTile c = col_tile(g, it.t, S);
+    const int k0 = c.k0;
+    auto noff = [&](int k) -> uint32_t { return (c.nb + (uint32_t)k * nps) * kSr; };
 
-    // b at nodes k0-1 .. k0+S (index i <-> node k0-1+i), clamped into the column.
-    TR bb[S + 2];
+    // 1. b (and q) at nodes k0-1 .. k0+S clamped into the column, the x neighbours and the
+    //    wavefront-edge y neighbours of nodes k0 .. k0+S-1 (node k clamped to mp)
+    TR bv[S + 2], qv[S + 2], xm[S], xp[S], ym[S], yp[S], qxm[S], qxp[S], qym[S], qyp[S];
 #pragma unroll
     for (int i = 0; i < S + 2; ++i) {
-      int k = k0 - 1 + i;
-      k = k < 0 ? 0 : (k > mp ? mp : k);
-      bb[i] = ldb(nb + (int64_t)k * g.nps);
+      const int k = min(max(k0 - 1 + i, 0), mp);
+      bv[i] = bld<TR>(rB, noff(k));
+      if (STEP) qv[i] = bld<TR>(rQ, noff(k));
     }
-
-    // Right-hand contributions of cell k0-1 to node k0.
-    TR gR = TR(0), dR = TR(0);
-    {
-      const int j = k0 - 1;
-      if (j >= 0 && j < mp) {
-        const CellOut<TR> c = eval_cell(Ip, Im, cb, g.cps, mp, j, bb[0], bb[1], inv_hp);
-        TR f = TR(0), f1 = TR(0), f2 = TR(0);
-        if (fabs(c.db) < TR(1)) phi3(c.db, f, f1, f2);
-        gR = vol * c.r * c.u1 + bh * f1 * inv_hp;
-        dR = vol * c.u1 * c.u1 + bh * f2 * wp2;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t n = c.nb + (uint32_t)min(k0 + s, mp) * nps;
+      const uint32_t oxm = c.hasxm ? (n - nxs) * kSr : kNullOff;
+      const uint32_t oxp = c.hasxp ? (n + nxs) * kSr : kNullOff;
+      const uint32_t oym = (lane == 0 && c.hasym) ? (n - nys) * kSr : kNullOff;
+      const uint32_t oyp = (lane == kWave - 1 && c.hasyp) ? (n + nys) * kSr : kNullOff;
+      xm[s] = bld<TR>(rB, oxm);
+      xp[s] = bld<TR>(rB, oxp);
+      ym[s] = bld<TR>(rB, oym);
+      yp[s] = bld<TR>(rB, oyp);
+      if (STEP) {
+        qxm[s] = bld<TR>(rQ, oxm);
+        qxp[s] = bld<TR>(rQ, oxp);
+        qym[s] = bld<TR>(rQ, oym);
+        qyp[s] = bld<TR>(rQ, oyp);
+      }
+    }
+    if (STEP) {
+#pragma unroll
+      for (int i = 0; i < S + 2; ++i) bv[i] += coef * qv[i];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        xm[s] += coef * qxm[s];
+        xp[s] += coef * qxp[s];
+        ym[s] += coef * qym[s];
+        yp[s] += coef * qyp[s];
       }
     }
 
+    // 2. image taps of cells k0-1 .. k0+S-1 (cell index k0-1+i for i = 0..S): the linear image
+    //    model is zero outside the column, which the out-of-range offset reproduces (a sample
+    //    position beyond +-(mp+2) cells has both taps outside, so it is clamped there first)
+    TR vp0[S + 1], vp1[S + 1], vm0[S + 1], vm1[S + 1], wp[S + 1], wm[S + 1];
+#pragma unroll
+    for (int i = 0; i <= S; ++i) {
+      const int j = k0 - 1 + i;
+      const TR t = clamp_abs((bv[i] + bv[i + 1]) * hih, lim);
+      const TR fp = floor(t), fm = floor(-t);
+      wp[i] = t - fp;
+      wm[i] = -t - fm;
+      const int kp = j + (int)fp, km = j + (int)fm;
+      const uint32_t rp = c.cb + (uint32_t)kp * cps, rm = c.cb + (uint32_t)km * cps;
+      vp0[i] = bld_img<TI, TR>(rIp, (uint32_t)kp < (uint32_t)mp ? rp * kSi : kNullOff);
+      vp1[i] = bld_img<TI, TR>(rIp, (uint32_t)(kp + 1) < (uint32_t)mp ? (rp + cps) * kSi : kNullOff);
+      vm0[i] = bld_img<TI, TR>(rIm, (uint32_t)km < (uint32_t)mp ? rm * kSi : kNullOff);
+      vm1[i] = bld_img<TI, TR>(rIm, (uint32_t)(km + 1) < (uint32_t)mp ? (rm + cps) * kSi : kNullOff);
+    }
+
+    // 3. per cell i (between nodes k0-1+i and k0+i): residual r, its derivatives u0, u1 with
+    //    respect to the lower and upper node, phi; then the cell's gradient and Hessian
+    //    contributions to its upper node (gU, dU), to its lower node (gD, dD) and the coupling
+    //    of the two nodes (oc)
+    TR gU[S + 1], dU[S + 1], gD[S + 1], dD[S + 1], oc[S + 1];
+    TR tr2 = TR(0), tf = TR(0), tviol = TR(0);
+#pragma unroll
+    for (int i = 0; i <= S; ++i) {
+      const TR db = (bv[i + 1] - bv[i]) * inv_hp;
+      const TR ep = vp1[i] - vp0[i], em = vm1[i] - vm0[i];
+      const TR valp = fma(wp[i], ep, vp0[i]), valm = fma(wm[i], em, vm0[i]);
+      const TR ap = TR(1) + db, am = TR(1) - db;
+      const TR r = valp * ap - valm * am;
+      const TR c1h = (ep * ap + em * am) * hih;   // (slope+ (1+Db) + slope- (1-Db)) / 2
+      const TR c2h = (valp + valm) * inv_hp;
+      const TR u0 = c1h - c2h, u1 = c1h + c2h;
+      TR f = TR(0), f1 = TR(0), f2 = TR(0);
+      const bool viol = !(fabs(db) < TR(1));
+      if (!viol) phi3(db, f, f1, f2);
+      const TR vr = vol * r, pf1 = bhi * f1, pf2 = bhw * f2;
+      gU[i] = fma(vr, u1, pf1);
+      dU[i] = fma(vol * u1, u1, pf2);
+      gD[i] = fma(vr, u0, -pf1);
+      dD[i] = fma(vol * u0, u0, pf2);
+      oc[i] = fma(vol * u0, u1, -pf2) - avw;
+      // cells of the column only (cell index 0 .. mp-1), nodes of the run only (i >= 1)
+      const int j = k0 - 1 + i;
+      if (i >= 1 && j < mp && c.colok) {
+        tr2 = fma(r, r, tr2);
+        tf += f;
+        tviol += viol ? TR(1) : TR(0);
+      }
+    }
+
+    // 4. per node k = k0 + s: cells k-1 (index s, its upper node) and k (index s+1, its lower
+    //    node), the Laplacian (Neumann) and the forward differences of S
+    TR tst = TR(0), tg2 = TR(0);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int k = k0 + s;
-      const bool nodeok = k <= mp;
-      const TR bk = bb[s + 1];
-      // y neighbours through lane shuffles; the first/last lane of the wave loads from memory.
-      TR bym = __shfl_up(bk, 1, kWave);
-      TR byp = __shfl_down(bk, 1, kWave);
-      const int kc = nodeok ? k : mp;
-      const int64_t n = nb + (int64_t)kc * g.nps;
-      if (lane == 0 && hasym) bym = ldb(n - g.nys);
-      if (lane == kWave - 1 && hasyp) byp = ldb(n + g.nys);
-      const TR bxm = hasxm ? ldb(n - g.nxs) : bk;
-      const TR bxp = hasxp ? ldb(n + g.nxs) : bk;
-
-      // Own cell k (left contributions to node k).
-      TR gL = TR(0), dL = TR(0), oc = TR(0);
-      TR nR = TR(0), ndR = TR(0);
-      if (nodeok && k < mp) {
-        const CellOut<TR> c = eval_cell(Ip, Im, cb, g.cps, mp, k, bk, bb[s + 2], inv_hp);
-        TR f = TR(0), f1 = TR(0), f2 = TR(0);
-        if (fabs(c.db) < TR(1)) {
-          phi3(c.db, f, f1, f2);
-        } else if (colok) {
-          acc[3] += 1.0;
-        }
-        gL = vol * c.r * c.u0 - bh * f1 * inv_hp;
-        dL = vol * c.u0 * c.u0 + bh * f2 * wp2;
-        oc = vol * c.u0 * c.u1 - bh * f2 * wp2 - avol * wp2;
-        nR = vol * c.r * c.u1 + bh * f1 * inv_hp;
-        ndR = vol * c.u1 * c.u1 + bh * f2 * wp2;
-        if (colok) {
-          acc[0] += (double)c.r * (double)c.r;
-          acc[2] += (double)f;
-        }
+      const bool nodeok = k <= mp, lo = k > 0, up = k < mp;
+      const TR bk = bv[s + 1];
+      const TR bym = from_lower_lane(bk, ym[s]), byp = from_upper_lane(bk, yp[s]);
+      const TR dpm = bk - bv[s], dpp = bv[s + 2] - bk;
+      const TR dxm = bk - xm[s], dxp = xp[s] - bk, dym = bk - bym, dyp = byp - bk;
+      TR lap = TR(0), ldg = TR(0), st = TR(0);
+      if (lo) { lap = fma(dpm, wp2, lap); ldg += wp2; }
+      if (up) { lap = fma(-dpp, wp2, lap); ldg += wp2; st = fma(dpp * dpp, wp2, st); }
+      if (c.hasxm) { lap = fma(dxm, wx2, lap); ldg += wx2; }
+      if (c.hasxp) { lap = fma(-dxp, wx2, lap); ldg += wx2; st = fma(dxp * dxp, wx2, st); }
+      if (c.hasym) { lap = fma(dym, wy2, lap); ldg += wy2; }
+      if (c.hasyp) { lap = fma(-dyp, wy2, lap); ldg += wy2; st = fma(dyp * dyp, wy2, st); }
+      const TR gk = (lo ? gU[s] : TR(0)) + (up ? gD[s + 1] : TR(0)) + avol * lap;
+      const TR dk = (lo ? dU[s] : TR(0)) + (up ? dD[s + 1] : TR(0)) + avol * ldg;
+      const bool out = nodeok && c.colok;
+      if (out) {
+        tst += st;
+        tg2 = fma(gk, gk, tg2);
       }
-      if (nodeok && colok) {
-        // Laplacian (Neumann) at node k and the forward differences of S.
-        TR lap = TR(0), ldg = TR(0);
-        double sterm = 0.0;
-        if (k > 0) {
-          lap += (bk - bb[s]) * wp2;
-          ldg += wp2;
-        }
-        if (k < mp) {
-          const TR d = bb[s + 2] - bk;
-          lap -= d * wp2;
-          ldg += wp2;
-          sterm += (double)(d * d * wp2);
-        }
-        if (hasxm) { lap += (bk - bxm) * wx2; ldg += wx2; }
-        if (hasxp) {
-          const TR d = bxp - bk;
-          lap -= d * wx2;
-          ldg += wx2;
-          sterm += (double)(d * d * wx2);
-        }
-        if (hasym) { lap += (bk - bym) * wy2; ldg += wy2; }
-        if (hasyp) {
-          const TR d = byp - bk;
-          lap -= d * wy2;
-          ldg += wy2;
-          sterm += (double)(d * d * wy2);
-        }
-        const TR gk = gR + gL + avol * lap;
-        acc[1] += sterm;
-        acc[4] += (double)gk * (double)gk;
-        if (grad) grad[n] = gk;
-        if (diag) {
-          diag[n] = dR + dL + avol * ldg;
-          off[n] = (k < mp) ? oc : TR(0);
-        }
-        if (bout) bout[n] = bk;
-      }
-      gR = nR;
-      dR = ndR;
+      const uint32_t o = out ? noff(k) : kNullOff;
+      bst<TR>(rG, o, gk);
+      bst<TR>(rD, o, dk);
+      bst<TR>(rO, o, up ? oc[s + 1] : TR(0));
+      bst<TR>(rBo, o, bk);
     }
+    // the tile's sums (at most S+1 terms each) join the FP64 block sums
+    acc[0] += (double)tr2;
+    acc[1] += (double)tst;
+    acc[2] += (double)tf;
+    acc[3] += (double)tviol;
+    acc[4] += (double)tg2;
   }
   store_partials<5, BLK>(acc, a.part, vb.id);
 }
 
 template <typename TI, typename TR, int S, int BLK>
 __global__ __launch_bounds__(BLK) void k_loss_grad(LossGradArgs a) {
-  loss_grad_body<TI, TR, S, BLK>(a, hw_block());
+  if (a.step)
+    loss_grad_body<TI, TR, S, BLK, true>(a, hw_block());
+  else
+    loss_grad_body<TI, TR, S, BLK, false>(a, hw_block());
 }
 
 // One launch over several volumes: tab[p] drives the workgroups starts[p] .. starts[p+1]-1.
@@ -255,10 +290,18 @@ __global__ __launch_bounds__(BLK) void k_loss_grad_batch(const LossGradArgs* __r
                                                          int n) {
   VBlock vb;
   const int p = batch_volume(starts, n, vb);
-  if (tab[p].run == 4)
-    loss_grad_body<TI, TR, 4, BLK>(tab[p], vb);
-  else
-    loss_grad_body<TI, TR, 2, BLK>(tab[p], vb);
+  const LossGradArgs& a = tab[p];
+  if (a.run == 4) {
+    if (a.step)
+      loss_grad_body<TI, TR, 4, BLK, true>(a, vb);
+    else
+      loss_grad_body<TI, TR, 4, BLK, false>(a, vb);
+  } else {
+    if (a.step)
+      loss_grad_body<TI, TR, 2, BLK, true>(a, vb);
+    else
+      loss_grad_body<TI, TR, 2, BLK, false>(a, vb);
+  }
 }
 
 // J, D, S, P from loss_grad's block sums (standalone entry point; one block).

@@ -26,11 +26,26 @@ __global__ __launch_bounds__(kBlock) void k_shift(ShiftArgs a) {
   const TI* __restrict__ P = static_cast<const TI*>(a.Ip);
   const TI* __restrict__ M = static_cast<const TI*>(a.Im);
   double lo = inf_d(), hi = 0.0;
+  // kU elements of each image per thread and round, all loads in flight together (indices
+  // clamped into the array; the surplus ones are not counted)
+  constexpr int kU = 8;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += stride) {
-    const double p = to_real(P[i], double()), m = to_real(M[i], double());
-    lo = fmin(lo, fmin(p, m));
-    hi = fmax(hi, fmax(fabs(p), fabs(m)));
+  for (int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x; i0 < a.n; i0 += kU * stride) {
+    TI pv[kU], mv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t i = min(i0 + u * stride, a.n - 1);
+      pv[u] = P[i];
+      mv[u] = M[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (i0 + u * stride < a.n) {
+        const double p = to_real(pv[u], double()), m = to_real(mv[u], double());
+        lo = fmin(lo, fmin(p, m));
+        hi = fmax(hi, fmax(fabs(p), fabs(m)));
+      }
+    }
   }
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) {
@@ -124,8 +139,6 @@ __global__ __launch_bounds__(kBlock) void k_ot(OtArgs a, int nc) {
   const TI* __restrict__ Ip = static_cast<const TI*>(a.Ip);
   const TI* __restrict__ Im = static_cast<const TI*>(a.Im);
   TR* __restrict__ b0 = static_cast<TR*>(a.b0);
-  const double s = shift_from(a.shift_part, a.shift_nprod, a.eps, g.ncell == 0);
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.st->ot_shift = s;
   const double hp = g.hp;
 
   const int c = threadIdx.x % nc;
@@ -144,14 +157,37 @@ __global__ __launch_bounds__(kBlock) void k_ot(OtArgs a, int nc) {
   if (threadIdx.x == 0) blockclip = 0ull;
 
   // 1. shifted cell values, local inclusive scans per segment: C[j+1] = sum_{j0 <= j' <= j}.
+  //    The cells of a segment are loaded kChunk at a time, all loads of a chunk in flight
+  //    together (indices clamped into the column, surplus values unused); the first chunk is
+  //    issued before the positivity shift is reduced, so the two overlap.
   const int L = (mp + nseg - 1) / nseg;
   const int j0 = min(mp, seg * L), j1 = min(mp, j0 + L);
+  constexpr int kChunk = 16;
+  TI vp[kChunk], vm[kChunk];
+  auto load_chunk = [&](int jb) {
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int j = max(0, min(jb + u, j1 - 1));
+      vp[u] = Ip[cb + (int64_t)j * g.cps];
+      vm[u] = Im[cb + (int64_t)j * g.cps];
+    }
+  };
+  load_chunk(j0);
+  const double s = shift_from(a.shift_part, a.shift_nprod, a.eps, g.ncell == 0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.st->ot_shift = s;
   double accp = 0.0, accm = 0.0;
-  for (int j = j0; j < j1; ++j) {
-    accp += to_real(Ip[cb + (int64_t)j * g.cps], double()) + s;
-    accm += to_real(Im[cb + (int64_t)j * g.cps], double()) + s;
-    cp[(j + 1) * stride] = accp;
-    cm[(j + 1) * stride] = accm;
+  for (int jb = j0; jb < j1; jb += kChunk) {
+    if (jb != j0) load_chunk(jb);
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int j = jb + u;
+      if (j < j1) {
+        accp += to_real(vp[u], double()) + s;
+        accm += to_real(vm[u], double()) + s;
+        cp[(j + 1) * stride] = accp;
+        cm[(j + 1) * stride] = accm;
+      }
+    }
   }
   segp[seg * nc + c] = accp;
   segm[seg * nc + c] = accm;
@@ -266,11 +302,15 @@ size_t ot_lds_bytes(int mp, int nc) {
   return ((size_t)(mp + 1) * nc * 3 + (size_t)nseg * nc * 2) * sizeof(double);
 }
 
-// Columns per workgroup: the most (up to 16) whose three FP64 column arrays fit the LDS budget.
+// Columns per workgroup: the most (up to 16) whose three FP64 column arrays leave room for four
+// workgroups per CU (160 KB of LDS); the inverse-CDF phase is chains of dependent LDS reads, so
+// resident workgroups matter more than columns per workgroup.  Long columns fall back to the most
+// that fit at all.
 int ot_cols_per_block(int mp) {
-  const size_t budget = 150 * 1024;
   for (int nc = 16; nc >= 1; nc >>= 1)
-    if (ot_lds_bytes(mp, nc) <= budget) return nc;
+    if (ot_lds_bytes(mp, nc) <= 40 * 1024) return nc;
+  for (int nc = 16; nc >= 1; nc >>= 1)
+    if (ot_lds_bytes(mp, nc) <= 150 * 1024) return nc;
   return 0;
 }
 

@@ -36,6 +36,23 @@ __device__ __forceinline__ double to_real(float v, double) { return static_cast<
 __device__ __forceinline__ float to_real(double v, float) { return static_cast<float>(v); }
 __device__ __forceinline__ double to_real(double v, double) { return v; }
 
+// Division by a loop-invariant divisor d >= 1 with one high multiply, an add and a shift
+// (Granlund and Montgomery, "Division by invariant integers using multiplication", 1994):
+// for 0 <= n < 2^31, n / d = (umulhi(n, mul) + n) >> shr with shr = ceil(log2 d) and
+// mul = floor(2^32 (2^shr - d) / d) + 1.
+struct FastDiv {
+  uint32_t d, mul, shr;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((uint64_t(1) << l) < d) ++l;
+  const uint64_t m = ((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1;
+  return FastDiv{d, (uint32_t)m, l};
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  return (__umulhi(n, f.mul) + n) >> f.shr;
+}
+
 // Geometry of one volume on one pyramid level.
 struct Geom {
   int32_t mp;       // cells along the PE axis (nodes: mp + 1)
@@ -46,6 +63,8 @@ struct Geom {
   int64_t nxs, nys, nps;  // node (field) strides of x, y and PE
   int64_t ncell, nnode;
   double hx, hy, hp, vol;
+  FastDiv by_ny;    // column -> (x, y) index
+  FastDiv by_nct;   // column-kernel tile -> (run along PE, chunk of 64 columns)
 };
 
 __host__ __device__ inline int64_t cell_base(const Geom& g, int64_t col) {
@@ -347,6 +366,83 @@ __device__ __forceinline__ void load_partials_cm(double (&out)[K], const double*
 #pragma unroll
       for (int j = 0; j < 4; ++j) out[k] += v[k][j];
   }
+}
+
+// Image sample at a byte offset of an image descriptor (kNullOff or outside the image: 0).
+template <typename TI, typename TR>
+__device__ __forceinline__ TR bld_img(BRes r, uint32_t off);
+template <>
+__device__ __forceinline__ float bld_img<float, float>(BRes r, uint32_t off) {
+  return bld<float>(r, off);
+}
+template <>
+__device__ __forceinline__ double bld_img<float, double>(BRes r, uint32_t off) {
+  return (double)bld<float>(r, off);
+}
+template <>
+__device__ __forceinline__ float bld_img<double, float>(BRes r, uint32_t off) {
+  return (float)bld<double>(r, off);
+}
+template <>
+__device__ __forceinline__ double bld_img<double, double>(BRes r, uint32_t off) {
+  return bld<double>(r, off);
+}
+template <>
+__device__ __forceinline__ float bld_img<bf16_t, float>(BRes r, uint32_t off) {
+  const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+  return __uint_as_float((uint32_t)h << 16);
+}
+template <>
+__device__ __forceinline__ double bld_img<bf16_t, double>(BRes r, uint32_t off) {
+  const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+  return (double)__uint_as_float((uint32_t)h << 16);
+}
+
+// Value of the next lower (wave_shr) or higher (wave_shl) lane of the wavefront; lane 0
+// (respectively 63), which has no such lane, gets `edge` (DPP wavefront shifts).
+template <int CTRL>
+__device__ __forceinline__ float dpp_wave(float v, float edge) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_wave(double v, double edge) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(edge), __double2loint(v), CTRL, 0xF,
+                                             0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(edge), __double2hiint(v), CTRL, 0xF,
+                                             0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <typename T>
+__device__ __forceinline__ T from_lower_lane(T v, T edge) { return dpp_wave<0x138>(v, edge); }
+template <typename T>
+__device__ __forceinline__ T from_upper_lane(T v, T edge) { return dpp_wave<0x130>(v, edge); }
+
+// One tile of a column kernel: 64 consecutive columns (one per lane) times a run of S nodes
+// along PE starting at node k0.  32-bit node and cell offsets (element units) of the lane's
+// column and its neighbour flags; lanes past the last column work on the last one (colok false).
+struct ColTile {
+  uint32_t nb, cb;      // node and cell index of the column's first node / cell
+  int k0;
+  bool colok, hasxm, hasxp, hasym, hasyp;
+};
+__device__ __forceinline__ ColTile col_tile(const Geom& g, int64_t tile, int S) {
+  ColTile c;
+  const uint32_t tt = (uint32_t)tile;
+  const uint32_t kc = fdiv(tt, g.by_nct), cc = tt - kc * g.by_nct.d;
+  const uint32_t ncol = (uint32_t)g.ncol;
+  const uint32_t col = cc * kWave + (threadIdx.x & (kWave - 1));
+  c.colok = col < ncol;
+  const uint32_t colc = c.colok ? col : ncol - 1;
+  const uint32_t ix = fdiv(colc, g.by_ny), iy = colc - ix * (uint32_t)g.ny;
+  c.nb = ix * (uint32_t)g.nxs + iy * (uint32_t)g.nys;
+  c.cb = ix * (uint32_t)g.cxs + iy * (uint32_t)g.cys;
+  c.k0 = (int)kc * S;
+  c.hasxm = ix > 0;
+  c.hasxp = ix + 1 < (uint32_t)g.nx;
+  c.hasym = iy > 0;
+  c.hasyp = iy + 1 < (uint32_t)g.ny;
+  return c;
 }
 
 __device__ __forceinline__ double inf_d() { return __longlong_as_double(0x7ff0000000000000LL); }
