@@ -275,12 +275,9 @@ __device__ __forceinline__ void loss_grad_body(const LossGradArgs& a, VBlock vb)
   store_partials<5, BLK>(acc, a.part, vb.id);
 }
 
-template <typename TI, typename TR, int S, int BLK>
+template <typename TI, typename TR, int S, int BLK, bool STEP>
 __global__ __launch_bounds__(BLK) void k_loss_grad(LossGradArgs a) {
-  if (a.step)
-    loss_grad_body<TI, TR, S, BLK, true>(a, hw_block());
-  else
-    loss_grad_body<TI, TR, S, BLK, false>(a, hw_block());
+  loss_grad_body<TI, TR, S, BLK, STEP>(a, hw_block());
 }
 
 // One launch over several volumes: tab[p] drives the workgroups starts[p] .. starts[p+1]-1.
@@ -314,26 +311,29 @@ __global__ __launch_bounds__(kReduceBlock) void k_loss_final(LossFinalArgs a) { 
 // and the two S sums.  A single-block decide kernel then takes the first (largest) gamma that
 // satisfies the Armijo condition, which is exactly what halving from gamma = 1 selects.
 // --------------------------------------------------------------------------------------------
-template <typename TI, typename TR, int S, int NC, int BLK>
+template <typename TI, typename TR, int S, int NC, int BLK, bool PASS0>
 __device__ __forceinline__ void trial_body(const TrialArgs& a, VBlock vb) {
   const State* st = a.st;
   if (load_flag(&st->gn_stop) || st->accepted) return;
   const Geom g = a.g;
-  const TI* __restrict__ Ip = static_cast<const TI*>(a.Ip);
-  const TI* __restrict__ Im = static_cast<const TI*>(a.Im);
-  const TR* __restrict__ b = static_cast<const TR*>(a.b);
-  const TR* __restrict__ q = static_cast<const TR*>(a.q);
-  const TR* __restrict__ gr = static_cast<const TR*>(a.grad);
   const int mp = g.mp;
-  const int64_t nct = (g.ncol + kWave - 1) / kWave;
-  const int64_t ntiles = nct * ((mp + 1 + S - 1) / S);
+  const int64_t ntiles = (int64_t)g.by_nct.d * ((mp + 1 + S - 1) / S);
   const int lane = threadIdx.x & (kWave - 1);
-  const bool pass0 = a.first == 0;
+
+  constexpr uint32_t kSr = sizeof(TR), kSi = sizeof(TI);
+  const uint32_t nbytes = (uint32_t)(g.nnode * (int64_t)kSr);
+  const uint32_t cbytes = (uint32_t)(g.ncell * (int64_t)kSi);
+  const BRes rIp = bres(a.Ip, cbytes), rIm = bres(a.Im, cbytes);
+  const BRes rB = bres(a.b, nbytes), rQ = bres(a.q, nbytes), rG = bres(a.grad, nbytes);
+  const uint32_t nps = (uint32_t)g.nps, nxs = (uint32_t)g.nxs, nys = (uint32_t)g.nys;
+  const uint32_t cps = (uint32_t)g.cps;
 
   const TR inv_hp = TR(1) / (TR)g.hp;
+  const TR hih = TR(0.5) * inv_hp;
   const TR wp2 = TR(1) / ((TR)g.hp * (TR)g.hp);
   const TR wx2 = TR(1) / ((TR)g.hx * (TR)g.hx);
   const TR wy2 = TR(1) / ((TR)g.hy * (TR)g.hy);
+  const TR lim = TR(mp + 2);
   TR gam[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) gam[c] = (TR)ldexp(1.0, -(a.first + c));
@@ -344,95 +344,135 @@ __device__ __forceinline__ void trial_body(const TrialArgs& a, VBlock vb) {
   for (int i = 0; i < K; ++i) v[i] = 0.0;
 
   for (WaveIter it = wave_iter(ntiles, vb); it.t < it.end; it.t += it.stride) {
-    const int64_t col = (it.t % nct) * kWave + lane;
-    const int k0 = (int)(it.t / nct) * S;
-    const bool colok = col < g.ncol;
-    const int64_t colc = colok ? col : g.ncol - 1;
-    const int64_t ix = colc / g.ny, iy = colc - (colc / g.ny) * g.ny;
-    const int64_t nb = ix * g.nxs + iy * g.nys;
-    const int64_t cb = ix * g.cxs + iy * g.cys;
-    TR bb[S + 1], qq[S + 1];
+    const ColTile c = col_tile(g, it.t, S);
+    const int k0 = c.k0;
+    auto noff = [&](int k) -> uint32_t { return (c.nb + (uint32_t)k * nps) * kSr; };
+    // b, q at nodes k0 .. k0+S (clamped to mp); first pass: grad and the upper x and y neighbours
+    // (y on the last lane of the wavefront; the others take it from the next lane)
+    TR bb[S + 1], qq[S + 1], gk[S], bxp[S], qxp[S], byp[S], qyp[S];
 #pragma unroll
-    for (int i = 0; i < S + 1; ++i) {
-      int k = k0 + i;
-      k = k > mp ? mp : k;
-      bb[i] = b[nb + (int64_t)k * g.nps];
-      qq[i] = q[nb + (int64_t)k * g.nps];
+    for (int i = 0; i <= S; ++i) {
+      const uint32_t o = noff(min(k0 + i, mp));
+      bb[i] = bld<TR>(rB, o);
+      qq[i] = bld<TR>(rQ, o);
     }
+    if (PASS0) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const uint32_t n = c.nb + (uint32_t)min(k0 + s, mp) * nps;
+        const uint32_t oxp = c.hasxp ? (n + nxs) * kSr : kNullOff;
+        const uint32_t oyp = (lane == kWave - 1 && c.hasyp) ? (n + nys) * kSr : kNullOff;
+        gk[s] = bld<TR>(rG, n * kSr);
+        bxp[s] = bld<TR>(rB, oxp);
+        qxp[s] = bld<TR>(rQ, oxp);
+        byp[s] = bld<TR>(rB, oyp);
+        qyp[s] = bld<TR>(rQ, oyp);
+      }
+    }
+    // image taps of cells k0 .. k0+S-1 for every candidate step
+    TR vp0[S][NC], vp1[S][NC], vm0[S][NC], vm1[S][NC], wp[S][NC], wm[S][NC];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int k = k0 + s;
-      const bool nodeok = k <= mp;
-      if (pass0) {
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) {
+        const TR b0 = fma(gam[cc], qq[s], bb[s]), b1 = fma(gam[cc], qq[s + 1], bb[s + 1]);
+        const TR t = clamp_abs((b0 + b1) * hih, lim);
+        const TR fp = floor(t), fm = floor(-t);
+        wp[s][cc] = t - fp;
+        wm[s][cc] = -t - fm;
+        const int kp = k + (int)fp, km = k + (int)fm;
+        const uint32_t rp = c.cb + (uint32_t)kp * cps, rm = c.cb + (uint32_t)km * cps;
+        vp0[s][cc] = bld_img<TI, TR>(rIp, (uint32_t)kp < (uint32_t)mp ? rp * kSi : kNullOff);
+        vp1[s][cc] =
+            bld_img<TI, TR>(rIp, (uint32_t)(kp + 1) < (uint32_t)mp ? (rp + cps) * kSi : kNullOff);
+        vm0[s][cc] = bld_img<TI, TR>(rIm, (uint32_t)km < (uint32_t)mp ? rm * kSi : kNullOff);
+        vm1[s][cc] =
+            bld_img<TI, TR>(rIm, (uint32_t)(km + 1) < (uint32_t)mp ? (rm + cps) * kSi : kNullOff);
+      }
+    }
+    // tile sums in the working precision (at most S terms each), then into the FP64 block sums
+    TR tgq = TR(0), tsbq = TR(0), tsqq = TR(0);
+    TR tr2[NC], tph[NC], tvi[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) tr2[cc] = tph[cc] = tvi[cc] = TR(0);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int k = k0 + s;
+      const bool nodeok = k <= mp && c.colok;
+      if (PASS0) {
         const TR bk = bb[s], qk = qq[s];
-        TR byp = __shfl_down(bk, 1, kWave);
-        TR qyp = __shfl_down(qk, 1, kWave);
-        const int kc = nodeok ? k : mp;
-        const int64_t n = nb + (int64_t)kc * g.nps;
-        const bool hasyp = iy < g.ny - 1, hasxp = ix < g.nx - 1;
-        if (lane == kWave - 1 && hasyp) {
-          byp = b[n + g.nys];
-          qyp = q[n + g.nys];
+        const TR by = from_upper_lane(bk, byp[s]), qy = from_upper_lane(qk, qyp[s]);
+        TR sbq = TR(0), sqq = TR(0);
+        if (k < mp) {
+          const TR db = bb[s + 1] - bk, dq = qq[s + 1] - qk;
+          sbq = fma(db * dq, wp2, sbq);
+          sqq = fma(dq * dq, wp2, sqq);
         }
-        if (nodeok && colok) {
-          double sbq = 0.0, sqq = 0.0;
-          if (k < mp) {
-            const TR db = bb[s + 1] - bk, dq = qq[s + 1] - qk;
-            sbq += (double)(db * dq * wp2);
-            sqq += (double)(dq * dq * wp2);
-          }
-          if (hasxp) {
-            const TR db = b[n + g.nxs] - bk, dq = q[n + g.nxs] - qk;
-            sbq += (double)(db * dq * wx2);
-            sqq += (double)(dq * dq * wx2);
-          }
-          if (hasyp) {
-            const TR db = byp - bk, dq = qyp - qk;
-            sbq += (double)(db * dq * wy2);
-            sqq += (double)(dq * dq * wy2);
-          }
-          v[0] += (double)gr[n] * (double)qk;
-          v[1] += sbq;
-          v[2] += sqq;
+        if (c.hasxp) {
+          const TR db = bxp[s] - bk, dq = qxp[s] - qk;
+          sbq = fma(db * dq, wx2, sbq);
+          sqq = fma(dq * dq, wx2, sqq);
+        }
+        if (c.hasyp) {
+          const TR db = by - bk, dq = qy - qk;
+          sbq = fma(db * dq, wy2, sbq);
+          sqq = fma(dq * dq, wy2, sqq);
+        }
+        if (nodeok) {
+          tgq = fma(gk[s], qk, tgq);
+          tsbq += sbq;
+          tsqq += sqq;
         }
       }
-      if (nodeok && k < mp && colok) {
+      if (nodeok && k < mp) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const TR b0 = bb[s] + gam[c] * qq[s];
-          const TR b1 = bb[s + 1] + gam[c] * qq[s + 1];
-          const TR ab = (b0 + b1) * TR(0.5);
+        for (int cc = 0; cc < NC; ++cc) {
+          const TR b0 = fma(gam[cc], qq[s], bb[s]), b1 = fma(gam[cc], qq[s + 1], bb[s + 1]);
           const TR db = (b1 - b0) * inv_hp;
-          const TR t = ab * inv_hp;
-          TR vp, sp, vm, sm;
-          interp_at(Ip, cb, g.cps, mp, k, t, inv_hp, vp, sp);
-          interp_at(Im, cb, g.cps, mp, k, -t, inv_hp, vm, sm);
-          const TR r = vp * (TR(1) + db) - vm * (TR(1) - db);
-          v[3 + 3 * c] += (double)r * (double)r;
+          const TR valp = fma(wp[s][cc], vp1[s][cc] - vp0[s][cc], vp0[s][cc]);
+          const TR valm = fma(wm[s][cc], vm1[s][cc] - vm0[s][cc], vm0[s][cc]);
+          const TR r = valp * (TR(1) + db) - valm * (TR(1) - db);
+          tr2[cc] = fma(r, r, tr2[cc]);
           if (fabs(db) < TR(1)) {
             const TR z2 = db * db;
-            v[4 + 3 * c] += (double)(z2 * z2 / (TR(1) - z2));
+            tph[cc] += z2 * z2 * recip(TR(1) - z2);
           } else {
-            v[5 + 3 * c] += 1.0;
+            tvi[cc] += TR(1);
           }
         }
       }
+    }
+    if (PASS0) {
+      v[0] += (double)tgq;
+      v[1] += (double)tsbq;
+      v[2] += (double)tsqq;
+    }
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      v[3 + 3 * cc] += (double)tr2[cc];
+      v[4 + 3 * cc] += (double)tph[cc];
+      v[5 + 3 * cc] += (double)tvi[cc];
     }
   }
   store_partials<K, BLK>(v, a.part, vb.id);
 }
 
-template <typename TI, typename TR, int S, int NC, int BLK>
+template <typename TI, typename TR, int S, int NC, int BLK, bool PASS0>
 __global__ __launch_bounds__(BLK) void k_trial(TrialArgs a) {
-  trial_body<TI, TR, S, NC, BLK>(a, hw_block());
+  trial_body<TI, TR, S, NC, BLK, PASS0>(a, hw_block());
 }
 
+// Shared launches: every volume of one launch is in the same pass, so `first` is uniform.
 template <typename TI, typename TR, int S, int NC, int BLK>
 __global__ __launch_bounds__(BLK) void k_trial_batch(const TrialArgs* __restrict__ tab,
                                                      const uint32_t* __restrict__ starts, int n) {
   VBlock vb;
   const int p = batch_volume(starts, n, vb);
-  trial_body<TI, TR, S, NC, BLK>(tab[p], vb);
+  if (tab[p].first == 0)
+    trial_body<TI, TR, S, NC, BLK, true>(tab[p], vb);
+  else
+    trial_body<TI, TR, S, NC, BLK, false>(tab[p], vb);
 }
 
 // Armijo decision on the pass just evaluated (one block per volume).
@@ -666,13 +706,22 @@ hipError_t launch_loss_grad(const LossGradArgs& a0, DType img, DType real, hipSt
                          [a, img, real](hipStream_t s2) { return launch_loss_grad(a, img, real, s2); });
   // timing tag 1: the launch also applies the previous step (reads q, writes b + gamma q)
   const int tag = a.step ? 1 : 0;
+#define RGP_LG(RUN, STEP)                                                                    \
+  RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH_T(kKindLossGrad, tag, a.g,                        \
+                                             (k_loss_grad<TI, TR, RUN, 256, STEP>), L.grid,  \
+                                             256, 0, s, a))
   if (L.S == 4) {
-    RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH_T(kKindLossGrad, tag, a.g,
-                                               (k_loss_grad<TI, TR, 4, 256>), L.grid, 256, 0, s, a));
+    if (a.step)
+      RGP_LG(4, true);
+    else
+      RGP_LG(4, false);
   } else {
-    RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH_T(kKindLossGrad, tag, a.g,
-                                               (k_loss_grad<TI, TR, 2, 256>), L.grid, 256, 0, s, a));
+    if (a.step)
+      RGP_LG(2, true);
+    else
+      RGP_LG(2, false);
   }
+#undef RGP_LG
   return hipGetLastError();
 }
 
@@ -688,9 +737,17 @@ hipError_t launch_trial(const TrialArgs& a, DType img, DType real, hipStream_t s
   if (active_recorder())
     return record_launch(RecKind::kTrial, a, L.grid, L.block, 0, (int)img, (int)real, a.nc,
                          [a, img, real](hipStream_t s2) { return launch_trial(a, img, real, s2); });
-#define RGP_TRIAL(NC, B)                                                                   \
+#define RGP_TRIAL_P(NC, B, P)                                                              \
   RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH_T(kKindTrial, NC, a.g,                          \
-                                             (k_trial<TI, TR, kRunTrial, NC, B>), L.grid, B, 0, s, a))
+                                             (k_trial<TI, TR, kRunTrial, NC, B, P>), L.grid, B, \
+                                             0, s, a))
+#define RGP_TRIAL(NC, B)          \
+  do {                            \
+    if (a.first == 0)             \
+      RGP_TRIAL_P(NC, B, true);   \
+    else                          \
+      RGP_TRIAL_P(NC, B, false);  \
+  } while (0)
   switch (a.nc) {
     case 1:
       if (L.block == 1024) RGP_TRIAL(1, 1024);
@@ -703,6 +760,7 @@ hipError_t launch_trial(const TrialArgs& a, DType img, DType real, hipStream_t s
     default: return hipErrorInvalidValue;
   }
 #undef RGP_TRIAL
+#undef RGP_TRIAL_P
   return hipGetLastError();
 }
 

@@ -38,61 +38,57 @@ namespace {
 constexpr int kRun = 4;
 }
 
+// Per tile every lane issues all loads of its run first (v and off at nodes k0-1 .. k0+S, diag,
+// the x neighbours, and on the first / last lane of the wavefront the y neighbours, which the
+// other lanes take from the adjacent lane); missing neighbours load 0 through kNullOff.
 template <typename TR, int S, int BLK>
 __global__ __launch_bounds__(BLK) void k_hvp(HvpArgs a) {
   const Geom g = a.g;
-  const TR* __restrict__ dg = static_cast<const TR*>(a.diag);
-  const TR* __restrict__ of = static_cast<const TR*>(a.off);
-  const TR* __restrict__ v = static_cast<const TR*>(a.v);
-  TR* __restrict__ Hv = static_cast<TR*>(a.Hv);
   const int mp = g.mp;
-  const int64_t nct = (g.ncol + kWave - 1) / kWave;
-  const int64_t ntiles = nct * ((mp + 1 + S - 1) / S);
+  const int64_t ntiles = (int64_t)g.by_nct.d * ((mp + 1 + S - 1) / S);
   const int lane = threadIdx.x & (kWave - 1);
+  constexpr uint32_t kSr = sizeof(TR);
+  const uint32_t nbytes = (uint32_t)(g.nnode * (int64_t)kSr);
+  const BRes rD = bres(a.diag, nbytes), rO = bres(a.off, nbytes);
+  const BRes rV = bres(a.v, nbytes), rH = bres(a.Hv, nbytes);
+  const uint32_t nps = (uint32_t)g.nps, nxs = (uint32_t)g.nxs, nys = (uint32_t)g.nys;
   const TR cx = (TR)(a.alpha * g.vol / (g.hx * g.hx));
   const TR cy = (TR)(a.alpha * g.vol / (g.hy * g.hy));
   double acc[1] = {0.0};
   for (WaveIter it = wave_iter(ntiles, hw_block()); it.t < it.end; it.t += it.stride) {
-    const int64_t col = (it.t % nct) * kWave + lane;
-    const int k0 = (int)(it.t / nct) * S;
-    const bool colok = col < g.ncol;
-    const int64_t colc = colok ? col : g.ncol - 1;
-    const int64_t ix = colc / g.ny, iy = colc - (colc / g.ny) * g.ny;
-    const int64_t nb = ix * g.nxs + iy * g.nys;
-    const bool hasxm = ix > 0, hasxp = ix < g.nx - 1, hasym = iy > 0, hasyp = iy < g.ny - 1;
-    TR vv[S + 2], oo[S + 1];
+    const ColTile c = col_tile(g, it.t, S);
+    const int k0 = c.k0;
+    TR vv[S + 2], oo[S + 1], dd[S], xm[S], xp[S], ym[S], yp[S];
 #pragma unroll
     for (int i = 0; i < S + 2; ++i) {
-      int k = k0 - 1 + i;
-      k = k < 0 ? 0 : (k > mp ? mp : k);
-      vv[i] = v[nb + (int64_t)k * g.nps];
-      if (i < S + 1) oo[i] = of[nb + (int64_t)k * g.nps];
+      const uint32_t o = (c.nb + (uint32_t)min(max(k0 - 1 + i, 0), mp) * nps) * kSr;
+      vv[i] = bld<TR>(rV, o);
+      if (i < S + 1) oo[i] = bld<TR>(rO, o);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t n = c.nb + (uint32_t)min(k0 + s, mp) * nps;
+      dd[s] = bld<TR>(rD, n * kSr);
+      xm[s] = bld<TR>(rV, c.hasxm ? (n - nxs) * kSr : kNullOff);
+      xp[s] = bld<TR>(rV, c.hasxp ? (n + nxs) * kSr : kNullOff);
+      ym[s] = bld<TR>(rV, (lane == 0 && c.hasym) ? (n - nys) * kSr : kNullOff);
+      yp[s] = bld<TR>(rV, (lane == kWave - 1 && c.hasyp) ? (n + nys) * kSr : kNullOff);
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int k = k0 + s;
-      const bool nodeok = k <= mp;
-      const int kc = nodeok ? k : mp;
-      const int64_t n = nb + (int64_t)kc * g.nps;
+      const bool out = k <= mp && c.colok;
       const TR vk = vv[s + 1];
-      TR vym = __shfl_up(vk, 1, kWave);
-      TR vyp = __shfl_down(vk, 1, kWave);
-      if (lane == 0 && hasym) vym = v[n - g.nys];
-      if (lane == kWave - 1 && hasyp) vyp = v[n + g.nys];
-      TR h = dg[n] * vk;
+      const TR vym = from_lower_lane(vk, ym[s]), vyp = from_upper_lane(vk, yp[s]);
+      TR h = dd[s] * vk;
       if (k > 0) h = fmad(oo[s], vv[s], h);
       if (k < mp) h = fmad(oo[s + 1], vv[s + 2], h);
-      TR crx = TR(0), cry = TR(0);
-      if (hasxm) crx += v[n - g.nxs];
-      if (hasxp) crx += v[n + g.nxs];
-      if (hasym) cry += vym;
-      if (hasyp) cry += vyp;
+      const TR crx = xm[s] + xp[s];  // missing x neighbours read 0
+      const TR cry = (c.hasym ? vym : TR(0)) + (c.hasyp ? vyp : TR(0));
       h = fmad(-cx, crx, h);
       h = fmad(-cy, cry, h);
-      if (nodeok && colok) {
-        Hv[n] = h;
-        acc[0] = fmad((double)vk, (double)h, acc[0]);
-      }
+      bst<TR>(rH, out ? (c.nb + (uint32_t)k * nps) * kSr : kNullOff, h);
+      if (out) acc[0] = fmad((double)vk, (double)h, acc[0]);
     }
   }
   if (a.part) store_partials<1, BLK>(acc, a.part, blockIdx.x);
