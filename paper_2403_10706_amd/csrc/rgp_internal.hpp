@@ -182,29 +182,48 @@ __device__ __forceinline__ double read_lane(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// Sum over the 64 lanes of a wavefront (all lanes active), returned to every lane: pairs of
-// lanes, then quads (quad permutations), halves of a row (lane i with 7 - i) and rows (lane i
-// with 15 - i) by DPP, which leaves each 16-lane row holding its total in every lane; the four
-// row totals are then added in a fixed order.  IEEE addition is commutative, so both lanes of a
-// pair hold bitwise the same value at every stage and the result is the same in every lane.
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_row<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_row<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_row<0x141>(v);  // row_half_mirror
-  v += dpp_row<0x140>(v);  // row_mirror
-  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+// Row broadcast (DPP, GFX9): every lane of the rows in ROWMASK gets lane 15 of the previous row
+// (CTRL 0x142) or lane 31 (CTRL 0x143); the other rows get 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_bcast(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sums over the 64 lanes of a wavefront (all lanes active) of K values at once, each stage applied
+// to all K so the K dependency chains interleave: pairs of lanes, then quads (quad permutations),
+// halves of a row (lane i with 7 - i) and rows (lane i with 15 - i) by DPP, which leaves every lane
+// of a 16-lane row with the row total; then row 1 += row 0 and row 3 += row 2, and rows 2, 3 +=
+// rows 0 + 1 (row broadcasts), so lane 63 holds (r3 + r2) + (r1 + r0), read out to all lanes.  The
+// order is fixed, so the result is bitwise the same in every wavefront that sums the same values.
+template <int K>
+__device__ __forceinline__ void wave_sums(double (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_row<0xB1>(v[k]);   // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_row<0x4E>(v[k]);   // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_row<0x141>(v[k]);  // row_half_mirror
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_row<0x140>(v[k]);  // row_mirror
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_bcast<0x142, 0xA>(v[k]);  // row_bcast:15 -> rows 1, 3
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_bcast<0x143, 0xC>(v[k]);  // row_bcast:31 -> rows 2, 3
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = read_lane(v[k], 63);
 }
 
 // Block sums in a fixed order (BLK = blockDim.x, every lane active): each wavefront reduces its
-// K values across its lanes (wave_sum), its first lane publishes them in LDS, and every thread
+// K values across its lanes (wave_sums), its first lane publishes them in LDS, and every thread
 // adds the BLK/64 wavefront totals in wavefront order.
 template <int K, int BLK>
 __device__ __forceinline__ void block_sum(double (&v)[K]) {
   constexpr int NW = BLK / kWave;
   __shared__ double sh[NW][K > 0 ? K : 1];
   const int w = threadIdx.x / kWave;
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  wave_sums<K>(v);
   if ((threadIdx.x & (kWave - 1)) == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) sh[w][k] = v[k];
