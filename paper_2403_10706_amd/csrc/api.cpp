@@ -315,9 +315,11 @@ hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const vo
       if ((e = launch_pcg_step(pa, real, s)) != hipSuccess) return e;
     }
 
+    // Armijo passes: gamma = 1 alone (it is accepted in most steps), then the remaining
+    // candidates 2^-1 .. 2^-9 in one pass; a pass after an accepted step exits at once
     int first = 0;
-    const int passes[3] = {1, 4, 5};
-    for (int p = 0; p < 3 && first < o->ls_max_trials; ++p) {
+    const int passes[2] = {1, kMaxTrialCand};
+    for (int p = 0; p < 2 && first < o->ls_max_trials; ++p) {
       const int nc = std::min(passes[p], o->ls_max_trials - first);
       TrialArgs ta{};
       ta.g = g;
@@ -1058,7 +1060,7 @@ hipError_t issue_batch(int32_t n, const std::vector<Recorder>& recs,
                                (DType)sl.var[1], s);
         break;
       case RecKind::kDecide:
-        e = launch_decide_batch(tab, n, s);
+        e = launch_decide_batch(tab, n, sl.var[0], s);
         break;
       case RecKind::kApply:
         e = launch_apply_step_batch(tab, starts, n, sl.grid, (DType)sl.var[0], s);

@@ -77,7 +77,7 @@ hipError_t launch_loss_grad_batch(const void* tab, const uint32_t* starts, int n
                                   DType img, DType real, hipStream_t s);
 hipError_t launch_trial_batch(const void* tab, const uint32_t* starts, int n, unsigned grid,
                               int nc, DType img, DType real, hipStream_t s);
-hipError_t launch_decide_batch(const void* tab, int n, hipStream_t s);
+hipError_t launch_decide_batch(const void* tab, int n, int nc, hipStream_t s);
 hipError_t launch_apply_step_batch(const void* tab, const uint32_t* starts, int n, unsigned grid,
                                    DType real, hipStream_t s);
 hipError_t launch_pcg_scalars_batch(const void* tab, int n, hipStream_t s);

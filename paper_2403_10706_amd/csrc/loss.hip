@@ -469,21 +469,27 @@ __global__ __launch_bounds__(BLK) void k_trial_batch(const TrialArgs* __restrict
                                                      const uint32_t* __restrict__ starts, int n) {
   VBlock vb;
   const int p = batch_volume(starts, n, vb);
-  if (tab[p].first == 0)
-    trial_body<TI, TR, S, NC, BLK, true>(tab[p], vb);
-  else
-    trial_body<TI, TR, S, NC, BLK, false>(tab[p], vb);
+  if constexpr (NC == 1) {
+    if (tab[p].first == 0) {
+      trial_body<TI, TR, S, NC, BLK, true>(tab[p], vb);
+      return;
+    }
+  }
+  trial_body<TI, TR, S, NC, BLK, false>(tab[p], vb);
 }
 
 // Armijo decision on the pass just evaluated (one block per volume).
+template <int NC>
 __device__ __forceinline__ void decide_body(const DecideArgs& a) {
   const State* st = a.st;
   if (load_flag(&st->gn_stop) || st->accepted) return;
-  decide_pass(a);
+  decide_pass<NC>(a);
 }
-__global__ __launch_bounds__(kReduceBlock) void k_decide(DecideArgs a) { decide_body(a); }
+template <int NC>
+__global__ __launch_bounds__(kReduceBlock) void k_decide(DecideArgs a) { decide_body<NC>(a); }
+template <int NC>
 __global__ __launch_bounds__(kReduceBlock) void k_decide_batch(const DecideArgs* __restrict__ tab) {
-  decide_body(tab[blockIdx.x]);
+  decide_body<NC>(tab[blockIdx.x]);
 }
 
 // b <- b + gamma q (in place, pointwise) with the accepted line-search step.
@@ -741,34 +747,49 @@ hipError_t launch_trial(const TrialArgs& a, DType img, DType real, hipStream_t s
   RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH_T(kKindTrial, NC, a.g,                          \
                                              (k_trial<TI, TR, kRunTrial, NC, B, P>), L.grid, B, \
                                              0, s, a))
-#define RGP_TRIAL(NC, B)          \
-  do {                            \
-    if (a.first == 0)             \
-      RGP_TRIAL_P(NC, B, true);   \
-    else                          \
-      RGP_TRIAL_P(NC, B, false);  \
-  } while (0)
+  // only the first pass (one candidate, first == 0) forms grad.q and the S cross sums
+  if (a.first == 0 && a.nc != 1) return hipErrorInvalidValue;
   switch (a.nc) {
     case 1:
-      if (L.block == 1024) RGP_TRIAL(1, 1024);
-      else RGP_TRIAL(1, 256);
+      if (a.first == 0) {
+        if (L.block == 1024) RGP_TRIAL_P(1, 1024, true);
+        else RGP_TRIAL_P(1, 256, true);
+      } else {
+        RGP_TRIAL_P(1, 256, false);
+      }
       break;
-    case 2: RGP_TRIAL(2, 256); break;
-    case 3: RGP_TRIAL(3, 256); break;
-    case 4: RGP_TRIAL(4, 256); break;
-    case 5: RGP_TRIAL(5, 256); break;
+    case 2: RGP_TRIAL_P(2, 256, false); break;
+    case 3: RGP_TRIAL_P(3, 256, false); break;
+    case 4: RGP_TRIAL_P(4, 256, false); break;
+    case 5: RGP_TRIAL_P(5, 256, false); break;
+    case 6: RGP_TRIAL_P(6, 256, false); break;
+    case 7: RGP_TRIAL_P(7, 256, false); break;
+    case 8: RGP_TRIAL_P(8, 256, false); break;
+    case 9: RGP_TRIAL_P(9, 256, false); break;
     default: return hipErrorInvalidValue;
   }
-#undef RGP_TRIAL
 #undef RGP_TRIAL_P
   return hipGetLastError();
 }
 
 hipError_t launch_decide(const DecideArgs& a, hipStream_t s) {
   if (active_recorder())
-    return record_launch(RecKind::kDecide, a, 1, kReduceBlock, 0, 0, 0, 0,
+    return record_launch(RecKind::kDecide, a, 1, kReduceBlock, 0, a.prev_nc, 0, 0,
                          [a](hipStream_t s2) { return launch_decide(a, s2); });
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(kReduceBlock), 0, s, a);
+#define RGP_DECIDE(NC) hipLaunchKernelGGL(k_decide<NC>, dim3(1), dim3(kReduceBlock), 0, s, a)
+  switch (a.prev_nc) {
+    case 1: RGP_DECIDE(1); break;
+    case 2: RGP_DECIDE(2); break;
+    case 3: RGP_DECIDE(3); break;
+    case 4: RGP_DECIDE(4); break;
+    case 5: RGP_DECIDE(5); break;
+    case 6: RGP_DECIDE(6); break;
+    case 7: RGP_DECIDE(7); break;
+    case 8: RGP_DECIDE(8); break;
+    case 9: RGP_DECIDE(9); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef RGP_DECIDE
   return hipGetLastError();
 }
 
@@ -824,15 +845,32 @@ hipError_t launch_trial_batch(const void* tab, const uint32_t* starts, int n, un
     case 3: RGP_TRIAL_B(3); break;
     case 4: RGP_TRIAL_B(4); break;
     case 5: RGP_TRIAL_B(5); break;
+    case 6: RGP_TRIAL_B(6); break;
+    case 7: RGP_TRIAL_B(7); break;
+    case 8: RGP_TRIAL_B(8); break;
+    case 9: RGP_TRIAL_B(9); break;
     default: return hipErrorInvalidValue;
   }
 #undef RGP_TRIAL_B
   return hipGetLastError();
 }
 
-hipError_t launch_decide_batch(const void* tab, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_decide_batch, dim3(n), dim3(kReduceBlock), 0, s,
-                     static_cast<const DecideArgs*>(tab));
+hipError_t launch_decide_batch(const void* tab, int n, int nc, hipStream_t s) {
+  const DecideArgs* t = static_cast<const DecideArgs*>(tab);
+#define RGP_DECIDE_B(NC) hipLaunchKernelGGL(k_decide_batch<NC>, dim3(n), dim3(kReduceBlock), 0, s, t)
+  switch (nc) {
+    case 1: RGP_DECIDE_B(1); break;
+    case 2: RGP_DECIDE_B(2); break;
+    case 3: RGP_DECIDE_B(3); break;
+    case 4: RGP_DECIDE_B(4); break;
+    case 5: RGP_DECIDE_B(5); break;
+    case 6: RGP_DECIDE_B(6); break;
+    case 7: RGP_DECIDE_B(7); break;
+    case 8: RGP_DECIDE_B(8); break;
+    case 9: RGP_DECIDE_B(9); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef RGP_DECIDE_B
   return hipGetLastError();
 }
 

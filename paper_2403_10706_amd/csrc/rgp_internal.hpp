@@ -110,7 +110,7 @@ constexpr int kStatFields = 12;
 
 // Partial sums: every reducing kernel writes kPartStride doubles per block (plain stores); a later
 // single-block kernel reduces them in block order.  Grids are capped at kMaxGrid blocks.
-constexpr int kPartStride = 24;
+constexpr int kPartStride = 32;
 constexpr int kMaxGrid = 2048;
 
 // Column-run tiling: a tile is 64 consecutive columns x S consecutive PE nodes, owned by one

@@ -88,6 +88,9 @@ struct ImageGradArgs {
   void* gIm;          // dJ/dI- (cells, field type)
 };
 
+// Largest number of candidate steps evaluated in one trial pass.
+constexpr int kMaxTrialCand = 9;
+
 struct TrialArgs {
   Geom g;
   const void* Ip;

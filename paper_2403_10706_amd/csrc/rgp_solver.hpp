@@ -64,16 +64,18 @@ __device__ __forceinline__ bool finalize_loss(const LossFinalArgs& a, bool write
 }
 
 // Trial-pass block sums: [0] grad.q, [1] sum dB.dQ/h^2, [2] sum dQ^2/h^2 (first pass only),
-// then per candidate c: [3+3c] sum r^2, [4+3c] sum phi, [5+3c] barrier violations.
-constexpr int kTrialSlots = 18;
+// then per candidate c: [3+3c] sum r^2, [4+3c] sum phi, [5+3c] barrier violations.  At most
+// kMaxTrialCand candidates per pass.
+constexpr int kTrialSlots = 3 + 3 * kMaxTrialCand;
 
 // Armijo decision over one pass (first index `first`, `nc` candidates): the largest gamma with
 // J(b + gamma q) <= J(b) + c gamma grad.q.  Returns the candidate index or -1.
+template <int NC>
 __device__ __forceinline__ int armijo_pick(const double* t, int first, int nc, const State& st,
                                            double gq, double sbq, double sqq, double vol,
                                            double alpha, double beta, double c, double& gamma) {
 #pragma unroll
-  for (int k = 0; k < (kTrialSlots - 3) / 3; ++k) {  // unrolled: t stays in registers
+  for (int k = 0; k < NC; ++k) {  // unrolled: t stays in registers
     if (k >= nc) break;
     const double gm = ldexp(1.0, -(first + k));
     const double D = 0.5 * vol * t[3 + 3 * k];
@@ -88,14 +90,16 @@ __device__ __forceinline__ int armijo_pick(const double* t, int first, int nc, c
   return -1;
 }
 
-// Decision on one finished pass, taken by a single-block kernel: every thread reads the state,
-// then all reduce the pass's block sums, then thread 0 updates the state.  Returns 1 when a step
-// was accepted, 0 when the search continues, -1 when it failed (no trials left).
+// Decision on one finished pass of NC candidates, taken by a single-block kernel: every thread
+// reads the state, then all reduce the pass's 3 + 3 NC block sums, then thread 0 updates the
+// state.  Returns 1 when a step was accepted, 0 when the search continues, -1 when it failed (no
+// trials left).
+template <int NC>
 __device__ __forceinline__ int decide_pass(const DecideArgs& a) {
   State* st = a.st;
   const State s = *st;
-  double t[kTrialSlots];
-  reduce_partials<kTrialSlots, kReduceBlock>(t, a.part_prev, a.nprod_prev);  // synchronises
+  double t[3 + 3 * NC];
+  reduce_partials<3 + 3 * NC, kReduceBlock>(t, a.part_prev, a.nprod_prev);  // synchronises
   double gq = s.gq, sbq = s.sbq, sqq = s.sqq;
   if (a.prev_first == 0) {
     gq = t[0];
@@ -103,8 +107,8 @@ __device__ __forceinline__ int decide_pass(const DecideArgs& a) {
     sqq = t[2];
   }
   double gamma = 0.0;
-  const int k = armijo_pick(t, a.prev_first, a.prev_nc, s, gq, sbq, sqq, a.vol, a.alpha, a.beta,
-                            a.armijo_c, gamma);
+  const int k = armijo_pick<NC>(t, a.prev_first, a.prev_nc, s, gq, sbq, sqq, a.vol, a.alpha,
+                                a.beta, a.armijo_c, gamma);
   const bool last = a.prev_first + a.prev_nc >= a.total;
   const int res = k >= 0 ? 1 : (last ? -1 : 0);
   if (threadIdx.x == 0) {

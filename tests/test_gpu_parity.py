@@ -217,6 +217,32 @@ def test_correct_single_level_c1(real):
     assert rel2(to_host(out["T_minus"]), ref.T_minus) <= _tol(real, 1e-10, 1e-4)
 
 
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_correct_line_search_backtracks(real):
+    """Images scaled x3000 make the objective strongly nonlinear: the Armijo search of every
+    Gauss-Newton step rejects gamma = 1 and accepts one of 2^-1 .. 2^-9 from the second trial
+    pass (here up to the 6th trial).  FP64: the same trial counts and steps as the oracle and the
+    same field; FP32: the final field within the parity bar."""
+    rgp = _rgp()
+    p = synth.make_workload("c1", scale=3000.0)
+    dt = REAL[real]
+    Ip, Im = rounded(p.I_plus, dt), rounded(p.I_minus, dt)
+    opts = rgp.Options(levels=1, gn_iters=6, pcg_iters=10, pcg_rtol=0.0)
+    out = rgp.correct(to_dev(Ip, dt), to_dev(Im, dt), p.pe, opts=opts)
+    ref = orc.solve(Ip, Im, p.pe, levels=1, gn_iters=6, pcg_iters=10, pcg_rtol=0.0)
+    want = [(h.trials, h.gamma) for h in ref.levels[0][2]]
+    assert max(t for t, _ in want) > 1  # the case really backtracks
+    _, recs = rgp.parse_stats(out["stats"], 1, 6)
+    got = [(int(r["trials"]), float(r["gamma"])) for r in recs[0]]
+    err = float(np.max(np.abs(to_host(out["b"]) - ref.b)))
+    say(f"[line search {real}] trials/gamma {got} (oracle {want}); max|b - b_oracle| = {err:.3e}")
+    if real == "f64":
+        assert got == want
+        assert err <= 1e-8
+    else:
+        assert err <= BFINAL_ATOL
+
+
 @pytest.mark.parametrize("shape,pe,levels", [((40, 48, 36), 1, 2), ((45, 30, 26), 0, 3),
                                              ((20, 22, 50), 2, 2)])
 def test_correct_multilevel(shape, pe, levels):
