@@ -679,11 +679,20 @@ __global__ __launch_bounds__(kBlock) void k_image_grad(ImageGradArgs a) {
   }
 }
 
+// loss_grad holds ~140 VGPRs (3 wavefronts per SIMD): a grid of one resident round (3 blocks of
+// 4 wavefronts on each of the 256 CUs) leaves no tail round, and the consumers of its block sums
+// (the PCG scalar phase of iteration 0) read 768 instead of 2048 of them.
 Launch plan_loss_grad(const Geom& g, DType real) {
-  return plan_tiles(g, loss_run(g), pick_block(g, real, loss_run(g)));
+  Launch L = plan_tiles(g, loss_run(g), pick_block(g, real, loss_run(g)));
+  if (L.grid > 768u) L.grid = 768u;
+  return L;
 }
+// The first trial pass holds ~65 VGPRs (7 wavefronts per SIMD): one resident round is 7 blocks of
+// 4 wavefronts per CU.
 Launch plan_trial(const Geom& g, DType real, int nc) {
-  return plan_tiles(g, kRunTrial, nc == 1 ? pick_block(g, real, kRunTrial) : 256);
+  Launch L = plan_tiles(g, kRunTrial, nc == 1 ? pick_block(g, real, kRunTrial) : 256);
+  if (L.grid > 1792u) L.grid = 1792u;
+  return L;
 }
 
 #define RGP_DISPATCH_TYPES(IMG, REAL, ...)                                              \
