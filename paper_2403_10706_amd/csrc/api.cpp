@@ -295,7 +295,7 @@ hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const vo
       sa.fused = Lpcg.fused;
       sa.lf = LossFinalArgs{k.slot(kPartLoss), Llg.grid, g.vol, o->alpha, o->beta, k.st,
                             nullptr, rec, 1};
-      if ((i == 0 || !sa.fused) && (e = launch_pcg_scalars(sa, s)) != hipSuccess) return e;
+      if (!sa.fused && (e = launch_pcg_scalars(sa, s)) != hipSuccess) return e;
       PcgArgs pa{};
       pa.g = g;
       pa.diag = w.Dg;
@@ -574,7 +574,7 @@ rgp_status rgp_pcg_solve(const rgp_grid* grid, rgp_dtype real_t, const void* hdi
     sa.fused = L.fused;
     sa.iters_out = iters_dev;
     sa.relres_out = relres_dev;
-    if (i == 0 || !sa.fused) RGP_HIP(launch_pcg_scalars(sa, s));
+    if (!sa.fused) RGP_HIP(launch_pcg_scalars(sa, s));
     PcgArgs pa{};
     pa.g = g;
     pa.diag = hdiag;

@@ -170,6 +170,25 @@ __device__ __forceinline__ PcgSlot pcg_scalar_phase(const PcgScalarArgs& a, cons
   return cur;
 }
 
+// Status of iteration 0 from this thread's share `l` of loss_grad's block sums (loaded with
+// load_partials_rm when gn_mode): in Gauss-Newton mode a stopped solve or a violated barrier at
+// the current iterate (J = +inf) gives Done.  Block 0 finalises J, D, S, P into the state (unless
+// the solve has stopped) and stores slot 0 for iteration 1.
+template <int BLK>
+__device__ __forceinline__ PcgSlot pcg_first_phase(const PcgScalarArgs& a, double (&l)[5],
+                                                   VBlock vb) {
+  bool stop = false, viol = false;
+  if (a.gn_mode) {
+    stop = load_flag(&a.st->gn_stop);
+    block_sum<5, BLK>(l);
+    viol = finalize_loss_sums(a.lf, l, !stop && vb.id == 0);
+  }
+  PcgSlot s0{};
+  s0.status = (stop || viol) ? kPcgDone : kPcgRunning;
+  if (vb.id == 0 && threadIdx.x == 0) a.slots[0] = s0;
+  return s0;
+}
+
 // One block.  Iteration 0: in Gauss-Newton mode, a stopped solve or a violated barrier at the
 // current iterate (J = +inf, finalised here from loss_grad's block sums) gives status Done.
 // Later iterations (when not fused into k_pcg_step): the scalar phase.
@@ -350,15 +369,19 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
     }
   };
 
-  // Fused: the previous iteration's block sums are loaded first, then the first unit's planes,
-  // so that the reduction waits for the former only and the latter arrive meanwhile.
-  const bool fused = !first && a.sc.fused;
-  const PcgSlot prev = a.sc.slots[fused ? (it - 1) & 1 : it & 1];
-  double tsum[7];
-  if (fused) load_partials_cm<7>(tsum, a.sc.part_prev, a.sc.nprod, it == 1 ? 7 : 5);
+  // Fused: the previous iteration's block sums (iteration 0: loss_grad's, in Gauss-Newton mode)
+  // are loaded first, then the first unit's planes, so that the reduction waits for the former
+  // only and the latter arrive meanwhile.
+  const bool fused = a.sc.fused;
+  const PcgSlot prev = a.sc.slots[(fused && !first) ? (it - 1) & 1 : it & 1];
+  double tsum[7], lsum[5];
+  if (fused && !first) load_partials_cm<7>(tsum, a.sc.part_prev, a.sc.nprod, it == 1 ? 7 : 5);
+  if (fused && first && a.sc.gn_mode) load_partials_rm<5>(lsum, a.sc.lf.part, a.sc.lf.nprod);
   int64_t u = ulo + lb;
   if (u < uhi) begin_unit(u);
-  const PcgSlot sl = fused ? pcg_scalar_phase<BLK>(a.sc, prev, tsum, vb) : prev;
+  const PcgSlot sl = !fused ? prev
+                            : (first ? pcg_first_phase<BLK>(a.sc, lsum, vb)
+                                     : pcg_scalar_phase<BLK>(a.sc, prev, tsum, vb));
   if (sl.status == kPcgDone) return;
   const TR al = first ? TR(0) : (TR)sl.alpha, be = first ? TR(0) : (TR)sl.beta;
   if (sl.status == kPcgFinish) {  // last update x += a p of the previous iteration (pointwise)

@@ -249,6 +249,28 @@ __device__ __forceinline__ void store_partials(double (&v)[K], double* part, uns
   }
 }
 
+// This thread's share of the row-major block sums part[b * kPartStride + k] (k < K) of nprod
+// producer blocks, loaded in independent batches; block_sum completes the reduction.
+template <int K>
+__device__ __forceinline__ void load_partials_rm(double (&out)[K], const double* part,
+                                                 unsigned nprod) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) out[k] = 0.0;
+  for (unsigned b0 = 0; b0 < nprod; b0 += 4u * blockDim.x) {
+    double v[4][K];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const unsigned b = b0 + j * blockDim.x + threadIdx.x;
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[j][k] = b < nprod ? part[(size_t)b * kPartStride + k] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int k = 0; k < K; ++k) out[k] += v[j][k];
+  }
+}
+
 // Every thread of the calling block obtains the sums over nprod producer blocks.  The loads are
 // issued in batches of 4 (2 for K > 8) blocks per thread, all independent, so that one batch costs
 // one memory round trip; the summation order is fixed.

@@ -139,11 +139,10 @@ struct HvpArgs {
   double* part;   // nullable: block sums of v.Hv
 };
 
-// Scalar phase of a PCG iteration: reduces the block sums of iteration iter-1 and derives the
-// coefficients and status of iteration iter (slots[iter & 1]).  Iteration 0 runs it in the
-// single-block k_pcg_scalars (which also finalises the objective in Gauss-Newton mode); later
-// iterations run it either there too or (fused) at the start of every block of k_pcg_step,
-// block 0 writing the slot.
+// Scalar phase of a PCG iteration: reduces the block sums of iteration iter-1 (iteration 0: of
+// loss_grad, finalising the objective in Gauss-Newton mode) and derives the coefficients and
+// status of iteration iter (slots[iter & 1]).  It runs either in the single-block
+// k_pcg_scalars or (fused) at the start of every block of k_pcg_step, block 0 writing the slot.
 struct PcgScalarArgs {
   State* st;
   PcgSlot* slots;           // [2]
@@ -152,7 +151,7 @@ struct PcgScalarArgs {
   int iter, maxit;
   double rtol;
   int gn_mode;
-  int fused;                // iter >= 1: 1 = k_pcg_step derives the slot, 0 = k_pcg_scalars does
+  int fused;                // 1 = k_pcg_step derives the slot, 0 = k_pcg_scalars does
   int32_t* iters_out;       // nullable
   double* relres_out;       // nullable
   LossFinalArgs lf;         // gn_mode, iteration 0: J, D, S, P of the current iterate

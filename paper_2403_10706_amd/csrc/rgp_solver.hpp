@@ -28,9 +28,10 @@ __device__ __forceinline__ int load_flag(const int32_t* f) {
   return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ bool finalize_loss(const LossFinalArgs& a, bool write) {
-  double t[5];
-  reduce_partials<5, kReduceBlock>(t, a.part, a.nprod);
+// J, D, S, P from the reduced block sums t of loss_grad; thread 0 of the calling block writes the
+// state when `write` is set.  Returns true when the barrier is violated (J = +inf).
+__device__ __forceinline__ bool finalize_loss_sums(const LossFinalArgs& a, const double (&t)[5],
+                                                   bool write) {
   const bool viol = t[3] > 0.0;
   if (write && threadIdx.x == 0) {
     State* st = a.st;
@@ -61,6 +62,13 @@ __device__ __forceinline__ bool finalize_loss(const LossFinalArgs& a, bool write
     }
   }
   return viol;
+}
+
+// One block of kReduceBlock threads: reduces loss_grad's block sums and finalises them.
+__device__ __forceinline__ bool finalize_loss(const LossFinalArgs& a, bool write) {
+  double t[5];
+  reduce_partials<5, kReduceBlock>(t, a.part, a.nprod);
+  return finalize_loss_sums(a, t, write);
 }
 
 // Trial-pass block sums: [0] grad.q, [1] sum dB.dQ/h^2, [2] sum dQ^2/h^2 (first pass only),
