@@ -9,9 +9,10 @@
 // of T+ = C_half^{-1} o C+, with C_half^{-1} = (C+^{-1} + C-^{-1}) / 2.  Guard: a column with
 // some |D b0| > guard_slope gets its slopes clipped and is re-integrated from b0_0 = 0.
 //
-// A workgroup owns NC adjacent columns; each column is split into NSEG = 256/NC segments, one per
-// thread.  Both CDFs are scanned in LDS (segment scan + segment offsets); the inverse for the
-// first node of a segment is a binary search, later nodes advance monotonically (merge path).
+// A workgroup owns a tile of adjacent columns, each split into segments of consecutive cells, one
+// per thread.  The raw sums are scanned in registers and across the segments of a wavefront; one
+// FP64 CDF per column sits in LDS at a time (first C+, then C-), searched once per segment and
+// walked forward from there (the queries of a segment ascend).
 #include "rgp_internal.hpp"
 #include "rgp_launch.hpp"
 #include "batch.hpp"
@@ -70,210 +71,263 @@ __global__ __launch_bounds__(kBlock) void k_shift(ShiftArgs a) {
   }
 }
 
-// Shift from the block-wise extrema (every thread of the calling block gets it).
-__device__ __forceinline__ double shift_from(const double* part, unsigned nprod, double eps,
-                                             bool empty) {
-  __shared__ double sl[kBlock / kWave], sh[kBlock / kWave];
-  double lo = inf_d(), hi = 0.0;
-  for (unsigned b = threadIdx.x; b < nprod; b += blockDim.x) {
-    lo = fmin(lo, part[(size_t)b * kPartStride + 0]);
-    hi = fmax(hi, part[(size_t)b * kPartStride + 1]);
+// Spline inverse of one ascending run of queries against a nodal CDF C_0..C_m held with stride NC
+// in LDS.  The bracket of r is the largest i in [-1, m] with C_i < r, with c0 = C_i and c1 = C_{i+1}
+// (-inf and +inf past the ends); r in (C_i, C_{i+1}] maps to i + (r - C_i)/(C_{i+1} - C_i).
+
+// a / d for finite d > 0: reciprocal estimate, two Newton-Raphson steps y <- y (2 - d y), and one
+// residual correction of the quotient (within an ulp or two of the rounded quotient).
+__device__ __forceinline__ double div_pos(double a, double d) {
+  double y = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-d, y, 1.0);
+  y = fma(y, e, y);
+  const double q = a * y;
+  return fma(fma(-d, q, a), y, q);
+}
+
+// Number of nodes whose CDF value is below r (the bracket index + 1): binary lifting over powers
+// of two from P/2 down, P the smallest power of two above m + 1, so every lane runs the same steps.
+template <int NC>
+__device__ __forceinline__ int count_below(const double* C, int m, double r) {
+  const int P = 1 << (32 - __clz(m + 1));
+  int pos = 0;
+  for (int step = P >> 1; step > 0; step >>= 1) {
+    const int t = pos + step - 1;
+    const double v = C[min(t, m) * NC];
+    pos = (t <= m && v < r) ? pos + step : pos;
   }
+  return pos;
+}
+
+// FIRST: x[u] = C^{-1}(q[u]) for u < n; else x[u] = f (x[u] - C^{-1}(q[u])).
+template <int NC, int LMAX, bool FIRST>
+__device__ __forceinline__ void invert_run(const double* C, int m, const double (&q)[LMAX], int n,
+                                           double f, double (&x)[LMAX]) {
+  int i = count_below<NC>(C, m, q[0]) - 1;
+  double c0 = i >= 0 ? C[max(i, 0) * NC] : -inf_d();
+  double c1 = i < m ? C[min(i + 1, m) * NC] : inf_d();
 #pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, off, kWave));
-    hi = fmax(hi, __shfl_xor(hi, off, kWave));
+  for (int u = 0; u < LMAX; ++u) {
+    if (u < n) {
+      const double r = q[u];
+      if (u > 0) {
+        while (c1 < r) {  // walk forward (c1 = +inf at i = m stops it)
+          ++i;
+          c0 = c1;
+          const double nx = C[min(i + 1, m) * NC];
+          c1 = i < m ? nx : inf_d();
+        }
+      }
+      double y = (double)i + div_pos(r - c0, c1 - c0);
+      y = i < 0 ? 0.0 : (i >= m ? (double)m : y);
+      x[u] = FIRST ? y : f * (x[u] - y);
+    }
   }
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  if (lane == 0) {
-    sl[wv] = lo;
-    sh[wv] = hi;
-  }
-  __syncthreads();
-  lo = inf_d();
-  hi = 0.0;
-  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
-    lo = fmin(lo, sl[w]);
-    hi = fmax(hi, sh[w]);
-  }
-  __syncthreads();
-  if (empty) lo = 0.0;
-  return fmax(0.0, -lo) + eps * hi;
 }
 
-// Largest i in [-1, m] with C[i] < r (C[-1] = -inf), i.e. lower_bound - 1.
-__device__ __forceinline__ int lower_idx(const double* C, int stride, int m, double r) {
-  int lo = 0, hi = m + 1;  // search first index with C >= r in [0, m+1)
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (C[mid * stride] < r) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo - 1;
+// Tiles of NC adjacent columns go to the XCDs in contiguous runs (the hardware deals workgroups to
+// the 8 XCDs round-robin), so the tiles that share a cache line of the images meet in one L2.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned G) {
+  if (G < 8u) return b;
+  const unsigned x = b % 8u, q = b / 8u, per = G / 8u, rem = G % 8u;
+  return x < rem ? x * (per + 1u) + q : rem * (per + 1u) + (x - rem) * per + q;
 }
 
-// Spline inverse in index units, starting the search at i (monotone advance).
-__device__ __forceinline__ double inv_from(const double* C, int stride, int m, double r, int& i) {
-  while (i + 1 <= m && C[(i + 1) * stride] < r) ++i;
-  if (i < 0) return 0.0;
-  if (i >= m) return (double)m;
-  const double c0 = C[i * stride], c1 = C[(i + 1) * stride];
-  return (double)i + (r - c0) / (c1 - c0);
-}
-
-template <typename TI, typename TR>
-__global__ __launch_bounds__(kBlock) void k_ot(OtArgs a, int nc) {
-  extern __shared__ double lds[];
-  const Geom g = a.g;
-  const int mp = g.mp;
-  const int nseg = kBlock / nc;
-  const int stride = nc;                         // LDS layout X[k * nc + c]
-  double* Cp = lds;                              // CDF of I+ (then scratch)
-  double* Cm = Cp + (size_t)(mp + 1) * nc;       // CDF of I- (then guard scan)
-  double* B0 = Cm + (size_t)(mp + 1) * nc;       // b0 per node
-  double* segp = B0 + (size_t)(mp + 1) * nc;     // [nseg][nc] segment sums
-  double* segm = segp + (size_t)nseg * nc;
-  __shared__ int colflag[kBlock];
+// One workgroup per tile of NC adjacent columns.  Thread (c, seg), c = tid % NC (adjacent lanes
+// read adjacent columns of a row), seg = tid / NC, owns the cells [j0, j0 + n) of its column,
+// n <= L = ceil(m / NSEG) <= LMAX, and the nodes j0+1 .. j0+n (segment 0 also node 0).
+//   1. Raw cell values are summed in registers; the shift s enters as S_k = R_k + k s.  Segment
+//      offsets: a scan over the segments of the wavefront (lanes NC apart), then the wavefront
+//      totals through LDS, in the same barrier as the block extrema that give s.
+//   2. C+ of the own nodes goes to LDS; the own C- values are its queries (b+ = C+^{-1}(C-_k)).
+//      Then C- replaces C+ in the same LDS array and the own C+ values are the queries.  One
+//      FP64 array per column keeps a full-resolution grid resident in a single round.
+//   3. Guard: the slope of the first own cell takes the previous segment's last node through LDS.
+template <typename TI, typename TR, int NC, int LMAX>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LMAX <= 12 ? 4 : LMAX <= 16 ? 3 : 1))) void k_ot(OtArgs a) {
+  constexpr int NSEG = kBlock / NC;
+  constexpr int NW = kBlock / kWave;
+  static_assert(NC >= 1 && NC <= kWave && kWave % NC == 0, "columns per tile");
+  extern __shared__ double lds[];  // one nodal CDF per column, node k of column c at [k * NC + c]
+  __shared__ double wtot[2][NW][NC];
+  __shared__ double ext[2][NW];
+  __shared__ double segx[NSEG][NC];  // last node of each segment, then clipped segment sums
+  __shared__ int colflag[NC];
   __shared__ unsigned long long blockclip;
 
-  const TI* __restrict__ Ip = static_cast<const TI*>(a.Ip);
-  const TI* __restrict__ Im = static_cast<const TI*>(a.Im);
-  TR* __restrict__ b0 = static_cast<TR*>(a.b0);
-  const double hp = g.hp;
-
-  const int c = threadIdx.x % nc;
-  const int seg = threadIdx.x / nc;
-  const int64_t col = (int64_t)blockIdx.x * nc + c;
+  const Geom g = a.g;
+  const int mp = g.mp;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int c = tid % NC, seg = tid / NC;
+  const int64_t col = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * NC + c;
   const bool colok = col < g.ncol;
-  const int64_t colc = colok ? col : g.ncol - 1;
-  const int64_t ix = colc / g.ny, iy = colc - (colc / g.ny) * g.ny;
-  const int64_t cb = ix * g.cxs + iy * g.cys;
-  const int64_t nb = ix * g.nxs + iy * g.nys;
-  double* cp = Cp + c;
-  double* cm = Cm + c;
-  double* bz = B0 + c;
+  const uint32_t colc = (uint32_t)(colok ? col : g.ncol - 1);
+  const uint32_t ix = fdiv(colc, g.by_ny), iy = colc - ix * (uint32_t)g.ny;
+  const int L = (mp + NSEG - 1) / NSEG;
+  const int j0 = min(mp, seg * L), n = min(mp, j0 + L) - j0;
 
-  colflag[threadIdx.x] = 0;
-  if (threadIdx.x == 0) blockclip = 0ull;
-
-  // 1. shifted cell values, local inclusive scans per segment: C[j+1] = sum_{j0 <= j' <= j}.
-  //    The cells of a segment are loaded kChunk at a time, all loads of a chunk in flight
-  //    together (indices clamped into the column, surplus values unused); the first chunk is
-  //    issued before the positivity shift is reduced, so the two overlap.
-  const int L = (mp + nseg - 1) / nseg;
-  const int j0 = min(mp, seg * L), j1 = min(mp, j0 + L);
-  constexpr int kChunk = 16;
-  TI vp[kChunk], vm[kChunk];
-  auto load_chunk = [&](int jb) {
+  // 1. loads of the own cells (all in flight together), then the block extrema of the shift kernel
+  const TI* __restrict__ srcp =
+      static_cast<const TI*>(a.Ip) + ((int64_t)ix * g.cxs + (int64_t)iy * g.cys + (int64_t)j0 * g.cps);
+  const TI* __restrict__ srcm =
+      static_cast<const TI*>(a.Im) + ((int64_t)ix * g.cxs + (int64_t)iy * g.cys + (int64_t)j0 * g.cps);
+  TI vp[LMAX], vm[LMAX];
 #pragma unroll
-    for (int u = 0; u < kChunk; ++u) {
-      const int j = max(0, min(jb + u, j1 - 1));
-      vp[u] = Ip[cb + (int64_t)j * g.cps];
-      vm[u] = Im[cb + (int64_t)j * g.cps];
+  for (int u = 0; u < LMAX; ++u) {
+    if (u < n) {
+      vp[u] = srcp[(int64_t)u * g.cps];
+      vm[u] = srcm[(int64_t)u * g.cps];
     }
-  };
-  load_chunk(j0);
-  const double s = shift_from(a.shift_part, a.shift_nprod, a.eps, g.ncell == 0);
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.st->ot_shift = s;
+  }
+  double lo = inf_d(), hi = 0.0;
+  for (unsigned b = tid; b < a.shift_nprod; b += kBlock) {
+    lo = fmin(lo, a.shift_part[(size_t)b * kPartStride + 0]);
+    hi = fmax(hi, a.shift_part[(size_t)b * kPartStride + 1]);
+  }
+  if (tid < NC) colflag[tid] = 0;
+  if (tid == 0) blockclip = 0ull;
+
+  double Cp[LMAX], Cm[LMAX];  // raw inclusive prefixes of the segment, later the own CDF values
   double accp = 0.0, accm = 0.0;
-  for (int jb = j0; jb < j1; jb += kChunk) {
-    if (jb != j0) load_chunk(jb);
 #pragma unroll
-    for (int u = 0; u < kChunk; ++u) {
-      const int j = jb + u;
-      if (j < j1) {
-        accp += to_real(vp[u], double()) + s;
-        accm += to_real(vm[u], double()) + s;
-        cp[(j + 1) * stride] = accp;
-        cm[(j + 1) * stride] = accm;
-      }
+  for (int u = 0; u < LMAX; ++u) {
+    if (u < n) {
+      accp += to_real(vp[u], double());
+      accm += to_real(vm[u], double());
+    }
+    Cp[u] = accp;
+    Cm[u] = accm;
+  }
+  double incp = accp, incm = accm;
+#pragma unroll
+  for (int d = NC; d < kWave; d <<= 1) {
+    const double tp = __shfl_up(incp, d, kWave), tm = __shfl_up(incm, d, kWave);
+    if (lane >= d) {
+      incp += tp;
+      incm += tm;
     }
   }
-  segp[seg * nc + c] = accp;
-  segm[seg * nc + c] = accm;
-  if (seg == 0) {
-    cp[0] = 0.0;
-    cm[0] = 0.0;
+  double offp = __shfl_up(incp, NC, kWave), offm = __shfl_up(incm, NC, kWave);
+  if (lane < NC) offp = offm = 0.0;
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, d, kWave));
+    hi = fmax(hi, __shfl_xor(hi, d, kWave));
+  }
+  if (lane >= kWave - NC) {
+    wtot[0][w][c] = incp;
+    wtot[1][w][c] = incm;
+  }
+  if (lane == 0) {
+    ext[0][w] = lo;
+    ext[1][w] = hi;
   }
   __syncthreads();
-  {
-    double offp = 0.0, offm = 0.0;
-    for (int q = 0; q < seg; ++q) {
-      offp += segp[q * nc + c];
-      offm += segm[q * nc + c];
+  double totp = 0.0, totm = 0.0;
+  lo = inf_d();
+  hi = 0.0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    const double xp = wtot[0][q][c], xm = wtot[1][q][c];
+    if (q < w) {
+      offp += xp;
+      offm += xm;
     }
-    for (int j = j0; j < j1; ++j) {
-      cp[(j + 1) * stride] += offp;
-      cm[(j + 1) * stride] += offm;
-    }
+    totp += xp;
+    totm += xm;
+    lo = fmin(lo, ext[0][q]);
+    hi = fmax(hi, ext[1][q]);
   }
-  __syncthreads();
-  const double Sp = cp[mp * stride], Sm = cm[mp * stride];
+  const double s = fmax(0.0, -lo) + a.eps * hi;
+  if (blockIdx.x == 0 && tid == 0) a.st->ot_shift = s;
+  const double Sp = totp + (double)mp * s, Sm = totm + (double)mp * s;
   const bool massok = Sp > 0.0 && Sm > 0.0;
-  __syncthreads();
-  if (massok) {  // C_k = S_k / S_m with C_0 = 0 and C_m = 1 exactly
-    for (int j = j0; j < j1; ++j) {
-      cp[(j + 1) * stride] = (j + 1 == mp) ? 1.0 : cp[(j + 1) * stride] / Sp;
-      cm[(j + 1) * stride] = (j + 1 == mp) ? 1.0 : cm[(j + 1) * stride] / Sm;
-    }
+  const double rSp = 1.0 / Sp, rSm = 1.0 / Sm;
+#pragma unroll
+  for (int u = 0; u < LMAX; ++u) {  // C_k = S_k / S_m for k = j0+1+u, C_m = 1 exactly
+    const int k = j0 + 1 + u;
+    Cp[u] = k >= mp ? 1.0 : ((offp + Cp[u]) + (double)k * s) * rSp;
+    Cm[u] = k >= mp ? 1.0 : ((offm + Cm[u]) + (double)k * s) * rSm;
   }
-  __syncthreads();
 
-  // 2. b0 at the nodes of this segment (nodes split evenly over the segments).
-  const int L2 = (mp + 1 + nseg - 1) / nseg;
-  const int k0 = min(mp + 1, seg * L2), k1 = min(mp + 1, k0 + L2);
-  {
-    int ip = -2, im = -2;
-    for (int k = k0; k < k1; ++k) {
-      double v = 0.0;
-      if (massok) {
-        const double rm = cm[k * stride], rp = cp[k * stride];
-        if (ip == -2) ip = lower_idx(cp, stride, mp, rm);
-        if (im == -2) im = lower_idx(cm, stride, mp, rp);
-        const double xp = inv_from(cp, stride, mp, rm, ip);
-        const double xm = inv_from(cm, stride, mp, rp, im);
-        v = 0.25 * hp * (xp - xm);
-      }
-      bz[k * stride] = v;
-    }
-  }
+  // 2. b+ = C+^{-1}(C-_k) against C+ in LDS, then b- = C-^{-1}(C+_k) against C- in LDS
+  double* C = lds + c;
+  double bv[LMAX];  // C+^{-1}(C-_k), then b0_k
+#pragma unroll
+  for (int u = 0; u < LMAX; ++u) bv[u] = 0.0;
+  if (seg == 0) C[0] = 0.0;
+#pragma unroll
+  for (int u = 0; u < LMAX; ++u)
+    if (u < n) C[(j0 + 1 + u) * NC] = Cp[u];
   __syncthreads();
+  if (massok && n > 0) invert_run<NC, LMAX, true>(C, mp, Cm, n, 0.0, bv);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < LMAX; ++u)
+    if (u < n) C[(j0 + 1 + u) * NC] = Cm[u];
+  __syncthreads();
+  const double hp = g.hp;
+  if (massok && n > 0) invert_run<NC, LMAX, false>(C, mp, Cp, n, 0.25 * hp, bv);
 
-  // 3. guard: clip slopes beyond +-guard_slope and re-integrate the column from b0_0 = 0.
+  // 3. guard: clip slopes beyond +-guard_slope and re-integrate the column from b0_0 = 0
   if (a.guard) {
+    double last = 0.0;
+#pragma unroll
+    for (int u = 0; u < LMAX; ++u)
+      if (u == n - 1) last = bv[u];
+    if (n > 0) segx[seg][c] = last;
+    __syncthreads();
+    const double b00 = (seg == 0 || n == 0) ? 0.0 : segx[seg - 1][c];
     unsigned long long nclip = 0;
-    for (int j = k0; j < k1 && j < mp; ++j) {
-      const double sl = (bz[(j + 1) * stride] - bz[j * stride]) / hp;
-      if (fabs(sl) > a.guard_slope) ++nclip;
+    const double dmax = a.guard_slope * hp;  // |D b0| > slope  <=>  |b0_{k+1} - b0_k| > slope h
+    double prev = b00;
+#pragma unroll
+    for (int u = 0; u < LMAX; ++u) {
+      if (u < n) {
+        if (fabs(bv[u] - prev) > dmax) ++nclip;
+        prev = bv[u];
+      }
     }
     if (nclip) {
       atomicOr(&colflag[c], 1);
       if (colok) atomicAdd(&blockclip, nclip);
     }
     __syncthreads();
-    const bool flagged = colflag[c] != 0;
-    if (flagged) {
-      double acc = 0.0;
-      for (int j = k0; j < k1 && j < mp; ++j) {
-        double sl = (bz[(j + 1) * stride] - bz[j * stride]) / hp;
-        sl = fmin(fmax(sl, -a.guard_slope), a.guard_slope);
-        acc += sl * hp;
-        cm[(j + 1) * stride] = acc;
+    if (blockclip) {
+      const bool flagged = colflag[c] != 0;
+      if (flagged) {
+        double acc = 0.0;
+        prev = b00;
+#pragma unroll
+        for (int u = 0; u < LMAX; ++u) {
+          if (u < n) {
+            const double d = fmin(fmax(bv[u] - prev, -dmax), dmax);
+            prev = bv[u];
+            acc += d;
+            bv[u] = acc;
+          }
+        }
+        segx[seg][c] = acc;
       }
-      segm[seg * nc + c] = acc;
+      __syncthreads();
+      if (flagged) {
+        double off = 0.0;
+        for (int q = 0; q < seg; ++q) off += segx[q][c];
+#pragma unroll
+        for (int u = 0; u < LMAX; ++u) bv[u] += off;
+      }
+      if (tid == 0 && a.guarded) atomicAdd(a.guarded, blockclip);
     }
-    __syncthreads();
-    if (flagged) {
-      double off = 0.0;
-      for (int q = 0; q < seg; ++q) off += segm[q * nc + c];
-      for (int k = k0; k < k1; ++k) bz[k * stride] = (k == k0) ? off : off + cm[k * stride];
-    }
-    if (threadIdx.x == 0 && blockclip && a.guarded) atomicAdd(a.guarded, blockclip);
-    __syncthreads();
   }
 
   if (colok) {
-    for (int k = k0; k < k1; ++k) b0[nb + (int64_t)k * g.nps] = (TR)bz[k * stride];
+    TR* __restrict__ out = static_cast<TR*>(a.b0) + ((int64_t)ix * g.nxs + (int64_t)iy * g.nys);
+    if (seg == 0) out[0] = (TR)0.0;
+#pragma unroll
+    for (int u = 0; u < LMAX; ++u)
+      if (u < n) out[(int64_t)(j0 + 1 + u) * g.nps] = (TR)bv[u];
   }
 }
 
@@ -297,44 +351,55 @@ hipError_t launch_shift(const ShiftArgs& a, DType img, hipStream_t s) {
   return hipGetLastError();
 }
 
-size_t ot_lds_bytes(int mp, int nc) {
-  const int nseg = kBlock / nc;
-  return ((size_t)(mp + 1) * nc * 3 + (size_t)nseg * nc * 2) * sizeof(double);
+// Columns per tile and register slots per segment: 16 threads per column while the segments
+// hold at most 16 cells, fewer columns (longer segments) for longer columns.
+struct OtShape {
+  int nc, lmax;
+};
+OtShape ot_shape(int mp) {
+  if (mp <= 128) return {16, 8};
+  if (mp <= 192) return {16, 12};
+  if (mp <= 256) return {16, 16};
+  if (mp <= 512) return {8, 16};
+  if (mp <= 1024) return {4, 16};
+  if (mp <= 4096) return {1, 16};
+  if (mp <= 8192) return {1, 32};
+  return {0, 0};
 }
 
-// Columns per workgroup: the most (up to 16) whose three FP64 column arrays leave room for four
-// workgroups per CU (160 KB of LDS); the inverse-CDF phase is chains of dependent LDS reads, so
-// resident workgroups matter more than columns per workgroup.  Long columns fall back to the most
-// that fit at all.
-int ot_cols_per_block(int mp) {
-  for (int nc = 16; nc >= 1; nc >>= 1)
-    if (ot_lds_bytes(mp, nc) <= 40 * 1024) return nc;
-  for (int nc = 16; nc >= 1; nc >>= 1)
-    if (ot_lds_bytes(mp, nc) <= 150 * 1024) return nc;
-  return 0;
+template <typename TI, typename TR, int NC, int LMAX>
+hipError_t launch_ot_tile(const OtArgs& a, hipStream_t s) {
+  const unsigned nb = (unsigned)((a.g.ncol + NC - 1) / NC);
+  const size_t lds = (size_t)(a.g.mp + 1) * NC * sizeof(double);
+  hipFuncSetAttribute((const void*)k_ot<TI, TR, NC, LMAX>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  RGP_LAUNCH(kKindOt, a.g, (k_ot<TI, TR, NC, LMAX>), nb, kBlock, lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename TI, typename TR>
+hipError_t launch_ot_typed(const OtArgs& a, hipStream_t s) {
+  const OtShape sh = ot_shape(a.g.mp);
+  if (sh.nc == 16 && sh.lmax == 8) return launch_ot_tile<TI, TR, 16, 8>(a, s);
+  if (sh.nc == 16 && sh.lmax == 12) return launch_ot_tile<TI, TR, 16, 12>(a, s);
+  if (sh.nc == 16) return launch_ot_tile<TI, TR, 16, 16>(a, s);
+  if (sh.nc == 8) return launch_ot_tile<TI, TR, 8, 16>(a, s);
+  if (sh.nc == 4) return launch_ot_tile<TI, TR, 4, 16>(a, s);
+  if (sh.nc == 1 && sh.lmax == 16) return launch_ot_tile<TI, TR, 1, 16>(a, s);
+  if (sh.nc == 1) return launch_ot_tile<TI, TR, 1, 32>(a, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_ot(const OtArgs& a, DType img, DType real, hipStream_t s) {
   if (active_recorder())
     return record_other([a, img, real](hipStream_t s2) { return launch_ot(a, img, real, s2); });
-  const int nc = ot_cols_per_block(a.g.mp);
-  if (nc == 0) return hipErrorInvalidValue;
-  const unsigned nb = (unsigned)((a.g.ncol + nc - 1) / nc);
-  const size_t lds = ot_lds_bytes(a.g.mp, nc);
-#define RGP_OT_LAUNCH(TI, TR)                                                         \
-  do {                                                                                \
-    hipFuncSetAttribute((const void*)k_ot<TI, TR>,                                   \
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);        \
-    RGP_LAUNCH(kKindOt, a.g, (k_ot<TI, TR>), nb, kBlock, lds, s, a, nc);              \
-  } while (0)
-  if (real == DType::F64 && img == DType::F64) RGP_OT_LAUNCH(double, double);
-  else if (real == DType::F32 && img == DType::F32) RGP_OT_LAUNCH(float, float);
-  else if (real == DType::F32 && img == DType::BF16) RGP_OT_LAUNCH(bf16_t, float);
-  else if (real == DType::F64 && img == DType::F32) RGP_OT_LAUNCH(float, double);
-  else if (real == DType::F64 && img == DType::BF16) RGP_OT_LAUNCH(bf16_t, double);
-  else return hipErrorInvalidValue;
-#undef RGP_OT_LAUNCH
-  return hipGetLastError();
+  if (ot_shape(a.g.mp).nc == 0 || a.shift_nprod > (unsigned)kMaxGrid) return hipErrorInvalidValue;
+  if (real == DType::F64 && img == DType::F64) return launch_ot_typed<double, double>(a, s);
+  if (real == DType::F32 && img == DType::F32) return launch_ot_typed<float, float>(a, s);
+  if (real == DType::F32 && img == DType::BF16) return launch_ot_typed<bf16_t, float>(a, s);
+  if (real == DType::F64 && img == DType::F32) return launch_ot_typed<float, double>(a, s);
+  if (real == DType::F64 && img == DType::BF16) return launch_ot_typed<bf16_t, double>(a, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace rgp

@@ -128,6 +128,32 @@ def test_ot_init_parity(shape, pe, real):
             assert int(to_host(ng)[0]) == ref.guarded_cells
 
 
+@pytest.mark.parametrize("shape,pe", [((3, 300, 5), 1), ((700, 3, 4), 0), ((2, 3000, 3), 1),
+                                      ((5000, 2, 2), 0), ((4, 3, 190), 2)])
+def test_ot_init_long_columns(shape, pe):
+    """Every tile shape of the OT kernel (16 columns of 8 or 12 or 16 cells per segment; 8, 4 and
+    1 columns per workgroup for longer columns), against the oracle in FP64."""
+    rgp = _rgp()
+    say(f"[ot_init long] shape={shape} pe={pe}")
+    p = _pair(shape, pe, seed=16)
+    dt = torch.float64
+    for guard in (True, False):
+        b0, ng = rgp.ot_init(to_dev(p.I_plus, dt), to_dev(p.I_minus, dt), pe, guard=guard)
+        ref = orc.ot_init(p.I_plus, p.I_minus, pe, (1.0, 1.0, 1.0), eps=1e-3, guard=guard)
+        err = float(np.max(np.abs(to_host(b0) - ref.b0)))
+        assert err <= 1e-9 * max(1.0, shape[pe] / 100.0), err
+        if guard:
+            assert int(to_host(ng)[0]) == ref.guarded_cells
+
+
+def test_ot_init_column_too_long_is_an_error():
+    rgp = _rgp()
+    z = torch.ones((9000, 2, 2), dtype=torch.float32, device="cuda")
+    with pytest.raises(rgp.RGPError):
+        rgp.ot_init(z, z, 0)
+    torch.cuda.synchronize()
+
+
 def test_ot_guard_and_empty_columns():
     rgp = _rgp()
     m = 30
