@@ -479,11 +479,26 @@ __global__ __launch_bounds__(BLK) void k_trial_batch(const TrialArgs* __restrict
 }
 
 // Armijo decision on the pass just evaluated (one block per volume).
+// The single-candidate pass (gamma = 1) is decided at every Gauss-Newton step that runs, so its
+// block sums are loaded together with the state (one memory round trip); a later pass is usually
+// skipped (a step was accepted), so its larger set of sums is loaded only once the state says it
+// ran.
 template <int NC>
 __device__ __forceinline__ void decide_body(const DecideArgs& a) {
   const State* st = a.st;
-  if (load_flag(&st->gn_stop) || st->accepted) return;
-  decide_pass<NC>(a);
+  double t[3 + 3 * NC];
+  // vector loads, so that they are counted with the block sums below (written by earlier kernels)
+  const int stop = load_flag(&st->gn_stop), acc = load_flag(&st->accepted);
+  if (NC == 1) {
+    partials_share<3 + 3 * NC>(t, a.part_prev, a.nprod_prev);
+    // keeps the loads above the test below (they are not needed on its early-out path, and
+    // would otherwise be sunk past it into a second memory round trip)
+    __asm__ volatile("" ::"v"(t[0]));
+  }
+  if (stop || acc) return;
+  const State s = *st;
+  if (NC != 1) partials_share<3 + 3 * NC>(t, a.part_prev, a.nprod_prev);
+  decide_pass<NC>(a, s, t);
 }
 template <int NC>
 __global__ __launch_bounds__(kReduceBlock) void k_decide(DecideArgs a) { decide_body<NC>(a); }

@@ -271,12 +271,12 @@ __device__ __forceinline__ void load_partials_rm(double (&out)[K], const double*
   }
 }
 
-// Every thread of the calling block obtains the sums over nprod producer blocks.  The loads are
-// issued in batches of 4 (2 for K > 8) blocks per thread, all independent, so that one batch costs
-// one memory round trip; the summation order is fixed.
-template <int K, int BLK>
-__device__ __forceinline__ void reduce_partials(double (&out)[K], const double* part,
-                                                unsigned nprod) {
+// This thread's share of the sums over nprod producer blocks (blocks threadIdx.x, + blockDim.x,
+// ...).  The loads are issued in batches of 4 (2 for K > 8) blocks per thread, all independent,
+// so that one batch costs one memory round trip; the summation order is fixed.
+template <int K>
+__device__ __forceinline__ void partials_share(double (&out)[K], const double* part,
+                                               unsigned nprod) {
 #pragma unroll
   for (int k = 0; k < K; ++k) out[k] = 0.0;
   constexpr int kB = K <= 8 ? 4 : 2;
@@ -293,6 +293,13 @@ __device__ __forceinline__ void reduce_partials(double (&out)[K], const double* 
 #pragma unroll
       for (int k = 0; k < K; ++k) out[k] += v[j][k];
   }
+}
+
+// Every thread of the calling block obtains the sums over nprod producer blocks.
+template <int K, int BLK>
+__device__ __forceinline__ void reduce_partials(double (&out)[K], const double* part,
+                                                unsigned nprod) {
+  partials_share<K>(out, part, nprod);
   block_sum<K, BLK>(out);
 }
 

@@ -98,16 +98,15 @@ __device__ __forceinline__ int armijo_pick(const double* t, int first, int nc, c
   return -1;
 }
 
-// Decision on one finished pass of NC candidates, taken by a single-block kernel: every thread
-// reads the state, then all reduce the pass's 3 + 3 NC block sums, then thread 0 updates the
-// state.  Returns 1 when a step was accepted, 0 when the search continues, -1 when it failed (no
-// trials left).
+// Decision on one finished pass of NC candidates, taken by a single-block kernel from the state
+// s and each thread's share t of the pass's 3 + 3 NC block sums (partials_share): the block adds
+// the shares, then thread 0 updates the state.  Returns 1 when a step was accepted, 0 when the
+// search continues, -1 when it failed (no trials left).
 template <int NC>
-__device__ __forceinline__ int decide_pass(const DecideArgs& a) {
+__device__ __forceinline__ int decide_pass(const DecideArgs& a, const State& s,
+                                           double (&t)[3 + 3 * NC]) {
   State* st = a.st;
-  const State s = *st;
-  double t[3 + 3 * NC];
-  reduce_partials<3 + 3 * NC, kReduceBlock>(t, a.part_prev, a.nprod_prev);  // synchronises
+  block_sum<3 + 3 * NC, kReduceBlock>(t);  // synchronises
   double gq = s.gq, sbq = s.sbq, sqq = s.sqq;
   if (a.prev_first == 0) {
     gq = t[0];
