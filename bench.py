@@ -20,6 +20,8 @@ Other modes (profiling helpers; their output goes under profiles/):
   --profile-summary D         text summary of a rocprofv3 --kernel-trace --stats run in D
   --batch N                   the batching benchmark: N uneven pairs, plain per-pair graphs
                               against one batched graph (its own JSON line)
+  --batch-profile-summary D   per-kernel GB/s of the batched launches from a rocprofv3
+                              --kernel-trace run of --batch 32 in D
 """
 import argparse
 import csv
@@ -321,6 +323,93 @@ def profile_summary(d):
               f"{statistics.median(v):9.2f} {sum(v) / 1e3:9.3f}")
 
 
+def copy_reference(dev, stream, reps=10):
+    """Measured bandwidth of a plain device-to-device copy (torch's copy kernel) at two sizes:
+    one that fits the 256 MB Infinity Cache together with its source (like the PCG step's working
+    set at 144x168x111) and one well beyond it (HBM-resident).  Traffic = bytes read + written."""
+    import torch
+    out = []
+    for mib in (64, 1024):
+        n = mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / reps
+        gbps = 2 * n * 4 / (us * 1e3)
+        out.append(dict(traffic_MiB=2 * mib, us=round(us, 2), GBps=round(gbps, 1),
+                        frac=round(gbps / HBM_PEAK_GBPS, 4)))
+        del src, dst
+    return out
+
+
+def batch_level_bytes(n=32, levels=LEVELS, img_bytes=2, f=4):
+    """Algorithmic bytes per batched launch on each pyramid level (finest first) of the uneven
+    batch (BF16 images, FP32 field): the sums over the pairs of the per-volume rules."""
+    import numpy as np
+
+    from synth.phantom import batch_specs
+    out = []
+    shapes = [(tuple(sp["shape"]), sp["pe"]) for sp in batch_specs(n)]
+    for lv in range(levels):
+        N = Nb = 0
+        for shape, pe in shapes:
+            s = shape
+            for _ in range(lv):
+                s = tuple((x + 1) // 2 for x in s)
+            N += int(np.prod(s))
+            Nb += int(np.prod([x + (1 if d == pe else 0) for d, x in enumerate(s)]))
+        out.append(dict(level=lv, cells=N, nodes=Nb,
+                        pcg_step=10 * Nb * f,
+                        loss_grad=2 * N * img_bytes + 6 * Nb * f,
+                        trial=2 * N * img_bytes + 2 * Nb * f))
+    return out
+
+
+def batch_profile_summary(d):
+    """Per-kernel GB/s of the batched launches (k_pcg_step_batch, k_loss_grad_batch and the
+    single-candidate k_trial_batch) in a rocprofv3 --kernel-trace run of `bench.py --batch 32`.
+    Each kernel's launches are grouped by grid size, largest grid = finest level; the median
+    launch duration is set against the level's algorithmic bytes (full PCG iterations; loss_grad
+    applying the step; the gamma = 1 trial pass)."""
+    trace = _csv_rows(d, "*kernel_trace.csv")
+    lv = batch_level_bytes()
+    print("# batched launches of the uneven 32-pair batch (BF16 images, FP32 field, 3 levels x 10 GN x 20 PCG)")
+    print("# bytes per launch: sums over the 32 pairs of 40 B/node (PCG step), 4 B/cell + 24 B/node")
+    print("# (loss_grad applying the step), 4 B/cell + 8 B/node (trial, gamma = 1)")
+    print(f"{'kernel':18s} {'level':>5s} {'grid':>9s} {'n':>5s} {'median_us':>10s} {'MB':>9s} "
+          f"{'GB/s':>8s} {'frac':>6s}")
+    rows = []
+    for key, match in (("pcg_step", "k_pcg_step_batch"), ("loss_grad", "k_loss_grad_batch"),
+                       ("trial", "k_trial_batch")):
+        groups = {}
+        for r in trace:
+            name = r["Kernel_Name"]
+            if match not in name:
+                continue
+            if key == "trial" and ", 1, 256>" not in name:
+                continue  # the multi-candidate pass, a no-op once gamma = 1 is accepted
+            dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            groups.setdefault(int(r["Grid_Size_X"]), []).append(dur)
+        for level, (grid, v) in enumerate(sorted(groups.items(), key=lambda kv: -kv[0])[:LEVELS]):
+            med = statistics.median(v)
+            by = lv[level][key]
+            gbps = by / (med * 1e3)
+            rows.append(dict(kernel=key, level=level, grid=grid, n=len(v), us_median=round(med, 2),
+                             bytes=by, GBps=round(gbps, 1), frac=round(gbps / HBM_PEAK_GBPS, 4)))
+            print(f"{key:18s} {level:5d} {grid:9d} {len(v):5d} {med:10.2f} {by / 1e6:9.1f} "
+                  f"{gbps:8.1f} {gbps / HBM_PEAK_GBPS:6.3f}")
+    return rows
+
+
 # ---------------------------------------------------------------------------------------------
 # batching: the uneven batch of pairs, plain per-pair graphs against one batched graph
 
@@ -417,6 +506,7 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--profile-summary", metavar="DIR")
+    ap.add_argument("--batch-profile-summary", metavar="DIR")
     ap.add_argument("--batch", type=int, metavar="N", default=0,
                     help="the batching benchmark over N uneven pairs instead of the headline")
     ap.add_argument("--batch-scale", type=float, default=1000.0)
@@ -425,6 +515,9 @@ def main():
         return traffic_summary(*args.traffic_summary)
     if args.profile_summary:
         return profile_summary(args.profile_summary)
+    if args.batch_profile_summary:
+        batch_profile_summary(args.batch_profile_summary)
+        return None
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
               "per-pair work is independent, so pairs shard across GPUs with no communication.",
@@ -536,6 +629,10 @@ def main():
             f"(median {rec['us_median']:7.2f})  {rec['achieved_GBps']:7.1f} GB/s  "
             f"frac {rec['frac']:.3f}")
 
+    copy = copy_reference(dev, side)
+    log("bench: plain copy " + ", ".join(f"{c['traffic_MiB']} MiB traffic {c['GBps']:.0f} GB/s"
+                                         for c in copy))
+
     nb = int(np.prod(rgp.field_shape(shape, pe)))
     dom = next(r for r in kernels.values() if r["kernel"] == "pcg_step" and r["nodes"] == nb)
     traffic = measured_traffic()
@@ -543,7 +640,8 @@ def main():
                     frac=dom["frac"], traffic=traffic,
                     kernel="k_pcg_step (finest level, 144x169x111 nodes, full PCG iterations)",
                     bytes_per_launch=dom["bytes_per_launch"], us_per_launch=dom["us_mean"],
-                    us_median=dom["us_median"], launches=dom["launches"], grid=dom["grid"])
+                    us_median=dom["us_median"], launches=dom["launches"], grid=dom["grid"],
+                    copy_reference=copy)
 
     cpu = None
     if not args.no_cpu_baseline:
