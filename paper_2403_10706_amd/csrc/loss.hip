@@ -455,7 +455,9 @@ __device__ __forceinline__ void trial_body(const TrialArgs& a, VBlock vb) {
       v[5 + 3 * cc] += (double)tvi[cc];
     }
   }
-  store_partials<K, BLK>(v, a.part, vb.id);
+  // column-major (sum k of block b at k * kMaxGrid + b): the single-block decision kernel then
+  // reads each sum of consecutive blocks from consecutive addresses
+  store_partials_cm<K, BLK>(v, a.part, vb.id);
 }
 
 template <typename TI, typename TR, int S, int NC, int BLK, bool PASS0>
@@ -479,6 +481,31 @@ __global__ __launch_bounds__(BLK) void k_trial_batch(const TrialArgs* __restrict
 }
 
 // Armijo decision on the pass just evaluated (one block per volume).
+// This thread's share of K column-major block sums (sum k of block b at k * kMaxGrid + b) over
+// nprod blocks: blocks threadIdx.x, + blockDim.x, ..., loaded kB blocks per sum at a time, all
+// independent (fewer for many sums, so that the loads stay in registers); fixed summation order.
+template <int K>
+__device__ __forceinline__ void trial_sums_share(double (&out)[K], const double* part,
+                                                 unsigned nprod) {
+  constexpr int kB = K <= 8 ? 4 : (K <= 16 ? 2 : 1);
+#pragma unroll
+  for (int k = 0; k < K; ++k) out[k] = 0.0;
+  for (unsigned b0 = 0; b0 < nprod; b0 += kB * blockDim.x) {
+    double v[K][kB];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int j = 0; j < kB; ++j) {
+        const unsigned b = b0 + j * blockDim.x + threadIdx.x;
+        v[k][j] = b < nprod ? part[(size_t)k * kMaxGrid + b] : 0.0;
+      }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int j = 0; j < kB; ++j) out[k] += v[k][j];
+  }
+}
+
 // The single-candidate pass (gamma = 1) is decided at every Gauss-Newton step that runs, so its
 // block sums are loaded together with the state (one memory round trip); a later pass is usually
 // skipped (a step was accepted), so its larger set of sums is loaded only once the state says it
@@ -490,14 +517,14 @@ __device__ __forceinline__ void decide_body(const DecideArgs& a) {
   // vector loads, so that they are counted with the block sums below (written by earlier kernels)
   const int stop = load_flag(&st->gn_stop), acc = load_flag(&st->accepted);
   if (NC == 1) {
-    partials_share<3 + 3 * NC>(t, a.part_prev, a.nprod_prev);
+    trial_sums_share<3 + 3 * NC>(t, a.part_prev, a.nprod_prev);
     // keeps the loads above the test below (they are not needed on its early-out path, and
     // would otherwise be sunk past it into a second memory round trip)
     __asm__ volatile("" ::"v"(t[0]));
   }
   if (stop || acc) return;
   const State s = *st;
-  if (NC != 1) partials_share<3 + 3 * NC>(t, a.part_prev, a.nprod_prev);
+  if (NC != 1) trial_sums_share<3 + 3 * NC>(t, a.part_prev, a.nprod_prev);
   decide_pass<NC>(a, s, t);
 }
 template <int NC>
