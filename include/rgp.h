@@ -106,7 +106,9 @@ rgp_status rgp_workspace_size(rgp_op op, const rgp_grid* grid, rgp_dtype real_t,
  * halfway map T- and the negated displacement of T+.  Columns with no mass get b0 = 0.  If
  * `guard` is set, a column whose slope |D b0| exceeds 0.99 somewhere gets its slopes clipped to
  * +-0.99 and is re-integrated from b0_0 = 0; the number of clipped cells is written to
- * *n_guarded_dev (nullable, uint64 on the device).  b0: field array (real_t) written in full. */
+ * *n_guarded_dev (nullable, uint64 on the device).  b0: field array (real_t) written in full.
+ * Columns of more than 8192 cells along the PE axis give RGP_ESHAPE (the correction entry points:
+ * on the coarsest level, unless the correction starts from a given field). */
 rgp_status rgp_ot_init(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
                        const void* I_minus, rgp_dtype real_t, void* b0, double ot_eps,
                        int32_t guard, uint64_t* n_guarded_dev, void* ws, size_t ws_bytes,

@@ -447,6 +447,7 @@ rgp_status rgp_ot_init(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus
                        void* stream) {
   rgp_status st = check_grid(grid);
   if (st != RGP_OK) return st;
+  if (!ot_column_supported((int)grid->m[grid->pe])) return RGP_ESHAPE;
   DType di, dr;
   if ((st = check_types(img_t, real_t, &di, &dr)) != RGP_OK) return st;
   if (!I_plus || !I_minus || !b0 || !(ot_eps >= 0.0)) return RGP_EINVAL;
@@ -649,6 +650,10 @@ rgp_status check_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_pl
   if ((st = check_opts(opts)) != RGP_OK) return st;
   if (!I_plus || !I_minus || !b_out) return RGP_EINVAL;
   if (opts->use_b_init && !b_init) return RGP_EINVAL;
+  // the OT initialisation runs on the coarsest level
+  Level lv[kMaxLevels];
+  if (make_levels(grid, opts->levels, lv) != 0) return RGP_ESHAPE;
+  if (!opts->use_b_init && !ot_column_supported(lv[opts->levels - 1].g.mp)) return RGP_ESHAPE;
   return need_ws(RGP_OP_CORRECT, grid, real_t, opts, ws, ws_bytes);
 }
 
@@ -944,6 +949,7 @@ rgp_status check_batch_grids(int32_t n, const rgp_grid* grids, rgp_dtype real_t,
     if (grids[p].m[2] + (grids[p].pe == 2 ? 1 : 0) > kBatchMaxContig) return RGP_ESHAPE;
     Level lv[kMaxLevels];
     if (make_levels(&grids[p], opts->levels, lv) != 0) return RGP_ESHAPE;
+    if (!ot_column_supported(lv[opts->levels - 1].g.mp)) return RGP_ESHAPE;
   }
   return RGP_OK;
 }

@@ -367,6 +367,8 @@ OtShape ot_shape(int mp) {
   return {0, 0};
 }
 
+bool ot_column_supported(int mp) { return ot_shape(mp).nc != 0; }
+
 template <typename TI, typename TR, int NC, int LMAX>
 hipError_t launch_ot_tile(const OtArgs& a, hipStream_t s) {
   const unsigned nb = (unsigned)((a.g.ncol + NC - 1) / NC);

@@ -283,6 +283,8 @@ hipError_t launch_pcg_step_plan(const PcgArgs& a, DType real, const PcgPlan& L, 
 hipError_t launch_pcg_scalars(const PcgScalarArgs& a, hipStream_t s);
 hipError_t launch_shift(const ShiftArgs& a, DType img, hipStream_t s);
 hipError_t launch_ot(const OtArgs& a, DType img, DType real, hipStream_t s);
+// Whether the OT kernel takes columns of mp cells along the PE axis (at most 8192).
+bool ot_column_supported(int mp);
 hipError_t launch_restrict(const RestrictArgs& a, DType src, DType dst, hipStream_t s);
 hipError_t launch_prolong(const ProlongArgs& a, DType real, hipStream_t s);
 hipError_t launch_reset(const SetStateArgs& a, hipStream_t s);

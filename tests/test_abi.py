@@ -126,6 +126,17 @@ def test_entry_points_reject_bad_arguments_without_device(lib):
     o.ls_max_trials = 10
     assert lib.rgp_correct(ctypes.byref(g), rgp.F32, fake, fake, rgp.F32, ctypes.byref(o), None,
                            fake, None, None, None, ctypes.c_void_p(0x1004), 1 << 30, None) == -8
+    # OT columns beyond the kernel's 8192 cells: RGP_ESHAPE before anything is launched
+    gl = rgp.make_grid((9000, 2, 2), 0)
+    assert lib.rgp_ot_init(ctypes.byref(gl), rgp.F32, fake, fake, rgp.F32, fake, 1e-3, 1, None,
+                           fake, 1 << 30, None) == -2
+    gc = rgp.make_grid((40000, 2, 2), 0)  # coarsest of 3 levels: 10000 cells along PE
+    o.levels = 3
+    assert lib.rgp_correct(ctypes.byref(gc), rgp.F32, fake, fake, rgp.F32, ctypes.byref(o), None,
+                           fake, None, None, None, fake, 1 << 30, None) == -2
+    o.levels = 4  # coarsest: 5000 cells; the workspace check comes next
+    assert lib.rgp_correct(ctypes.byref(gc), rgp.F32, fake, fake, rgp.F32, ctypes.byref(o), None,
+                           fake, None, None, None, fake, 16, None) == -8
 
 
 def test_batch_workspace_size_and_limits(lib):

@@ -149,8 +149,9 @@ def test_ot_init_long_columns(shape, pe):
 def test_ot_init_column_too_long_is_an_error():
     rgp = _rgp()
     z = torch.ones((9000, 2, 2), dtype=torch.float32, device="cuda")
-    with pytest.raises(rgp.RGPError):
+    with pytest.raises(rgp.RGPError) as e:
         rgp.ot_init(z, z, 0)
+    assert e.value.code == -2  # RGP_ESHAPE, before anything is launched
     torch.cuda.synchronize()
 
 
