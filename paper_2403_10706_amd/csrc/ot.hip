@@ -373,8 +373,11 @@ template <typename TI, typename TR, int NC, int LMAX>
 hipError_t launch_ot_tile(const OtArgs& a, hipStream_t s) {
   const unsigned nb = (unsigned)((a.g.ncol + NC - 1) / NC);
   const size_t lds = (size_t)(a.g.mp + 1) * NC * sizeof(double);
-  hipFuncSetAttribute((const void*)k_ot<TI, TR, NC, LMAX>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (lds > 48 * 1024) {  // long columns: raise the dynamic LDS limit of the kernel
+    const hipError_t e = hipFuncSetAttribute((const void*)k_ot<TI, TR, NC, LMAX>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   RGP_LAUNCH(kKindOt, a.g, (k_ot<TI, TR, NC, LMAX>), nb, kBlock, lds, s, a);
   return hipGetLastError();
 }

@@ -129,10 +129,11 @@ def test_ot_init_parity(shape, pe, real):
 
 
 @pytest.mark.parametrize("shape,pe", [((3, 300, 5), 1), ((700, 3, 4), 0), ((2, 3000, 3), 1),
-                                      ((5000, 2, 2), 0), ((4, 3, 190), 2)])
+                                      ((5000, 2, 2), 0), ((7000, 2, 1), 0), ((4, 3, 190), 2)])
 def test_ot_init_long_columns(shape, pe):
     """Every tile shape of the OT kernel (16 columns of 8 or 12 or 16 cells per segment; 8, 4 and
-    1 columns per workgroup for longer columns), against the oracle in FP64."""
+    1 columns per workgroup for longer columns; 7000 cells need more than 48 KB of LDS), against
+    the oracle in FP64."""
     rgp = _rgp()
     say(f"[ot_init long] shape={shape} pe={pe}")
     p = _pair(shape, pe, seed=16)
