@@ -219,7 +219,9 @@ rgp_status rgp_correct_batch_plan(int32_t n, const rgp_grid* grids, rgp_dtype im
  * workspace's own vectors (a correction workspace; their contents are overwritten, the parts the
  * library relies on are left as rgp_correct needs them) and records the fastest in a
  * process-wide table that every later plain or batched launch on that geometry and field type
- * uses.  Synchronises `stream`; RGP_EINVAL while the stream is being captured.  xl_out: host
+ * uses.  A candidate's figure is the median kernel duration of 9 timed launches (events taken at
+ * each kernel's start and end; a timing session of rgp_timing_start does not see these launches).
+ * Synchronises `stream`; RGP_EINVAL while the stream is being captured.  xl_out: host
  * array of opts->levels int32 (nullable) receiving the chosen XL per level, finest first. */
 rgp_status rgp_autotune(const rgp_grid* grid, rgp_dtype real_t, const rgp_solver_opts* opts,
                         void* ws, size_t ws_bytes, void* stream, int32_t* xl_out);
