@@ -32,7 +32,10 @@ Readings of points the paper leaves open (each one is also listed in the design 
 * R13 PCG relative residual is measured against |grad J|;
 * R14 Armijo with c = 1e-4, gamma = 1, halving, at most ``ls_max_trials`` trial steps;
 * R16 pyramid: 2x2x2 mean restriction (ceil(m/2) cells), linear prolongation on the staggered grid
-  with constant extrapolation at the outer half cells; b keeps physical units.
+  with constant extrapolation at the outer half cells; b keeps physical units;
+* R19 optional blur of the OT field: 3x3x3 Gaussian, standard deviation 1 voxel, weights
+  normalised to sum 1, periodic over the field's node grid (the paper applies it as an FFT
+  convolution, which wraps around).
 """
 from __future__ import annotations
 
@@ -597,6 +600,22 @@ def ot_init(Ip: np.ndarray, Im: np.ndarray, pe: int, h: Sequence[float], *, eps=
     return OTResult(from_cols(b0.reshape(sh + (m + 1,)), pe), clipped, s)
 
 
+def gaussian_blur3(b: np.ndarray, sigma: float = 1.0) -> np.ndarray:
+    """Optional smoothing of the OT field (Sec. 2.2, last step; Sec. 2.4, the InitializeOT
+    description): convolution with the 3x3x3 Gaussian of standard deviation ``sigma`` (in voxels),
+    normalised to sum 1, with periodic wrap-around (R19).  Written as the 27-term sum."""
+    b = np.asarray(b, dtype=np.float64)
+    offs = (-1, 0, 1)
+    w = {(i, j, k): math.exp(-(i * i + j * j + k * k) / (2.0 * sigma * sigma))
+         for i in offs for j in offs for k in offs}
+    total = sum(w.values())
+    out = np.zeros_like(b)
+    for (i, j, k), wt in w.items():
+        # out[x] = sum_d w(d) b[x + d], indices taken modulo the extents
+        out += (wt / total) * np.roll(b, shift=(-i, -j, -k), axis=(0, 1, 2))
+    return out
+
+
 # --------------------------------------------------------------------------------------------
 # Caller-layout wrappers
 # --------------------------------------------------------------------------------------------
@@ -669,7 +688,7 @@ def pyramid(Ip, Im, h, levels):
 
 def solve(Ip, Im, pe, h=(1.0, 1.0, 1.0), *, alpha=ALPHA, beta=BETA, levels=1, gn_iters=5,
           pcg_iters=10, pcg_rtol=0.0, armijo_c=1e-4, ls_max_trials=10, ot_eps=1e-3,
-          ot_guard=True, b_init=None) -> SolveResult:
+          ot_guard=True, ot_blur=False, b_init=None) -> SolveResult:
     """The whole path: pyramid, OT on the coarsest level (or ``b_init`` there), GN-PCG on every
     level coarse to fine with prolongation in between, then the Jacobian-modulation correction
     (Sec. 2.4.7)."""
@@ -679,8 +698,8 @@ def solve(Ip, Im, pe, h=(1.0, 1.0, 1.0), *, alpha=ALPHA, beta=BETA, levels=1, gn
     guarded = 0
     if b_init is None:
         ot = ot_init(Pc, Mc, pe, hcst, eps=ot_eps, guard=ot_guard)
-        b = ot.b0
-        b_ot = ot.b0.copy()
+        b = gaussian_blur3(ot.b0) if ot_blur else ot.b0
+        b_ot = b.copy()
         guarded = ot.guarded_cells
     else:
         b = np.asarray(b_init, dtype=np.float64)

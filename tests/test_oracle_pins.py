@@ -562,3 +562,49 @@ def test_image_gradient_random_directions_and_polarity_swap():
     sp, sm = rgp.image_gradient_cols(Im, Ip, -b, hc)
     np.testing.assert_allclose(sp, gm, rtol=1e-13, atol=1e-15)
     np.testing.assert_allclose(sm, gp, rtol=1e-13, atol=1e-15)
+
+
+# ---- optional blur of the OT field (3x3x3 Gaussian, sigma 1, periodic) ---------------------------
+
+def _blur_fft(b, sigma=1.0):
+    """The same blur as a circular FFT convolution (how the paper applies it): the 27 weights are
+    placed at their offsets modulo the extents (adding up where a short axis folds them)."""
+    K = np.zeros(b.shape)
+    for i in (-1, 0, 1):
+        for j in (-1, 0, 1):
+            for k in (-1, 0, 1):
+                K[i % b.shape[0], j % b.shape[1], k % b.shape[2]] += np.exp(
+                    -(i * i + j * j + k * k) / (2 * sigma * sigma))
+    K /= K.sum()
+    return np.real(np.fft.ifftn(np.fft.fftn(b) * np.fft.fftn(K)))
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 7), (2, 9, 4), (1, 5, 3), (8, 3, 1)])
+def test_blur_matches_fft_circular_convolution(shape):
+    b = np.random.default_rng(41).standard_normal(shape)
+    assert np.max(np.abs(rgp.gaussian_blur3(b) - _blur_fft(b))) < 1e-13
+
+
+def test_blur_of_a_corner_delta_gives_the_wrapped_gaussian_weights():
+    b = np.zeros((5, 6, 7))
+    b[0, 0, 0] = 1.0
+    out = rgp.gaussian_blur3(b)
+    a = math.exp(-0.5)
+    z = (1 + 2 * a) ** 3  # sum of the 27 weights exp(-|d|^2 / 2)
+    assert out[0, 0, 0] == pytest.approx(1.0 / z, rel=1e-14)
+    assert out[4, 0, 0] == pytest.approx(a / z, rel=1e-14)            # offset -1 wraps to m-1
+    assert out[1, 5, 0] == pytest.approx(a * a / z, rel=1e-14)
+    assert out[4, 5, 6] == pytest.approx(a ** 3 / z, rel=1e-14)
+    assert out[2, 0, 0] == 0.0 and out[0, 3, 3] == 0.0                  # outside the 3x3x3 box
+    assert out.sum() == pytest.approx(1.0, rel=1e-14)
+
+
+def test_blur_keeps_constants_and_the_total_and_is_separable():
+    b = np.random.default_rng(42).standard_normal((6, 5, 7))
+    assert np.max(np.abs(rgp.gaussian_blur3(np.full((4, 5, 6), 2.5)) - 2.5)) < 1e-14
+    assert rgp.gaussian_blur3(b).sum() == pytest.approx(b.sum(), abs=1e-12)
+    a = math.exp(-0.5)
+    sep = b
+    for ax in range(3):  # three 1D passes with [a, 1, a] / (1 + 2a)
+        sep = (a * np.roll(sep, 1, axis=ax) + sep + a * np.roll(sep, -1, axis=ax)) / (1 + 2 * a)
+    assert np.max(np.abs(rgp.gaussian_blur3(b) - sep)) < 1e-14
