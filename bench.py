@@ -91,6 +91,8 @@ def algorithmic_bytes(rec, f=4, fi=4, maxit=PCG_ITERS):
         return 2 * fi * c + f * n
     if k == "shift":           # reads I+, I-
         return 2 * fi * c
+    if k == "blur":            # reads b, writes the blurred b
+        return 2 * f * n
     return 0
 
 
@@ -101,6 +103,7 @@ BYTES_RULE = {
     "hvp": "reads v,diag,off, writes Hv (16 B/node)",
     "ot": "reads I+,I-, writes b0 (8 B/cell + 4 B/node)",
     "shift": "reads I+,I- (8 B/cell)",
+    "blur": "reads b, writes blurred b (8 B/node)",
 }
 
 
@@ -598,7 +601,7 @@ def main():
     log(f"bench: eager with kernel timing {eager_ms:.3f} ms/pair ({len(recs)} timed launches)")
     kernels = summarize_records(recs)
 
-    # stand-alone calls at full resolution: loss_grad, gn_hvp, ot_init (R launches each)
+    # stand-alone calls at full resolution: loss_grad, gn_hvp, ot_init, the OT blur (R launches each)
     R = 20
     lg_ws = torch.zeros(rgp.workspace_size(rgp.OP_LOSS_GRAD, shape, pe, (1, 1, 1), dt),
                         dtype=torch.uint8, device=dev)
@@ -620,6 +623,9 @@ def main():
         rgp.gn_hvp_into(hd, ho, v, Hv, vhv, shape, pe, lg_ws, stream=side)
     for _ in range(R):
         rgp.ot_init_into(Ip, Im, pe, b0, ot_ws, stream=side)
+    b0b = torch.empty_like(b0)
+    for _ in range(R):
+        rgp.blur_field(b0, shape, pe, out=b0b, stream=side)
     torch.cuda.synchronize()
     solo = rgp.timing_stop(1 << 12)
     for name, rec in summarize_records(solo).items():

@@ -70,6 +70,8 @@ typedef struct {
   double ot_eps;         /* positivity shift of the OT init: eps * max|I| (1e-3) */
   int32_t ot_guard;      /* clip OT slopes to +-0.99 and re-integrate (1) */
   int32_t use_b_init;    /* 1: start from b_init on the coarsest level instead of OT */
+  int32_t ot_blur;       /* 1: blur the OT field (rgp_blur_field) before the first GN step (0) */
+  int32_t reserved;
 } rgp_solver_opts;
 
 /* Number of doubles per Gauss-Newton record in the stats buffer of rgp_correct. */
@@ -123,6 +125,15 @@ rgp_status rgp_ot_init(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus
  * hoff[k] the coupling of PE nodes k and k+1 (0 at the last node); the cross-axis couplings are
  * -alpha vol / h_d^2.  hdiag and hoff are both given or both NULL.  Their contents are
  * unspecified when J = +inf. */
+/* Optional smoothing of an OT initial field (Sec. 2.2, last step; Sec. 2.4, the OT
+ * initialisation's blurring operator): b_out = G * b_in with the 3x3x3 Gaussian of standard
+ * deviation 1 voxel, weights exp(-|d|^2/2) over the offsets d in {-1,0,1}^3 normalised to sum 1,
+ * periodic over the node grid of `grid` (the paper applies it as an FFT convolution, which
+ * wraps around).  b_in, b_out: distinct device field arrays of real_t (RGP_F32 or RGP_F64; b_in ==
+ * b_out gives RGP_EINVAL).  Enqueued on `stream`; needs no workspace. */
+rgp_status rgp_blur_field(const rgp_grid* grid, rgp_dtype real_t, const void* b_in, void* b_out,
+                          void* stream);
+
 rgp_status rgp_loss_grad(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
                          const void* I_minus, rgp_dtype real_t, const void* b, double alpha,
                          double beta, double* jdsp_dev, void* grad, void* hdiag, void* hoff,
@@ -242,7 +253,8 @@ typedef enum {
   RGP_KERNEL_TRIAL = 2,      /* Armijo trial objectives */
   RGP_KERNEL_HVP = 3,        /* stand-alone GN Hessian-vector product */
   RGP_KERNEL_OT = 4,         /* column-wise optimal-transport initialisation (Sec. 2.2) */
-  RGP_KERNEL_SHIFT = 5       /* positivity shift of the OT initialisation */
+  RGP_KERNEL_SHIFT = 5,      /* positivity shift of the OT initialisation */
+  RGP_KERNEL_BLUR = 6        /* optional Gaussian blur of the OT field */
 } rgp_kernel_kind;
 typedef struct {
   int32_t kernel;

@@ -33,7 +33,7 @@ Readings of points the paper leaves open (each one is also listed in the design 
 * R14 Armijo with c = 1e-4, gamma = 1, halving, at most ``ls_max_trials`` trial steps;
 * R16 pyramid: 2x2x2 mean restriction (ceil(m/2) cells), linear prolongation on the staggered grid
   with constant extrapolation at the outer half cells; b keeps physical units;
-* R19 optional blur of the OT field: 3x3x3 Gaussian, standard deviation 1 voxel, weights
+* R25 optional blur of the OT field: 3x3x3 Gaussian, standard deviation 1 voxel, weights
   normalised to sum 1, periodic over the field's node grid (the paper applies it as an FFT
   convolution, which wraps around).
 """
@@ -603,7 +603,7 @@ def ot_init(Ip: np.ndarray, Im: np.ndarray, pe: int, h: Sequence[float], *, eps=
 def gaussian_blur3(b: np.ndarray, sigma: float = 1.0) -> np.ndarray:
     """Optional smoothing of the OT field (Sec. 2.2, last step; Sec. 2.4, the InitializeOT
     description): convolution with the 3x3x3 Gaussian of standard deviation ``sigma`` (in voxels),
-    normalised to sum 1, with periodic wrap-around (R19).  Written as the 27-term sum."""
+    normalised to sum 1, with periodic wrap-around (R25).  Written as the 27-term sum."""
     b = np.asarray(b, dtype=np.float64)
     offs = (-1, 0, 1)
     w = {(i, j, k): math.exp(-(i * i + j * j + k * k) / (2.0 * sigma * sigma))

@@ -248,6 +248,7 @@ rgp_status check_opts(const rgp_solver_opts* o) {
   if (o->pcg_iters < 1 || o->pcg_iters > 1000) return RGP_EINVAL;
   if (o->ls_max_trials < 1 || o->ls_max_trials > 10) return RGP_EINVAL;
   if (!(o->pcg_rtol >= 0.0) || !(o->armijo_c >= 0.0) || !(o->ot_eps >= 0.0)) return RGP_EINVAL;
+  if (o->ot_blur != 0 && o->ot_blur != 1) return RGP_EINVAL;
   return RGP_OK;
 }
 
@@ -395,6 +396,7 @@ void rgp_default_opts(rgp_solver_opts* o) {
   o->ot_eps = 1e-3;
   o->ot_guard = 1;
   o->use_b_init = 0;
+  o->ot_blur = 0;
 }
 
 rgp_status rgp_workspace_size(rgp_op op, const rgp_grid* grid, rgp_dtype real_t,
@@ -472,6 +474,22 @@ rgp_status rgp_ot_init(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus
   oa.guard_slope = kGuardSlope;
   oa.guarded = gd;
   RGP_HIP(launch_ot(oa, di, dr, s));
+  return RGP_OK;
+}
+
+rgp_status rgp_blur_field(const rgp_grid* grid, rgp_dtype real_t, const void* b_in, void* b_out,
+                          void* stream) {
+  rgp_status st = check_grid(grid);
+  if (st != RGP_OK) return st;
+  DType dr;
+  if (!dtype_of(real_t, &dr) || dr == DType::BF16) return RGP_EDTYPE;
+  if (!b_in || !b_out || b_in == b_out) return RGP_EINVAL;
+  BlurArgs ba{};
+  ba.src = b_in;
+  ba.dst = b_out;
+  for (int d = 0; d < 3; ++d) ba.n[d] = (uint32_t)(grid->m[d] + (d == grid->pe ? 1 : 0));
+  ba.cells = grid->m[0] * grid->m[1] * grid->m[2];
+  RGP_HIP(launch_blur(ba, dr, static_cast<hipStream_t>(stream)));
   return RGP_OK;
 }
 
@@ -727,6 +745,15 @@ rgp_status enqueue_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_
   }
 
   int cur = 0;
+  if (!opts->use_b_init && opts->ot_blur) {
+    BlurArgs ba{};
+    ba.src = w.B[0];
+    ba.dst = w.B[1];
+    for (int d = 0; d < 3; ++d) ba.n[d] = (uint32_t)(top.m[d] + (d == grid->pe ? 1 : 0));
+    ba.cells = top.g.ncell;
+    RGP_HIP(launch_blur(ba, dr, s));
+    cur = 1;
+  }
   for (int l = L - 1; l >= 0; --l) {
     if (l < L - 1) {
       ProlongArgs pa{};

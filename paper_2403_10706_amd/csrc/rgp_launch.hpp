@@ -248,7 +248,8 @@ enum KernelKind : int {
   kKindHvp = 3,
   kKindOt = 4,
   kKindShift = 5,
-  kKindCount = 6
+  kKindBlur = 6,
+  kKindCount = 7
 };
 bool timing_slot(int kind, int tag, unsigned grid, int64_t cells, int64_t nodes, hipStream_t s,
                  hipEvent_t* e0, hipEvent_t* e1);
@@ -283,6 +284,15 @@ hipError_t launch_pcg_step_plan(const PcgArgs& a, DType real, const PcgPlan& L, 
 hipError_t launch_pcg_scalars(const PcgScalarArgs& a, hipStream_t s);
 hipError_t launch_shift(const ShiftArgs& a, DType img, hipStream_t s);
 hipError_t launch_ot(const OtArgs& a, DType img, DType real, hipStream_t s);
+// Optional blur of the OT field: dst = 3x3x3 Gaussian (sigma 1 voxel) of src, periodic over the
+// node grid n[0] x n[1] x n[2].
+struct BlurArgs {
+  const void* src;
+  void* dst;
+  uint32_t n[3];
+  int64_t cells;
+};
+hipError_t launch_blur(const BlurArgs& a, DType real, hipStream_t s);
 // Whether the OT kernel takes columns of mp cells along the PE axis (at most 8192).
 bool ot_column_supported(int mp);
 hipError_t launch_restrict(const RestrictArgs& a, DType src, DType dst, hipStream_t s);

@@ -49,18 +49,20 @@ class SolverOpts(ctypes.Structure):
                 ("pcg_iters", ctypes.c_int32), ("ls_max_trials", ctypes.c_int32),
                 ("pcg_rtol", ctypes.c_double), ("armijo_c", ctypes.c_double),
                 ("ot_eps", ctypes.c_double), ("ot_guard", ctypes.c_int32),
-                ("use_b_init", ctypes.c_int32)]
+                ("use_b_init", ctypes.c_int32), ("ot_blur", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 EXPORTS = ("rgp_status_string", "rgp_last_hip_error", "rgp_default_opts", "rgp_workspace_size",
            "rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
            "rgp_apply_correction", "rgp_correct", "rgp_correct_plan", "rgp_plan_launch",
            "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop", "rgp_loss_grad_images",
-           "rgp_batch_workspace_size", "rgp_correct_batch_plan", "rgp_autotune")
+           "rgp_batch_workspace_size", "rgp_correct_batch_plan", "rgp_autotune", "rgp_blur_field")
 
 # rgp_kernel_kind
-KERNEL_PCG_STEP, KERNEL_LOSS_GRAD, KERNEL_TRIAL, KERNEL_HVP, KERNEL_OT, KERNEL_SHIFT = range(6)
-KERNEL_NAMES = ("pcg_step", "loss_grad", "trial", "hvp", "ot", "shift")
+KERNEL_PCG_STEP, KERNEL_LOSS_GRAD, KERNEL_TRIAL, KERNEL_HVP, KERNEL_OT, KERNEL_SHIFT, \
+    KERNEL_BLUR = range(7)
+KERNEL_NAMES = ("pcg_step", "loss_grad", "trial", "hvp", "ot", "shift", "blur")
 
 
 class TimingRecord(ctypes.Structure):
@@ -109,7 +111,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rgp_correct_batch_plan.argtypes = [i32, gp, ctypes.c_int, vp, vp, ctypes.c_int, op, vp, vp,
                                            vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_void_p)]
     lib.rgp_timing_stop.argtypes = [ctypes.POINTER(TimingRecord), i32, ctypes.POINTER(i32)]
-    for name in ("rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
+    lib.rgp_blur_field.argtypes = [gp, ctypes.c_int, vp, vp, vp]
+    for name in ("rgp_blur_field", "rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
                  "rgp_apply_correction", "rgp_correct", "rgp_workspace_size", "rgp_correct_plan",
                  "rgp_plan_launch", "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop",
                  "rgp_loss_grad_images", "rgp_batch_workspace_size", "rgp_correct_batch_plan",
@@ -222,6 +225,20 @@ def ot_init(I_plus: torch.Tensor, I_minus: torch.Tensor, pe: int, h=(1.0, 1.0, 1
     return out, ng
 
 
+def blur_field(b: torch.Tensor, shape, pe: int, *, out=None, stream=None):
+    """Optional 3x3x3 Gaussian blur (sigma 1 voxel, periodic) of a field on the grid of image
+    shape `shape` (see rgp_blur_field).  Returns the blurred field (a new tensor unless `out`)."""
+    _dev_check(b)
+    if tuple(b.shape) != field_shape(tuple(shape), pe):
+        raise ValueError(f"field shape {tuple(b.shape)} != {field_shape(tuple(shape), pe)}")
+    if out is None:
+        out = torch.empty_like(b)
+    g = make_grid(tuple(shape), pe)
+    _check("rgp_blur_field", load().rgp_blur_field(ctypes.byref(g), dtype_code(b.dtype), _ptr(b),
+                                                   _ptr(out), _stream_ptr(stream)))
+    return out
+
+
 def loss_grad(I_plus, I_minus, b, pe, h=(1.0, 1.0, 1.0), alpha=300.0, beta=1e-4, *,
               want_grad=True, want_hess=True, ws=None, stream=None):
     """Objective (device tensor [J, D, S, P] in FP64), gradient and banded GN Hessian."""
@@ -310,6 +327,7 @@ class Options:
     armijo_c: float = 1e-4
     ot_eps: float = 1e-3
     ot_guard: bool = True
+    ot_blur: bool = False
 
     def to_c(self, use_b_init: bool = False) -> SolverOpts:
         o = SolverOpts()
@@ -319,6 +337,7 @@ class Options:
         o.pcg_rtol, o.armijo_c, o.ot_eps = float(self.pcg_rtol), float(self.armijo_c), float(self.ot_eps)
         o.ot_guard = int(bool(self.ot_guard))
         o.use_b_init = int(bool(use_b_init))
+        o.ot_blur = int(bool(self.ot_blur))
         return o
 
 

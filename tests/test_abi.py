@@ -126,6 +126,10 @@ def test_entry_points_reject_bad_arguments_without_device(lib):
     o.ls_max_trials = 10
     assert lib.rgp_correct(ctypes.byref(g), rgp.F32, fake, fake, rgp.F32, ctypes.byref(o), None,
                            fake, None, None, None, ctypes.c_void_p(0x1004), 1 << 30, None) == -8
+    # the blur of the OT field works out of place, on FP32 or FP64 fields
+    assert lib.rgp_blur_field(ctypes.byref(g), rgp.F32, fake, fake, None) == -1
+    assert lib.rgp_blur_field(ctypes.byref(g), rgp.BF16, fake, ctypes.c_void_p(0x2000), None) == -3
+    assert lib.rgp_blur_field(None, rgp.F32, fake, ctypes.c_void_p(0x2000), None) == -1
     # OT columns beyond the kernel's 8192 cells: RGP_ESHAPE before anything is launched
     gl = rgp.make_grid((9000, 2, 2), 0)
     assert lib.rgp_ot_init(ctypes.byref(gl), rgp.F32, fake, fake, rgp.F32, fake, 1e-3, 1, None,

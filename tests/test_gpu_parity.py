@@ -156,6 +156,39 @@ def test_ot_init_column_too_long_is_an_error():
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("real", ["f64", "f32"])
+@pytest.mark.parametrize("shape,pe", SHAPES + [((1, 5, 3), 1), ((2, 3, 2), 2)])
+def test_blur_field_parity(shape, pe, real):
+    """Optional 3x3x3 Gaussian blur of the OT field (periodic), against the oracle; extents of 1
+    and 2 fold the wrapped neighbours onto the same node."""
+    rgp = _rgp()
+    say(f"[blur] shape={shape} pe={pe} real={real}")
+    dt = REAL[real]
+    fs = tuple(s + (d == pe) for d, s in enumerate(shape))
+    b = rounded(np.random.default_rng(17).standard_normal(fs) * 3.0, dt)
+    out = rgp.blur_field(to_dev(b, dt), shape, pe)
+    ref = orc.gaussian_blur3(b)
+    err = float(np.max(np.abs(to_host(out) - ref)))
+    assert err <= _tol(real, 1e-12, 3e-6), err
+
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_correct_with_ot_blur(real):
+    """The correction with the optional blur of the OT field: the blurred start and the final field
+    against the oracle's solve with the same option, on two levels (the blur runs on the coarser)."""
+    rgp = _rgp()
+    p = synth.make_workload("c1")
+    dt = REAL[real]
+    Ip, Im = rounded(p.I_plus, dt), rounded(p.I_minus, dt)
+    opts = rgp.Options(levels=2, gn_iters=3, pcg_iters=10, pcg_rtol=0.0, ot_blur=True)
+    out = rgp.correct(to_dev(Ip, dt), to_dev(Im, dt), p.pe, opts=opts)
+    ref = orc.solve(Ip, Im, p.pe, levels=2, gn_iters=3, pcg_iters=10, pcg_rtol=0.0, ot_blur=True)
+    plain = orc.solve(Ip, Im, p.pe, levels=2, gn_iters=3, pcg_iters=10, pcg_rtol=0.0)
+    err = float(np.max(np.abs(to_host(out["b"]) - ref.b)))
+    assert err <= _tol(real, 1e-8, BFINAL_ATOL), err
+    assert float(np.max(np.abs(ref.b_ot - plain.b_ot))) > 0.1  # the blur changes the start
+
+
 def test_ot_guard_and_empty_columns():
     rgp = _rgp()
     m = 30
