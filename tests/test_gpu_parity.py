@@ -588,6 +588,34 @@ BATCH_SPECS = [((40, 48, 36), 1), ((45, 30, 26), 0), ((33, 41, 29), 1), ((28, 36
                ((50, 22, 31), 1)]
 
 
+def test_batch_plan_with_ot_blur_matches_per_pair():
+    """The optional blur of the OT field inside a batched plan (it runs pair by pair in the shared
+    graph): every pair's final field equals its per-pair correction with the same option, and
+    the first pair agrees with the oracle's solve with the blur."""
+    rgp = _rgp()
+    specs = BATCH_SPECS[:3]
+    pairs = [_pair(sh, pe, seed=60 + i, scale=30.0) for i, (sh, pe) in enumerate(specs)]
+    pes = [pe for _, pe in specs]
+    opts = rgp.Options(levels=2, gn_iters=3, pcg_iters=8, pcg_rtol=0.0, ot_blur=True)
+    dt = torch.float32
+    host = [(rounded(p.I_plus, dt), rounded(p.I_minus, dt)) for p in pairs]
+    Ip = [to_dev(a, dt) for a, _ in host]
+    Im = [to_dev(c, dt) for _, c in host]
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        bp = rgp.BatchPlan(Ip, Im, pes, opts, stream=s)
+        bp.launch(s)
+        s.synchronize()
+    for i, (sh, pe) in enumerate(specs):
+        ref = rgp.correct(Ip[i], Im[i], pe, opts=opts, real_dtype=dt)
+        err = float(torch.max(torch.abs(bp.b[i] - ref["b"])))
+        assert err <= 1e-3, (i, err)
+    a, c = host[0]
+    ora = orc.solve(a, c, pes[0], levels=2, gn_iters=3, pcg_iters=8, pcg_rtol=0.0, ot_blur=True)
+    assert float(np.max(np.abs(to_host(bp.b[0]) - ora.b))) <= BFINAL_ATOL
+
+
 @pytest.mark.parametrize("img", ["f32", "bf16"])
 def test_batch_plan_matches_per_pair(img):
     """Five pairs of different shapes, PE along dims 0 and 1, one captured graph whose
