@@ -337,56 +337,56 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LMAX <= 
 // Optional blur of the OT field: the 3x3x3 Gaussian of standard deviation 1 voxel, normalised
 // to sum 1, is the product of three 1D factors [a, 1, a] / (1 + 2a) with a = exp(-1/2); neighbour
 // indices wrap around every axis (the paper applies the blur as an FFT convolution).  One node
-// per thread (adjacent lanes, adjacent nodes of the contiguous axis); the 27 taps hit L1/L2.
-// Runs of 8 nodes per thread (10 loads per neighbourhood row instead of 24) measured 3x slower:
-// lanes 8 nodes apart break the coalescing of every load.
+// per thread, adjacent lanes on adjacent nodes of the contiguous axis; the node index splits with
+// multiply-shift divisions and the 27 taps hit L1/L2.  Measured alternatives: runs of 8 nodes per
+// thread (3x slower: lanes 8 nodes apart break the coalescing) and taking the two neighbours
+// along the contiguous axis from the adjacent lanes (DPP; 7 % slower).
 // ------------------------------------------------------------------------------------------
 template <typename TR>
-__global__ __launch_bounds__(kBlock) void k_blur(BlurArgs a, TR we, TR wc) {
+__global__ __launch_bounds__(kBlock) void k_blur(BlurArgs a, TR we, TR wc, FastDiv by_n2,
+                                                 FastDiv by_n1) {
   const uint32_t n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
-  const uint32_t total = n0 * n1 * n2;
+  const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n0 * n1 * n2) return;
   const TR* __restrict__ src = static_cast<const TR*>(a.src);
-  TR* __restrict__ dst = static_cast<TR*>(a.dst);
   const TR w[3] = {we, wc, we};
-  for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < total; t += gridDim.x * kBlock) {
-    const uint32_t i2 = t % n2, r = t / n2, i1 = r % n1, i0 = r / n1;
-    const uint32_t j0[3] = {i0 == 0 ? n0 - 1 : i0 - 1, i0, i0 + 1 == n0 ? 0u : i0 + 1};
-    const uint32_t j1[3] = {i1 == 0 ? n1 - 1 : i1 - 1, i1, i1 + 1 == n1 ? 0u : i1 + 1};
-    const uint32_t j2[3] = {i2 == 0 ? n2 - 1 : i2 - 1, i2, i2 + 1 == n2 ? 0u : i2 + 1};
-    TR v[3][3][3];
+  const uint32_t r = fdiv(t, by_n2), i2 = t - r * n2, i0 = fdiv(r, by_n1), i1 = r - i0 * n1;
+  const uint32_t j0[3] = {i0 == 0 ? n0 - 1 : i0 - 1, i0, i0 + 1 == n0 ? 0u : i0 + 1};
+  const uint32_t j1[3] = {i1 == 0 ? n1 - 1 : i1 - 1, i1, i1 + 1 == n1 ? 0u : i1 + 1};
+  const uint32_t j2[3] = {i2 == 0 ? n2 - 1 : i2 - 1, i2, i2 + 1 == n2 ? 0u : i2 + 1};
+  TR v[3][3][3];
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
+  for (int p = 0; p < 3; ++p)
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
+    for (int q = 0; q < 3; ++q)
 #pragma unroll
-        for (int u = 0; u < 3; ++u) v[p][q][u] = src[(j0[p] * n1 + j1[q]) * n2 + j2[u]];
-    TR acc = TR(0);
+      for (int u = 0; u < 3; ++u) v[p][q][u] = src[(j0[p] * n1 + j1[q]) * n2 + j2[u]];
+  TR acc = TR(0);
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-      TR s1 = TR(0);
+  for (int p = 0; p < 3; ++p) {
+    TR s1 = TR(0);
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
-        s1 += w[q] * (w[0] * v[p][q][0] + w[1] * v[p][q][1] + w[2] * v[p][q][2]);
-      acc += w[p] * s1;
-    }
-    dst[t] = acc;
+    for (int q = 0; q < 3; ++q)
+      s1 += w[q] * (w[0] * v[p][q][0] + w[1] * v[p][q][1] + w[2] * v[p][q][2]);
+    acc += w[p] * s1;
   }
+  static_cast<TR*>(a.dst)[t] = acc;
 }
 
 hipError_t launch_blur(const BlurArgs& a, DType real, hipStream_t s) {
   if (active_recorder())
     return record_other([a, real](hipStream_t s2) { return launch_blur(a, real, s2); });
   const int64_t total = (int64_t)a.n[0] * a.n[1] * a.n[2];
-  if (total < 1 || total > (int64_t(1) << 31)) return hipErrorInvalidValue;
-  int64_t nb = (total + kBlock - 1) / kBlock;
-  if (nb > 4096) nb = 4096;
+  if (total < 1 || total > (int64_t(1) << 30)) return hipErrorInvalidValue;
+  const unsigned nb = (unsigned)((total + kBlock - 1) / kBlock);
   const double ea = std::exp(-0.5), z = 1.0 + 2.0 * ea;
+  const FastDiv d2 = make_fastdiv(a.n[2]), d1 = make_fastdiv(a.n[1]);
   if (real == DType::F64)
-    RGP_LAUNCH_N(kKindBlur, a.cells, total, k_blur<double>, (unsigned)nb, kBlock, 0, s, a,
-                 ea / z, 1.0 / z);
+    RGP_LAUNCH_N(kKindBlur, a.cells, total, k_blur<double>, nb, kBlock, 0, s, a, ea / z, 1.0 / z,
+                 d2, d1);
   else if (real == DType::F32)
-    RGP_LAUNCH_N(kKindBlur, a.cells, total, k_blur<float>, (unsigned)nb, kBlock, 0, s, a,
-                 (float)(ea / z), (float)(1.0 / z));
+    RGP_LAUNCH_N(kKindBlur, a.cells, total, k_blur<float>, nb, kBlock, 0, s, a, (float)(ea / z),
+                 (float)(1.0 / z), d2, d1);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
