@@ -35,7 +35,12 @@ Readings of points the paper leaves open (each one is also listed in the design 
   with constant extrapolation at the outer half cells; b keeps physical units;
 * R25 optional blur of the OT field: 3x3x3 Gaussian, standard deviation 1 voxel, weights
   normalised to sum 1, periodic over the field's node grid (the paper applies it as an FFT
-  convolution, which wraps around).
+  convolution, which wraps around);
+* R27 failures of a solve are reported, first one wins, by a status code: an image with a
+  non-finite value (no Gauss-Newton step is taken, the initial field is zero when OT would
+  have made it), a level that starts from a field outside the barrier (J = +inf: the level
+  stops with b unchanged), a step that no Armijo trial accepts (the level stops with b
+  unchanged).  Later levels still run.
 """
 from __future__ import annotations
 
@@ -47,6 +52,12 @@ import numpy as np
 
 ALPHA = 300.0  # smoothness weight fixed in Sec. 2.1
 BETA = 1e-4    # barrier weight fixed in Sec. 2.1
+
+# Status of a whole solve (R27); 0 when nothing failed.
+STATUS_OK = 0
+STATUS_NONFINITE = -4    # an input image holds a NaN or an infinity
+STATUS_BARRIER = -5      # a level started from a field with |D b| >= 1 somewhere (J = +inf)
+STATUS_LINESEARCH = -6   # no Armijo trial was accepted in some Gauss-Newton step
 
 
 # --------------------------------------------------------------------------------------------
@@ -675,6 +686,7 @@ class SolveResult:
     b_ot: Optional[np.ndarray]
     ot_guarded: int
     levels: list          # per level: (shape, h, list of GNStep)
+    status: int = STATUS_OK
 
 
 def pyramid(Ip, Im, h, levels):
@@ -691,30 +703,43 @@ def solve(Ip, Im, pe, h=(1.0, 1.0, 1.0), *, alpha=ALPHA, beta=BETA, levels=1, gn
           ot_guard=True, ot_blur=False, b_init=None) -> SolveResult:
     """The whole path: pyramid, OT on the coarsest level (or ``b_init`` there), GN-PCG on every
     level coarse to fine with prolongation in between, then the Jacobian-modulation correction
-    (Sec. 2.4.7)."""
+    (Sec. 2.4.7).  Failures are reported in ``status`` (R27)."""
+    finite = bool(np.all(np.isfinite(Ip)) and np.all(np.isfinite(Im)))
+    status = STATUS_OK if finite else STATUS_NONFINITE
     pyr = pyramid(Ip, Im, h, levels)
     Pc, Mc, hcst = pyr[-1]
     b_ot = None
     guarded = 0
-    if b_init is None:
+    if b_init is not None:
+        b = np.asarray(b_init, dtype=np.float64)
+    elif not finite:
+        b = np.zeros(Pc.shape[:pe] + (Pc.shape[pe] + 1,) + Pc.shape[pe + 1:])
+        b_ot = b.copy()
+    else:
         ot = ot_init(Pc, Mc, pe, hcst, eps=ot_eps, guard=ot_guard)
         b = gaussian_blur3(ot.b0) if ot_blur else ot.b0
         b_ot = b.copy()
         guarded = ot.guarded_cells
-    else:
-        b = np.asarray(b_init, dtype=np.float64)
     lev = []
     for li in range(levels - 1, -1, -1):
         P, M, hh = pyr[li]
         if li < levels - 1:
             b = prolong_field(b, P.shape, pe)
+        if not finite:
+            lev.append((P.shape, hh, []))
+            continue
         b, hist = gauss_newton(P, M, b, pe, hh, alpha=alpha, beta=beta, gn_iters=gn_iters,
                                pcg_iters=pcg_iters, pcg_rtol=pcg_rtol, armijo_c=armijo_c,
                                ls_max_trials=ls_max_trials)
         lev.append((P.shape, hh, hist))
+        if status == STATUS_OK and hist:
+            if math.isinf(hist[0].J):
+                status = STATUS_BARRIER
+            elif not hist[-1].accepted:
+                status = STATUS_LINESEARCH
     P, M, hh = pyr[0]
     return SolveResult(b, transform(P, b, pe, hh, +1.0), transform(M, b, pe, hh, -1.0), b_ot,
-                       guarded, lev)
+                       guarded, lev, status)
 
 
 # --------------------------------------------------------------------------------------------

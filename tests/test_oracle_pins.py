@@ -491,6 +491,130 @@ def test_prolong_reproduces_linear_fields(pe):
     assert np.allclose(const, -1.25, rtol=0, atol=1e-15)
 
 
+@pytest.mark.parametrize("pe", [0, 1, 2])
+def test_prolong_outer_half_cells_are_constant(pe):
+    """Hand-computed prolongation (R16) of a separable coarse field f0(i) + f1(j) + f2(k) from
+    coarse cells (2, 2) across and 1 cell (2 nodes) along PE to fine cells (4, 3) across and 2
+    cells (3 nodes) along PE.  Fine cell centres in coarse index units: (j + 1/2)/2 - 1/2, i.e.
+    -0.25, 0.25, 0.75, 1.25 for 4 fine cells; fine nodes: k/2.  The outer half cells (-0.25 and
+    1.25) take the nearest coarse value (linear extrapolation would give -2.5 and 12.5 below)."""
+    f0c, f0f = [0.0, 10.0], [0.0, 2.5, 7.5, 10.0]        # cross axis, 2 -> 4 cells
+    f1c, f1f = [3.0, -1.0], [3.0, 2.0, 0.0]              # cross axis, 2 -> 3 cells
+    f2c, f2f = [1.0, 5.0], [1.0, 3.0, 5.0]               # PE axis, 2 -> 3 nodes
+    bc_cols = (np.asarray(f0c)[:, None, None] + np.asarray(f1c)[None, :, None]
+               + np.asarray(f2c)[None, None, :])
+    want_cols = (np.asarray(f0f)[:, None, None] + np.asarray(f1f)[None, :, None]
+                 + np.asarray(f2f)[None, None, :])
+    bc = np.moveaxis(bc_cols, -1, pe)
+    fine_cells = [4, 3]
+    fine_cells.insert(pe, 2)
+    got = rgp.prolong_field(bc, fine_cells, pe)
+    np.testing.assert_allclose(np.moveaxis(got, pe, -1), want_cols, rtol=0, atol=1e-13)
+
+
+# ------------------------------------------------------------------------------------------
+# Failure branches of the Gauss-Newton solve and the status of a solve (R14, R27)
+# ------------------------------------------------------------------------------------------
+
+def test_gauss_newton_stops_with_b_unchanged_when_no_trial_is_accepted():
+    """The 32x32x24 pair with images x3000 and one Armijo trial: gamma = 1 fails at the first
+    step, so the iteration stops there (no further steps), b is returned bitwise unchanged, and
+    the record says accepted = False, gamma = 0, one trial.  The rejection is confirmed with the
+    plain-loop objective at b + q."""
+    import synth
+    from oracle import loops
+    p = synth.make_workload("c1", scale=3000.0)
+    b0 = rgp.ot_init(p.I_plus, p.I_minus, p.pe, p.h).b0
+    b, hist = rgp.gauss_newton(p.I_plus, p.I_minus, b0, p.pe, p.h, gn_iters=3, pcg_iters=10,
+                               ls_max_trials=1)
+    assert len(hist) == 1
+    st = hist[0]
+    assert not st.accepted and st.trials == 1 and st.gamma == 0.0
+    assert np.array_equal(b, b0)
+    hc = rgp.col_spacing(p.h, p.pe)
+    Pc, Mc, bcol = (rgp.to_cols(x, p.pe) for x in (p.I_plus, p.I_minus, b0))
+    obj, g, lin = rgp.objective_gradient_cols(Pc, Mc, bcol, hc)
+    q = rgp.pcg(lambda v: rgp.gn_matvec_cols(lin, v), -g, rgp.gn_diag_cols(lin), 10, 0.0).x
+    J_trial = loops.objective(Pc, Mc, bcol + q, hc, rgp.ALPHA, rgp.BETA)[0]
+    assert J_trial > obj.J + 1e-4 * float(np.sum(g * q))
+
+
+def test_ot_shift_with_negative_intensities():
+    """Hand-computed shifts (R7): s = max(0, -min) + eps * max|.| over both images, where the
+    largest magnitude may be a negative value."""
+    Ip = np.array([-2.0, 1.0, 3.0]).reshape(1, 1, 3)
+    Im = np.array([0.5, -1.0, 4.0]).reshape(1, 1, 3)
+    assert rgp.ot_shift(Ip, Im, 0.25) == 2.0 + 0.25 * 4.0
+    Ip = np.array([-5.0, 1.0]).reshape(1, 1, 2)
+    Im = np.array([2.0, 3.0]).reshape(1, 1, 2)
+    assert rgp.ot_shift(Ip, Im, 0.2) == 5.0 + 0.2 * 5.0
+    assert rgp.ot_shift(-Ip, -Im, 0.0) == 3.0
+    assert rgp.ot_shift(np.abs(Ip), np.abs(Im), 0.0) == 0.0
+
+
+def test_ot_of_images_with_negative_values_is_that_of_the_shifted_images():
+    """OT with a negative minimum equals OT of the images already shifted by that same amount
+    with no further shift (their minimum is then positive); with eps = 0 the OT field does not
+    change when a constant is added to both images before the shift is taken."""
+    import synth
+    p = synth.make_workload("c1")
+    rng = np.random.default_rng(5)
+    Ip = p.I_plus - 0.3 + 0.05 * rng.standard_normal(p.shape)
+    Im = p.I_minus - 0.3 + 0.05 * rng.standard_normal(p.shape)
+    assert min(Ip.min(), Im.min()) < 0
+    eps = 1e-3
+    s = rgp.ot_shift(Ip, Im, eps)
+    a = rgp.ot_init(Ip, Im, p.pe, p.h, eps=eps, guard=False)
+    b = rgp.ot_init(Ip + s, Im + s, p.pe, p.h, eps=0.0, guard=False)
+    assert a.shift == s and b.shift == 0.0
+    np.testing.assert_allclose(a.b0, b.b0, rtol=0, atol=1e-12)
+    a0 = rgp.ot_init(Ip, Im, p.pe, p.h, eps=0.0, guard=False)
+    c0 = rgp.ot_init(Ip + 0.2, Im + 0.2, p.pe, p.h, eps=0.0, guard=False)
+    np.testing.assert_allclose(c0.shift + 0.2, a0.shift, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(a0.b0, c0.b0, rtol=0, atol=1e-9)
+
+
+def test_solve_status_nonfinite_image():
+    """A NaN in one image: no Gauss-Newton step runs on any level, the initial field is zero in
+    place of OT (or the caller's b_init), and the status is the non-finite code."""
+    import synth
+    p = synth.make_pair((12, 14, 10), 1, seed=3, n_blobs=8, blob_sigma=(2.0, 4.0),
+                        blob_amp=(0.2, 1.0), bmax=1.5, lobe_tau=(3.0, 5.0), n_lobes=2,
+                        noise="gauss", noise_sigma=0.01)
+    Ip = p.I_plus.copy()
+    Ip[3, 4, 5] = np.nan
+    r = rgp.solve(Ip, p.I_minus, p.pe, levels=2, gn_iters=2, pcg_iters=4)
+    assert r.status == rgp.STATUS_NONFINITE
+    assert np.all(r.b == 0.0) and all(len(lv[2]) == 0 for lv in r.levels)
+    b_init = 0.1 * np.ones((12, 15, 10))
+    Im = p.I_minus.copy()
+    Im[0, 0, 0] = np.inf
+    r = rgp.solve(p.I_plus, Im, p.pe, levels=1, gn_iters=2, pcg_iters=4, b_init=b_init)
+    assert r.status == rgp.STATUS_NONFINITE and np.array_equal(r.b, b_init)
+
+
+def test_solve_status_barrier_and_line_search():
+    """A caller field with a slope of 2 somewhere: J = +inf at the first step, the level stops
+    with b unchanged and the status is the barrier code.  Images x30000 with one Armijo trial:
+    the first step fails on both levels (the finer one still runs, from the prolonged field), the
+    status is the line-search code and the result is the prolonged OT field."""
+    import synth
+    p = synth.make_workload("c1")
+    b = 0.05 * np.ones((32, 33, 24))
+    b[5, 10, 7] += 2.0
+    r = rgp.solve(p.I_plus, p.I_minus, p.pe, levels=1, gn_iters=3, pcg_iters=4, b_init=b)
+    assert r.status == rgp.STATUS_BARRIER
+    assert np.array_equal(r.b, b) and len(r.levels[0][2]) == 1
+    assert math.isinf(r.levels[0][2][0].J) and not r.levels[0][2][0].accepted
+    p = synth.make_workload("c1", scale=30000.0)
+    r = rgp.solve(p.I_plus, p.I_minus, p.pe, levels=2, gn_iters=3, pcg_iters=10,
+                  ls_max_trials=1)
+    assert r.status == rgp.STATUS_LINESEARCH
+    assert [len(lv[2]) for lv in r.levels] == [1, 1]
+    assert not r.levels[0][2][0].accepted and not r.levels[1][2][0].accepted
+    np.testing.assert_array_equal(r.b, rgp.prolong_field(r.b_ot, p.shape, p.pe))
+
+
 # ------------------------------------------------------------------------------------------
 # End to end: a pair distorted with a known field gets that field back
 # ------------------------------------------------------------------------------------------
