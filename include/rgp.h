@@ -40,6 +40,15 @@ typedef enum {
   RGP_EINVAL = -1,      /* null pointer, bad option value or enum */
   RGP_ESHAPE = -2,      /* grid extents out of range */
   RGP_EDTYPE = -3,      /* unsupported dtype combination */
+  /* The next three are found on the device while a correction runs, so they are never returned
+   * by a call: the solve reports the first of them in its stats header (RGP_STAT_HEADER). */
+  RGP_ENONFINITE = -4,  /* an input image holds a NaN or an infinity: no Gauss-Newton step is
+                           taken on any level, and the initial field is zero (OT) or b_init */
+  RGP_EBARRIER = -5,    /* a level started from a field with |d b / d v| >= 1 somewhere, where the
+                           barrier of Eq. (3) is infinite (a caller's b_init, or an OT field with
+                           the guard off): that level stops with b unchanged */
+  RGP_ELINESEARCH = -6, /* no Armijo trial was accepted in some Gauss-Newton step (Sec. 2.3.1):
+                           that level stops with b unchanged; later levels still run */
   RGP_EHIP = -7,        /* a HIP runtime call failed (see rgp_last_hip_error) */
   RGP_EWORKSPACE = -8   /* workspace missing or smaller than rgp_workspace_size() */
 } rgp_status;
@@ -76,8 +85,9 @@ typedef struct {
 
 /* Number of doubles per Gauss-Newton record in the stats buffer of rgp_correct. */
 #define RGP_STAT_FIELDS 12
-/* Stats buffer layout: [0] OT guarded cells, [1] OT shift, [2..3] reserved, then one record of
- * RGP_STAT_FIELDS doubles per GN step, coarsest level first:
+/* Stats buffer layout: [0] OT guarded cells, [1] OT shift, [2] status of the solve (0, or the
+ * first of RGP_ENONFINITE, RGP_EBARRIER, RGP_ELINESEARCH that happened), [3] reserved, then one
+ * record of RGP_STAT_FIELDS doubles per GN step, coarsest level first:
  * J, D, S, P, |grad J|, grad.q, PCG iterations, PCG relative residual, gamma, Armijo trials,
  * accepted (0/1), reserved.  Records of steps that did not run (the solve stopped) are NaN. */
 #define RGP_STAT_HEADER 4
@@ -105,7 +115,8 @@ rgp_status rgp_workspace_size(rgp_op op, const rgp_grid* grid, rgp_dtype real_t,
  * Per PE column: images shifted positive by s = max(0, -min I) + ot_eps * max|I| (one global
  * scalar over both images), nodal CDFs C+ and C- (FP64 scans), linear-spline pseudo-inverses,
  * and b0_k = h_pe/4 [C+^{-1}(C-_k) - C-^{-1}(C+_k)] - the average of the displacement of the
- * halfway map T- and the negated displacement of T+.  Columns with no mass get b0 = 0.  If
+ * halfway map T- and the negated displacement of T+.  Columns with no mass get b0 = 0, and so
+ * does every column when an image holds a NaN or an infinity.  If
  * `guard` is set, a column whose slope |D b0| exceeds 0.99 somewhere gets its slopes clipped to
  * +-0.99 and is re-integrated from b0_0 = 0; the number of clipped cells is written to
  * *n_guarded_dev (nullable, uint64 on the device).  b0: field array (real_t) written in full.
@@ -181,7 +192,9 @@ rgp_status rgp_apply_correction(const rgp_grid* grid, rgp_dtype img_t, const voi
  * Jacobian-modulation correction of the finest images.  A step that no trial accepts stops the
  * level with b unchanged.  b_out: finest field (real_t); T_plus/T_minus (nullable, img_t);
  * stats_dev: nullable device buffer of RGP_STAT_HEADER + levels*gn_iters*RGP_STAT_FIELDS
- * doubles. */
+ * doubles.  Failures found on the device (a non-finite input, a level starting outside the
+ * barrier, a failed line search: RGP_ENONFINITE, RGP_EBARRIER, RGP_ELINESEARCH) do not abort:
+ * the first one is written to stats_dev[2], and b_out is still written. */
 rgp_status rgp_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
                        const void* I_minus, rgp_dtype real_t, const rgp_solver_opts* opts,
                        const void* b_init, void* b_out, void* T_plus, void* T_minus,

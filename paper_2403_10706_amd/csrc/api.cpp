@@ -374,6 +374,9 @@ const char* rgp_status_string(rgp_status s) {
     case RGP_EINVAL: return "invalid argument";
     case RGP_ESHAPE: return "grid extents out of range";
     case RGP_EDTYPE: return "unsupported dtype combination";
+    case RGP_ENONFINITE: return "an input image holds a non-finite value";
+    case RGP_EBARRIER: return "a level started outside the barrier (|d b / d v| >= 1)";
+    case RGP_ELINESEARCH: return "no Armijo trial step was accepted";
     case RGP_EHIP: return "HIP runtime error";
     case RGP_EWORKSPACE: return "workspace missing or too small";
   }
@@ -725,6 +728,11 @@ rgp_status enqueue_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_
   const Level& top = lv[L - 1];
   if (opts->use_b_init) {
     RGP_HIP(copy_d2d(w.B[0], b_init, top.g.nnode * rs, s));
+    // input scan for non-finite values (the OT path does it in its shift kernel)
+    RGP_HIP(launch_shift(ShiftArgs{imgs[L - 1][0], imgs[L - 1][1], top.g.ncell,
+                                   w.ctl.slot(kPartShift), w.ctl.guarded},
+                         ity[L - 1], s));
+    RGP_HIP(launch_scan_status(w.ctl.slot(kPartShift), shift_grid(top.g.ncell), w.ctl.st, s));
   } else {
     RGP_HIP(launch_shift(ShiftArgs{imgs[L - 1][0], imgs[L - 1][1], top.g.ncell,
                                    w.ctl.slot(kPartShift), w.ctl.guarded},

@@ -98,7 +98,8 @@ __device__ __forceinline__ void loss_grad_body(const LossGradArgs& a, VBlock vb)
   const int lane = threadIdx.x & (kWave - 1);
 
   if (a.level_start && vb.id == 0 && threadIdx.x == 0) {
-    st->gn_stop = 0;
+    // a non-finite input image (found by the input scan) stops every level before its first step
+    st->gn_stop = st->status == RGP_ENONFINITE ? 1 : 0;
     st->accepted = 0;
   }
   TR coef = TR(0);

@@ -22,13 +22,15 @@
 namespace rgp {
 
 // ------------------------------------------------------------------------------------------
-// Positivity shift: block-wise min and max|.| over both images; the OT kernel combines them.
+// Positivity shift: block-wise min and max|.| over both images, and whether any value is not
+// finite (NaN or an infinity); the OT kernel combines them.  This is also the input scan of a
+// correction that starts from a given field.
 // ------------------------------------------------------------------------------------------
 template <typename TI>
 __global__ __launch_bounds__(kBlock) void k_shift(ShiftArgs a) {
   const TI* __restrict__ P = static_cast<const TI*>(a.Ip);
   const TI* __restrict__ M = static_cast<const TI*>(a.Im);
-  double lo = inf_d(), hi = 0.0;
+  double lo = inf_d(), hi = 0.0, bad = 0.0;
   // kU elements of each image per thread and round, all loads in flight together (indices
   // clamped into the array; the surplus ones are not counted)
   constexpr int kU = 8;
@@ -47,6 +49,8 @@ __global__ __launch_bounds__(kBlock) void k_shift(ShiftArgs a) {
         const double p = to_real(pv[u], double()), m = to_real(mv[u], double());
         lo = fmin(lo, fmin(p, m));
         hi = fmax(hi, fmax(fabs(p), fabs(m)));
+        // |v| < inf fails for NaN and for the infinities
+        if (!(fabs(p) < inf_d()) || !(fabs(m) < inf_d())) bad = 1.0;
       }
     }
   }
@@ -54,23 +58,42 @@ __global__ __launch_bounds__(kBlock) void k_shift(ShiftArgs a) {
   for (int off = kWave / 2; off > 0; off >>= 1) {
     lo = fmin(lo, __shfl_xor(lo, off, kWave));
     hi = fmax(hi, __shfl_xor(hi, off, kWave));
+    bad = fmax(bad, __shfl_xor(bad, off, kWave));
   }
-  __shared__ double sl[kBlock / kWave], sh[kBlock / kWave];
+  __shared__ double sl[kBlock / kWave], sh[kBlock / kWave], sb[kBlock / kWave];
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   if (lane == 0) {
     sl[wv] = lo;
     sh[wv] = hi;
+    sb[wv] = bad;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 0; w < kBlock / kWave; ++w) {
       lo = fmin(lo, sl[w]);
       hi = fmax(hi, sh[w]);
+      bad = fmax(bad, sb[w]);
     }
     a.part[(size_t)blockIdx.x * kPartStride + 0] = lo;
     a.part[(size_t)blockIdx.x * kPartStride + 1] = hi;
+    a.part[(size_t)blockIdx.x * kPartStride + 2] = bad;
     if (blockIdx.x == 0 && a.guarded) *a.guarded = 0ull;
   }
+}
+
+// Status of a correction that starts from a given field (no OT kernel reads the scan): one block
+// combines the non-finite flags of the input scan's blocks.
+__global__ __launch_bounds__(kBlock) void k_scan_status(const double* part, unsigned nprod,
+                                                        State* st) {
+  double bad = 0.0;
+  for (unsigned b = threadIdx.x; b < nprod; b += kBlock)
+    bad = fmax(bad, part[(size_t)b * kPartStride + 2]);
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  if (bad > 0.0) any = 1;  // benign race: every writer stores 1
+  __syncthreads();
+  if (threadIdx.x == 0 && any && st->status == 0) st->status = RGP_ENONFINITE;
 }
 
 // Spline inverse of one ascending run of queries against a nodal CDF C_0..C_m held with stride NC
@@ -154,7 +177,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LMAX <= 
   static_assert(NC >= 1 && NC <= kWave && kWave % NC == 0, "columns per tile");
   extern __shared__ double lds[];  // one nodal CDF per column, node k of column c at [k * NC + c]
   __shared__ double wtot[2][NW][NC];
-  __shared__ double ext[2][NW];
+  __shared__ double ext[3][NW];
   __shared__ double segx[NSEG][NC];  // last node of each segment, then clipped segment sums
   __shared__ int colflag[NC];
   __shared__ unsigned long long blockclip;
@@ -183,10 +206,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LMAX <= 
       vm[u] = srcm[(int64_t)u * g.cps];
     }
   }
-  double lo = inf_d(), hi = 0.0;
+  double lo = inf_d(), hi = 0.0, bad = 0.0;
   for (unsigned b = tid; b < a.shift_nprod; b += kBlock) {
     lo = fmin(lo, a.shift_part[(size_t)b * kPartStride + 0]);
     hi = fmax(hi, a.shift_part[(size_t)b * kPartStride + 1]);
+    bad = fmax(bad, a.shift_part[(size_t)b * kPartStride + 2]);
   }
   if (tid < NC) colflag[tid] = 0;
   if (tid == 0) blockclip = 0ull;
@@ -217,6 +241,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LMAX <= 
   for (int d = kWave / 2; d > 0; d >>= 1) {
     lo = fmin(lo, __shfl_xor(lo, d, kWave));
     hi = fmax(hi, __shfl_xor(hi, d, kWave));
+    bad = fmax(bad, __shfl_xor(bad, d, kWave));
   }
   if (lane >= kWave - NC) {
     wtot[0][w][c] = incp;
@@ -225,6 +250,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LMAX <= 
   if (lane == 0) {
     ext[0][w] = lo;
     ext[1][w] = hi;
+    ext[2][w] = bad;
   }
   __syncthreads();
   double totp = 0.0, totm = 0.0;
@@ -241,11 +267,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LMAX <= 
     totm += xm;
     lo = fmin(lo, ext[0][q]);
     hi = fmax(hi, ext[1][q]);
+    bad = fmax(bad, ext[2][q]);
   }
   const double s = fmax(0.0, -lo) + a.eps * hi;
-  if (blockIdx.x == 0 && tid == 0) a.st->ot_shift = s;
+  if (blockIdx.x == 0 && tid == 0) {
+    a.st->ot_shift = s;
+    if (bad > 0.0 && a.st->status == 0) a.st->status = RGP_ENONFINITE;
+  }
   const double Sp = totp + (double)mp * s, Sm = totm + (double)mp * s;
-  const bool massok = Sp > 0.0 && Sm > 0.0;
+  // images with a non-finite value give the zero field (as a column without mass does)
+  const bool massok = Sp > 0.0 && Sm > 0.0 && bad == 0.0;
   const double rSp = 1.0 / Sp, rSm = 1.0 / Sm;
 #pragma unroll
   for (int u = 0; u < LMAX; ++u) {  // C_k = S_k / S_m for k = j0+1+u, C_m = 1 exactly
@@ -397,6 +428,15 @@ unsigned shift_grid(int64_t n) {
   if (nb < 1) nb = 1;
   if (nb > 256) nb = 256;  // every OT block combines these block extrema
   return (unsigned)nb;
+}
+
+hipError_t launch_scan_status(const double* part, unsigned nprod, State* st, hipStream_t s) {
+  if (active_recorder())
+    return record_other([part, nprod, st](hipStream_t s2) {
+      return launch_scan_status(part, nprod, st, s2);
+    });
+  hipLaunchKernelGGL(k_scan_status, dim3(1), dim3(kBlock), 0, s, part, nprod, st);
+  return hipGetLastError();
 }
 
 hipError_t launch_shift(const ShiftArgs& a, DType img, hipStream_t s) {

@@ -7,12 +7,16 @@
 //
 // One PCG iteration is one kernel.  Every block first reduces the block sums of iteration i-1
 // in block order (bitwise reproducible) to a_{i-1} = r.z / p.w and the next r^T z and r^T r
-// from the recurrences r'.z' = r.z - 2a r.w/d + a^2 w.w/d and r'.r' = r.r - 2a r.w + a^2 w.w
-// (Chronopoulos-Gear), so one grid-wide reduction per iteration suffices and nothing needs
-// atomics or fences.  It then applies the update (x += a p, r -= a w, p = r/d + b p), recomputing
-// p at the stencil halo from the previous vectors (which therefore live in ping-pong buffers),
-// forms w = H p and stores its block sums of p.w, r.w/d, w.w/d, r.w and w.w.  In exact
-// arithmetic the iterates are those of textbook PCG.
+// from one step of the recurrences r'.z' = r.z - 2a r.w/d + a^2 w.w/d and
+// r'.r' = r.r - 2a r.w + a^2 w.w (Chronopoulos-Gear), so one grid-wide reduction per iteration
+// suffices and nothing needs atomics or fences.  r.z and r.r on the right are the sums of the
+// stored residual of iteration i-1 itself, never earlier recurrence values, so rounding errors
+// of early iterations (when |r| is large) do not accumulate into the stop test and the CG
+// coefficient of late ones.  It then applies the update (x += a p, r -= a w, p = r/d + b p),
+// recomputing p at the stencil halo from the previous vectors (which therefore live in
+// ping-pong buffers), forms w = H p and stores its block sums of p.w, r.w/d, w.w/d, r.w, w.w,
+// and r.z and r.r of the residual it stored.  In exact arithmetic the iterates are those of
+// textbook PCG.
 //
 // The compiler does not fuse multiplies and adds in this file (contraction off below); the
 // arithmetic spells out every fused multiply-add.  Each kernel variant (march shape, prefetch
@@ -111,17 +115,14 @@ __device__ __forceinline__ void pcg_outputs(const PcgScalarArgs& a, const PcgSlo
 }
 
 // Slot of iteration it >= 1 from the running slot of iteration it-1 and the block sums t of
-// iteration it-1: [0] p.w, [1] r.w/d, [2] w.w/d, [3] r.w, [4] w.w, and at it == 1 [5] r.r/d and
-// [6] r.r of the initial residual.  `fin` is set when the solve ends here.
+// iteration it-1: [0] p.w, [1] r.w/d, [2] w.w/d, [3] r.w, [4] w.w, [5] r.r/d and [6] r.r of the
+// residual that iteration stored (at it == 1 the right-hand side, whose r.r is |rhs|^2).  `fin`
+// is set when the solve ends here.
 __device__ __forceinline__ PcgSlot pcg_advance(const PcgSlot& prev, const double (&t)[7], int it,
                                                int maxit, double rtol, bool& fin) {
   PcgSlot cur = prev;
-  double rz = prev.rz, rr = prev.rr, bn = prev.bnorm2;
-  if (it == 1) {
-    rz = t[5];
-    rr = t[6];
-    bn = t[6];
-  }
+  const double rz = t[5], rr = t[6];
+  const double bn = it == 1 ? t[6] : prev.bnorm2;
   const double pw = t[0];
   cur.bnorm2 = bn;
   if (!(bn > 0.0) || !(pw > 0.0)) {  // zero right-hand side or p^T H p <= 0: keep x
@@ -197,7 +198,7 @@ __device__ __forceinline__ void pcg_scalars_body(const PcgScalarArgs& a) {
   if (a.iter > 0) {
     const PcgSlot prev = a.slots[(a.iter - 1) & 1];
     double t[7];
-    load_partials_cm<7>(t, a.part_prev, a.nprod, a.iter == 1 ? 7 : 5);
+    load_partials_cm<7>(t, a.part_prev, a.nprod, 7);
     pcg_scalar_phase<kReduceBlock>(a, prev, t, VBlock{0u, 1u});
     return;
   }
@@ -375,7 +376,7 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
   const bool fused = a.sc.fused;
   const PcgSlot prev = a.sc.slots[(fused && !first) ? (it - 1) & 1 : it & 1];
   double tsum[7], lsum[5];
-  if (fused && !first) load_partials_cm<7>(tsum, a.sc.part_prev, a.sc.nprod, it == 1 ? 7 : 5);
+  if (fused && !first) load_partials_cm<7>(tsum, a.sc.part_prev, a.sc.nprod, 7);
   if (fused && first && a.sc.gn_mode) load_partials_rm<5>(lsum, a.sc.lf.part, a.sc.lf.nprod);
   int64_t u = ulo + lb;
   if (u < uhi) begin_unit(u);
@@ -484,17 +485,16 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
       }
       bst<TR>(rWo, off_at(own[i], node(o, i)), w);
       if (own[i]) {
-        // FP64 products and sums (r.w/d as z.w, w.w/d and r.r/d with the stored 1/d)
+        // FP64 products and sums (r.w/d as z.w, w.w/d and r.r/d with the stored 1/d); r and z
+        // are this iteration's stored residual and its Jacobi step
         const double r = (double)Rc[i], ww = (double)w, z = (double)Zc[i], id = (double)Ic[i];
         acc[0] = fmad((double)pk, ww, acc[0]);
         acc[1] = fmad(z, ww, acc[1]);
         acc[2] = fmad(ww * ww, id, acc[2]);
         acc[3] = fmad(r, ww, acc[3]);
         acc[4] = fmad(ww, ww, acc[4]);
-        if (first) {
-          acc[5] = fmad(r, z, acc[5]);
-          acc[6] = fmad(r, r, acc[6]);
-        }
+        acc[5] = fmad(r, z, acc[5]);
+        acc[6] = fmad(r, r, acc[6]);
       }
     }
 #pragma unroll

@@ -120,7 +120,7 @@ __global__ void k_stats_header(double* stats, const State* st, const unsigned lo
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     stats[0] = (double)*guarded;
     stats[1] = st->ot_shift;
-    stats[2] = 0.0;
+    stats[2] = (double)st->status;
     stats[3] = 0.0;
   }
 }

@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rgp.h"
+
 namespace rgp {
 
 constexpr int kWave = 64;         // CDNA wavefront width
@@ -84,7 +86,11 @@ struct State {
   // line search
   double gq, sbq, sqq;      // grad.q, sum dB.dQ / h^2, sum dQ.dQ / h^2 (S is quadratic in gamma)
   double gamma;
-  int32_t accepted, trials, gn_stop, pad0;
+  // status: the first failure of the solve (an rgp_status code, 0 while none): RGP_ENONFINITE
+  // (an input image holds a NaN or an infinity; every level then stops before its first step),
+  // RGP_EBARRIER (a level started from a field outside the barrier), RGP_ELINESEARCH (no Armijo
+  // trial was accepted in some step); the last two stop only the level they happen on
+  int32_t accepted, trials, gn_stop, status;
   // PCG summary of the current GN step
   double relres;
   int32_t pcg_iters, pad1;

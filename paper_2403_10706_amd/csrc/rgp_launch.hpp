@@ -189,7 +189,7 @@ struct ShiftArgs {
   const void* Ip;
   const void* Im;
   int64_t n;
-  double* part;                  // block min / max|.|
+  double* part;                  // block min, max|.| and non-finite flag (0 or 1)
   unsigned long long* guarded;   // zeroed by block 0 (the OT kernel counts into it)
 };
 
@@ -283,6 +283,9 @@ hipError_t launch_pcg_step(const PcgArgs& a, DType real, hipStream_t s);
 hipError_t launch_pcg_step_plan(const PcgArgs& a, DType real, const PcgPlan& L, hipStream_t s);
 hipError_t launch_pcg_scalars(const PcgScalarArgs& a, hipStream_t s);
 hipError_t launch_shift(const ShiftArgs& a, DType img, hipStream_t s);
+// Sets st->status to RGP_ENONFINITE when the input scan (the shift kernel's block sums) found a
+// non-finite image value.
+hipError_t launch_scan_status(const double* part, unsigned nprod, State* st, hipStream_t s);
 hipError_t launch_ot(const OtArgs& a, DType img, DType real, hipStream_t s);
 // Optional blur of the OT field: dst = 3x3x3 Gaussian (sigma 1 voxel) of src, periodic over the
 // node grid n[0] x n[1] x n[2].

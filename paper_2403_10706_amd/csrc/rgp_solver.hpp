@@ -52,6 +52,7 @@ __device__ __forceinline__ bool finalize_loss_sums(const LossFinalArgs& a, const
     st->relres = 0.0;
     if (a.gn_mode && viol) {
       __hip_atomic_store(&st->gn_stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (st->status == 0) st->status = RGP_EBARRIER;
       if (a.record) write_record(a.record, *st);
     }
     if (a.jdsp) {
@@ -132,6 +133,7 @@ __device__ __forceinline__ int decide_pass(const DecideArgs& a, const State& s,
       n.gamma = 0.0;
       n.gn_stop = 1;
       n.trials = a.total;
+      if (n.status == 0) n.status = RGP_ELINESEARCH;
     }
     *st = n;
     if (res != 0 && a.record) write_record(a.record, n);

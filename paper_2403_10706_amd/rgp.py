@@ -19,8 +19,11 @@ LIB_PATH = os.path.join(_HERE, "librgp.so")
 
 RGP_OK = 0
 STATUS = {0: "ok", -1: "invalid argument", -2: "grid extents out of range",
-          -3: "unsupported dtype combination", -7: "HIP runtime error",
-          -8: "workspace missing or too small"}
+          -3: "unsupported dtype combination", -4: "an input image holds a non-finite value",
+          -5: "a level started outside the barrier", -6: "no Armijo trial step was accepted",
+          -7: "HIP runtime error", -8: "workspace missing or too small"}
+# Device-side failures of a correction, reported in stats[2] (never returned by a call).
+ENONFINITE, EBARRIER, ELINESEARCH = -4, -5, -6
 F64, F32, BF16 = 0, 1, 2
 OP_OT_INIT, OP_LOSS_GRAD, OP_GN_HVP, OP_PCG_SOLVE, OP_CORRECT, OP_APPLY_CORRECTION = range(6)
 STAT_FIELDS = 12
@@ -180,28 +183,35 @@ def workspace_size(op: int, shape, pe, h, real_dtype, opts: Optional[SolverOpts]
 
 
 class Workspace:
-    """Device workspace cache (one buffer per device, grown on demand)."""
+    """Device workspace cache: one buffer per (device, stream), grown on demand.  Calls that
+    share a workspace must not overlap, so calls on different streams get different buffers; a
+    buffer is allocated on, and only ever used from, its own stream."""
 
     def __init__(self):
         self._buf = {}
 
-    def get(self, nbytes: int, device) -> torch.Tensor:
+    def get(self, nbytes: int, device, stream=None) -> torch.Tensor:
         dev = torch.device(device)
-        buf = self._buf.get(dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        key = (dev, int(stream.cuda_stream))
+        buf = self._buf.get(key)
         if buf is None or buf.numel() < nbytes:
-            # zero-filled once: the library keeps its counters at zero afterwards
-            buf = torch.zeros(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
-            self._buf[dev] = buf
+            # zero-filled once, as the library asks of a new workspace; allocated while `stream`
+            # is current, so torch's allocator orders its reuse after that stream's work
+            with torch.cuda.stream(stream):
+                buf = torch.zeros(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
+            self._buf[key] = buf
         return buf
 
 
 _WS = Workspace()
 
 
-def _ws(op, shape, pe, h, real_dtype, device, opts=None, ws=None):
+def _ws(op, shape, pe, h, real_dtype, device, opts=None, ws=None, stream=None):
     need = workspace_size(op, shape, pe, h, real_dtype, opts)
     if ws is None:
-        ws = _WS.get(need, device)
+        ws = _WS.get(need, device, stream)
     if ws.numel() < need:
         raise ValueError(f"workspace too small ({ws.numel()} < {need} bytes)")
     return ws, need
@@ -216,7 +226,7 @@ def ot_init(I_plus: torch.Tensor, I_minus: torch.Tensor, pe: int, h=(1.0, 1.0, 1
     if out is None:
         out = torch.empty(field_shape(shape, pe), dtype=real_dtype, device=I_plus.device)
     ng = torch.zeros(1, dtype=torch.int64, device=I_plus.device)
-    wsb, need = _ws(OP_OT_INIT, shape, pe, h, real_dtype, I_plus.device, ws=ws)
+    wsb, need = _ws(OP_OT_INIT, shape, pe, h, real_dtype, I_plus.device, ws=ws, stream=stream)
     g = make_grid(shape, pe, h)
     _check("rgp_ot_init", load().rgp_ot_init(
         ctypes.byref(g), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
@@ -251,7 +261,7 @@ def loss_grad(I_plus, I_minus, b, pe, h=(1.0, 1.0, 1.0), alpha=300.0, beta=1e-4,
     grad = torch.empty_like(b) if want_grad else None
     hd = torch.empty_like(b) if want_hess else None
     ho = torch.empty_like(b) if want_hess else None
-    wsb, _ = _ws(OP_LOSS_GRAD, shape, pe, h, b.dtype, dev, ws=ws)
+    wsb, _ = _ws(OP_LOSS_GRAD, shape, pe, h, b.dtype, dev, ws=ws, stream=stream)
     g = make_grid(shape, pe, h)
     _check("rgp_loss_grad", load().rgp_loss_grad(
         ctypes.byref(g), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
@@ -265,7 +275,7 @@ def gn_hvp(hdiag, hoff, v, shape, pe, h=(1.0, 1.0, 1.0), alpha=300.0, *, ws=None
     _dev_check(hdiag, hoff, v)
     Hv = torch.empty_like(v)
     vhv = torch.empty(1, dtype=torch.float64, device=v.device)
-    wsb, _ = _ws(OP_GN_HVP, shape, pe, h, v.dtype, v.device, ws=ws)
+    wsb, _ = _ws(OP_GN_HVP, shape, pe, h, v.dtype, v.device, ws=ws, stream=stream)
     g = make_grid(shape, pe, h)
     _check("rgp_gn_hvp", load().rgp_gn_hvp(
         ctypes.byref(g), dtype_code(v.dtype), _ptr(hdiag), _ptr(hoff), float(alpha), _ptr(v),
@@ -292,7 +302,7 @@ def pcg_solve(hdiag, hoff, rhs, shape, pe, h=(1.0, 1.0, 1.0), alpha=300.0, *, ma
     x = torch.empty_like(rhs)
     it = torch.zeros(1, dtype=torch.int32, device=rhs.device)
     rr = torch.zeros(1, dtype=torch.float64, device=rhs.device)
-    wsb, _ = _ws(OP_PCG_SOLVE, shape, pe, h, rhs.dtype, rhs.device, ws=ws)
+    wsb, _ = _ws(OP_PCG_SOLVE, shape, pe, h, rhs.dtype, rhs.device, ws=ws, stream=stream)
     g = make_grid(shape, pe, h)
     _check("rgp_pcg_solve", load().rgp_pcg_solve(
         ctypes.byref(g), dtype_code(rhs.dtype), _ptr(hdiag), _ptr(hoff), float(alpha), _ptr(rhs),
@@ -363,7 +373,7 @@ def correct(I_plus, I_minus, pe, h=(1.0, 1.0, 1.0), opts: Optional[Options] = No
     Tm = torch.empty_like(I_minus) if want_images else None
     stats = (torch.empty(STAT_HEADER + opts.levels * opts.gn_iters * STAT_FIELDS,
                          dtype=torch.float64, device=dev) if want_stats else None)
-    wsb, _ = _ws(OP_CORRECT, shape, pe, h, real_dtype, dev, opts=copts, ws=ws)
+    wsb, _ = _ws(OP_CORRECT, shape, pe, h, real_dtype, dev, opts=copts, ws=ws, stream=stream)
     g = make_grid(shape, pe, h)
     _check("rgp_correct", load().rgp_correct(
         ctypes.byref(g), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
@@ -375,7 +385,8 @@ def correct(I_plus, I_minus, pe, h=(1.0, 1.0, 1.0), opts: Optional[Options] = No
 def parse_stats(stats: torch.Tensor, levels: int, gn_iters: int):
     """Host view of a stats buffer: (header dict, list of per-level lists of record dicts)."""
     s = stats.detach().double().cpu().numpy()
-    head = dict(ot_guarded=int(s[0]) if math.isfinite(s[0]) else -1, ot_shift=float(s[1]))
+    head = dict(ot_guarded=int(s[0]) if math.isfinite(s[0]) else -1, ot_shift=float(s[1]),
+                status=int(s[2]) if math.isfinite(s[2]) else 0)
     recs = s[STAT_HEADER:].reshape(levels, gn_iters, STAT_FIELDS)
     out = []
     for lv in range(levels):
@@ -547,7 +558,7 @@ def autotune(shape, pe, real_dtype, opts: "Options", *, h=(1.0, 1.0, 1.0), ws=No
     g = make_grid(tuple(shape), pe, h)
     c = opts.to_c()
     dev = torch.device("cuda", torch.cuda.current_device())
-    wsb, _ = _ws(OP_CORRECT, tuple(shape), pe, h, real_dtype, dev, opts=c, ws=ws)
+    wsb, _ = _ws(OP_CORRECT, tuple(shape), pe, h, real_dtype, dev, opts=c, ws=ws, stream=stream)
     out = (ctypes.c_int32 * opts.levels)()
     _check("rgp_autotune", load().rgp_autotune(ctypes.byref(g), dtype_code(real_dtype),
                                                ctypes.byref(c), _ptr(wsb), wsb.numel(),

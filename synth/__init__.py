@@ -12,6 +12,7 @@ from .phantom import (  # noqa: F401
     make_pair,
     make_workload,
     make_batch,
+    make_batch_pair,
     blob_phantom,
     smooth_field,
     push_forward,

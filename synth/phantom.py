@@ -34,6 +34,7 @@ __all__ = [
     "make_pair",
     "make_workload",
     "make_batch",
+    "make_batch_pair",
     "blob_phantom",
     "smooth_field",
     "push_forward",
@@ -245,20 +246,26 @@ def batch_specs(n=32, first_seed=100):
     return specs
 
 
+def _batch_pair(sp, scale, size_cap):
+    shape = sp["shape"]
+    if size_cap is not None:
+        shape = tuple(min(int(s), int(size_cap)) for s in shape)
+    return make_pair(shape, sp["pe"], seed=sp["seed"], n_blobs=200,
+                     blob_sigma=(2.0, 8.0), blob_amp=(0.2, 1.0), bmax=sp["bmax"]
+                     if size_cap is None else min(sp["bmax"], size_cap / 8.0),
+                     n_lobes=5, lobe_tau=(12.0, 24.0) if size_cap is None else
+                     (size_cap / 6.0, size_cap / 3.0), noise="rician",
+                     noise_sigma=0.02, scale=scale)
+
+
 def make_batch(n=32, first_seed=100, scale=1.0, size_cap=None):
     """The uneven batch: n pairs of different sizes and phase-encoding axes.
 
     ``size_cap`` (optional) shrinks every extent to at most that many cells, for quick tests.
     """
-    out = []
-    for sp in batch_specs(n, first_seed):
-        shape = sp["shape"]
-        if size_cap is not None:
-            shape = tuple(min(int(s), int(size_cap)) for s in shape)
-        out.append(make_pair(shape, sp["pe"], seed=sp["seed"], n_blobs=200,
-                             blob_sigma=(2.0, 8.0), blob_amp=(0.2, 1.0), bmax=sp["bmax"]
-                             if size_cap is None else min(sp["bmax"], size_cap / 8.0),
-                             n_lobes=5, lobe_tau=(12.0, 24.0) if size_cap is None else
-                             (size_cap / 6.0, size_cap / 3.0), noise="rician",
-                             noise_sigma=0.02, scale=scale))
-    return out
+    return [_batch_pair(sp, scale, size_cap) for sp in batch_specs(n, first_seed)]
+
+
+def make_batch_pair(index, n=32, first_seed=100, scale=1.0):
+    """Pair ``index`` of ``make_batch(n, first_seed, scale)`` alone (the same arrays)."""
+    return _batch_pair(batch_specs(n, first_seed)[index], scale, None)

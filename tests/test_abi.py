@@ -38,6 +38,13 @@ def test_status_strings_and_defaults(lib):
     from paper_2403_10706_amd import rgp
     assert lib.rgp_status_string(0) == b"ok"
     assert lib.rgp_status_string(-8).startswith(b"workspace")
+    # the device-side failures of a correction have their own codes and texts
+    texts = {c: lib.rgp_status_string(c) for c in range(-8, 1)}
+    assert len(set(texts.values())) == 9 and b"unknown" not in b"".join(texts.values())
+    assert (rgp.ENONFINITE, rgp.EBARRIER, rgp.ELINESEARCH) == (-4, -5, -6)
+    src = open(HEADER).read()
+    for name, code in (("RGP_ENONFINITE", -4), ("RGP_EBARRIER", -5), ("RGP_ELINESEARCH", -6)):
+        assert re.search(rf"{name}\s*=\s*{code}\b", src), name
     o = rgp.SolverOpts()
     lib.rgp_default_opts(ctypes.byref(o))
     assert o.alpha == 300.0 and o.beta == 1e-4 and o.pcg_iters == 10 and o.pcg_rtol == 0.1
