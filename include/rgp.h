@@ -127,15 +127,6 @@ rgp_status rgp_ot_init(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus
                        int32_t guard, uint64_t* n_guarded_dev, void* ws, size_t ws_bytes,
                        void* stream);
 
-/* Objective J = D + alpha S + beta P of Eq. (6) at b, with D the SSD of the mass-preserving
- * transforms of Eq. (1)-(2), S the smoothness term of Eq. (5) (seven-point negative Laplacian on
- * the staggered field, Neumann boundaries) and P the barrier of Eq. (3); all with weight vol/2.
- * jdsp_dev (device, 4 doubles, nullable): J, D, S, P (J = P = +inf when the barrier is violated).
- * Optional outputs (field arrays, nullable): grad = grad J; hdiag/hoff = the Gauss-Newton
- * Hessian of Sec. 2.3.1 in banded form - hdiag its diagonal (the Jacobi preconditioner) and
- * hoff[k] the coupling of PE nodes k and k+1 (0 at the last node); the cross-axis couplings are
- * -alpha vol / h_d^2.  hdiag and hoff are both given or both NULL.  Their contents are
- * unspecified when J = +inf. */
 /* Optional smoothing of an OT initial field (Sec. 2.2, last step; Sec. 2.4, the OT
  * initialisation's blurring operator): b_out = G * b_in with the 3x3x3 Gaussian of standard
  * deviation 1 voxel, weights exp(-|d|^2/2) over the offsets d in {-1,0,1}^3 normalised to sum 1,
@@ -145,6 +136,15 @@ rgp_status rgp_ot_init(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus
 rgp_status rgp_blur_field(const rgp_grid* grid, rgp_dtype real_t, const void* b_in, void* b_out,
                           void* stream);
 
+/* Objective J = D + alpha S + beta P of Eq. (6) at b, with D the SSD of the mass-preserving
+ * transforms of Eq. (1)-(2), S the smoothness term of Eq. (5) (seven-point negative Laplacian on
+ * the staggered field, Neumann boundaries) and P the barrier of Eq. (3); all with weight vol/2.
+ * jdsp_dev (device, 4 doubles, nullable): J, D, S, P (J = P = +inf when the barrier is violated).
+ * Optional outputs (field arrays, nullable): grad = grad J; hdiag/hoff = the Gauss-Newton
+ * Hessian of Sec. 2.3.1 in banded form - hdiag its diagonal (the Jacobi preconditioner) and
+ * hoff[k] the coupling of PE nodes k and k+1 (0 at the last node); the cross-axis couplings are
+ * -alpha vol / h_d^2.  hdiag and hoff are both given or both NULL.  Their contents are
+ * unspecified when J = +inf. */
 rgp_status rgp_loss_grad(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
                          const void* I_minus, rgp_dtype real_t, const void* b, double alpha,
                          double beta, double* jdsp_dev, void* grad, void* hdiag, void* hoff,
