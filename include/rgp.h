@@ -150,6 +150,23 @@ rgp_status rgp_loss_grad(const rgp_grid* grid, rgp_dtype img_t, const void* I_pl
                          double beta, double* jdsp_dev, void* grad, void* hdiag, void* hoff,
                          void* ws, size_t ws_bytes, void* stream);
 
+/* rgp_loss_grad without a workspace, for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * outputs and arithmetic as rgp_loss_grad (bitwise the same results), minus ws/ws_bytes: the
+ * state block and the per-block FP64 sums live in a fixed library-owned device array of
+ * 512.25 KiB per GPU (one copy on each device the library runs on, held until the process
+ * ends), looked up on the first call on each device.  The call allocates nothing and needs the
+ * stream's device to be the current device.  Every call on a GPU uses that GPU's one array, so
+ * calls that overlap on one GPU (two streams, two threads, or a concurrent capture replay) race
+ * and must be serialised by the caller; each call writes all of the array it reads, so nothing
+ * needs clearing between calls.  Errors as rgp_loss_grad; RGP_EWORKSPACE if a launch would need
+ * more block sums than the array holds (not reachable with the current launch plans), RGP_EHIP
+ * if the array's device address cannot be obtained. */
+rgp_status rgp_loss_grad_noalloc(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                                 const void* I_minus, rgp_dtype real_t, const void* b,
+                                 double alpha, double beta, double* jdsp_dev, void* grad,
+                                 void* hdiag, void* hoff, void* stream);
+
 /* Gauss-Newton Hessian-vector product Hv = H_J v (Sec. 2.3.1, Eq. 7) with H_J given by the
  * hdiag/hoff produced by rgp_loss_grad at the same grid and alpha.  vHv_dev (nullable, device
  * double) receives v^T H v. */

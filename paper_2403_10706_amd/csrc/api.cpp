@@ -496,23 +496,34 @@ rgp_status rgp_blur_field(const rgp_grid* grid, rgp_dtype real_t, const void* b_
   return RGP_OK;
 }
 
-rgp_status rgp_loss_grad(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
-                         const void* I_minus, rgp_dtype real_t, const void* b, double alpha,
-                         double beta, double* jdsp_dev, void* grad, void* hdiag, void* hoff,
-                         void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Argument checks of rgp_loss_grad and rgp_loss_grad_noalloc (everything but the workspace).
+rgp_status check_loss_grad(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                           const void* I_minus, rgp_dtype real_t, const void* b, double alpha,
+                           double beta, const void* hdiag, const void* hoff, DType* di,
+                           DType* dr) {
   rgp_status st = check_grid(grid);
   if (st != RGP_OK) return st;
-  DType di, dr;
-  if ((st = check_types(img_t, real_t, &di, &dr)) != RGP_OK) return st;
+  if ((st = check_types(img_t, real_t, di, dr)) != RGP_OK) return st;
   if (!I_plus || !I_minus || !b) return RGP_EINVAL;
   if ((hdiag == nullptr) != (hoff == nullptr)) return RGP_EINVAL;
   if (!(alpha >= 0.0) || !(beta >= 0.0) || !std::isfinite(alpha) || !std::isfinite(beta))
     return RGP_EINVAL;
-  if ((st = need_ws(RGP_OP_LOSS_GRAD, grid, real_t, nullptr, ws, ws_bytes)) != RGP_OK) return st;
-  const hipStream_t s = static_cast<hipStream_t>(stream);
+  return RGP_OK;
+}
+
+// The launches of one objective/gradient evaluation: loss_grad writes its FP64 block sums to
+// `part` (kMaxGrid * kPartStride doubles), and the final reduction turns them into J, D, S, P,
+// using `st` as its state block.  Every block sum the reduction reads is written by the same
+// launch, so neither buffer has to hold anything on entry.
+rgp_status enqueue_loss_grad(const rgp_grid* grid, DType di, DType dr, const void* I_plus,
+                             const void* I_minus, const void* b, double alpha, double beta,
+                             double* jdsp_dev, void* grad, void* hdiag, void* hoff, State* st,
+                             double* part, hipStream_t s) {
   const Geom g = geom_of(grid);
-  Carver c(ws);
-  Control k = carve_control(c);
   LossGradArgs la{};
   la.g = g;
   la.Ip = I_plus;
@@ -523,16 +534,85 @@ rgp_status rgp_loss_grad(const rgp_grid* grid, rgp_dtype img_t, const void* I_pl
   la.off = hoff;
   la.alpha = alpha;
   la.beta = beta;
-  la.st = k.st;
-  la.part = k.slot(kPartLoss);
+  la.st = st;
+  la.part = part;
   RGP_HIP(launch_loss_grad(la, di, dr, s));
   if (jdsp_dev) {
     const Launch L = plan_loss_grad(g, dr);
     RGP_HIP(launch_loss_final(
-        LossFinalArgs{k.slot(kPartLoss), L.grid, g.vol, alpha, beta, k.st, jdsp_dev, nullptr, 0},
-        s));
+        LossFinalArgs{part, L.grid, g.vol, alpha, beta, st, jdsp_dev, nullptr, 0}, s));
   }
   return RGP_OK;
+}
+
+// ---- allocation-free objective/gradient ----------------------------------------------------
+// rgp_loss_grad_noalloc keeps its state block and loss_grad's block sums in this file-scope
+// device array instead of a caller workspace.  Each GPU holds its own copy (at its own address)
+// for the life of the process.  In host code `scratch` only names the symbol: its device address
+// comes from hipGetSymbolAddress, taken once per device and kept in g_scratch_addr.
+constexpr size_t kScratchStateBytes = 256;
+constexpr size_t kScratchBytes =
+    kScratchStateBytes + (size_t)kMaxGrid * kPartStride * sizeof(double);  // 512.25 KiB
+static_assert(sizeof(State) <= kScratchStateBytes, "State must fit the scratch header");
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device (looked up on first use).
+rgp_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  RGP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return RGP_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    RGP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return RGP_EHIP;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return RGP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rgp_status rgp_loss_grad(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                         const void* I_minus, rgp_dtype real_t, const void* b, double alpha,
+                         double beta, double* jdsp_dev, void* grad, void* hdiag, void* hoff,
+                         void* ws, size_t ws_bytes, void* stream) {
+  DType di, dr;
+  rgp_status st = check_loss_grad(grid, img_t, I_plus, I_minus, real_t, b, alpha, beta, hdiag,
+                                  hoff, &di, &dr);
+  if (st != RGP_OK) return st;
+  if ((st = need_ws(RGP_OP_LOSS_GRAD, grid, real_t, nullptr, ws, ws_bytes)) != RGP_OK) return st;
+  Carver c(ws);
+  Control k = carve_control(c);
+  return enqueue_loss_grad(grid, di, dr, I_plus, I_minus, b, alpha, beta, jdsp_dev, grad, hdiag,
+                           hoff, k.st, k.slot(kPartLoss), static_cast<hipStream_t>(stream));
+}
+
+rgp_status rgp_loss_grad_noalloc(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                                 const void* I_minus, rgp_dtype real_t, const void* b,
+                                 double alpha, double beta, double* jdsp_dev, void* grad,
+                                 void* hdiag, void* hoff, void* stream) {
+  DType di, dr;
+  rgp_status st = check_loss_grad(grid, img_t, I_plus, I_minus, real_t, b, alpha, beta, hdiag,
+                                  hoff, &di, &dr);
+  if (st != RGP_OK) return st;
+  // the launch's block sums must fit the scratch (loss_grad grids are capped at kMaxGrid blocks)
+  const Launch L = plan_loss_grad(geom_of(grid), dr);
+  if (L.grid < 1 || L.grid > (unsigned)kMaxGrid) return RGP_EWORKSPACE;
+  void* base = nullptr;
+  if ((st = scratch_of_current_device(&base)) != RGP_OK) return st;
+  unsigned char* p = static_cast<unsigned char*>(base);
+  return enqueue_loss_grad(grid, di, dr, I_plus, I_minus, b, alpha, beta, jdsp_dev, grad, hdiag,
+                           hoff, reinterpret_cast<State*>(p),
+                           reinterpret_cast<double*>(p + kScratchStateBytes),
+                           static_cast<hipStream_t>(stream));
 }
 
 rgp_status rgp_gn_hvp(const rgp_grid* grid, rgp_dtype real_t, const void* hdiag,

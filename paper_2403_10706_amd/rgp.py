@@ -60,7 +60,8 @@ EXPORTS = ("rgp_status_string", "rgp_last_hip_error", "rgp_default_opts", "rgp_w
            "rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
            "rgp_apply_correction", "rgp_correct", "rgp_correct_plan", "rgp_plan_launch",
            "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop", "rgp_loss_grad_images",
-           "rgp_batch_workspace_size", "rgp_correct_batch_plan", "rgp_autotune", "rgp_blur_field")
+           "rgp_batch_workspace_size", "rgp_correct_batch_plan", "rgp_autotune", "rgp_blur_field",
+           "rgp_loss_grad_noalloc")
 
 # rgp_kernel_kind
 KERNEL_PCG_STEP, KERNEL_LOSS_GRAD, KERNEL_TRIAL, KERNEL_HVP, KERNEL_OT, KERNEL_SHIFT, \
@@ -97,6 +98,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rgp_ot_init.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int, vp, f64, i32, vp, vp, sz, vp]
     lib.rgp_loss_grad.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int, vp, f64, f64, vp, vp, vp,
                                   vp, vp, sz, vp]
+    lib.rgp_loss_grad_noalloc.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int, vp, f64, f64,
+                                          vp, vp, vp, vp, vp]
     lib.rgp_gn_hvp.argtypes = [gp, ctypes.c_int, vp, vp, f64, vp, vp, vp, vp, sz, vp]
     lib.rgp_pcg_solve.argtypes = [gp, ctypes.c_int, vp, vp, f64, vp, vp, i32, f64, vp, vp, vp, sz,
                                   vp]
@@ -117,6 +120,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rgp_blur_field.argtypes = [gp, ctypes.c_int, vp, vp, vp]
     for name in ("rgp_blur_field", "rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
                  "rgp_apply_correction", "rgp_correct", "rgp_workspace_size", "rgp_correct_plan",
+                 "rgp_loss_grad_noalloc",
                  "rgp_plan_launch", "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop",
                  "rgp_loss_grad_images", "rgp_batch_workspace_size", "rgp_correct_batch_plan",
                  "rgp_autotune"):
@@ -268,6 +272,23 @@ def loss_grad(I_plus, I_minus, b, pe, h=(1.0, 1.0, 1.0), alpha=300.0, beta=1e-4,
         dtype_code(b.dtype), _ptr(b), float(alpha), float(beta), _ptr(jdsp), _ptr(grad), _ptr(hd),
         _ptr(ho), _ptr(wsb), wsb.numel(), _stream_ptr(stream)))
     return jdsp, grad, hd, ho
+
+
+def loss_grad_noalloc(I_plus, I_minus, b, pe, h=(1.0, 1.0, 1.0), alpha=300.0, beta=1e-4, *,
+                      jdsp=None, grad=None, hdiag=None, hoff=None, stream=None):
+    """rgp_loss_grad_noalloc into caller-given outputs (any of them None): no workspace, and
+    nothing is allocated here when every wanted output is given.  Returns (jdsp, grad, hdiag,
+    hoff) as passed."""
+    _dev_check(I_plus, I_minus, b)
+    shape = tuple(I_plus.shape)
+    if tuple(b.shape) != field_shape(shape, pe):
+        raise ValueError(f"field shape {tuple(b.shape)} != {field_shape(shape, pe)}")
+    g = make_grid(shape, pe, h)
+    _check("rgp_loss_grad_noalloc", load().rgp_loss_grad_noalloc(
+        ctypes.byref(g), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
+        dtype_code(b.dtype), _ptr(b), float(alpha), float(beta), _ptr(jdsp), _ptr(grad),
+        _ptr(hdiag), _ptr(hoff), _stream_ptr(stream)))
+    return jdsp, grad, hdiag, hoff
 
 
 def gn_hvp(hdiag, hoff, v, shape, pe, h=(1.0, 1.0, 1.0), alpha=300.0, *, ws=None, stream=None):

@@ -108,6 +108,13 @@ def test_entry_points_reject_bad_arguments_without_device(lib):
     # hdiag without hoff
     assert lib.rgp_loss_grad(ctypes.byref(g), rgp.F32, fake, fake, rgp.F32, fake, 300.0, 1e-4,
                              fake, None, fake, None, fake, 1 << 30, None) == -1
+    # the allocation-free variant checks the same arguments before it touches the device
+    assert lib.rgp_loss_grad_noalloc(ctypes.byref(g), rgp.F32, fake, fake, rgp.F32, None, 300.0,
+                                     1e-4, fake, None, None, None, None) == -1
+    assert lib.rgp_loss_grad_noalloc(ctypes.byref(g), rgp.F32, fake, fake, rgp.F32, fake, 300.0,
+                                     1e-4, fake, None, fake, None, None) == -1
+    assert lib.rgp_loss_grad_noalloc(ctypes.byref(g), rgp.F64, fake, fake, rgp.F32, fake, 300.0,
+                                     1e-4, fake, None, None, None, None) == -3
     # FP64 images with FP32 arithmetic is not offered
     assert lib.rgp_loss_grad(ctypes.byref(g), rgp.F64, fake, fake, rgp.F32, fake, 300.0, 1e-4,
                              fake, None, None, None, fake, 1 << 30, None) == -3
