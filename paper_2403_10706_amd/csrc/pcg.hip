@@ -84,13 +84,15 @@ __global__ __launch_bounds__(BLK) void k_hvp(HvpArgs a) {
       const bool out = k <= mp && c.colok;
       const TR vk = vv[s + 1];
       const TR vym = from_lower_lane(vk, ym[s]), vyp = from_upper_lane(vk, yp[s]);
-      TR h = dd[s] * vk;
-      if (k > 0) h = fmad(oo[s], vv[s], h);
-      if (k < mp) h = fmad(oo[s + 1], vv[s + 2], h);
-      const TR crx = xm[s] + xp[s];  // missing x neighbours read 0
-      const TR cry = (c.hasym ? vym : TR(0)) + (c.hasyp ? vyp : TR(0));
-      h = fmad(-cx, crx, h);
-      h = fmad(-cy, cry, h);
+      // accumulated in FP64 and rounded once, as in the PCG step
+      double hd = (double)dd[s] * (double)vk;
+      if (k > 0) hd = fmad((double)oo[s], (double)vv[s], hd);
+      if (k < mp) hd = fmad((double)oo[s + 1], (double)vv[s + 2], hd);
+      const double crx = (double)xm[s] + (double)xp[s];  // missing x neighbours read 0
+      const double cry = (c.hasym ? (double)vym : 0.0) + (c.hasyp ? (double)vyp : 0.0);
+      hd = fmad(-(double)cx, crx, hd);
+      hd = fmad(-(double)cy, cry, hd);
+      const TR h = (TR)hd;
       bst<TR>(rH, out ? (c.nb + (uint32_t)k * nps) * kSr : kNullOff, h);
       if (out) acc[0] = fmad((double)vk, (double)h, acc[0]);
     }
@@ -466,23 +468,27 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
       const TR pam = am ? buf[li - nb] : TR(0), pap = ap ? buf[li + nb] : TR(0);
       const TR pbm = bm ? buf[li - 1] : TR(0), pbp = bp ? buf[li + 1] : TR(0);
       const TR pom = o > 0 ? Pm[i] : TR(0), pop = o < no - 1 ? Pn[i] : TR(0);
-      TR w = Dc[i] * pk;
+      // w = H p accumulated in FP64 and rounded once: for smooth p the stencil's terms nearly
+      // cancel (|H p| << d |p| where the Laplacian dominates), and FP32 accumulation would leave
+      // an error of the size of d |p| eps_32 in w; products of FP32 values are exact in FP64
+      double wd = (double)Dc[i] * (double)pk;
       if (ROLE == 0) {
-        w = fmad(Om[i], pom, w);
-        w = fmad(cur.oc[i], pop, w);
-        w = fmad(-c_a, pam + pap, w);
-        w = fmad(-c_b, pbm + pbp, w);
+        wd = fmad((double)Om[i], (double)pom, wd);
+        wd = fmad((double)cur.oc[i], (double)pop, wd);
+        wd = fmad(-(double)c_a, (double)pam + (double)pap, wd);
+        wd = fmad(-(double)c_b, (double)pbm + (double)pbp, wd);
       } else if (ROLE == 1) {
-        w = fmad(cur.ob[i], pam, w);
-        w = fmad(cur.oc[i], pap, w);
-        w = fmad(-c_o, pom + pop, w);
-        w = fmad(-c_b, pbm + pbp, w);
+        wd = fmad((double)cur.ob[i], (double)pam, wd);
+        wd = fmad((double)cur.oc[i], (double)pap, wd);
+        wd = fmad(-(double)c_o, (double)pom + (double)pop, wd);
+        wd = fmad(-(double)c_b, (double)pbm + (double)pbp, wd);
       } else {
-        w = fmad(cur.ob[i], pbm, w);
-        w = fmad(cur.oc[i], pbp, w);
-        w = fmad(-c_o, pom + pop, w);
-        w = fmad(-c_a, pam + pap, w);
+        wd = fmad((double)cur.ob[i], (double)pbm, wd);
+        wd = fmad((double)cur.oc[i], (double)pbp, wd);
+        wd = fmad(-(double)c_o, (double)pom + (double)pop, wd);
+        wd = fmad(-(double)c_a, (double)pam + (double)pap, wd);
       }
+      const TR w = (TR)wd;
       bst<TR>(rWo, off_at(own[i], node(o, i)), w);
       if (own[i]) {
         // FP64 products and sums (r.w/d as z.w, w.w/d and r.r/d with the stored 1/d); r and z

@@ -90,12 +90,11 @@ def test_pcg_parity(shape, pe, real):
         say(f"[pcg] shape={shape} pe={pe} real={real} maxit={maxit} rtol={rtol}: iterations "
             f"{its} (oracle {ref.iters}), |x - x_oracle|/|x_oracle| = {err:.2e}, relres "
             f"{got:.6e} (oracle {ref.relres:.6e})")
+        # the stop iteration is the oracle's, also in FP32 with rtol 0.1 and 0.02: the
+        # recurrence for |r|^2 restarts every iteration from the stored residual's own sums
         assert its == ref.iters, (its, ref.iters)
-        assert err <= _tol(real, 1e-9, VEC_RTOL * max(1.0, its / 10.0))
-        if real == "f64":
-            assert got == pytest.approx(ref.relres, rel=1e-6)
-        else:
-            assert abs(got - ref.relres) <= 1e-4
+        assert err <= _tol(real, 1e-9, VEC_RTOL)
+        assert got == pytest.approx(ref.relres, rel=_tol(real, 1e-9, 1e-5))
 
 
 def test_pcg_zero_rhs_gives_zero():
@@ -634,9 +633,8 @@ def test_autograd_gradcheck_fp64():
 def test_autograd_c2_bf16_directional_fd():
     """The 144x168x111 pair with BF16 images and an FP32 field: the device gradient against the
     oracle's FP64 gradient on the same BF16 images (1e-4), and along 64 seeded random directions
-    (max|d| = 1 voxel) against central differences (h = 1e-3) of the FP64 oracle J: relative
-    1e-3 (the kinks of the linear image model limit the differences) plus the FP32 gradient
-    error bound 1e-4 |g| |d|."""
+    (max|d| = 1 voxel) against central differences (h = 1e-3) of the FP64 oracle J within 1e-3
+    relative (the kinks of the linear image model limit the differences)."""
     from paper_2403_10706_amd import autograd as ag
     _rgp()
     p = synth.make_workload("c2")
@@ -662,10 +660,9 @@ def test_autograd_c2_bf16_directional_fd():
         Jm = orc.objective(Ip, Im, b - 1e-3 * d, p.pe, h).J
         fd = (Jp - Jm) / 2e-3
         an = float(np.sum(g * d))
-        bound = 1e-3 * abs(fd) + 1e-4 * gn * float(np.linalg.norm(d))
-        worst = max(worst, abs(fd - an) / bound)
-        assert abs(fd - an) <= bound, (k, fd, an)
-    say(f"[autograd c2 bf16] worst |fd - g.d| / bound = {worst:.3f}")
+        worst = max(worst, abs(fd - an) / abs(fd))
+        assert abs(fd - an) <= 1e-3 * abs(fd), (k, fd, an)
+    say(f"[autograd c2 bf16] worst |fd - g.d| / |fd| = {worst:.2e} (|grad J| = {gn:.3e})")
 
 
 # ---- batching: pairs of uneven shapes and PE axes in shared launches -------------------------
@@ -794,3 +791,99 @@ def test_autotune_then_correct():
         bp.launch(s)
         s.synchronize()
     assert torch.equal(bp.b[0], after["b"])
+
+
+# ---- full size, nonlinear regime: oracle golden samples ---------------------------------------
+
+def _golden(name):
+    import os
+    return np.load(os.path.join(os.path.dirname(__file__), "golden", f"{name}_solve_sample.npz"))
+
+
+def _check_against_golden(tag, gold, b, Tp, Tm, stats, levels, gn, batol, real):
+    """Final field at the sampled nodes, the per-step line-search record and the corrected
+    images at the sampled cells, against the oracle's golden sample."""
+    rgp = _rgp()
+    err = float(np.max(np.abs(to_host(b).ravel()[gold["b_index"]] - gold["b"])))
+    head, recs = rgp.parse_stats(stats, levels, gn)
+    tr = np.array([[r["trials"] for r in lv] for lv in recs])
+    ac = np.array([[r["accepted"] for r in lv] for lv in recs])
+    gm = np.array([[r["gamma"] for r in lv] for lv in recs])
+    J = np.array([[r["J"] for r in lv] for lv in recs])
+    jerr = float(np.max(np.abs(J - gold["J"]) / np.abs(gold["J"])))
+    say(f"[{tag}] max|b - b_oracle| over {gold['b'].size} nodes = {err:.3e} voxel (oracle max|b| "
+        f"= {float(gold['b_absmax']):.3f}); max rel J error over the steps {jerr:.2e}; trials "
+        f"device {tr.astype(int).tolist()} oracle {gold['trials'].astype(int).tolist()}")
+    assert err <= batol, err
+    assert head["status"] == int(gold["status"])
+    assert head["ot_guarded"] == int(gold["ot_guarded"])
+    # the line search takes the same decisions: trial counts, acceptance and step sizes
+    assert np.array_equal(tr, gold["trials"]) and np.array_equal(ac, gold["accepted"])
+    assert np.array_equal(gm, gold["gamma"])
+    assert jerr <= (1e-10 if real == "f64" else J_RTOL), jerr
+    # corrected images come back in the images' type: FP32 (arithmetic error only) or BF16, whose
+    # storage alone rounds each value by up to 2^-9 relative; the BF16 bar is twice that
+    ci = gold["cell_index"]
+    tbar = {torch.float64: 1e-9, torch.float32: 1e-4, torch.bfloat16: 2.0 ** -8}[Tp.dtype]
+    ep = rel2(to_host(Tp).ravel()[ci], gold["T_plus"])
+    em = rel2(to_host(Tm).ravel()[ci], gold["T_minus"])
+    say(f"[{tag}] corrected images ({Tp.dtype}) at {ci.size} cells: relative error {ep:.2e}, "
+        f"{em:.2e}")
+    assert ep <= tbar and em <= tbar, (ep, em)
+
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_correct_c2x1000_nonlinear_regime(real):
+    """144x168x111 (PE along dim 1) with the images scaled by 1000 (the distance term dominates,
+    the field reaches ~8 voxels and the line search backtracks), images rounded to FP32, 3 levels
+    x 10 GN x 20 PCG (rtol 0): the final field within 0.01 voxel of the oracle's (FP64 device
+    arithmetic: 1e-6), the same Armijo decisions at every step, J within 1e-5
+    (tests/golden/c2x1000_solve_sample.npz from tests/golden/make_nonlinear_golden.py)."""
+    rgp = _rgp()
+    gold = _golden("c2x1000")
+    p = synth.make_workload("c2", scale=float(gold["scale"]))
+    assert tuple(gold["shape"]) == tuple(p.shape) and int(gold["pe"]) == p.pe
+    dt = REAL[real]
+    Ip, Im = rounded(p.I_plus, torch.float32), rounded(p.I_minus, torch.float32)
+    opts = rgp.Options(levels=3, gn_iters=10, pcg_iters=20, pcg_rtol=0.0)
+    out = rgp.correct(to_dev(Ip, dt), to_dev(Im, dt), p.pe, opts=opts)
+    _check_against_golden(f"c2x1000 {real}", gold, out["b"], out["T_plus"], out["T_minus"],
+                          out["stats"], 3, 10, _tol(real, 1e-6, BFINAL_ATOL), real)
+
+
+C5_GOLDEN_PAIRS = (1, 6, 29)
+
+
+def test_c5_pairs_nonlinear_regime_plain_and_batched():
+    """Three pairs of the 32-pair uneven batch at full size (126x151x75 PE 0, 96x152x80 PE 1,
+    138x138x120 PE 0; max displacements 7.5-11.8 voxels), images scaled by 1000 and stored in
+    BF16, FP32 field, 3 levels x 10 GN x 20 PCG: each pair corrected alone and the three
+    corrected together by one batched plan, both against the oracle's golden sample (final field
+    within 0.01 voxel, same Armijo decisions, J within 1e-5), and batched equal to alone."""
+    rgp = _rgp()
+    it, dt = torch.bfloat16, torch.float32
+    opts = rgp.Options(levels=3, gn_iters=10, pcg_iters=20, pcg_rtol=0.0)
+    golds, Ips, Ims, pes, alone = [], [], [], [], []
+    for i in C5_GOLDEN_PAIRS:
+        gold = _golden(f"c5_pair{i}")
+        p = synth.make_batch_pair(i, scale=float(gold["scale"]))
+        assert tuple(gold["shape"]) == tuple(p.shape) and int(gold["pe"]) == p.pe
+        Ip, Im = to_dev(p.I_plus, it), to_dev(p.I_minus, it)
+        out = rgp.correct(Ip, Im, p.pe, opts=opts, real_dtype=dt)
+        _check_against_golden(f"c5 pair {i} alone", gold, out["b"], out["T_plus"],
+                              out["T_minus"], out["stats"], 3, 10, BFINAL_ATOL, "f32")
+        golds.append(gold)
+        Ips.append(Ip)
+        Ims.append(Im)
+        pes.append(p.pe)
+        alone.append(out["b"])
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        bp = rgp.BatchPlan(Ips, Ims, pes, opts, stream=s, want_stats=True)
+        bp.launch(s)
+        s.synchronize()
+    for k, i in enumerate(C5_GOLDEN_PAIRS):
+        assert torch.equal(bp.b[k], alone[k]), i
+        _check_against_golden(f"c5 pair {i} batched", golds[k], bp.b[k], bp.T_plus[k],
+                              bp.T_minus[k], bp.stats[k], 3, 10, BFINAL_ATOL, "f32")
