@@ -8,7 +8,15 @@ prolongation between levels, and the Jacobian-modulation correction - all throug
 Inputs are resident in HBM before the timed region.  The correction is captured once into a HIP
 graph (rgp_correct_plan) and one step is one replay; an eager pass of the same correction follows
 with the library's kernel timing on (HIP events recorded at the start and end of every hot
-kernel, rgp_timing_*), from which the per-kernel rooflines are computed.
+kernel, rgp_timing_*), from which the per-kernel rooflines are computed.  The roofline's
+`achieved` counts 52 B per cell per PCG iteration (the hot-path measurement table's figure);
+`moved_bytes` beside it counts the 40 B per node the fused PCG kernel must move.
+
+The same line carries the batched leg (`batch`, unless --batch-pairs 0): 32 uneven pairs
+(BF16 images scaled x1000, FP32 field, same schedule) corrected by one batched graph against one
+graph per pair, and the batched Gauss-Newton launches timed in an eager batched correction (their
+working set is HBM-resident, ~2.8 GB per finest-level PCG iteration), and `cpu_baseline`: the
+FP64 oracle's whole correction of the headline pair on one thread of the host.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 
@@ -96,6 +104,21 @@ def algorithmic_bytes(rec, f=4, fi=4, maxit=PCG_ITERS):
     return 0
 
 
+def survey_bytes(rec, f=4, fi=4):
+    """Algorithmic bytes per launch under the hot-path measurement table's per-unit figures
+    (N cells, Nb field nodes): a PCG iteration (HVP and CG vector updates, ~13 array passes)
+    52 N; loss_grad with the Jacobi diagonal 2 N s_img + 3 Nb f, without it 2 N s_img + 2 Nb f;
+    gn_hvp (recomputing from the images) 2 N s_img + 3 Nb f; ot_init 2 N s_img + Nb f."""
+    k, n, c = rec["kernel"], rec["nodes"], rec["cells"]
+    if k == "pcg_step":
+        return 52 * c * f // 4
+    if k in ("loss_grad", "hvp"):
+        return 2 * fi * c + 3 * f * n
+    if k == "ot":
+        return 2 * fi * c + f * n
+    return algorithmic_bytes(rec, f, fi)
+
+
 BYTES_RULE = {
     "pcg_step": "full iteration: reads x,r,p,w,diag,off, writes x,r,p,w (40 B/node)",
     "loss_grad": "reads I+,I-,b[,q], writes grad,diag,off[,b+gq] (8 B/cell + 16 or 24 B/node)",
@@ -137,14 +160,28 @@ def summarize_records(recs, maxit=PCG_ITERS):
 
 # ---------------------------------------------------------------------------------------------
 
-def cpu_baseline(pair, levels, gn_iters, pcg_iters, sample_gn=5):
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload.
+def host_cpu():
+    """CPU model and the logical CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, os.cpu_count(), avail
 
-    Sample: the pyramid, OT on the coarsest level, `sample_gn` of the gn_iters Gauss-Newton steps
-    (each with the full PCG iteration count) on every level, the prolongations and the final
-    correction (about 12 s on one core).  The per-pair time counts the measured GN steps
-    gn_iters / sample_gn times.
-    """
+
+def cpu_baseline(pair, levels, gn_iters, pcg_iters):
+    """The FP64 oracle, as it stands, on the whole correction of the same pair: pyramid, OT on
+    the coarsest level, every Gauss-Newton step of every level (PCG pcg_iters, rtol 0), the
+    prolongations and the final correction, on one thread (about 25 s)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -152,35 +189,17 @@ def cpu_baseline(pair, levels, gn_iters, pcg_iters, sample_gn=5):
 
     Ip = pair.I_plus.astype(np.float32).astype(np.float64)
     Im = pair.I_minus.astype(np.float32).astype(np.float64)
-    pe = pair.pe
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        pyr = orc.pyramid(Ip, Im, pair.h, levels)
-        P, M, hh = pyr[-1]
-        b = orc.ot_init(P, M, pe, hh).b0
-        t_fixed = time.perf_counter() - t0
-        t_gn = 0.0
-        for li in range(levels - 1, -1, -1):
-            P, M, hh = pyr[li]
-            if li < levels - 1:
-                t1 = time.perf_counter()
-                b = orc.prolong_field(b, P.shape, pe)
-                t_fixed += time.perf_counter() - t1
-            t1 = time.perf_counter()
-            b, _ = orc.gauss_newton(P, M, b, pe, hh, gn_iters=sample_gn, pcg_iters=pcg_iters,
-                                    pcg_rtol=0.0)
-            t_gn += time.perf_counter() - t1
-        t1 = time.perf_counter()
-        orc.transform(Ip, b, pe, pair.h, 1.0)
-        orc.transform(Im, b, pe, pair.h, -1.0)
-        t_fixed += time.perf_counter() - t1
-    sample_s = t_fixed + t_gn
-    per_pair = t_fixed + t_gn * gn_iters / sample_gn
+        orc.solve(Ip, Im, pair.pe, pair.h, levels=levels, gn_iters=gn_iters,
+                  pcg_iters=pcg_iters, pcg_rtol=0.0)
+        per_pair = time.perf_counter() - t0
+    model, ncpu, avail = host_cpu()
     return dict(value=1.0 / per_pair, unit="pairs/s", cores=1, kind="oracle",
-                sample=(f"pyramid + OT + {sample_gn} of {gn_iters} GN steps (PCG {pcg_iters}) per "
-                        f"level + prolongations + correction, {sample_s:.1f} s measured; per-pair "
-                        f"time {per_pair:.1f} s extrapolated (GN steps x {gn_iters / sample_gn:g}); "
-                        "FP64 NumPy, 1 thread"))
+                sample=(f"one whole correction of the same pair ({levels} levels x {gn_iters} GN "
+                        f"x {pcg_iters} PCG, OT, correction), {per_pair:.1f} s; FP64 NumPy, one "
+                        "thread"),
+                host_cpu=model, host_logical_cpus=ncpu, cpus_available=avail)
 
 
 # ---------------------------------------------------------------------------------------------
@@ -416,41 +435,62 @@ def batch_profile_summary(d):
 # ---------------------------------------------------------------------------------------------
 # batching: the uneven batch of pairs, plain per-pair graphs against one batched graph
 
-def batch_bench(n, steps, scale):
+def _gen_batch_pair(args):
+    i, n, scale = args
+    import numpy as np
+
+    import synth
+    p = synth.make_batch_pair(i, n=n, scale=scale)
+    return (p.I_plus.astype(np.float32), p.I_minus.astype(np.float32),
+            np.asarray(p.b_true, np.float32), p.pe, tuple(p.shape))
+
+
+def gen_batch(n, scale):
+    """The uneven batch's pairs, generated in worker processes (call before the GPU is touched:
+    the workers are forked)."""
+    import multiprocessing as mp
+    nproc = max(1, min(8, host_cpu()[2] // 2, n))
+    with mp.get_context("fork").Pool(nproc) as pool:
+        return pool.map(_gen_batch_pair, [(i, n, scale) for i in range(n)])
+
+
+def batch_bench(pairs, steps, scale):
     """n synthetic pairs of uneven sizes (dims 96..200 x 96..200 x 60..132), PE along dim 0 or 1,
     BF16 images, FP32 field, 3 levels x 10 GN x 20 PCG.  Plain: one captured graph per pair
     (rgp_correct_plan) replayed pair after pair on one stream; batched: one captured graph for
     all pairs (rgp_correct_batch_plan).  Both use the same images; the final fields are compared
-    with each other and with the true fields the pairs were synthesised from."""
+    with each other and with the true fields the pairs were synthesised from.  Then one eager
+    batched correction (rgp_correct_batch) with kernel timing gives the batched launches'
+    durations: their working set (level 0: ~2.8 GB per PCG iteration) is HBM-resident."""
     import numpy as np
     import torch
 
-    import synth
     from paper_2403_10706_amd import rgp
 
     rgp.load()
+    n = len(pairs)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    log(f"bench --batch: generating {n} uneven pairs")
-    pairs = synth.make_batch(n, scale=scale)
     bf = torch.bfloat16
-    Ip = [torch.as_tensor(p.I_plus).to(dev, bf).contiguous() for p in pairs]
-    Im = [torch.as_tensor(p.I_minus).to(dev, bf).contiguous() for p in pairs]
-    pes = [p.pe for p in pairs]
+    Ip = [torch.as_tensor(p[0]).to(dev, bf).contiguous() for p in pairs]
+    Im = [torch.as_tensor(p[1]).to(dev, bf).contiguous() for p in pairs]
+    pes = [p[3] for p in pairs]
+    shapes = [p[4] for p in pairs]
     opts = rgp.Options(levels=LEVELS, gn_iters=GN_ITERS, pcg_iters=PCG_ITERS, pcg_rtol=0.0)
     side = torch.cuda.Stream()
     torch.cuda.synchronize()
     torch.cuda.set_stream(side)
     # plain: one graph per pair, one shared workspace (the pairs run one after another)
-    wsz = max(rgp.workspace_size(rgp.OP_CORRECT, tuple(p.shape), p.pe, (1.0, 1.0, 1.0),
-                                 torch.float32, opts.to_c()) for p in pairs)
+    wsz = max(rgp.workspace_size(rgp.OP_CORRECT, sh, pe, (1.0, 1.0, 1.0), torch.float32,
+                                 opts.to_c()) for sh, pe in zip(shapes, pes))
     ws = torch.zeros(wsz, dtype=torch.uint8, device=dev)
-    bp_out = [torch.empty(rgp.field_shape(tuple(p.shape), p.pe), dtype=torch.float32,
-                          device=dev) for p in pairs]
+    bp_out = [torch.empty(rgp.field_shape(sh, pe), dtype=torch.float32, device=dev)
+              for sh, pe in zip(shapes, pes)]
     Tp = [torch.empty_like(t) for t in Ip]
     Tm = [torch.empty_like(t) for t in Im]
+    log(f"bench batch: autotuning {n} geometries")
     for i in range(n):
-        rgp.autotune(tuple(pairs[i].shape), pes[i], torch.float32, opts, ws=ws, stream=side)
+        rgp.autotune(shapes[i], pes[i], torch.float32, opts, ws=ws, stream=side)
     plans = [rgp.Plan(Ip[i], Im[i], pes[i], opts, bp_out[i], Tp[i], Tm[i], ws, stream=side)
              for i in range(n)]
     batch = rgp.BatchPlan(Ip, Im, pes, opts, stream=side)
@@ -469,32 +509,59 @@ def batch_bench(n, steps, scale):
 
     plain()
     batch.launch(side)
+    log(f"bench batch: timing {steps} plain passes and {steps} batched replays")
     t_plain = timed(plain, steps)
     t_batch = timed(lambda: batch.launch(side), steps)
     d_bp, e_plain, e_batch = [], [], []
     for i, p in enumerate(pairs):
         bb = batch.b[i].double().cpu().numpy()
         bq = bp_out[i].double().cpu().numpy()
+        bt = p[2].astype(np.float64)
         d_bp.append(float(np.max(np.abs(bb - bq))))
-        e_plain.append(float(np.sqrt(np.mean((bq - p.b_true) ** 2))))
-        e_batch.append(float(np.sqrt(np.mean((bb - p.b_true) ** 2))))
+        e_plain.append(float(np.sqrt(np.mean((bq - bt) ** 2))))
+        e_batch.append(float(np.sqrt(np.mean((bb - bt) ** 2))))
     for pl in plans:
         pl.close()
+    # one eager batched correction with kernel timing (the graph's launches are not timed)
+    torch.cuda.synchronize()
+    rgp.timing_start(1 << 16)
+    batch.run_eager(side)
+    torch.cuda.synchronize()
+    recs = rgp.timing_stop(1 << 16)
     batch.close()
-    cells = int(sum(np.prod(p.shape) for p in pairs))
-    line = dict(metric=f"pairs corrected/s, {n} uneven pairs (BF16 images, FP32 field)",
-                unit="pairs/s", batched=round(n / t_batch, 3), plain=round(n / t_plain, 3),
-                speedup=round(t_plain / t_batch, 3), ms_batched=round(1e3 * t_batch, 3),
-                ms_plain=round(1e3 * t_plain, 3), steps=steps, cells=cells, image_scale=scale,
-                max_abs_b_batched_vs_plain=max(d_bp),
-                rms_error_vs_true_plain=round(float(np.mean(e_plain)), 6),
-                rms_error_vs_true_batched=round(float(np.mean(e_batch)), 6),
-                config=dict(levels=LEVELS, gn_iters=GN_ITERS, pcg_iters=PCG_ITERS,
-                            shapes=[list(p.shape) for p in pairs], pe=pes),
-                device=torch.cuda.get_device_name(0))
-    log(f"bench --batch: plain {n / t_plain:.2f} pairs/s, batched {n / t_batch:.2f} pairs/s "
+    kernels = {}
+    for name, rec in summarize_records(recs).items():
+        if rec["kernel"] not in ("pcg_step", "loss_grad", "trial"):
+            continue
+        if rec["cells"] < sum(int(np.prod(sh)) for sh in shapes) // 80:
+            continue   # a single pair's launch (the batch shares only the Gauss-Newton kernels)
+        rb = dict(rec)
+        # full PCG iterations, the gamma = 1 trial pass, loss_grad with or without the step
+        tag = (1 if name.endswith("+step") else 0) if rec["kernel"] == "loss_grad" else 1
+        b = algorithmic_bytes(dict(kernel=rec["kernel"], nodes=rec["nodes"], cells=rec["cells"],
+                                   tag=tag), fi=2)
+        rb["bytes_per_launch"] = b
+        rb["achieved_GBps"] = round(b / (rec["us_mean"] * 1e3), 1)
+        rb["frac"] = round(rb["achieved_GBps"] / HBM_PEAK_GBPS, 4)
+        rb["bytes_rule"] = BYTES_RULE[rec["kernel"]].replace("8 B/cell", "4 B/cell (BF16)")
+        kernels["batched:" + name] = rb
+    for name, rec in kernels.items():
+        log(f"bench batch: {name:40s} n={rec['launches']:4d} {rec['us_mean']:9.2f} us "
+            f"{rec['achieved_GBps']:7.1f} GB/s frac {rec['frac']:.3f}")
+    cells = int(sum(int(np.prod(sh)) for sh in shapes))
+    out = dict(workload=f"{n} uneven pairs, dims 96-200 x 96-200 x 60-132, PE along dim 0 or 1, "
+                        f"BF16 images x{scale:g}, FP32 field, {LEVELS} levels x {GN_ITERS} GN x "
+                        f"{PCG_ITERS} PCG",
+               unit="pairs/s", batched=round(n / t_batch, 3), plain=round(n / t_plain, 3),
+               speedup=round(t_plain / t_batch, 3), ms_batched=round(1e3 * t_batch, 3),
+               ms_plain=round(1e3 * t_plain, 3), steps=steps, cells=cells,
+               max_abs_b_batched_vs_plain=max(d_bp),
+               rms_error_vs_true_plain=round(float(np.mean(e_plain)), 6),
+               rms_error_vs_true_batched=round(float(np.mean(e_batch)), 6),
+               kernels=kernels)
+    log(f"bench batch: plain {n / t_plain:.2f} pairs/s, batched {n / t_batch:.2f} pairs/s "
         f"(x{t_plain / t_batch:.2f}); max|b_batched - b_plain| = {max(d_bp):.2e}")
-    print(json.dumps(line), flush=True)
+    return out
 
 
 # ---------------------------------------------------------------------------------------------
@@ -513,6 +580,8 @@ def main():
     ap.add_argument("--batch", type=int, metavar="N", default=0,
                     help="the batching benchmark over N uneven pairs instead of the headline")
     ap.add_argument("--batch-scale", type=float, default=1000.0)
+    ap.add_argument("--batch-pairs", type=int, default=32,
+                    help="pairs of the batched leg of the default run (0: leave it out)")
     args = ap.parse_args()
     if args.traffic_summary:
         return traffic_summary(*args.traffic_summary)
@@ -529,7 +598,16 @@ def main():
     if args.pmc_probe:
         return pmc_probe()
     if args.batch:
-        return batch_bench(args.batch, max(1, args.steps // 4), args.batch_scale)
+        log(f"bench --batch: generating {args.batch} uneven pairs")
+        res = batch_bench(gen_batch(args.batch, args.batch_scale), max(1, args.steps // 4),
+                          args.batch_scale)
+        print(json.dumps(res), flush=True)
+        return None
+    # the batched leg's pairs are generated first, in forked workers, before the GPU is touched
+    batch_pairs = None
+    if args.batch_pairs > 0:
+        log(f"bench: generating the {args.batch_pairs} uneven pairs of the batched leg")
+        batch_pairs = gen_batch(args.batch_pairs, args.batch_scale)
 
     import numpy as np
     import torch
@@ -642,18 +720,32 @@ def main():
     nb = int(np.prod(rgp.field_shape(shape, pe)))
     dom = next(r for r in kernels.values() if r["kernel"] == "pcg_step" and r["nodes"] == nb)
     traffic = measured_traffic()
-    roofline = dict(bound="hbm", achieved=dom["achieved_GBps"], peak=HBM_PEAK_GBPS, unit="GB/s",
-                    frac=dom["frac"], traffic=traffic,
+    # achieved: the measurement table's per-unit figure for a PCG iteration (52 B per cell)
+    # over the measured mean launch; moved_bytes: what this fused kernel must move (40 B/node)
+    sb = survey_bytes(dict(kernel="pcg_step", nodes=dom["nodes"], cells=dom["cells"], tag=1))
+    s_gbps = sb / (dom["us_mean"] * 1e3)
+    roofline = dict(bound="hbm", achieved=round(s_gbps, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
+                    frac=round(s_gbps / HBM_PEAK_GBPS, 4), traffic=traffic,
                     kernel="k_pcg_step (finest level, 144x169x111 nodes, full PCG iterations)",
-                    bytes_per_launch=dom["bytes_per_launch"], us_per_launch=dom["us_mean"],
+                    bytes_rule="52 B per cell per PCG iteration (HVP + CG vector updates)",
+                    bytes_per_launch=sb, us_per_launch=dom["us_mean"],
                     us_median=dom["us_median"], launches=dom["launches"], grid=dom["grid"],
+                    moved_bytes=dict(bytes_rule=dom["bytes_rule"],
+                                     bytes_per_launch=dom["bytes_per_launch"],
+                                     achieved=dom["achieved_GBps"], frac=dom["frac"]),
                     copy_reference=copy)
+
+    plan.close()
+    batch = None
+    if batch_pairs:
+        batch = batch_bench(batch_pairs, max(1, args.steps // 4), args.batch_scale)
+        del batch_pairs
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("bench: timing the FP64 oracle on a bounded sample (about 12 s)")
+        log("bench: timing the FP64 oracle on one whole correction (about 25 s)")
         cpu = cpu_baseline(pair, LEVELS, GN_ITERS, PCG_ITERS)
-        log(f"bench: oracle {1.0 / cpu['value']:.1f} s/pair extrapolated")
+        log(f"bench: oracle {1.0 / cpu['value']:.1f} s/pair ({cpu['host_cpu']})")
 
     line = dict(
         metric=METRIC, value=round(value, 3), unit="pairs/s", n_gpus=1, steps=args.steps,
@@ -664,10 +756,9 @@ def main():
                     shape=list(shape), pe_dim=pe, levels=LEVELS, gn_iters=GN_ITERS,
                     pcg_iters=PCG_ITERS, global_batch=1, pcg_march_lengths=tuned_xl),
         gpu_ms_per_step=round(gpu_ms / args.steps, 4), eager_ms_per_step=round(eager_ms, 4),
-        roofline=roofline, kernels=kernels, cpu_baseline=cpu,
+        roofline=roofline, kernels=kernels, batch=batch, cpu_baseline=cpu,
         device=torch.cuda.get_device_name(0),
     )
-    plan.close()
     print(json.dumps(line), flush=True)
 
 

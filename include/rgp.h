@@ -254,6 +254,18 @@ rgp_status rgp_correct_batch_plan(int32_t n, const rgp_grid* grids, rgp_dtype im
                                   double* const* stats_dev, void* ws, size_t ws_bytes,
                                   void* stream, rgp_plan* plan);
 
+/* The batched correction without a graph: the same arguments, launches and results as
+ * rgp_correct_batch_plan followed by one rgp_plan_launch, enqueued directly on `stream` (each
+ * Gauss-Newton kernel one launch over all pairs).  It synchronises `stream` once, to upload the
+ * launch tables into ws, before it enqueues the correction (RGP_EINVAL while the stream is being
+ * captured).  Launches are seen by a kernel-timing session (rgp_timing_start), each record
+ * carrying the cells and nodes summed over the pairs. */
+rgp_status rgp_correct_batch(int32_t n, const rgp_grid* grids, rgp_dtype img_t,
+                             const void* const* I_plus, const void* const* I_minus,
+                             rgp_dtype real_t, const rgp_solver_opts* opts, void* const* b_out,
+                             void* const* T_plus, void* const* T_minus, double* const* stats_dev,
+                             void* ws, size_t ws_bytes, void* stream);
+
 /* Autotuner of the PCG tile shape (batching extension): for every pyramid level of `grid` under
  * `opts` (one level when opts is NULL) it times the candidate march lengths of the PCG step - a
  * work unit is 256 consecutive positions of the contiguous node plane times XL planes - on the

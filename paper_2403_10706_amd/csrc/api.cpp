@@ -1101,6 +1101,8 @@ struct BatchSlot {
   unsigned grid = 0;
   size_t lds = 0;
   int var[4] = {0, 0, 0, 0};
+  int64_t cells = 0, nodes = 0;  // summed over the pairs (kernel timing)
+  int tag = 0;
 };
 
 // Records the correction of every pair (their workspaces laid out back to back from ws) and
@@ -1164,6 +1166,9 @@ rgp_status record_batch(int32_t n, const rgp_grid* grids, rgp_dtype img_t,
       const RecLaunch& r = recs[(size_t)p].launches[i];
       tab.insert(tab.end(), r.args.begin(), r.args.end());
       starts[(size_t)p + 1] = starts[(size_t)p] + r.grid;
+      sl.cells += r.cells;
+      sl.nodes += r.nodes;
+      sl.tag = r.tag;
       sl.lds = std::max(sl.lds, r.lds);
       geo.push_back(r.geo);
       if (r0.kind == RecKind::kPcgStep) sl.var[3] = std::max(sl.var[3], r.geo.XL);
@@ -1192,11 +1197,12 @@ hipError_t issue_batch(int32_t n, const std::vector<Recorder>& recs,
     const uint32_t* starts = reinterpret_cast<const uint32_t*>(arena_dev + sl.starts);
     switch (sl.kind) {
       case RecKind::kLossGrad:
-        e = launch_loss_grad_batch(tab, starts, n, sl.grid, (DType)sl.var[0], (DType)sl.var[1], s);
+        e = launch_loss_grad_batch(tab, starts, n, sl.grid, (DType)sl.var[0], (DType)sl.var[1],
+                                   sl.cells, sl.nodes, sl.tag, s);
         break;
       case RecKind::kTrial:
         e = launch_trial_batch(tab, starts, n, sl.grid, sl.var[2], (DType)sl.var[0],
-                               (DType)sl.var[1], s);
+                               (DType)sl.var[1], sl.cells, sl.nodes, s);
         break;
       case RecKind::kDecide:
         e = launch_decide_batch(tab, n, sl.var[0], s);
@@ -1209,7 +1215,8 @@ hipError_t issue_batch(int32_t n, const std::vector<Recorder>& recs,
         break;
       case RecKind::kPcgStep:
         e = launch_pcg_step_batch(tab, reinterpret_cast<const MarchGeo*>(arena_dev + sl.geo),
-                                  starts, n, sl.grid, sl.lds, (DType)sl.var[0], sl.var[3], s);
+                                  starts, n, sl.grid, sl.lds, (DType)sl.var[0], sl.var[3],
+                                  sl.cells, sl.nodes, sl.tag, s);
         break;
       default:
         e = hipErrorInvalidValue;
@@ -1240,15 +1247,16 @@ rgp_status rgp_batch_workspace_size(int32_t n, const rgp_grid* grids, rgp_dtype 
   return RGP_OK;
 }
 
-rgp_status rgp_correct_batch_plan(int32_t n, const rgp_grid* grids, rgp_dtype img_t,
-                                  const void* const* I_plus, const void* const* I_minus,
-                                  rgp_dtype real_t, const rgp_solver_opts* opts,
-                                  void* const* b_out, void* const* T_plus, void* const* T_minus,
-                                  double* const* stats_dev, void* ws, size_t ws_bytes,
-                                  void* stream, rgp_plan* plan) {
-  if (!plan) return RGP_EINVAL;
-  *plan = nullptr;
-  if (!stream) return RGP_EINVAL;  // the legacy default stream cannot be captured
+namespace {
+
+// Checks the arguments of a batched correction, records every pair's sequence and uploads the
+// shared launches' tables to the workspace (synchronising `s` once: the host tables die here).
+rgp_status prepare_batch(int32_t n, const rgp_grid* grids, rgp_dtype img_t,
+                         const void* const* I_plus, const void* const* I_minus, rgp_dtype real_t,
+                         const rgp_solver_opts* opts, void* const* b_out, void* const* T_plus,
+                         void* const* T_minus, double* const* stats_dev, void* ws, size_t ws_bytes,
+                         hipStream_t s, std::vector<Recorder>& recs,
+                         std::vector<BatchSlot>& slots, unsigned char** arena_dev) {
   rgp_status st = check_batch_grids(n, grids, real_t, opts);
   if (st != RGP_OK) return st;
   DType di, dr;
@@ -1263,19 +1271,56 @@ rgp_status rgp_correct_batch_plan(int32_t n, const rgp_grid* grids, rgp_dtype im
   if ((st = rgp_batch_workspace_size(n, grids, real_t, opts, &need)) != RGP_OK) return st;
   if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
     return RGP_EWORKSPACE;
-  std::vector<Recorder> recs;
-  std::vector<BatchSlot> slots;
   std::vector<unsigned char> arena;
   size_t pairs = 0;
   st = record_batch(n, grids, img_t, I_plus, I_minus, real_t, opts, b_out, T_plus, T_minus,
                     stats_dev, static_cast<unsigned char*>(ws), recs, slots, arena, pairs);
   if (st != RGP_OK) return st;
-  const hipStream_t s = static_cast<hipStream_t>(stream);
-  unsigned char* arena_dev = static_cast<unsigned char*>(ws) + pairs;
+  *arena_dev = static_cast<unsigned char*>(ws) + pairs;
   if (!arena.empty()) {
-    RGP_HIP(hipMemcpyAsync(arena_dev, arena.data(), arena.size(), hipMemcpyHostToDevice, s));
-    RGP_HIP(hipStreamSynchronize(s));  // the host tables are released on return
+    RGP_HIP(hipMemcpyAsync(*arena_dev, arena.data(), arena.size(), hipMemcpyHostToDevice, s));
+    RGP_HIP(hipStreamSynchronize(s));
   }
+  return RGP_OK;
+}
+
+}  // namespace
+
+rgp_status rgp_correct_batch(int32_t n, const rgp_grid* grids, rgp_dtype img_t,
+                             const void* const* I_plus, const void* const* I_minus,
+                             rgp_dtype real_t, const rgp_solver_opts* opts, void* const* b_out,
+                             void* const* T_plus, void* const* T_minus, double* const* stats_dev,
+                             void* ws, size_t ws_bytes, void* stream) {
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  RGP_HIP(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) return RGP_EINVAL;  // it synchronises the stream
+  std::vector<Recorder> recs;
+  std::vector<BatchSlot> slots;
+  unsigned char* arena_dev = nullptr;
+  rgp_status st = prepare_batch(n, grids, img_t, I_plus, I_minus, real_t, opts, b_out, T_plus,
+                                T_minus, stats_dev, ws, ws_bytes, s, recs, slots, &arena_dev);
+  if (st != RGP_OK) return st;
+  RGP_HIP(issue_batch(n, recs, slots, arena_dev, s));
+  return RGP_OK;
+}
+
+rgp_status rgp_correct_batch_plan(int32_t n, const rgp_grid* grids, rgp_dtype img_t,
+                                  const void* const* I_plus, const void* const* I_minus,
+                                  rgp_dtype real_t, const rgp_solver_opts* opts,
+                                  void* const* b_out, void* const* T_plus, void* const* T_minus,
+                                  double* const* stats_dev, void* ws, size_t ws_bytes,
+                                  void* stream, rgp_plan* plan) {
+  if (!plan) return RGP_EINVAL;
+  *plan = nullptr;
+  if (!stream) return RGP_EINVAL;  // the legacy default stream cannot be captured
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<Recorder> recs;
+  std::vector<BatchSlot> slots;
+  unsigned char* arena_dev = nullptr;
+  rgp_status st = prepare_batch(n, grids, img_t, I_plus, I_minus, real_t, opts, b_out, T_plus,
+                                T_minus, stats_dev, ws, ws_bytes, s, recs, slots, &arena_dev);
+  if (st != RGP_OK) return st;
   RGP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   const hipError_t e = issue_batch(n, recs, slots, arena_dev, s);
   hipGraph_t graph = nullptr;

@@ -33,6 +33,8 @@ struct RecLaunch {
   unsigned grid = 0, block = 0;
   size_t lds = 0;
   int var[4] = {0, 0, 0, 0};        // template parameters that a shared launch needs equal
+  int64_t cells = 0, nodes = 0;     // volume the launch covers (kernel timing of shared launches)
+  int tag = 0;                      // kernel timing tag (as the plain launch's)
   std::function<hipError_t(hipStream_t)> replay;  // the plain launch of this one volume
 };
 
@@ -64,6 +66,15 @@ inline hipError_t record_launch(RecKind kind, const A& a, unsigned grid, unsigne
   return hipSuccess;
 }
 
+// Notes the volume and timing tag of the launch just recorded.
+inline hipError_t note_volume(int64_t cells, int64_t nodes, int tag) {
+  RecLaunch& r = active_recorder()->launches.back();
+  r.cells = cells;
+  r.nodes = nodes;
+  r.tag = tag;
+  return hipSuccess;
+}
+
 inline hipError_t record_other(std::function<hipError_t(hipStream_t)> replay) {
   RecLaunch r;
   r.replay = std::move(replay);
@@ -72,11 +83,14 @@ inline hipError_t record_other(std::function<hipError_t(hipStream_t)> replay) {
 }
 
 // Shared launches: tab points to n argument blocks in device memory, starts to n+1 workgroup
-// offsets (one workgroup per volume for the single-block kernels).
+// offsets (one workgroup per volume for the single-block kernels).  cells/nodes/tag: the summed
+// volume and the timing tag that a kernel-timing session records for the launch.
 hipError_t launch_loss_grad_batch(const void* tab, const uint32_t* starts, int n, unsigned grid,
-                                  DType img, DType real, hipStream_t s);
+                                  DType img, DType real, int64_t cells, int64_t nodes, int tag,
+                                  hipStream_t s);
 hipError_t launch_trial_batch(const void* tab, const uint32_t* starts, int n, unsigned grid,
-                              int nc, DType img, DType real, hipStream_t s);
+                              int nc, DType img, DType real, int64_t cells, int64_t nodes,
+                              hipStream_t s);
 hipError_t launch_decide_batch(const void* tab, int n, int nc, hipStream_t s);
 hipError_t launch_apply_step_batch(const void* tab, const uint32_t* starts, int n, unsigned grid,
                                    DType real, hipStream_t s);
@@ -84,6 +98,6 @@ hipError_t launch_pcg_scalars_batch(const void* tab, int n, hipStream_t s);
 // max_xl: the longest march of the volumes (units of at most 3 planes load them all up front)
 hipError_t launch_pcg_step_batch(const void* tab, const MarchGeo* geo, const uint32_t* starts,
                                  int n, unsigned grid, size_t lds, DType real, int max_xl,
-                                 hipStream_t s);
+                                 int64_t cells, int64_t nodes, int tag, hipStream_t s);
 
 }  // namespace rgp

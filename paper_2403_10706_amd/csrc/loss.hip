@@ -759,11 +759,13 @@ hipError_t launch_loss_grad(const LossGradArgs& a0, DType img, DType real, hipSt
   const Launch L = plan_loss_grad(a0.g, real);
   LossGradArgs a = a0;
   a.run = L.S;
-  if (active_recorder())
-    return record_launch(RecKind::kLossGrad, a, L.grid, L.block, 0, (int)img, (int)real, 0,
-                         [a, img, real](hipStream_t s2) { return launch_loss_grad(a, img, real, s2); });
   // timing tag 1: the launch also applies the previous step (reads q, writes b + gamma q)
   const int tag = a.step ? 1 : 0;
+  if (active_recorder()) {
+    record_launch(RecKind::kLossGrad, a, L.grid, L.block, 0, (int)img, (int)real, 0,
+                  [a, img, real](hipStream_t s2) { return launch_loss_grad(a, img, real, s2); });
+    return note_volume(a.g.ncell, a.g.nnode, tag);
+  }
 #define RGP_LG(RUN, STEP)                                                                    \
   RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH_T(kKindLossGrad, tag, a.g,                        \
                                              (k_loss_grad<TI, TR, RUN, 256, STEP>), L.grid,  \
@@ -792,9 +794,11 @@ hipError_t launch_loss_final(const LossFinalArgs& a, hipStream_t s) {
 
 hipError_t launch_trial(const TrialArgs& a, DType img, DType real, hipStream_t s) {
   const Launch L = plan_trial(a.g, real, a.nc);
-  if (active_recorder())
-    return record_launch(RecKind::kTrial, a, L.grid, L.block, 0, (int)img, (int)real, a.nc,
-                         [a, img, real](hipStream_t s2) { return launch_trial(a, img, real, s2); });
+  if (active_recorder()) {
+    record_launch(RecKind::kTrial, a, L.grid, L.block, 0, (int)img, (int)real, a.nc,
+                  [a, img, real](hipStream_t s2) { return launch_trial(a, img, real, s2); });
+    return note_volume(a.g.ncell, a.g.nnode, a.nc);
+  }
 #define RGP_TRIAL_P(NC, B, P)                                                              \
   RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH_T(kKindTrial, NC, a.g,                          \
                                              (k_trial<TI, TR, kRunTrial, NC, B, P>), L.grid, B, \
@@ -878,19 +882,23 @@ hipError_t launch_image_grad(const ImageGradArgs& a, DType img, DType real, hipS
 // ---- shared launches over several volumes -----------------------------------------------------
 
 hipError_t launch_loss_grad_batch(const void* tab, const uint32_t* starts, int n, unsigned grid,
-                                  DType img, DType real, hipStream_t s) {
+                                  DType img, DType real, int64_t cells, int64_t nodes, int tag,
+                                  hipStream_t s) {
   const LossGradArgs* t = static_cast<const LossGradArgs*>(tab);
-  RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_loss_grad_batch<TI, TR, 256>),
-                                                   dim3(grid), dim3(256), 0, s, t, starts, n));
+  RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH_TN(kKindLossGrad, tag, cells, nodes,
+                                              (k_loss_grad_batch<TI, TR, 256>), grid, 256, 0, s,
+                                              t, starts, n));
   return hipGetLastError();
 }
 
 hipError_t launch_trial_batch(const void* tab, const uint32_t* starts, int n, unsigned grid,
-                              int nc, DType img, DType real, hipStream_t s) {
+                              int nc, DType img, DType real, int64_t cells, int64_t nodes,
+                              hipStream_t s) {
   const TrialArgs* t = static_cast<const TrialArgs*>(tab);
 #define RGP_TRIAL_B(NC)                                                                      \
-  RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_trial_batch<TI, TR, kRunTrial, NC, 256>), \
-                                                   dim3(grid), dim3(256), 0, s, t, starts, n))
+  RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH_TN(kKindTrial, NC, cells, nodes,                  \
+                                              (k_trial_batch<TI, TR, kRunTrial, NC, 256>), grid, \
+                                              256, 0, s, t, starts, n))
   switch (nc) {
     case 1: RGP_TRIAL_B(1); break;
     case 2: RGP_TRIAL_B(2); break;

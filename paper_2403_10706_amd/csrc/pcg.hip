@@ -697,9 +697,11 @@ hipError_t launch_pcg_step(const PcgArgs& a, DType real, hipStream_t s) {
 }
 
 hipError_t launch_pcg_step_plan(const PcgArgs& a, DType real, const PcgPlan& L, hipStream_t s) {
-  if (active_recorder())
-    return record_launch(RecKind::kPcgStep, a, L.grid, L.block, L.lds, (int)real, L.npt, L.hmax,
-                         [a, real](hipStream_t s2) { return launch_pcg_step(a, real, s2); }, &L.m);
+  if (active_recorder()) {
+    record_launch(RecKind::kPcgStep, a, L.grid, L.block, L.lds, (int)real, L.npt, L.hmax,
+                  [a, real](hipStream_t s2) { return launch_pcg_step(a, real, s2); }, &L.m);
+    return note_volume(a.g.ncell, a.g.nnode, a.sc.iter);
+  }
   if (2 * L.m.nb > L.hmax * (int)L.block) return hipErrorInvalidValue;
   if (real != DType::F64 && real != DType::F32) return hipErrorInvalidValue;
   const bool f64 = real == DType::F64;
@@ -740,26 +742,26 @@ hipError_t launch_pcg_scalars_batch(const void* tab, int n, hipStream_t s) {
 
 hipError_t launch_pcg_step_batch(const void* tab, const MarchGeo* geo, const uint32_t* starts,
                                  int n, unsigned grid, size_t lds, DType real, int max_xl,
-                                 hipStream_t s) {
+                                 int64_t cells, int64_t nodes, int tag, hipStream_t s) {
   const PcgArgs* t = static_cast<const PcgArgs*>(tab);
   const bool whole = max_xl <= 3;
+#define RGP_PCG_B(TR, PF)                                                                     \
+  RGP_LAUNCH_TN(kKindPcgStep, tag, cells, nodes, (k_pcg_step_batch<TR, 256, 1, 2, PF>), grid, \
+                256, lds, s, t, geo, starts, n)
   if (real == DType::F64) {
     if (whole)
-      hipLaunchKernelGGL((k_pcg_step_batch<double, 256, 1, 2, 3>), dim3(grid), dim3(256), lds, s,
-                         t, geo, starts, n);
+      RGP_PCG_B(double, 3);
     else
-      hipLaunchKernelGGL((k_pcg_step_batch<double, 256, 1, 2, 1>), dim3(grid), dim3(256), lds, s,
-                         t, geo, starts, n);
+      RGP_PCG_B(double, 1);
   } else if (real == DType::F32) {
     if (whole)
-      hipLaunchKernelGGL((k_pcg_step_batch<float, 256, 1, 2, 3>), dim3(grid), dim3(256), lds, s,
-                         t, geo, starts, n);
+      RGP_PCG_B(float, 3);
     else
-      hipLaunchKernelGGL((k_pcg_step_batch<float, 256, 1, 2, 1>), dim3(grid), dim3(256), lds, s,
-                         t, geo, starts, n);
+      RGP_PCG_B(float, 1);
   } else {
     return hipErrorInvalidValue;
   }
+#undef RGP_PCG_B
   return hipGetLastError();
 }
 

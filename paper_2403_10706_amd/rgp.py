@@ -61,7 +61,7 @@ EXPORTS = ("rgp_status_string", "rgp_last_hip_error", "rgp_default_opts", "rgp_w
            "rgp_apply_correction", "rgp_correct", "rgp_correct_plan", "rgp_plan_launch",
            "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop", "rgp_loss_grad_images",
            "rgp_batch_workspace_size", "rgp_correct_batch_plan", "rgp_autotune", "rgp_blur_field",
-           "rgp_loss_grad_noalloc")
+           "rgp_loss_grad_noalloc", "rgp_correct_batch")
 
 # rgp_kernel_kind
 KERNEL_PCG_STEP, KERNEL_LOSS_GRAD, KERNEL_TRIAL, KERNEL_HVP, KERNEL_OT, KERNEL_SHIFT, \
@@ -116,11 +116,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rgp_autotune.argtypes = [gp, ctypes.c_int, op, vp, sz, vp, ctypes.POINTER(i32)]
     lib.rgp_correct_batch_plan.argtypes = [i32, gp, ctypes.c_int, vp, vp, ctypes.c_int, op, vp, vp,
                                            vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_void_p)]
+    lib.rgp_correct_batch.argtypes = [i32, gp, ctypes.c_int, vp, vp, ctypes.c_int, op, vp, vp, vp,
+                                      vp, vp, sz, vp]
     lib.rgp_timing_stop.argtypes = [ctypes.POINTER(TimingRecord), i32, ctypes.POINTER(i32)]
     lib.rgp_blur_field.argtypes = [gp, ctypes.c_int, vp, vp, vp]
     for name in ("rgp_blur_field", "rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
                  "rgp_apply_correction", "rgp_correct", "rgp_workspace_size", "rgp_correct_plan",
-                 "rgp_loss_grad_noalloc",
+                 "rgp_loss_grad_noalloc", "rgp_correct_batch",
                  "rgp_plan_launch", "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop",
                  "rgp_loss_grad_images", "rgp_batch_workspace_size", "rgp_correct_batch_plan",
                  "rgp_autotune"):
@@ -556,6 +558,14 @@ class BatchPlan:
             n, self._grids, dtype_code(I_plus[0].dtype), vp[0], vp[1], dtype_code(real_dtype),
             ctypes.byref(self._opts), vp[2], vp[3], vp[4], vp[5], _ptr(self.ws), self.ws.numel(),
             _stream_ptr(stream), ctypes.byref(self._handle)))
+
+    def run_eager(self, stream=None):
+        """The same correction enqueued directly (rgp_correct_batch), without the graph."""
+        vp = [a[0] if a is not None else None for a in self._arrs]
+        _check("rgp_correct_batch", load().rgp_correct_batch(
+            self.n, self._grids, dtype_code(self._keep[0][0].dtype), vp[0], vp[1],
+            dtype_code(self.b[0].dtype), ctypes.byref(self._opts), vp[2], vp[3], vp[4], vp[5],
+            _ptr(self.ws), self.ws.numel(), _stream_ptr(stream or self.stream)))
 
     def launch(self, stream=None):
         _check("rgp_plan_launch", load().rgp_plan_launch(self._handle,
