@@ -700,10 +700,14 @@ def pyramid(Ip, Im, h, levels):
 
 def solve(Ip, Im, pe, h=(1.0, 1.0, 1.0), *, alpha=ALPHA, beta=BETA, levels=1, gn_iters=5,
           pcg_iters=10, pcg_rtol=0.0, armijo_c=1e-4, ls_max_trials=10, ot_eps=1e-3,
-          ot_guard=True, ot_blur=False, b_init=None) -> SolveResult:
+          ot_guard=True, ot_blur=False, b_init=None, solver="gn",
+          lbfgs_memory=10) -> SolveResult:
     """The whole path: pyramid, OT on the coarsest level (or ``b_init`` there), GN-PCG on every
     level coarse to fine with prolongation in between, then the Jacobian-modulation correction
-    (Sec. 2.4.7).  Failures are reported in ``status`` (R27)."""
+    (Sec. 2.4.7).  Failures are reported in ``status`` (R27).  ``solver`` = "lbfgs" runs
+    ``gn_iters`` L-BFGS steps per level instead (Sec. 2.3.3; ``oracle.lbfgs``)."""
+    if solver not in ("gn", "lbfgs"):
+        raise ValueError(solver)
     finite = bool(np.all(np.isfinite(Ip)) and np.all(np.isfinite(Im)))
     status = STATUS_OK if finite else STATUS_NONFINITE
     pyr = pyramid(Ip, Im, h, levels)
@@ -728,9 +732,15 @@ def solve(Ip, Im, pe, h=(1.0, 1.0, 1.0), *, alpha=ALPHA, beta=BETA, levels=1, gn
         if not finite:
             lev.append((P.shape, hh, []))
             continue
-        b, hist = gauss_newton(P, M, b, pe, hh, alpha=alpha, beta=beta, gn_iters=gn_iters,
-                               pcg_iters=pcg_iters, pcg_rtol=pcg_rtol, armijo_c=armijo_c,
-                               ls_max_trials=ls_max_trials)
+        if solver == "lbfgs":
+            from . import lbfgs as _lb
+            b, hist = _lb.lbfgs_level(P, M, b, pe, hh, alpha=alpha, beta=beta, iters=gn_iters,
+                                      memory=lbfgs_memory, armijo_c=armijo_c,
+                                      ls_max_trials=ls_max_trials)
+        else:
+            b, hist = gauss_newton(P, M, b, pe, hh, alpha=alpha, beta=beta, gn_iters=gn_iters,
+                                   pcg_iters=pcg_iters, pcg_rtol=pcg_rtol, armijo_c=armijo_c,
+                                   ls_max_trials=ls_max_trials)
         lev.append((P.shape, hh, hist))
         if status == STATUS_OK and hist:
             if math.isinf(hist[0].J):

@@ -732,3 +732,74 @@ def test_blur_keeps_constants_and_the_total_and_is_separable():
     for ax in range(3):  # three 1D passes with [a, 1, a] / (1 + 2a)
         sep = (a * np.roll(sep, 1, axis=ax) + sep + a * np.roll(sep, -1, axis=ax)) / (1 + 2 * a)
     assert np.max(np.abs(rgp.gaussian_blur3(b) - sep)) < 1e-14
+
+
+# ---- L-BFGS (Sec. 2.3.3) ----------------------------------------------------------------------
+
+def test_lbfgs_two_loop_equals_dense_bfgs_updates():
+    """The two-loop recursion applies the inverse Hessian that the BFGS update formula builds
+    from H0 = (s^T y / y^T y) I of the newest pair, one pair at a time (oldest first):
+    H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T, written out densely."""
+    from oracle import lbfgs as lb
+    rng = np.random.default_rng(70)
+    n, k = 12, 5
+    Q = rng.standard_normal((n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    pairs = []
+    for _ in range(k):
+        s = rng.standard_normal(n)
+        y = A @ s
+        pairs.append((s, y, 1.0 / float(s @ y)))
+    g = rng.standard_normal(n)
+    s_new, y_new, _ = pairs[-1]
+    H = (float(s_new @ y_new) / float(y_new @ y_new)) * np.eye(n)
+    I = np.eye(n)
+    for s, y, rho in pairs:
+        H = (I - rho * np.outer(s, y)) @ H @ (I - rho * np.outer(y, s)) + rho * np.outer(s, s)
+    np.testing.assert_allclose(lb.two_loop(g, pairs), H @ g, rtol=1e-11, atol=1e-12)
+    # the secant condition of the newest pair holds for the dense H
+    np.testing.assert_allclose(H @ y_new, s_new, rtol=1e-10)
+
+
+def test_lbfgs_minimises_a_convex_quadratic():
+    """On f(x) = x^T A x / 2 - c^T x (A SPD, condition ~1e2) the driver with Armijo steps reaches
+    A^{-1} c: a wrong sign of y or s, a dropped pair or a wrong H0 stalls it."""
+    from oracle import lbfgs as lb
+    rng = np.random.default_rng(71)
+    n = 30
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = Q @ np.diag(np.linspace(1.0, 100.0, n)) @ Q.T
+    c = rng.standard_normal(n)
+
+    def fun(x, want_grad=True):
+        J = 0.5 * float(x @ A @ x) - float(c @ x)
+        return J, (A @ x - c if want_grad else None)
+
+    x, hist = lb.lbfgs(fun, np.zeros(n), iters=120, memory=8)
+    np.testing.assert_allclose(x, np.linalg.solve(A, c), rtol=0, atol=1e-7)
+    # every step is accepted until |g|^2 reaches the rounding level of J (the line search then
+    # cannot see a decrease and the run stops there)
+    assert all(h.accepted for h in hist if h.gnorm > 1e-6)
+    assert max(h.pcg_iters for h in hist) == 8        # pairs in use never exceed the memory
+
+
+def test_lbfgs_first_step_and_armijo_invariants():
+    """On the small workload scaled by 1000: the first direction is -g / max|g| (so g.d =
+    -|g|^2 / max|g|), every accepted step satisfies the Armijo condition, J decreases, and the
+    number of pairs grows by one per step up to the memory."""
+    import synth
+    from oracle import lbfgs as lb
+    p = synth.make_workload("c1", scale=1000.0)
+    b0 = np.zeros(rgp.to_cols(np.zeros(p.shape), p.pe).shape[:-1] + (p.shape[p.pe] + 1,))
+    Ipc, Imc = rgp.to_cols(p.I_plus, p.pe), rgp.to_cols(p.I_minus, p.pe)
+    hc = rgp.col_spacing((1.0, 1.0, 1.0), p.pe)
+    _, g0, _ = rgp.objective_gradient_cols(Ipc, Imc, b0, hc)
+    b, hist = lb.lbfgs_cols(Ipc, Imc, b0, hc, iters=12, memory=4)
+    gm = float(np.max(np.abs(g0)))
+    assert hist[0].gq == pytest.approx(-float(np.sum(g0 * g0)) / gm, rel=1e-12)
+    assert hist[0].pcg_relres == pytest.approx(1.0 / gm, rel=1e-15)
+    assert [h.pcg_iters for h in hist] == [0, 1, 2, 3, 4, 4, 4, 4, 4, 4, 4, 4]
+    for a, nxt in zip(hist[:-1], hist[1:]):
+        assert a.accepted
+        assert nxt.J <= a.J + 1e-4 * a.gamma * a.gq
+        assert nxt.J < a.J
