@@ -66,6 +66,12 @@ typedef struct {
   double h[3];
 } rgp_grid;
 
+/* Per-level optimiser of the full solve. */
+typedef enum {
+  RGP_SOLVER_GN = 0,    /* Gauss-Newton with Jacobi-preconditioned CG (Sec. 2.3.1), the default */
+  RGP_SOLVER_LBFGS = 1  /* L-BFGS on the explicit gradient (Sec. 2.3.3) */
+} rgp_solver;
+
 /* Options of the full solve (rgp_correct).  rgp_default_opts() fills the paper's defaults. */
 typedef struct {
   double alpha;          /* smoothness weight (300 in Sec. 2.1) */
@@ -80,6 +86,16 @@ typedef struct {
   int32_t ot_guard;      /* clip OT slopes to +-0.99 and re-integrate (1) */
   int32_t use_b_init;    /* 1: start from b_init on the coarsest level instead of OT */
   int32_t ot_blur;       /* 1: blur the OT field (rgp_blur_field) before the first GN step (0) */
+  int32_t solver;        /* rgp_solver (RGP_SOLVER_GN) */
+  int32_t lbfgs_memory;  /* RGP_SOLVER_LBFGS: curvature pairs kept, 1..32 (10).  With L-BFGS,
+                            gn_iters counts L-BFGS steps per level; pcg_iters and pcg_rtol are
+                            not used.  A step's direction is -H g by the two-loop recursion with
+                            H0 = (s^T y / y^T y) I of the newest pair, a pair is kept only when
+                            s^T y > 1e-10 |s| |y|, and a step without pairs (the first of every
+                            level) takes d = -g / max|g|; the step size is the Armijo search of
+                            the Gauss-Newton solve.  In a stats record the PCG iteration field
+                            holds the pairs used and the PCG residual field holds H0's scale
+                            (1 / max|g| without pairs). */
   int32_t reserved;
 } rgp_solver_opts;
 

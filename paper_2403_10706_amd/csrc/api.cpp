@@ -187,9 +187,17 @@ struct CorrectWs {
   void* R[2];
   void* P[2];
   void* W[2];
+  // L-BFGS only: the gradient of the previous step, the pair rings (mem + 1 slots each) and the
+  // metadata of two consecutive steps
+  void* G2 = nullptr;
+  void* S = nullptr;
+  void* Y = nullptr;
+  LbfgsMeta* meta = nullptr;
 };
 
-CorrectWs carve_correct(void* ws, const Level* lv, int levels, DType real) {
+// Lays the correction's buffers out from ws (a null ws only counts); *bytes: the total size.
+CorrectWs carve_correct(void* ws, const Level* lv, int levels, DType real,
+                        const rgp_solver_opts* o, size_t* bytes = nullptr) {
   Carver c(ws);
   CorrectWs w;
   w.ctl = carve_control(c);
@@ -211,22 +219,20 @@ CorrectWs carve_correct(void* ws, const Level* lv, int levels, DType real) {
     w.P[i] = c.take(nb);
     w.W[i] = c.take(nb);
   }
-  // total recorded in c.off by the caller through carve size
-  (void)c;
+  if (o->solver == RGP_SOLVER_LBFGS) {
+    w.G2 = c.take(nb);
+    w.S = c.take(nb * (size_t)(o->lbfgs_memory + 1));
+    w.Y = c.take(nb * (size_t)(o->lbfgs_memory + 1));
+    w.meta = static_cast<LbfgsMeta*>(c.take(2 * sizeof(LbfgsMeta)));
+  }
+  if (bytes) *bytes = align_up(c.off);
   return w;
 }
 
-size_t correct_bytes(const Level* lv, int levels, DType real) {
-  Carver c(nullptr);
-  carve_control(c);
-  const size_t rs = dsize(real);
-  for (int l = 1; l < levels; ++l) {
-    c.take(lv[l].g.ncell * rs);
-    c.take(lv[l].g.ncell * rs);
-  }
-  const size_t nb = lv[0].g.nnode * rs;
-  for (int i = 0; i < 12; ++i) c.take(nb);
-  return align_up(c.off);
+size_t correct_bytes(const Level* lv, int levels, DType real, const rgp_solver_opts* o) {
+  size_t bytes = 0;
+  carve_correct(nullptr, lv, levels, real, o, &bytes);
+  return bytes;
 }
 
 #define RGP_HIP(call)                          \
@@ -249,7 +255,138 @@ rgp_status check_opts(const rgp_solver_opts* o) {
   if (o->ls_max_trials < 1 || o->ls_max_trials > 10) return RGP_EINVAL;
   if (!(o->pcg_rtol >= 0.0) || !(o->armijo_c >= 0.0) || !(o->ot_eps >= 0.0)) return RGP_EINVAL;
   if (o->ot_blur != 0 && o->ot_blur != 1) return RGP_EINVAL;
+  if (o->solver != RGP_SOLVER_GN && o->solver != RGP_SOLVER_LBFGS) return RGP_EINVAL;
+  if (o->solver == RGP_SOLVER_LBFGS && (o->lbfgs_memory < 1 || o->lbfgs_memory > kLbfgsMaxMem))
+    return RGP_EINVAL;
   return RGP_OK;
+}
+
+// The Armijo passes of one step on the direction in w.X: gamma = 1 alone (it is accepted in most
+// steps), then the remaining candidates 2^-1 .. 2^-9 in one pass; a pass after an accepted step
+// exits at once.
+hipError_t armijo_passes(const CorrectWs& w, const Geom& g, const void* Ip, const void* Im,
+                         DType img, DType real, const rgp_solver_opts* o, const void* b,
+                         const void* grad, double* rec, hipStream_t s) {
+  hipError_t e;
+  const Control& k = w.ctl;
+  int first = 0;
+  const int passes[2] = {1, kMaxTrialCand};
+  for (int p = 0; p < 2 && first < o->ls_max_trials; ++p) {
+    const int nc = std::min(passes[p], o->ls_max_trials - first);
+    TrialArgs ta{};
+    ta.g = g;
+    ta.Ip = Ip;
+    ta.Im = Im;
+    ta.b = b;
+    ta.q = w.X;
+    ta.grad = grad;
+    ta.alpha = o->alpha;
+    ta.beta = o->beta;
+    ta.armijo_c = o->armijo_c;
+    ta.st = k.st;
+    ta.part = k.slot(kPartTrial0 + p);
+    ta.first = first;
+    ta.nc = nc;
+    if ((e = launch_trial(ta, img, real, s)) != hipSuccess) return e;
+    DecideArgs da{};
+    da.part_prev = ta.part;
+    da.nprod_prev = plan_trial(g, real, nc).grid;
+    da.prev_first = first;
+    da.prev_nc = nc;
+    da.total = o->ls_max_trials;
+    da.vol = g.vol;
+    da.alpha = o->alpha;
+    da.beta = o->beta;
+    da.armijo_c = o->armijo_c;
+    da.st = k.st;
+    da.record = rec;
+    if ((e = launch_decide(da, s)) != hipSuccess) return e;
+    first += nc;
+  }
+  return hipSuccess;
+}
+
+// `gn_iters` L-BFGS steps on one level (Sec. 2.3.3).  Each step: the objective and gradient at
+// the current iterate (applying the previous accepted step), the new curvature pair, the two-loop
+// recursion into w.X, and the Armijo passes of the Gauss-Newton solve.  The gradients of
+// consecutive steps alternate between w.G and w.G2.  b enters and leaves in B[cur].
+hipError_t run_level_lbfgs(const CorrectWs& w, const Geom& g, const void* Ip, const void* Im,
+                           DType img, DType real, const rgp_solver_opts* o, int& cur,
+                           double* records, hipStream_t s) {
+  hipError_t e;
+  const Control& k = w.ctl;
+  const Launch Llg = plan_loss_grad(g, real);
+  const unsigned nblk = lbfgs_grid(g.nnode);
+  const int mem = o->lbfgs_memory;
+  void* grads[2] = {w.G, w.G2};
+  for (int it = 0; it < o->gn_iters; ++it) {
+    double* rec = records ? records + (size_t)it * kStatFields : nullptr;
+    void* gcur = grads[it & 1];
+    LossGradArgs la{};
+    la.g = g;
+    la.Ip = Ip;
+    la.Im = Im;
+    la.b_in = w.B[cur];
+    la.q = w.X;
+    la.step = it > 0;
+    la.level_start = it == 0;
+    la.b_out = it > 0 ? w.B[1 - cur] : nullptr;
+    la.grad = gcur;
+    la.alpha = o->alpha;
+    la.beta = o->beta;
+    la.st = k.st;
+    la.part = k.slot(kPartLoss);
+    if ((e = launch_loss_grad(la, img, real, s)) != hipSuccess) return e;
+    if (it > 0) cur = 1 - cur;
+
+    const int np = std::min(it, mem);
+    LbfgsArgs a{};
+    a.n = g.nnode;
+    a.g = gcur;
+    a.g_old = grads[(it + 1) & 1];
+    a.x = w.X;
+    a.S = w.S;
+    a.Y = w.Y;
+    a.meta_prev = w.meta + ((it + 1) & 1);
+    a.meta = w.meta + (it & 1);
+    a.part_max = k.slot(kPartHvp);
+    a.st = k.st;
+    a.mem = mem;
+    a.np = np;
+    a.nprod_in = nblk;
+    int slot = 0;   // partial-sum slot the next kernel writes (they alternate)
+    auto chain = [&](int phase, int j, bool last) -> hipError_t {
+      a.phase = phase;
+      a.j = j;
+      a.last = last ? 1 : 0;
+      a.part_in = k.slot(kPartPcg0 + (1 - slot));
+      a.part_out = k.slot(kPartPcg0 + slot);
+      slot = 1 - slot;
+      return launch_lbfgs(a, real, s);
+    };
+    // the new pair needs gamma of the previous step: before the state is reset below
+    if (it > 0 && (e = chain(kLbPair, 0, false)) != hipSuccess) return e;
+    if ((e = launch_loss_final(LossFinalArgs{k.slot(kPartLoss), Llg.grid, g.vol, o->alpha,
+                                             o->beta, k.st, nullptr, rec, 1},
+                               s)) != hipSuccess)
+      return e;
+    for (int j = 0; j <= np; ++j)
+      if ((e = chain(kLbLoop1, j, false)) != hipSuccess) return e;
+    if ((e = chain(kLbMid, 0, np == 0)) != hipSuccess) return e;
+    for (int t = 1; t <= np; ++t)
+      if ((e = chain(kLbLoop2, t, t == np)) != hipSuccess) return e;
+    if ((e = armijo_passes(w, g, Ip, Im, img, real, o, w.B[cur], gcur, rec, s)) != hipSuccess)
+      return e;
+  }
+  if (o->gn_iters > 0) {
+    ApplyArgs aa{};
+    aa.b = w.B[cur];
+    aa.q = w.X;
+    aa.st = k.st;
+    aa.n = g.nnode;
+    if ((e = launch_apply_step(aa, real, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // `gn_iters` Gauss-Newton steps on one level.  b enters in B[cur]; on return the final field is
@@ -316,42 +453,8 @@ hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const vo
       if ((e = launch_pcg_step(pa, real, s)) != hipSuccess) return e;
     }
 
-    // Armijo passes: gamma = 1 alone (it is accepted in most steps), then the remaining
-    // candidates 2^-1 .. 2^-9 in one pass; a pass after an accepted step exits at once
-    int first = 0;
-    const int passes[2] = {1, kMaxTrialCand};
-    for (int p = 0; p < 2 && first < o->ls_max_trials; ++p) {
-      const int nc = std::min(passes[p], o->ls_max_trials - first);
-      TrialArgs ta{};
-      ta.g = g;
-      ta.Ip = Ip;
-      ta.Im = Im;
-      ta.b = w.B[cur];
-      ta.q = w.X;
-      ta.grad = w.G;
-      ta.alpha = o->alpha;
-      ta.beta = o->beta;
-      ta.armijo_c = o->armijo_c;
-      ta.st = k.st;
-      ta.part = k.slot(kPartTrial0 + p);
-      ta.first = first;
-      ta.nc = nc;
-      if ((e = launch_trial(ta, img, real, s)) != hipSuccess) return e;
-      DecideArgs da{};
-      da.part_prev = ta.part;
-      da.nprod_prev = plan_trial(g, real, nc).grid;
-      da.prev_first = first;
-      da.prev_nc = nc;
-      da.total = o->ls_max_trials;
-      da.vol = g.vol;
-      da.alpha = o->alpha;
-      da.beta = o->beta;
-      da.armijo_c = o->armijo_c;
-      da.st = k.st;
-      da.record = rec;
-      if ((e = launch_decide(da, s)) != hipSuccess) return e;
-      first += nc;
-    }
+    if ((e = armijo_passes(w, g, Ip, Im, img, real, o, w.B[cur], w.G, rec, s)) != hipSuccess)
+      return e;
   }
   if (o->gn_iters > 0) {
     ApplyArgs aa{};
@@ -400,6 +503,8 @@ void rgp_default_opts(rgp_solver_opts* o) {
   o->ot_guard = 1;
   o->use_b_init = 0;
   o->ot_blur = 0;
+  o->solver = RGP_SOLVER_GN;
+  o->lbfgs_memory = 10;
 }
 
 rgp_status rgp_workspace_size(rgp_op op, const rgp_grid* grid, rgp_dtype real_t,
@@ -426,7 +531,7 @@ rgp_status rgp_workspace_size(rgp_op op, const rgp_grid* grid, rgp_dtype real_t,
       if ((st = check_opts(opts)) != RGP_OK) return st;
       Level lv[kMaxLevels];
       if (make_levels(grid, opts->levels, lv) != 0) return RGP_ESHAPE;
-      *bytes = correct_bytes(lv, opts->levels, dr);
+      *bytes = correct_bytes(lv, opts->levels, dr, opts);
       return RGP_OK;
     }
     default:
@@ -775,7 +880,7 @@ rgp_status enqueue_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_
   const int L = opts->levels;
   Level lv[kMaxLevels];
   if (make_levels(grid, L, lv) != 0) return RGP_ESHAPE;
-  CorrectWs w = carve_correct(ws, lv, L, dr);
+  CorrectWs w = carve_correct(ws, lv, L, dr, opts);
   const size_t rs = dsize(dr);
 
   RGP_HIP(launch_reset(SetStateArgs{w.ctl.st, w.ctl.guarded}, s));
@@ -858,7 +963,10 @@ rgp_status enqueue_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_
     double* rec = stats_dev ? stats_dev + RGP_STAT_HEADER +
                                   (size_t)(L - 1 - l) * opts->gn_iters * kStatFields
                             : nullptr;
-    hipError_t e = run_level(w, lv[l].g, imgs[l][0], imgs[l][1], ity[l], dr, opts, cur, rec, s);
+    hipError_t e =
+        opts->solver == RGP_SOLVER_LBFGS
+            ? run_level_lbfgs(w, lv[l].g, imgs[l][0], imgs[l][1], ity[l], dr, opts, cur, rec, s)
+            : run_level(w, lv[l].g, imgs[l][0], imgs[l][1], ity[l], dr, opts, cur, rec, s);
     if (e != hipSuccess) {
       g_last_hip = (int)e;
       return RGP_EHIP;
@@ -1090,7 +1198,7 @@ rgp_status check_batch_grids(int32_t n, const rgp_grid* grids, rgp_dtype real_t,
 size_t pair_bytes(const rgp_grid* g, const rgp_solver_opts* o, DType dr) {
   Level lv[kMaxLevels];
   make_levels(g, o->levels, lv);
-  return align_up(correct_bytes(lv, o->levels, dr));
+  return align_up(correct_bytes(lv, o->levels, dr, o));
 }
 
 // One shared launch of the merged sequence: where its tables sit in the arena.
@@ -1367,7 +1475,7 @@ rgp_status rgp_autotune(const rgp_grid* grid, rgp_dtype real_t, const rgp_solver
   if (cs != hipStreamCaptureStatusNone) return RGP_EINVAL;  // timing needs eager launches
   Level lv[kMaxLevels];
   if (make_levels(grid, o.levels, lv) != 0) return RGP_ESHAPE;
-  const CorrectWs w = carve_correct(ws, lv, o.levels, dr);
+  const CorrectWs w = carve_correct(ws, lv, o.levels, dr, &o);
   // Each candidate runs 2 untimed and kReps timed launches; a timed launch carries its own pair
   // of events, recorded by the launch at the kernel's start and end (kernel time only, whatever
   // the host's launch rate), and the candidate's figure is the median launch.

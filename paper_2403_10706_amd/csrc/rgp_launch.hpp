@@ -270,6 +270,42 @@ bool timing_slot(int kind, int tag, unsigned grid, int64_t cells, int64_t nodes,
 #define RGP_LAUNCH(KIND, G, KERNEL, GRID, BLOCK, LDS, S, ...) \
   RGP_LAUNCH_TN(KIND, 0, (G).ncell, (G).nnode, KERNEL, GRID, BLOCK, LDS, S, __VA_ARGS__)
 
+// L-BFGS direction (lbfgs.hip): pair memory at most kLbfgsMaxMem; a pair is kept when
+// s^T y > kLbfgsCurvature |s| |y|.
+constexpr int kLbfgsMaxMem = 32;
+constexpr double kLbfgsCurvature = 1e-10;
+struct LbfgsMeta {
+  double rho[kLbfgsMaxMem + 1];    // 1 / s^T y per ring slot
+  double alpha[kLbfgsMaxMem + 1];  // first-loop coefficients, by newest-first pair index
+  double h0;                       // s^T y / y^T y of the newest pair kept
+  int32_t head;                    // the free ring slot (the next pair is written there)
+  int32_t count;                   // pairs kept
+};
+enum LbfgsPhase : int32_t { kLbPair = 0, kLbLoop1 = 1, kLbMid = 2, kLbLoop2 = 3 };
+struct LbfgsArgs {
+  int64_t n;                  // field nodes
+  const void* g;              // gradient at the current iterate
+  const void* g_old;          // gradient at the previous iterate (kLbPair)
+  void* x;                    // previous direction (kLbPair); q, r in the loops; d at the end
+  void* S;                    // ring of mem + 1 slots of n values each
+  void* Y;
+  LbfgsMeta* meta_prev;       // metadata of the previous step of the level
+  LbfgsMeta* meta;            // metadata of this step
+  const double* part_in;      // column-major block sums of the previous kernel of the chain
+  unsigned nprod_in;
+  double* part_out;           // this kernel's block sums
+  double* part_max;           // block maxima of |g| (kLbLoop1 j = 0 writes, kLbMid reads)
+  State* st;
+  int32_t mem;                // pairs kept at most
+  int32_t phase;
+  int32_t j;                  // loop index (kLbLoop1: 0..np, kLbLoop2: 1..np)
+  int32_t np;                 // pairs this step can have at most (min(step, mem))
+  int32_t last;               // this kernel ends the chain: it writes d = -r
+  unsigned nblk;              // set by the launcher
+};
+unsigned lbfgs_grid(int64_t n);
+hipError_t launch_lbfgs(const LbfgsArgs& a, DType real, hipStream_t s);
+
 hipError_t launch_loss_grad(const LossGradArgs& a, DType img, DType real, hipStream_t s);
 hipError_t launch_loss_final(const LossFinalArgs& a, hipStream_t s);
 hipError_t launch_trial(const TrialArgs& a, DType img, DType real, hipStream_t s);

@@ -25,6 +25,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "grid extents out of range",
 # Device-side failures of a correction, reported in stats[2] (never returned by a call).
 ENONFINITE, EBARRIER, ELINESEARCH = -4, -5, -6
 F64, F32, BF16 = 0, 1, 2
+SOLVERS = {"gn": 0, "lbfgs": 1}
 OP_OT_INIT, OP_LOSS_GRAD, OP_GN_HVP, OP_PCG_SOLVE, OP_CORRECT, OP_APPLY_CORRECTION = range(6)
 STAT_FIELDS = 12
 STAT_HEADER = 4
@@ -53,6 +54,7 @@ class SolverOpts(ctypes.Structure):
                 ("pcg_rtol", ctypes.c_double), ("armijo_c", ctypes.c_double),
                 ("ot_eps", ctypes.c_double), ("ot_guard", ctypes.c_int32),
                 ("use_b_init", ctypes.c_int32), ("ot_blur", ctypes.c_int32),
+                ("solver", ctypes.c_int32), ("lbfgs_memory", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
@@ -361,6 +363,8 @@ class Options:
     ot_eps: float = 1e-3
     ot_guard: bool = True
     ot_blur: bool = False
+    solver: str = "gn"          # "gn" (Gauss-Newton-PCG) or "lbfgs"
+    lbfgs_memory: int = 10
 
     def to_c(self, use_b_init: bool = False) -> SolverOpts:
         o = SolverOpts()
@@ -371,6 +375,8 @@ class Options:
         o.ot_guard = int(bool(self.ot_guard))
         o.use_b_init = int(bool(use_b_init))
         o.ot_blur = int(bool(self.ot_blur))
+        o.solver = SOLVERS[self.solver]
+        o.lbfgs_memory = int(self.lbfgs_memory)
         return o
 
 

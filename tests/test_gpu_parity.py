@@ -887,3 +887,94 @@ def test_c5_pairs_nonlinear_regime_plain_and_batched():
         assert torch.equal(bp.b[k], alone[k]), i
         _check_against_golden(f"c5 pair {i} batched", golds[k], bp.b[k], bp.T_plus[k],
                               bp.T_minus[k], bp.stats[k], 3, 10, BFINAL_ATOL, "f32")
+
+
+def test_batch_eager_equals_plan():
+    """rgp_correct_batch (the batched correction enqueued without a graph) gives bitwise the
+    fields and statistics of the batched plan's replay."""
+    rgp = _rgp()
+    specs = BATCH_SPECS[:3]
+    pairs = [_pair(sh, pe, seed=80 + i, scale=30.0) for i, (sh, pe) in enumerate(specs)]
+    pes = [pe for _, pe in specs]
+    opts = rgp.Options(levels=2, gn_iters=3, pcg_iters=6, pcg_rtol=0.0)
+    dt = torch.float32
+    Ip = [to_dev(p.I_plus, dt) for p in pairs]
+    Im = [to_dev(p.I_minus, dt) for p in pairs]
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        bp = rgp.BatchPlan(Ip, Im, pes, opts, stream=s, want_stats=True)
+        bp.launch(s)
+        s.synchronize()
+        b_plan = [b.clone() for b in bp.b]
+        st_plan = [t.clone() for t in bp.stats]
+        for b in bp.b:
+            b.fill_(3.0)
+        bp.run_eager(s)
+        s.synchronize()
+    for i in range(len(specs)):
+        assert torch.equal(bp.b[i], b_plan[i]), i
+        assert torch.equal(torch.nan_to_num(bp.stats[i], nan=-1.0),
+                           torch.nan_to_num(st_plan[i], nan=-1.0)), i
+
+
+# ---- L-BFGS as the per-level solver (Sec. 2.3.3) ------------------------------------------------
+
+def _check_lbfgs_records(recs, ref_levels, real):
+    for lv, (_, _, hist) in enumerate(ref_levels):
+        for k, got in enumerate(recs[lv]):
+            if k >= len(hist):
+                assert math.isnan(got["J"]), (lv, k, got)
+                continue
+            w = hist[k]
+            assert (got["accepted"], got["trials"], got["pcg_iters"]) == \
+                (float(w.accepted), float(w.trials), float(w.pcg_iters)), (lv, k, got, w)
+            assert got["gamma"] == w.gamma, (lv, k, got, w)
+            assert got["J"] == pytest.approx(w.J, rel=_tol(real, 1e-10, J_RTOL))
+            # the pair count and H0's scale (1 / max|g| when no pair is kept)
+            assert got["pcg_relres"] == pytest.approx(w.pcg_relres, rel=_tol(real, 1e-9, 1e-3))
+
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
+@pytest.mark.parametrize("scale,levels,iters,memory", [(1.0, 1, 12, 4), (1000.0, 2, 10, 3),
+                                                       (30.0, 1, 25, 10)])
+def test_correct_lbfgs_parity(real, scale, levels, iters, memory):
+    """L-BFGS steps per level instead of Gauss-Newton: the field, and per step the objective,
+    the pairs used, H0's scale, the trial count and the step size, equal the oracle's."""
+    rgp = _rgp()
+    say(f"[lbfgs] real={real} scale={scale} levels={levels} iters={iters} memory={memory}")
+    p = synth.make_workload("c1", scale=scale)
+    dt = REAL[real]
+    Ip, Im = rounded(p.I_plus, dt), rounded(p.I_minus, dt)
+    opts = rgp.Options(levels=levels, gn_iters=iters, solver="lbfgs", lbfgs_memory=memory)
+    out = rgp.correct(to_dev(Ip, dt), to_dev(Im, dt), p.pe, opts=opts)
+    ref = orc.solve(Ip, Im, p.pe, levels=levels, gn_iters=iters, solver="lbfgs",
+                    lbfgs_memory=memory)
+    head, recs = rgp.parse_stats(out["stats"], levels, iters)
+    assert head["status"] == ref.status
+    _check_lbfgs_records(recs, ref.levels, real)
+    err = float(np.max(np.abs(to_host(out["b"]) - ref.b)))
+    say(f"[lbfgs] max|b - b_oracle| = {err:.3e} voxel (max|b| {np.abs(ref.b).max():.3f})")
+    assert err <= _tol(real, 1e-8, BFINAL_ATOL), err
+
+
+def test_batch_plan_lbfgs_matches_per_pair():
+    """The batched plan with L-BFGS levels (the L-BFGS kernels run pair by pair inside the shared
+    graph) gives every pair bitwise its per-pair result."""
+    rgp = _rgp()
+    specs = BATCH_SPECS[:3]
+    pairs = [_pair(sh, pe, seed=90 + i, scale=30.0) for i, (sh, pe) in enumerate(specs)]
+    pes = [pe for _, pe in specs]
+    opts = rgp.Options(levels=2, gn_iters=6, solver="lbfgs", lbfgs_memory=3)
+    dt = torch.float32
+    Ip = [to_dev(p.I_plus, dt) for p in pairs]
+    Im = [to_dev(p.I_minus, dt) for p in pairs]
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        bp = rgp.BatchPlan(Ip, Im, pes, opts, stream=s)
+        bp.launch(s)
+        s.synchronize()
+    for i, (sh, pe) in enumerate(specs):
+        ref = rgp.correct(Ip[i], Im[i], pe, opts=opts, real_dtype=dt)
+        assert torch.equal(bp.b[i], ref["b"]), i
