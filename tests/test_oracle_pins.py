@@ -803,3 +803,65 @@ def test_lbfgs_first_step_and_armijo_invariants():
         assert a.accepted
         assert nxt.J <= a.J + 1e-4 * a.gamma * a.gq
         assert nxt.J < a.J
+
+
+# ---- least-squares correction (Sec. 2.4.7) ----------------------------------------------------
+
+def test_lsq_push_forward_is_the_distortion_model():
+    """The push-forward matrix applied to the true image reproduces the synthetic distortion of
+    the input generator (an independent implementation through cumulative mass and np.interp),
+    for both polarities, and its transpose is its adjoint."""
+    import synth
+    from synth.phantom import push_forward
+    from oracle import lsq
+    p = synth.make_workload("c1")
+    bc, xc = rgp.to_cols(p.b_true, p.pe), rgp.to_cols(p.I_true, p.pe)
+    for sign in (1.0, -1.0):
+        ref = push_forward(p.I_true, p.b_true, p.pe, p.h, sign)
+        got = rgp.from_cols(lsq.push(bc, xc, 1.0, sign), p.pe)
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
+        u = np.random.default_rng(72).standard_normal(xc.shape)
+        lhs = float(np.sum(lsq.push(bc, xc, 1.0, sign) * u))
+        rhs = float(np.sum(xc * lsq.push_T(bc, u, 1.0, sign)))
+        assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_lsq_recovers_the_true_image_from_a_noise_free_pair():
+    """Both acquisitions synthesised from a known image and field without noise: the
+    least-squares correction with that field gives the image back."""
+    import synth
+    from synth.phantom import push_forward
+    from oracle import lsq
+    p = synth.make_workload("c1")
+    Ip = push_forward(p.I_true, p.b_true, p.pe, p.h, 1.0)
+    Im = push_forward(p.I_true, p.b_true, p.pe, p.h, -1.0)
+    x, it = lsq.lsq_correct(Ip, Im, p.b_true, p.pe, maxit=200, rtol=1e-13)
+    np.testing.assert_allclose(x, p.I_true, rtol=0, atol=1e-9 * np.abs(p.I_true).max())
+
+
+def test_lsq_cgls_equals_dense_least_squares_and_zero_field():
+    """On a tiny grid CGLS run to convergence equals np.linalg.lstsq on the dense stacked
+    push-forward matrices of every column; with b = 0 both matrices are the identity and the
+    solution is the mean of the two images after one iteration."""
+    from oracle import lsq
+    rng = np.random.default_rng(73)
+    shape, pe = (3, 9, 4), 1
+    b = 0.7 * rng.standard_normal((3, 10, 4))
+    b *= 0.8 / np.max(np.abs(np.diff(b, axis=pe)))
+    Ip, Im = rng.uniform(0, 1, shape), rng.uniform(0, 1, shape)
+    x, _ = lsq.lsq_correct(Ip, Im, b, pe, maxit=60, rtol=1e-15)
+    bc, xc = rgp.to_cols(b, pe), rgp.to_cols(x, pe)
+    Pc, Mc = rgp.to_cols(Ip, pe), rgp.to_cols(Im, pe)
+    m = shape[pe]
+    E = np.eye(m)
+    for a in range(bc.shape[0]):
+        for c in range(bc.shape[1]):
+            col = bc[a, c]
+            Mp = np.stack([lsq.push(col[None], E[j][None], 1.0, 1.0)[0] for j in range(m)], 1)
+            Mm = np.stack([lsq.push(col[None], E[j][None], 1.0, -1.0)[0] for j in range(m)], 1)
+            A = np.vstack([Mp, Mm])
+            ref = np.linalg.lstsq(A, np.concatenate([Pc[a, c], Mc[a, c]]), rcond=None)[0]
+            np.testing.assert_allclose(xc[a, c], ref, rtol=0, atol=1e-10)
+    x0, it0 = lsq.lsq_correct(Ip, Im, np.zeros_like(b), pe, maxit=5, rtol=1e-12)
+    np.testing.assert_allclose(x0, 0.5 * (Ip + Im), rtol=0, atol=1e-14)
+    assert int(it0.max()) == 1
