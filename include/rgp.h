@@ -217,6 +217,22 @@ rgp_status rgp_apply_correction(const rgp_grid* grid, rgp_dtype img_t, const voi
                                 const void* I_minus, rgp_dtype real_t, const void* b,
                                 void* T_plus, void* T_minus, void* stream);
 
+/* Least-squares correction (Sec. 2.4.7): one corrected image from both inputs and the field.
+ * Per PE column the field defines the push-forward matrices M+ and M- that carry a true image to
+ * the two distorted ones - the mass-conserving remap of the distortion model: true cell j (between
+ * the nodes x_j and x_{j+1}) moves to [x_j +- b_j, x_{j+1} +- b_{j+1}], its mass spread evenly
+ * there and integrated over the output cells, mass leaving the column lost - and I_out minimises
+ * |M+ I - I+|^2 + |M- I - I-|^2, found by CGLS from I = 0: at most maxit (1..100000)
+ * iterations, a column stopping when |M^T r| < rtol |M^T [I+; I-]| or when its search direction
+ * vanishes.  I_out: cell array of img_t (written in full); iters_dev: nullable device int32 array
+ * of one count per column, columns numbered by their two cross-axis indices in the arrays' order
+ * (slower axis first).  Needs |d_v b| < 1 (else the output is unspecified, finite writes only).
+ * Columns of more than 2340 cells (FP32 field) or 1170 cells (FP64) give RGP_ESHAPE.  Enqueued on
+ * `stream`; needs no workspace. */
+rgp_status rgp_correct_lsq(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                           const void* I_minus, rgp_dtype real_t, const void* b, int32_t maxit,
+                           double rtol, void* I_out, int32_t* iters_dev, void* stream);
+
 /* The whole hot path: image pyramid (2x2x2 means, `levels` levels), OT initialisation on the
  * coarsest level (or b_init there when opts->use_b_init; b_init has the coarsest level's
  * staggered shape), then on every level from coarse to fine `gn_iters` Gauss-Newton steps

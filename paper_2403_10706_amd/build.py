@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librgp.so")
 
-SOURCES = ["api.cpp", "loss.hip", "pcg.hip", "ot.hip", "pyramid.hip", "lbfgs.hip"]
+SOURCES = ["api.cpp", "loss.hip", "pcg.hip", "ot.hip", "pyramid.hip", "lbfgs.hip", "lsq.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -822,6 +822,29 @@ rgp_status rgp_loss_grad_images(const rgp_grid* grid, rgp_dtype img_t, const voi
   return RGP_OK;
 }
 
+rgp_status rgp_correct_lsq(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
+                           const void* I_minus, rgp_dtype real_t, const void* b, int32_t maxit,
+                           double rtol, void* I_out, int32_t* iters_dev, void* stream) {
+  rgp_status st = check_grid(grid);
+  if (st != RGP_OK) return st;
+  DType di, dr;
+  if ((st = check_types(img_t, real_t, &di, &dr)) != RGP_OK) return st;
+  if (!I_plus || !I_minus || !b || !I_out || maxit < 1 || maxit > 100000 || !(rtol >= 0.0))
+    return RGP_EINVAL;
+  if (lsq_cols_per_block((int)grid->m[grid->pe], dr) < 1) return RGP_ESHAPE;
+  LsqArgs la{};
+  la.g = geom_of(grid);
+  la.Ip = I_plus;
+  la.Im = I_minus;
+  la.b = b;
+  la.I_out = I_out;
+  la.iters = iters_dev;
+  la.maxit = maxit;
+  la.rtol = rtol;
+  RGP_HIP(launch_lsq(la, di, dr, static_cast<hipStream_t>(stream)));
+  return RGP_OK;
+}
+
 rgp_status rgp_apply_correction(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus,
                                 const void* I_minus, rgp_dtype real_t, const void* b,
                                 void* T_plus, void* T_minus, void* stream) {

@@ -738,22 +738,6 @@ Launch plan_trial(const Geom& g, DType real, int nc) {
   return L;
 }
 
-#define RGP_DISPATCH_TYPES(IMG, REAL, ...)                                              \
-  do {                                                                                  \
-    if ((REAL) == DType::F64 && (IMG) == DType::F64) {                                  \
-      using TI = double; using TR = double; __VA_ARGS__;                                \
-    } else if ((REAL) == DType::F32 && (IMG) == DType::F32) {                           \
-      using TI = float; using TR = float; __VA_ARGS__;                                  \
-    } else if ((REAL) == DType::F32 && (IMG) == DType::BF16) {                          \
-      using TI = bf16_t; using TR = float; __VA_ARGS__;                                 \
-    } else if ((REAL) == DType::F64 && (IMG) == DType::F32) {                           \
-      using TI = float; using TR = double; __VA_ARGS__;                                 \
-    } else if ((REAL) == DType::F64 && (IMG) == DType::BF16) {                          \
-      using TI = bf16_t; using TR = double; __VA_ARGS__;                                \
-    } else {                                                                            \
-      return hipErrorInvalidValue;                                                      \
-    }                                                                                   \
-  } while (0)
 
 hipError_t launch_loss_grad(const LossGradArgs& a0, DType img, DType real, hipStream_t s) {
   const Launch L = plan_loss_grad(a0.g, real);

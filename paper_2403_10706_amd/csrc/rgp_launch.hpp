@@ -304,7 +304,41 @@ struct LbfgsArgs {
   unsigned nblk;              // set by the launcher
 };
 unsigned lbfgs_grid(int64_t n);
+
+// Least-squares correction (lsq.hip).
+struct LsqArgs {
+  Geom g;
+  const void* Ip;
+  const void* Im;
+  const void* b;
+  void* I_out;
+  int32_t* iters;        // per column (nullable)
+  int32_t maxit;
+  double rtol;
+  int32_t cols_per_block;  // set by the launcher
+};
+int lsq_cols_per_block(int mp, DType real);
+hipError_t launch_lsq(const LsqArgs& a, DType img, DType real, hipStream_t s);
 hipError_t launch_lbfgs(const LbfgsArgs& a, DType real, hipStream_t s);
+
+// Runs __VA_ARGS__ with TI (image storage type) and TR (arithmetic type) bound to the supported
+// combinations; returns hipErrorInvalidValue from the caller otherwise.
+#define RGP_DISPATCH_TYPES(IMG, REAL, ...)                                              \
+  do {                                                                                  \
+    if ((REAL) == DType::F64 && (IMG) == DType::F64) {                                  \
+      using TI = double; using TR = double; __VA_ARGS__;                                \
+    } else if ((REAL) == DType::F32 && (IMG) == DType::F32) {                           \
+      using TI = float; using TR = float; __VA_ARGS__;                                  \
+    } else if ((REAL) == DType::F32 && (IMG) == DType::BF16) {                          \
+      using TI = bf16_t; using TR = float; __VA_ARGS__;                                 \
+    } else if ((REAL) == DType::F64 && (IMG) == DType::F32) {                           \
+      using TI = float; using TR = double; __VA_ARGS__;                                 \
+    } else if ((REAL) == DType::F64 && (IMG) == DType::BF16) {                          \
+      using TI = bf16_t; using TR = double; __VA_ARGS__;                                \
+    } else {                                                                            \
+      return hipErrorInvalidValue;                                                      \
+    }                                                                                   \
+  } while (0)
 
 hipError_t launch_loss_grad(const LossGradArgs& a, DType img, DType real, hipStream_t s);
 hipError_t launch_loss_final(const LossFinalArgs& a, hipStream_t s);

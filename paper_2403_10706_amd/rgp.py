@@ -63,7 +63,7 @@ EXPORTS = ("rgp_status_string", "rgp_last_hip_error", "rgp_default_opts", "rgp_w
            "rgp_apply_correction", "rgp_correct", "rgp_correct_plan", "rgp_plan_launch",
            "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop", "rgp_loss_grad_images",
            "rgp_batch_workspace_size", "rgp_correct_batch_plan", "rgp_autotune", "rgp_blur_field",
-           "rgp_loss_grad_noalloc", "rgp_correct_batch")
+           "rgp_loss_grad_noalloc", "rgp_correct_batch", "rgp_correct_lsq")
 
 # rgp_kernel_kind
 KERNEL_PCG_STEP, KERNEL_LOSS_GRAD, KERNEL_TRIAL, KERNEL_HVP, KERNEL_OT, KERNEL_SHIFT, \
@@ -120,11 +120,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                            vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_void_p)]
     lib.rgp_correct_batch.argtypes = [i32, gp, ctypes.c_int, vp, vp, ctypes.c_int, op, vp, vp, vp,
                                       vp, vp, sz, vp]
+    lib.rgp_correct_lsq.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int, vp, i32, f64, vp, vp,
+                                    vp]
     lib.rgp_timing_stop.argtypes = [ctypes.POINTER(TimingRecord), i32, ctypes.POINTER(i32)]
     lib.rgp_blur_field.argtypes = [gp, ctypes.c_int, vp, vp, vp]
     for name in ("rgp_blur_field", "rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
                  "rgp_apply_correction", "rgp_correct", "rgp_workspace_size", "rgp_correct_plan",
-                 "rgp_loss_grad_noalloc", "rgp_correct_batch",
+                 "rgp_loss_grad_noalloc", "rgp_correct_batch", "rgp_correct_lsq",
                  "rgp_plan_launch", "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop",
                  "rgp_loss_grad_images", "rgp_batch_workspace_size", "rgp_correct_batch_plan",
                  "rgp_autotune"):
@@ -334,6 +336,23 @@ def pcg_solve(hdiag, hoff, rhs, shape, pe, h=(1.0, 1.0, 1.0), alpha=300.0, *, ma
         _ptr(x), int(maxit), float(rtol), _ptr(it), _ptr(rr), _ptr(wsb), wsb.numel(),
         _stream_ptr(stream)))
     return x, it, rr
+
+
+def correct_lsq(I_plus, I_minus, b, pe, h=(1.0, 1.0, 1.0), *, maxit=30, rtol=1e-6,
+                want_iters=True, stream=None):
+    """Least-squares corrected image (rgp_correct_lsq) in the images' dtype, and the CGLS
+    iterations per column (int32 device tensor of the two cross-axis extents) or None."""
+    _dev_check(I_plus, I_minus, b)
+    shape = tuple(I_plus.shape)
+    out = torch.empty_like(I_plus)
+    cross = tuple(n for d, n in enumerate(shape) if d != pe)
+    it = torch.empty(cross, dtype=torch.int32, device=b.device) if want_iters else None
+    g = make_grid(shape, pe, h)
+    _check("rgp_correct_lsq", load().rgp_correct_lsq(
+        ctypes.byref(g), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
+        dtype_code(b.dtype), _ptr(b), int(maxit), float(rtol), _ptr(out), _ptr(it),
+        _stream_ptr(stream)))
+    return out, it
 
 
 def apply_correction(I_plus, I_minus, b, pe, h=(1.0, 1.0, 1.0), *, stream=None):

@@ -978,3 +978,87 @@ def test_batch_plan_lbfgs_matches_per_pair():
     for i, (sh, pe) in enumerate(specs):
         ref = rgp.correct(Ip[i], Im[i], pe, opts=opts, real_dtype=dt)
         assert torch.equal(bp.b[i], ref["b"]), i
+
+
+# ---- least-squares correction (Sec. 2.4.7) ----------------------------------------------------
+
+LSQ_CASES = [((32, 32, 24), 1), ((37, 29, 23), 0), ((19, 26, 41), 2), ((70, 9, 130), 0)]
+
+
+@pytest.mark.parametrize("img,real", [("f64", "f64"), ("f32", "f32"), ("bf16", "f32")])
+@pytest.mark.parametrize("shape,pe", LSQ_CASES)
+def test_correct_lsq_parity(shape, pe, img, real):
+    """The least-squares corrected image and the CGLS iterations of every column against the
+    oracle's, on a noisy pair with its true field: a fixed iteration count (rtol 0) and a
+    relative-residual stop."""
+    from oracle import lsq as olsq
+    rgp = _rgp()
+    say(f"[lsq] shape={shape} pe={pe} img={img} real={real}")
+    p = _pair(shape, pe, seed=17)
+    it_t, dt = IMG[img], REAL[real]
+    Ip, Im = rounded(p.I_plus, it_t), rounded(p.I_minus, it_t)
+    b = rounded(p.b_true, dt)
+    for maxit, rtol in ((12, 0.0), (200, 1e-5)):
+        out, its = rgp.correct_lsq(to_dev(Ip, it_t), to_dev(Im, it_t), to_dev(b, dt), pe,
+                                   maxit=maxit, rtol=rtol)
+        ref, ref_it = olsq.lsq_correct(Ip, Im, b, pe, maxit=maxit, rtol=rtol)
+        err = rel2(to_host(out), ref)
+        nit = to_host(its).astype(np.int64)
+        say(f"[lsq] maxit={maxit} rtol={rtol}: |I - I_oracle|/|I_oracle| = {err:.2e}; "
+            f"iterations max {nit.max()} (oracle {ref_it.max()}), columns differing "
+            f"{int(np.sum(nit != ref_it))}")
+        if real == "f64":
+            assert err <= 1e-10
+            assert np.array_equal(nit, ref_it)
+        else:
+            bar = 2.0 ** -8 if img == "bf16" else VEC_RTOL   # BF16 output storage rounds 2^-9
+            assert err <= bar, err
+            if rtol == 0.0:
+                assert np.array_equal(nit, ref_it)
+            else:   # a column near its stop threshold may stop one iteration apart
+                assert np.max(np.abs(nit - ref_it)) <= 1 and np.mean(nit != ref_it) <= 0.02
+
+
+def test_correct_lsq_recovers_true_image_and_zero_field():
+    """Noise-free pair: the device's least-squares correction gives the true image back; with
+    b = 0 it is the mean of the two images after one iteration."""
+    from synth.phantom import push_forward
+    rgp = _rgp()
+    p = synth.make_workload("c2")
+    Ip = push_forward(p.I_true, p.b_true, p.pe, p.h, 1.0)
+    Im = push_forward(p.I_true, p.b_true, p.pe, p.h, -1.0)
+    dt = torch.float32
+    out, its = rgp.correct_lsq(to_dev(Ip, dt), to_dev(Im, dt), to_dev(p.b_true, dt), p.pe,
+                               maxit=300, rtol=1e-7)
+    err = float(np.max(np.abs(to_host(out) - p.I_true))) / float(np.abs(p.I_true).max())
+    say(f"[lsq c2 noise-free] max|I - I_true| / max|I_true| = {err:.2e}, iterations max "
+        f"{int(to_host(its).max())}")
+    assert err <= 1e-4
+    z = torch.zeros(rgp.field_shape(p.shape, p.pe), dtype=dt, device="cuda")
+    out0, its0 = rgp.correct_lsq(to_dev(Ip, dt), to_dev(Im, dt), z, p.pe, maxit=5, rtol=1e-6)
+    mean = 0.5 * (to_dev(Ip, dt) + to_dev(Im, dt))
+    assert float(torch.max(torch.abs(out0 - mean))) <= 1e-6 * float(torch.max(torch.abs(mean)))
+    assert int(its0.max()) == 1
+
+
+def test_correct_lsq_c2_sampled_columns():
+    """144x168x111 with the noisy pair and its true field, FP32, 30 CGLS iterations: 512 seeded
+    columns against the oracle run on those columns alone."""
+    from oracle import lsq as olsq
+    rgp = _rgp()
+    p = synth.make_workload("c2")
+    dt = torch.float32
+    Ip, Im, b = rounded(p.I_plus, dt), rounded(p.I_minus, dt), rounded(p.b_true, dt)
+    out, its = rgp.correct_lsq(to_dev(Ip, dt), to_dev(Im, dt), to_dev(b, dt), p.pe, maxit=30,
+                               rtol=0.0)
+    Pc, Mc, bc = orc.to_cols(Ip, p.pe), orc.to_cols(Im, p.pe), orc.to_cols(b, p.pe)
+    oc = orc.to_cols(to_host(out), p.pe)
+    rng = np.random.default_rng(512)
+    flat = rng.choice(Pc.shape[0] * Pc.shape[1], size=512, replace=False)
+    ia, ib = np.unravel_index(flat, Pc.shape[:2])
+    ref, ref_it = olsq.lsq_cols(Pc[ia, ib][None], Mc[ia, ib][None], bc[ia, ib][None], 1.0,
+                                maxit=30, rtol=0.0)
+    err = rel2(oc[ia, ib], ref[0])
+    say(f"[lsq c2 sampled] |I - I_oracle|/|I_oracle| over 512 columns = {err:.2e}")
+    assert err <= VEC_RTOL
+    assert np.array_equal(to_host(its).astype(np.int64)[ia, ib], ref_it[0])
