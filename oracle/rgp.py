@@ -701,12 +701,13 @@ def pyramid(Ip, Im, h, levels):
 def solve(Ip, Im, pe, h=(1.0, 1.0, 1.0), *, alpha=ALPHA, beta=BETA, levels=1, gn_iters=5,
           pcg_iters=10, pcg_rtol=0.0, armijo_c=1e-4, ls_max_trials=10, ot_eps=1e-3,
           ot_guard=True, ot_blur=False, b_init=None, solver="gn",
-          lbfgs_memory=10) -> SolveResult:
+          lbfgs_memory=10, admm_rho0=None) -> SolveResult:
     """The whole path: pyramid, OT on the coarsest level (or ``b_init`` there), GN-PCG on every
     level coarse to fine with prolongation in between, then the Jacobian-modulation correction
     (Sec. 2.4.7).  Failures are reported in ``status`` (R27).  ``solver`` = "lbfgs" runs
-    ``gn_iters`` L-BFGS steps per level instead (Sec. 2.3.3; ``oracle.lbfgs``)."""
-    if solver not in ("gn", "lbfgs"):
+    ``gn_iters`` L-BFGS steps per level instead (Sec. 2.3.3; ``oracle.lbfgs``), "admm"
+    ``gn_iters`` ADMM iterations (Sec. 2.3.2; ``oracle.admm``; PCG settings per column)."""
+    if solver not in ("gn", "lbfgs", "admm"):
         raise ValueError(solver)
     finite = bool(np.all(np.isfinite(Ip)) and np.all(np.isfinite(Im)))
     status = STATUS_OK if finite else STATUS_NONFINITE
@@ -732,7 +733,12 @@ def solve(Ip, Im, pe, h=(1.0, 1.0, 1.0), *, alpha=ALPHA, beta=BETA, levels=1, gn
         if not finite:
             lev.append((P.shape, hh, []))
             continue
-        if solver == "lbfgs":
+        if solver == "admm":
+            from . import admm as _ad
+            b, hist = _ad.admm_level(P, M, b, pe, hh, alpha=alpha, beta=beta, iters=gn_iters,
+                                     pcg_iters=pcg_iters, pcg_rtol=pcg_rtol, rho0=admm_rho0,
+                                     armijo_c=armijo_c, ls_max_trials=ls_max_trials)
+        elif solver == "lbfgs":
             from . import lbfgs as _lb
             b, hist = _lb.lbfgs_level(P, M, b, pe, hh, alpha=alpha, beta=beta, iters=gn_iters,
                                       memory=lbfgs_memory, armijo_c=armijo_c,

@@ -865,3 +865,122 @@ def test_lsq_cgls_equals_dense_least_squares_and_zero_field():
     x0, it0 = lsq.lsq_correct(Ip, Im, np.zeros_like(b), pe, maxit=5, rtol=1e-12)
     np.testing.assert_allclose(x0, 0.5 * (Ip + Im), rtol=0, atol=1e-14)
     assert int(it0.max()) == 1
+
+
+# ---- ADMM (Sec. 2.3.2, Eq. 8-11) --------------------------------------------------------------
+
+def _dense_pe_laplacian(bshape, hp):
+    """Neumann second differences along the last (PE) axis, written out densely."""
+    n = int(np.prod(bshape))
+    L = np.zeros((n, n))
+    idx = np.arange(n).reshape(bshape)
+    m1 = bshape[-1]
+    for k in range(m1 - 1):
+        a, b = idx[..., k].ravel(), idx[..., k + 1].ravel()
+        L[a, a] += 1.0 / hp ** 2
+        L[b, b] += 1.0 / hp ** 2
+        L[a, b] -= 1.0 / hp ** 2
+        L[b, a] -= 1.0 / hp ** 2
+    return L
+
+
+def test_admm_b_update_gradient_and_bands_dense():
+    """F_rho = D + alpha S3 + beta P + (rho vol / 2)|b - c|^2: its gradient and Gauss-Newton
+    bands equal the plain-loop data and barrier parts (alpha = 0) plus a densely written PE
+    Laplacian and the proximal identity; its value matches the plain-loop objective plus those
+    terms; the bands are tridiagonal per column."""
+    from oracle import admm
+    Ip, Im, b, hc = _tiny(12, shape=(3, 4, 6), base=0.7, amp=0.25)
+    rng = np.random.default_rng(74)
+    c = b + 0.05 * rng.standard_normal(b.shape)
+    rho = 37.0
+    vol = hc[0] * hc[1] * hc[2]
+    L3 = _dense_pe_laplacian(b.shape, hc[2])
+    g, dg, of = admm.f_rho_gradient(Ip, Im, b, hc, c, rho, ALPHA, BETA)
+    gref = loops.gradient(Ip, Im, b, hc, 0.0, BETA).ravel() + ALPHA * vol * L3 @ b.ravel() \
+        + rho * vol * (b - c).ravel()
+    assert np.linalg.norm(g.ravel() - gref) <= 1e-13 * np.linalg.norm(gref)
+    H = loops.gn_hessian(Ip, Im, b, hc, 0.0, BETA) + ALPHA * vol * L3 + rho * vol * np.eye(b.size)
+    v = rng.standard_normal(b.shape)
+    np.testing.assert_allclose(admm.tri_matvec(dg, of, v).ravel(), H @ v.ravel(), rtol=1e-12,
+                               atol=1e-12 * np.abs(H).max())
+    np.testing.assert_allclose(dg.ravel(), np.diag(H), rtol=1e-13)
+    J, D, Sp, P = admm.f_rho(Ip, Im, b, hc, c, rho, ALPHA, BETA)
+    Jl, Dl, _, Pl = loops.objective(Ip, Im, b, hc, ALPHA, BETA)
+    s3 = 0.5 * vol * float(b.ravel() @ L3 @ b.ravel())
+    prox = 0.5 * rho * vol * float(np.sum((b - c) ** 2))
+    assert J == pytest.approx(Dl + ALPHA * s3 + BETA * Pl + prox, rel=1e-13)
+    assert ALPHA * Sp == pytest.approx(ALPHA * s3 + prox, rel=1e-13)
+
+
+def test_admm_z_update_equals_dense_solve_of_the_periodic_problem():
+    """The FFT z-update solves (alpha L12 + rho I) z = rho v, with L12 the Hessian of
+    G / (alpha vol) recovered from G's values (G is quadratic: A_ij = G(e_i + e_j) - G(e_i) -
+    G(e_j)); the periodic differences are those of the definition, extents 1, 2 and 5 included."""
+    from oracle import admm
+    rng = np.random.default_rng(75)
+    hc = (1.3, 0.8, 1.1)
+    vol = hc[0] * hc[1] * hc[2]
+    for shape in ((5, 4, 3), (1, 3, 2), (2, 5, 2)):
+        n = int(np.prod(shape))
+        E = np.eye(n)
+        Gd = np.array([admm.g_value(E[i].reshape(shape), hc, 1.0) for i in range(n)])
+        A = np.zeros((n, n))
+        for i in range(n):
+            for j in range(n):
+                A[i, j] = admm.g_value((E[i] + E[j]).reshape(shape), hc, 1.0) - Gd[i] - Gd[j]
+        v = rng.standard_normal(shape)
+        rho, alpha = 3.7, 2.0
+        z = np.linalg.solve(alpha * A / vol + rho * np.eye(n), rho * v.ravel())
+        np.testing.assert_allclose(admm.z_update(v, rho, alpha, hc).ravel(), z, rtol=1e-12,
+                                   atol=1e-12)
+
+
+def test_admm_block_pcg_per_column_and_dense_solves():
+    """BlockPCG run to convergence equals the dense solve of every column's tridiagonal system;
+    a column's result does not depend on the other columns (a change to one leaves the rest)."""
+    from oracle import admm
+    rng = np.random.default_rng(76)
+    shape = (3, 4, 9)
+    off = -0.4 - 0.2 * rng.uniform(size=shape)
+    off[..., -1] = 0.0
+    diag = 2.5 + rng.uniform(size=shape)
+    rhs = rng.standard_normal(shape)
+    x, its, rel = admm.block_pcg(diag, off, rhs, 50, 1e-14)
+    for a in range(3):
+        for c in range(4):
+            T = np.diag(diag[a, c]) + np.diag(off[a, c, :-1], 1) + np.diag(off[a, c, :-1], -1)
+            np.testing.assert_allclose(x[a, c], np.linalg.solve(T, rhs[a, c]), rtol=1e-11,
+                                       atol=1e-12)
+    rhs2 = rhs.copy()
+    rhs2[1, 2] *= 3.0
+    x2, _, _ = admm.block_pcg(diag, off, rhs2, 3, 0.0)
+    x3, _, _ = admm.block_pcg(diag, off, rhs, 3, 0.0)
+    mask = np.ones((3, 4), bool)
+    mask[1, 2] = False
+    np.testing.assert_array_equal(x2[mask], x3[mask])
+
+
+def test_admm_reaches_a_stationary_point_of_the_split_objective():
+    """Many ADMM iterations on the small workload (images x30) from b = 0 drive the gradient of
+    D + alpha (S3 + periodic S1 + S2) + beta P - the objective the splitting minimises - to below
+    1/200 of its initial norm; rho changes only by factors of 2."""
+    import synth
+    from oracle import admm
+    p = synth.make_workload("c1", scale=30.0)
+    Ipc, Imc = rgp.to_cols(p.I_plus, p.pe), rgp.to_cols(p.I_minus, p.pe)
+    hc = rgp.col_spacing((1.0, 1.0, 1.0), p.pe)
+    vol = hc[0] * hc[1] * hc[2]
+
+    def grad(b):
+        _, g, _ = rgp.objective_gradient_cols(Ipc, Imc, b, hc)
+        return (g - ALPHA * vol * rgp.laplacian(b, hc) + ALPHA * vol * admm.pe_laplacian(b, hc[2])
+                + ALPHA * vol * admm.cross_laplacian_periodic(b, hc))
+
+    b0 = np.zeros(Ipc.shape[:-1] + (Ipc.shape[-1] + 1,))
+    b, hist = admm.admm_cols(Ipc, Imc, b0, hc, iters=200, pcg_iters=10, pcg_rtol=0.1)
+    assert all(h.accepted for h in hist)
+    assert np.linalg.norm(grad(b)) <= 5e-3 * np.linalg.norm(grad(b0))
+    rhos = np.array([h.rho for h in hist])
+    ratio = rhos[1:] / rhos[:-1]
+    assert np.all(np.isin(ratio, [0.5, 1.0, 2.0])) and np.any(ratio != 1.0)
