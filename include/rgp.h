@@ -69,7 +69,8 @@ typedef struct {
 /* Per-level optimiser of the full solve. */
 typedef enum {
   RGP_SOLVER_GN = 0,    /* Gauss-Newton with Jacobi-preconditioned CG (Sec. 2.3.1), the default */
-  RGP_SOLVER_LBFGS = 1  /* L-BFGS on the explicit gradient (Sec. 2.3.3) */
+  RGP_SOLVER_LBFGS = 1, /* L-BFGS on the explicit gradient (Sec. 2.3.3) */
+  RGP_SOLVER_ADMM = 2   /* ADMM with column-parallel PCG and a transform z-update (Sec. 2.3.2) */
 } rgp_solver;
 
 /* Options of the full solve (rgp_correct).  rgp_default_opts() fills the paper's defaults. */
@@ -97,6 +98,22 @@ typedef struct {
                             holds the pairs used and the PCG residual field holds H0's scale
                             (1 / max|g| without pairs). */
   int32_t reserved;
+  double admm_rho0;      /* RGP_SOLVER_ADMM: initial augmentation parameter rho on every level
+                            (<= 0: alpha).  With ADMM, gn_iters counts ADMM iterations per level,
+                            each one Gauss-Newton step on F(b) + (rho vol / 2)|b - z + u|^2 with
+                            F = D + alpha S_PE + beta P (the search direction by Jacobi PCG on
+                            every PE column independently: pcg_iters iterations at most, a
+                            column stopping at relative residual pcg_rtol), then
+                            z = argmin alpha (S_A + S_B)(z) + (rho vol / 2)|b - z + u|^2 with
+                            periodic differences across the PE axis, u += b - z, and rho doubled
+                            (u halved) when |b - z| > 10 rho |z - z_old|, halved (u doubled) when
+                            rho |z - z_old| > 10 |b - z|.  z = b, u = 0 at the start of every
+                            level; b is the result.  In a stats record S holds
+                            S_PE + (rho / alpha)(vol / 2)|b - z + u|^2 (J = D + alpha S + beta P is
+                            the b-update's objective), the PCG fields the largest column
+                            iteration count and relative residual, and field 11 the rho used.
+                            Supports at most 512 field nodes along PE and 1024 along the other
+                            axes (else RGP_ESHAPE). */
 } rgp_solver_opts;
 
 /* Number of doubles per Gauss-Newton record in the stats buffer of rgp_correct. */

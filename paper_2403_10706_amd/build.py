@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librgp.so")
 
-SOURCES = ["api.cpp", "loss.hip", "pcg.hip", "ot.hip", "pyramid.hip", "lbfgs.hip", "lsq.hip"]
+SOURCES = ["api.cpp", "loss.hip", "pcg.hip", "ot.hip", "pyramid.hip", "lbfgs.hip", "lsq.hip",
+           "admm.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

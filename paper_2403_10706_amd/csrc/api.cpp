@@ -255,7 +255,11 @@ rgp_status check_opts(const rgp_solver_opts* o) {
   if (o->ls_max_trials < 1 || o->ls_max_trials > 10) return RGP_EINVAL;
   if (!(o->pcg_rtol >= 0.0) || !(o->armijo_c >= 0.0) || !(o->ot_eps >= 0.0)) return RGP_EINVAL;
   if (o->ot_blur != 0 && o->ot_blur != 1) return RGP_EINVAL;
-  if (o->solver != RGP_SOLVER_GN && o->solver != RGP_SOLVER_LBFGS) return RGP_EINVAL;
+  if (o->solver != RGP_SOLVER_GN && o->solver != RGP_SOLVER_LBFGS &&
+      o->solver != RGP_SOLVER_ADMM)
+    return RGP_EINVAL;
+  if (o->solver == RGP_SOLVER_ADMM && (!(o->alpha > 0.0) || !std::isfinite(o->admm_rho0)))
+    return RGP_EINVAL;
   if (o->solver == RGP_SOLVER_LBFGS && (o->lbfgs_memory < 1 || o->lbfgs_memory > kLbfgsMaxMem))
     return RGP_EINVAL;
   return RGP_OK;
@@ -266,7 +270,8 @@ rgp_status check_opts(const rgp_solver_opts* o) {
 // exits at once.
 hipError_t armijo_passes(const CorrectWs& w, const Geom& g, const void* Ip, const void* Im,
                          DType img, DType real, const rgp_solver_opts* o, const void* b,
-                         const void* grad, double* rec, hipStream_t s) {
+                         const void* grad, double* rec, hipStream_t s,
+                         const void* prox_c = nullptr) {
   hipError_t e;
   const Control& k = w.ctl;
   int first = 0;
@@ -287,6 +292,7 @@ hipError_t armijo_passes(const CorrectWs& w, const Geom& g, const void* Ip, cons
     ta.part = k.slot(kPartTrial0 + p);
     ta.first = first;
     ta.nc = nc;
+    ta.prox_c = prox_c;
     if ((e = launch_trial(ta, img, real, s)) != hipSuccess) return e;
     DecideArgs da{};
     da.part_prev = ta.part;
@@ -385,6 +391,112 @@ hipError_t run_level_lbfgs(const CorrectWs& w, const Geom& g, const void* Ip, co
     aa.st = k.st;
     aa.n = g.nnode;
     if ((e = launch_apply_step(aa, real, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// `gn_iters` ADMM iterations on one level (Sec. 2.3.2).  Per iteration: the b-update (the
+// objective, gradient and tridiagonal Gauss-Newton blocks of F_rho at b, block PCG per column,
+// the Armijo passes on F_rho, b += gamma q), the z-update (four transform passes, the last also
+// updating u and c = z - u), the adaptation of rho and the rescaling of u it asks for.  z, u and
+// c live in the PCG vectors of the workspace (unused by ADMM), the transform passes' scratch in
+// two more of them.  b enters and leaves in B[cur].
+hipError_t run_level_admm(const CorrectWs& w, const Geom& g, const int64_t m[3], int pe,
+                          const double h[3], const void* Ip, const void* Im, DType img,
+                          DType real, const rgp_solver_opts* o, int cur, double* records,
+                          hipStream_t s) {
+  hipError_t e;
+  const Control& k = w.ctl;
+  const Launch Llg = plan_loss_grad(g, real);
+  void* z = w.R[0];
+  void* u = w.R[1];
+  void* c = w.P[0];
+  void* t1 = w.P[1];
+  void* t2 = w.W[0];
+  int ax[2], na = 0;
+  for (int d = 0; d < 3; ++d)
+    if (d != pe) ax[na++] = d;
+  const int A = ax[0], B = ax[1];   // B: the faster cross axis
+  int32_t n[3];
+  for (int d = 0; d < 3; ++d) n[d] = (int32_t)(m[d] + (d == pe ? 1 : 0));
+  AdmmVecArgs va{};
+  va.n = g.nnode;
+  va.b = w.B[cur];
+  va.z = z;
+  va.u = u;
+  va.c = c;
+  va.rho0 = o->admm_rho0 > 0.0 ? o->admm_rho0 : o->alpha;
+  va.st = k.st;
+  if ((e = launch_admm_vec(va, true, real, s)) != hipSuccess) return e;
+  for (int it = 0; it < o->gn_iters; ++it) {
+    double* rec = records ? records + (size_t)it * kStatFields : nullptr;
+    LossGradArgs la{};
+    la.g = g;
+    la.Ip = Ip;
+    la.Im = Im;
+    la.b_in = w.B[cur];
+    la.step = 0;
+    la.level_start = it == 0;
+    la.grad = w.G;
+    la.diag = w.Dg;
+    la.off = w.Of;
+    la.alpha = o->alpha;
+    la.beta = o->beta;
+    la.st = k.st;
+    la.part = k.slot(kPartLoss);
+    la.prox_c = c;
+    if ((e = launch_loss_grad(la, img, real, s)) != hipSuccess) return e;
+    if ((e = launch_loss_final(LossFinalArgs{k.slot(kPartLoss), Llg.grid, g.vol, o->alpha,
+                                             o->beta, k.st, nullptr, rec, 1},
+                               s)) != hipSuccess)
+      return e;
+    BlockPcgArgs bp{};
+    bp.g = g;
+    bp.diag = w.Dg;
+    bp.off = w.Of;
+    bp.grad = w.G;
+    bp.x = w.X;
+    bp.maxit = o->pcg_iters;
+    bp.rtol = o->pcg_rtol;
+    bp.st = k.st;
+    bp.part = k.slot(kPartPcg0);
+    if ((e = launch_block_pcg(bp, real, s)) != hipSuccess) return e;
+    if ((e = armijo_passes(w, g, Ip, Im, img, real, o, w.B[cur], w.G, rec, s, c)) != hipSuccess)
+      return e;
+    ApplyArgs aa{};
+    aa.b = w.B[cur];
+    aa.q = w.X;
+    aa.st = k.st;
+    aa.n = g.nnode;
+    if ((e = launch_apply_step(aa, real, s)) != hipSuccess) return e;
+    // z-update: B from rho (b + u), A with the scaling, A, B with the multiplier update
+    DhtArgs da{};
+    for (int d = 0; d < 3; ++d) da.n[d] = n[d];
+    da.b = w.B[cur];
+    da.u = u;
+    da.c = c;
+    da.alpha = o->alpha;
+    da.st = k.st;
+    da.part = k.slot(kPartPcg1);
+    const int modes[4] = {kDhtFirst, kDhtScale, kDhtPlain, kDhtLast};
+    const int axes[4] = {B, A, A, B};
+    const void* srcs[4] = {nullptr, t1, t2, t1};
+    void* dsts[4] = {t1, t2, t1, z};
+    for (int p = 0; p < 4; ++p) {
+      da.mode = modes[p];
+      da.axis = axes[p];
+      da.other_axis = axes[p] == A ? B : A;
+      da.inv_h2[0] = 1.0 / (h[da.axis] * h[da.axis]);
+      da.inv_h2[1] = 1.0 / (h[da.other_axis] * h[da.other_axis]);
+      da.src = srcs[p];
+      da.dst = dsts[p];
+      if ((e = launch_dht(da, real, s)) != hipSuccess) return e;
+    }
+    int lpb = 0;
+    const unsigned nprod = dht_grid(n, B, &lpb);
+    if ((e = launch_admm_rho(AdmmRhoArgs{k.st, k.slot(kPartPcg1), nprod, rec}, s)) != hipSuccess)
+      return e;
+    if ((e = launch_admm_vec(va, false, real, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -505,6 +617,7 @@ void rgp_default_opts(rgp_solver_opts* o) {
   o->ot_blur = 0;
   o->solver = RGP_SOLVER_GN;
   o->lbfgs_memory = 10;
+  o->admm_rho0 = 0.0;
 }
 
 rgp_status rgp_workspace_size(rgp_op op, const rgp_grid* grid, rgp_dtype real_t,
@@ -883,6 +996,11 @@ rgp_status check_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_pl
   Level lv[kMaxLevels];
   if (make_levels(grid, opts->levels, lv) != 0) return RGP_ESHAPE;
   if (!opts->use_b_init && !ot_column_supported(lv[opts->levels - 1].g.mp)) return RGP_ESHAPE;
+  if (opts->solver == RGP_SOLVER_ADMM) {
+    if (block_pcg_npl((int)grid->m[grid->pe]) == 0) return RGP_ESHAPE;
+    for (int d = 0; d < 3; ++d)
+      if (d != grid->pe && grid->m[d] > kDhtMaxN) return RGP_ESHAPE;
+  }
   return need_ws(RGP_OP_CORRECT, grid, real_t, opts, ws, ws_bytes);
 }
 
@@ -986,10 +1104,14 @@ rgp_status enqueue_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_
     double* rec = stats_dev ? stats_dev + RGP_STAT_HEADER +
                                   (size_t)(L - 1 - l) * opts->gn_iters * kStatFields
                             : nullptr;
-    hipError_t e =
-        opts->solver == RGP_SOLVER_LBFGS
-            ? run_level_lbfgs(w, lv[l].g, imgs[l][0], imgs[l][1], ity[l], dr, opts, cur, rec, s)
-            : run_level(w, lv[l].g, imgs[l][0], imgs[l][1], ity[l], dr, opts, cur, rec, s);
+    hipError_t e;
+    if (opts->solver == RGP_SOLVER_LBFGS)
+      e = run_level_lbfgs(w, lv[l].g, imgs[l][0], imgs[l][1], ity[l], dr, opts, cur, rec, s);
+    else if (opts->solver == RGP_SOLVER_ADMM)
+      e = run_level_admm(w, lv[l].g, lv[l].m, grid->pe, lv[l].h, imgs[l][0], imgs[l][1],
+                         ity[l], dr, opts, cur, rec, s);
+    else
+      e = run_level(w, lv[l].g, imgs[l][0], imgs[l][1], ity[l], dr, opts, cur, rec, s);
     if (e != hipSuccess) {
       g_last_hip = (int)e;
       return RGP_EHIP;

@@ -125,6 +125,10 @@ __device__ __forceinline__ void loss_grad_body(const LossGradArgs& a, VBlock vb)
   const BRes rD = bres(a.diag, a.diag ? nbytes : 0u), rO = bres(a.off, a.diag ? nbytes : 0u);
   const uint32_t nps = (uint32_t)g.nps, nxs = (uint32_t)g.nxs, nys = (uint32_t)g.nys;
   const uint32_t cps = (uint32_t)g.cps;
+  const bool prox = a.prox_c != nullptr;
+  const BRes rC = bres(a.prox_c, prox ? nbytes : 0u);
+  const double rho = prox ? st->admm_rho : 0.0;
+  const TR prv = (TR)(rho * g.vol), prw = (TR)(prox ? rho / a.alpha : 0.0);
 
   const TR inv_hp = TR(1) / (TR)g.hp;
   const TR wp2 = TR(1) / ((TR)g.hp * (TR)g.hp);
@@ -139,7 +143,8 @@ __device__ __forceinline__ void loss_grad_body(const LossGradArgs& a, VBlock vb)
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // r^2, S terms, phi, violations, g^2
 
   for (WaveIter it = wave_iter(ntiles, vb); it.t < it.end; it.t += it.stride) {
-    const ColTile c = col_tile(g, it.t, S);
+    ColTile c = col_tile(g, it.t, S);
+    if (prox) c.hasxm = c.hasxp = c.hasym = c.hasyp = false;  // F_rho: PE smoothness only
     const int k0 = c.k0;
     auto noff = [&](int k) -> uint32_t { return (c.nb + (uint32_t)k * nps) * kSr; };
 
@@ -253,8 +258,14 @@ __device__ __forceinline__ void loss_grad_body(const LossGradArgs& a, VBlock vb)
       if (c.hasxp) { lap = fma(-dxp, wx2, lap); ldg += wx2; st = fma(dxp * dxp, wx2, st); }
       if (c.hasym) { lap = fma(dym, wy2, lap); ldg += wy2; }
       if (c.hasyp) { lap = fma(-dyp, wy2, lap); ldg += wy2; st = fma(dyp * dyp, wy2, st); }
-      const TR gk = (lo ? gU[s] : TR(0)) + (up ? gD[s + 1] : TR(0)) + avol * lap;
-      const TR dk = (lo ? dU[s] : TR(0)) + (up ? dD[s + 1] : TR(0)) + avol * ldg;
+      TR gk = (lo ? gU[s] : TR(0)) + (up ? gD[s + 1] : TR(0)) + avol * lap;
+      TR dk = (lo ? dU[s] : TR(0)) + (up ? dD[s + 1] : TR(0)) + avol * ldg;
+      if (prox) {   // (rho vol / 2)|b - c|^2: gradient rho vol e, diagonal rho vol
+        const TR e = bk - bld<TR>(rC, noff(min(k, mp)));
+        gk = fma(prv, e, gk);
+        dk += prv;
+        st = fma(prw * e, e, st);
+      }
       const bool out = nodeok && c.colok;
       if (out) {
         tst += st;
@@ -328,6 +339,9 @@ __device__ __forceinline__ void trial_body(const TrialArgs& a, VBlock vb) {
   const BRes rB = bres(a.b, nbytes), rQ = bres(a.q, nbytes), rG = bres(a.grad, nbytes);
   const uint32_t nps = (uint32_t)g.nps, nxs = (uint32_t)g.nxs, nys = (uint32_t)g.nys;
   const uint32_t cps = (uint32_t)g.cps;
+  const bool prox = a.prox_c != nullptr;
+  const BRes rC = bres(a.prox_c, prox ? nbytes : 0u);
+  const TR prw = (TR)(prox ? st->admm_rho / a.alpha : 0.0);
 
   const TR inv_hp = TR(1) / (TR)g.hp;
   const TR hih = TR(0.5) * inv_hp;
@@ -345,7 +359,8 @@ __device__ __forceinline__ void trial_body(const TrialArgs& a, VBlock vb) {
   for (int i = 0; i < K; ++i) v[i] = 0.0;
 
   for (WaveIter it = wave_iter(ntiles, vb); it.t < it.end; it.t += it.stride) {
-    const ColTile c = col_tile(g, it.t, S);
+    ColTile c = col_tile(g, it.t, S);
+    if (prox) c.hasxm = c.hasxp = c.hasym = c.hasyp = false;  // F_rho: PE smoothness only
     const int k0 = c.k0;
     auto noff = [&](int k) -> uint32_t { return (c.nb + (uint32_t)k * nps) * kSr; };
     // b, q at nodes k0 .. k0+S (clamped to mp); first pass: grad and the upper x and y neighbours
@@ -419,6 +434,11 @@ __device__ __forceinline__ void trial_body(const TrialArgs& a, VBlock vb) {
           const TR db = by - bk, dq = qy - qk;
           sbq = fma(db * dq, wy2, sbq);
           sqq = fma(dq * dq, wy2, sqq);
+        }
+        if (prox) {   // the proximal term as part of S: (rho / alpha)(e q, q^2) with e = b - c
+          const TR e = bk - bld<TR>(rC, noff(min(k, mp)));
+          sbq = fma(prw * e, qk, sbq);
+          sqq = fma(prw * qk, qk, sqq);
         }
         if (nodeok) {
           tgq = fma(gk[s], qk, tgq);

@@ -96,7 +96,10 @@ struct State {
   int32_t pcg_iters, pad1;
   // OT
   double ot_shift;
-  double pad[4];
+  // ADMM: the current augmentation parameter rho and the factor the last adaptation applies to
+  // the scaled multiplier u
+  double admm_rho, admm_ufac;
+  double pad[2];
 };
 
 // PCG recurrence scalars, double-buffered by iteration parity: kernel i reads slot (i-1)&1 and its

@@ -65,6 +65,10 @@ struct LossGradArgs {
   int step;           // apply the accepted line-search step first
   int level_start;    // first GN step of a level: block 0 clears gn_stop / accepted
   int run;            // PE nodes per thread of the launch (set by the launcher)
+  // ADMM's b-update (F_rho of Sec. 2.3.2): smoothness along the PE axis only, and the proximal
+  // term (rho vol / 2)|b - prox_c|^2 with rho = st->admm_rho; its value joins the S sum as
+  // (rho / alpha) (b - c)^2, so that J = D + alpha S + beta P stays the recorded form
+  const void* prox_c;  // nullable: the plain objective of Eq. (6)
 };
 
 // Reduction of loss_grad's block sums into J, D, S, P (one block, or every PCG block of
@@ -102,6 +106,7 @@ struct TrialArgs {
   State* st;
   double* part;             // block sums: [gq, sbq, sqq, then (sum r^2, sum phi, violations) per candidate]
   int first, nc;            // gamma_c = 2^-(first + c), c < nc
+  const void* prox_c;       // nullable: ADMM's b-update (as in LossGradArgs)
 };
 
 struct DecideArgs {
@@ -304,6 +309,62 @@ struct LbfgsArgs {
   unsigned nblk;              // set by the launcher
 };
 unsigned lbfgs_grid(int64_t n);
+
+// ADMM (admm.hip).
+constexpr double kAdmmMu = 10.0, kAdmmTau = 2.0;  // rho adaptation: ratio and factor
+constexpr int kDhtMaxN = 1024;                   // longest cross axis of the z-update
+struct BlockPcgArgs {      // per-column Jacobi PCG on the tridiagonal blocks (diag, off)
+  Geom g;
+  const void* diag;
+  const void* off;
+  const void* grad;        // right-hand side -grad
+  void* x;                 // solution (nodes of every column written)
+  int32_t maxit;
+  double rtol;
+  State* st;               // gn_stop; receives the largest iteration count and residual
+  double* part;            // per-block maxima (column-major, 2 sums)
+  unsigned nblk;           // set by the launcher
+};
+enum DhtMode : int32_t { kDhtFirst = 0, kDhtScale = 1, kDhtPlain = 2, kDhtLast = 3 };
+struct DhtArgs {           // one pass of the z-update (normalised Hartley transform along axis)
+  int32_t n[3];            // node extents of the field array
+  int32_t axis;            // transform axis (a cross axis)
+  int32_t other_axis;      // the other cross axis (kDhtScale)
+  int32_t mode;
+  const void* src;         // input of kDhtScale / kDhtPlain / kDhtLast
+  void* dst;               // output (kDhtLast: z, read first as z_old)
+  const void* b;           // kDhtFirst, kDhtLast
+  void* u;                 // kDhtFirst (read), kDhtLast (updated)
+  void* c;                 // kDhtLast: c = z - u
+  double alpha;
+  double inv_h2[2];        // 1 / h^2 of axis and other_axis (kDhtScale)
+  State* st;               // rho, gn_stop
+  double* part;            // kDhtLast: block sums of (b - z)^2 and (z - z_old)^2
+  int32_t lines_per_block; // set by the launcher
+  unsigned nblk;           // set by the launcher
+};
+struct AdmmRhoArgs {
+  State* st;
+  const double* part;
+  unsigned nprod;
+  double* record;          // nullable: field 11 receives the rho the iteration used
+};
+struct AdmmVecArgs {
+  int64_t n;
+  const void* b;
+  void* z;
+  void* u;
+  void* c;
+  double rho0;             // init only
+  State* st;
+};
+int block_pcg_npl(int mp);       // nodes per lane (0: the column is too long)
+unsigned block_pcg_grid(int64_t ncol);
+hipError_t launch_block_pcg(const BlockPcgArgs& a, DType real, hipStream_t s);
+unsigned dht_grid(const int32_t n[3], int axis, int* lines_per_block);
+hipError_t launch_dht(const DhtArgs& a, DType real, hipStream_t s);
+hipError_t launch_admm_rho(const AdmmRhoArgs& a, hipStream_t s);
+hipError_t launch_admm_vec(const AdmmVecArgs& a, bool init, DType real, hipStream_t s);
 
 // Least-squares correction (lsq.hip).
 struct LsqArgs {

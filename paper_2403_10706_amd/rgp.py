@@ -25,7 +25,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "grid extents out of range",
 # Device-side failures of a correction, reported in stats[2] (never returned by a call).
 ENONFINITE, EBARRIER, ELINESEARCH = -4, -5, -6
 F64, F32, BF16 = 0, 1, 2
-SOLVERS = {"gn": 0, "lbfgs": 1}
+SOLVERS = {"gn": 0, "lbfgs": 1, "admm": 2}
 OP_OT_INIT, OP_LOSS_GRAD, OP_GN_HVP, OP_PCG_SOLVE, OP_CORRECT, OP_APPLY_CORRECTION = range(6)
 STAT_FIELDS = 12
 STAT_HEADER = 4
@@ -55,7 +55,7 @@ class SolverOpts(ctypes.Structure):
                 ("ot_eps", ctypes.c_double), ("ot_guard", ctypes.c_int32),
                 ("use_b_init", ctypes.c_int32), ("ot_blur", ctypes.c_int32),
                 ("solver", ctypes.c_int32), ("lbfgs_memory", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("admm_rho0", ctypes.c_double)]
 
 
 EXPORTS = ("rgp_status_string", "rgp_last_hip_error", "rgp_default_opts", "rgp_workspace_size",
@@ -382,8 +382,9 @@ class Options:
     ot_eps: float = 1e-3
     ot_guard: bool = True
     ot_blur: bool = False
-    solver: str = "gn"          # "gn" (Gauss-Newton-PCG) or "lbfgs"
+    solver: str = "gn"          # "gn" (Gauss-Newton-PCG), "lbfgs" or "admm"
     lbfgs_memory: int = 10
+    admm_rho0: float = 0.0      # <= 0: alpha
 
     def to_c(self, use_b_init: bool = False) -> SolverOpts:
         o = SolverOpts()
@@ -396,6 +397,7 @@ class Options:
         o.ot_blur = int(bool(self.ot_blur))
         o.solver = SOLVERS[self.solver]
         o.lbfgs_memory = int(self.lbfgs_memory)
+        o.admm_rho0 = float(self.admm_rho0)
         return o
 
 

@@ -1062,3 +1062,68 @@ def test_correct_lsq_c2_sampled_columns():
     say(f"[lsq c2 sampled] |I - I_oracle|/|I_oracle| over 512 columns = {err:.2e}")
     assert err <= VEC_RTOL
     assert np.array_equal(to_host(its).astype(np.int64)[ia, ib], ref_it[0])
+
+
+# ---- ADMM as the per-level solver (Sec. 2.3.2) -------------------------------------------------
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
+@pytest.mark.parametrize("shape,pe,scale,levels,iters", [
+    ((32, 32, 24), 1, 1.0, 1, 8), ((37, 29, 23), 0, 30.0, 1, 10), ((19, 26, 41), 2, 30.0, 1, 8),
+    ((32, 32, 24), 1, 1000.0, 2, 6)])
+def test_correct_admm_parity(real, shape, pe, scale, levels, iters):
+    """ADMM iterations per level instead of Gauss-Newton: the field and, per iteration, the
+    b-update's objective, the largest column PCG iteration count and residual, the step size,
+    the trial count and the rho used, equal the oracle's (column PCG 10 iterations, rtol 0.1)."""
+    rgp = _rgp()
+    say(f"[admm] real={real} shape={shape} pe={pe} scale={scale} levels={levels} iters={iters}")
+    p = _pair(shape, pe, seed=44, scale=scale)
+    dt = REAL[real]
+    Ip, Im = rounded(p.I_plus, dt), rounded(p.I_minus, dt)
+    opts = rgp.Options(levels=levels, gn_iters=iters, pcg_iters=10, pcg_rtol=0.1, solver="admm")
+    out = rgp.correct(to_dev(Ip, dt), to_dev(Im, dt), pe, opts=opts)
+    ref = orc.solve(Ip, Im, pe, levels=levels, gn_iters=iters, pcg_iters=10, pcg_rtol=0.1,
+                    solver="admm")
+    head, recs = rgp.parse_stats(out["stats"], levels, iters)
+    assert head["status"] == ref.status
+    for lv, (_, _, hist) in enumerate(ref.levels):
+        for k, got in enumerate(recs[lv]):
+            if k >= len(hist):
+                assert math.isnan(got["J"])
+                continue
+            w = hist[k]
+            assert (got["accepted"], got["trials"]) == (float(w.accepted), float(w.trials)), \
+                (lv, k, got, w)
+            assert got["gamma"] == w.gamma, (lv, k, got, w)
+            assert got["J"] == pytest.approx(w.J, rel=_tol(real, 1e-10, J_RTOL)), (lv, k)
+            assert got["pcg_iters"] == float(w.pcg_iters), (lv, k, got, w)
+            # the largest column residual comes from the least converged column (on the x1000
+            # pair its residual is above 5 times its start after 10 iterations: an ill-conditioned
+            # block where FP32 and FP64 CG agree to the third digit only)
+            assert got["pcg_relres"] == pytest.approx(w.pcg_relres, rel=_tol(real, 1e-8, 2e-2))
+            if w.accepted:
+                assert got["reserved"] == w.rho, (lv, k, got, w)
+    err = float(np.max(np.abs(to_host(out["b"]) - ref.b)))
+    say(f"[admm] max|b - b_oracle| = {err:.3e} voxel (max|b| {np.abs(ref.b).max():.3f})")
+    assert err <= _tol(real, 1e-8, BFINAL_ATOL), err
+
+
+def test_batch_plan_admm_matches_per_pair():
+    """The batched plan with ADMM levels (the objective and Armijo launches shared in their
+    proximal mode, the ADMM kernels pair by pair) gives every pair bitwise its per-pair field."""
+    rgp = _rgp()
+    specs = BATCH_SPECS[:3]
+    pairs = [_pair(sh, pe, seed=95 + i, scale=30.0) for i, (sh, pe) in enumerate(specs)]
+    pes = [pe for _, pe in specs]
+    opts = rgp.Options(levels=2, gn_iters=5, pcg_iters=10, pcg_rtol=0.1, solver="admm")
+    dt = torch.float32
+    Ip = [to_dev(p.I_plus, dt) for p in pairs]
+    Im = [to_dev(p.I_minus, dt) for p in pairs]
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        bp = rgp.BatchPlan(Ip, Im, pes, opts, stream=s)
+        bp.launch(s)
+        s.synchronize()
+    for i, (sh, pe) in enumerate(specs):
+        ref = rgp.correct(Ip[i], Im[i], pe, opts=opts, real_dtype=dt)
+        assert torch.equal(bp.b[i], ref["b"]), i
