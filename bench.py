@@ -26,6 +26,7 @@ Other modes (profiling helpers; their output goes under profiles/):
   --traffic-summary F W       HBM traffic of the finest-level PCG step from the two --pmc runs
                               (directories F and W), scaled by the copy kernel's counters
   --profile-summary D         text summary of a rocprofv3 --kernel-trace --stats run in D
+  --counter-summary D         per-kernel SQ instruction counters of a rocprofv3 --pmc run in D
   --batch N                   the batching benchmark: N uneven pairs, plain per-pair graphs
                               against one batched graph (its own JSON line)
   --batch-profile-summary D   per-kernel GB/s of the batched launches from a rocprofv3
@@ -291,6 +292,31 @@ def traffic_summary(fetch_dir, write_dir):
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec, indent=1))
+
+
+def counter_summary(d):
+    """Per-kernel means of the SQ counters of a rocprofv3 --pmc run (one row per kernel name and
+    grid): instructions per wavefront by kind, and the share of busy cycles."""
+    rows = _csv_rows(d, "*counter_collection.csv")
+    names = sorted({r["Counter_Name"] for r in rows})
+    per = {}
+    for r in rows:
+        key = (r["Kernel_Name"].split("(")[0][:60], int(r.get("Grid_Size", 0)))
+        per.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    print(f"# rocprofv3 --pmc {' '.join(names)}: mean per dispatch; per-wave figures divide by SQ_WAVES")
+    hdr = f"{'kernel':60s} {'grid':>9s} {'n':>5s} " + " ".join(f"{n[8:] if n.startswith('SQ_INSTS_') else n:>12s}" for n in names)
+    print(hdr)
+    for (k, g), c in sorted(per.items(), key=lambda kv: -kv[0][1]):
+        n = len(next(iter(c.values())))
+        means = {name: statistics.mean(v) for name, v in c.items()}
+        waves = means.get("SQ_WAVES", 0.0)
+        cols = []
+        for name in names:
+            v = means.get(name, float("nan"))
+            if name.startswith("SQ_INSTS_") and waves > 0:
+                v = v / waves   # per wavefront
+            cols.append(f"{v:12.1f}")
+        print(f"{k:60s} {g:9d} {n:5d} " + " ".join(cols))
 
 
 def profile_summary(d):
@@ -576,6 +602,7 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--profile-summary", metavar="DIR")
+    ap.add_argument("--counter-summary", metavar="DIR")
     ap.add_argument("--batch-profile-summary", metavar="DIR")
     ap.add_argument("--batch", type=int, metavar="N", default=0,
                     help="the batching benchmark over N uneven pairs instead of the headline")
@@ -587,6 +614,8 @@ def main():
         return traffic_summary(*args.traffic_summary)
     if args.profile_summary:
         return profile_summary(args.profile_summary)
+    if args.counter_summary:
+        return counter_summary(args.counter_summary)
     if args.batch_profile_summary:
         batch_profile_summary(args.batch_profile_summary)
         return None
