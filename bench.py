@@ -699,6 +699,31 @@ def main():
     value = args.steps / wall
     log(f"bench: {ms_per_step:.3f} ms/pair wall, {gpu_ms / args.steps:.3f} ms/pair on the stream")
 
+    # ---- the same pair in the nonlinear regime: images x1000 (the distance term dominates, the
+    # field reaches ~8 voxels and the line search backtracks); its own captured plan ----
+    Ip_nl = Ip * 1000.0
+    Im_nl = Im * 1000.0
+    b_nl = torch.empty_like(b)
+    st_nl = torch.empty(rgp.STAT_HEADER + LEVELS * GN_ITERS * rgp.STAT_FIELDS,
+                        dtype=torch.float64, device=dev)
+    plan_nl = rgp.Plan(Ip_nl, Im_nl, pe, opts, b_nl, torch.empty_like(Ip), torch.empty_like(Im),
+                       ws, stats=st_nl, stream=side)
+    for _ in range(max(1, args.warmup)):
+        plan_nl.launch(side)
+    wall_nl, _ = timed(lambda: plan_nl.launch(side), args.steps)
+    _, recs_nl = rgp.parse_stats(st_nl, LEVELS, GN_ITERS)
+    trials_nl = [int(r["trials"]) for lv in recs_nl for r in lv]
+    plan_nl.close()
+    nonlinear = dict(workload="the same pair with the images x1000 (same schedule)",
+                     value=round(args.steps / wall_nl, 3), unit="pairs/s",
+                     ms_per_step=round(1e3 * wall_nl / args.steps, 4),
+                     armijo_trials_per_step=trials_nl,
+                     steps_that_backtracked=sum(t > 1 for t in trials_nl),
+                     max_abs_b=round(float(torch.max(torch.abs(b_nl))), 4))
+    log(f"bench: nonlinear regime (x1000) {nonlinear['value']:.2f} pairs/s, "
+        f"{nonlinear['steps_that_backtracked']} of {len(trials_nl)} steps backtracked")
+    del Ip_nl, Im_nl
+
     # ---- eager pass with kernel timing: per-kernel durations from HIP events ----
     ne = max(1, args.eager_steps)
     rgp.timing_start(1 << 16)
@@ -785,7 +810,7 @@ def main():
                     shape=list(shape), pe_dim=pe, levels=LEVELS, gn_iters=GN_ITERS,
                     pcg_iters=PCG_ITERS, global_batch=1, pcg_march_lengths=tuned_xl),
         gpu_ms_per_step=round(gpu_ms / args.steps, 4), eager_ms_per_step=round(eager_ms, 4),
-        roofline=roofline, kernels=kernels, batch=batch, cpu_baseline=cpu,
+        roofline=roofline, kernels=kernels, nonlinear=nonlinear, batch=batch, cpu_baseline=cpu,
         device=torch.cuda.get_device_name(0),
     )
     print(json.dumps(line), flush=True)

@@ -39,16 +39,24 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build librgp)")
 
 
-def build(verbose: bool = False, jobs: int = 5) -> str:
-    """Compile every source for gfx950 and link librgp.so next to this file."""
+def build(verbose: bool = False, jobs: int = 5, asan: bool = False) -> str:
+    """Compile every source for gfx950 and link librgp.so next to this file.
+
+    asan=True builds librgp_asan.so instead: the host code instrumented with AddressSanitizer
+    (the device code is built as usual), for the host-side checks of the C ABI."""
     cc = hipcc()
+    flags = list(HIPCC_FLAGS)
+    lib = LIB
+    if asan:
+        flags += ["-O1", "-g", "-fno-omit-frame-pointer", "-Xarch_host", "-fsanitize=address"]
+        lib = os.path.join(HERE, "librgp_asan.so")
     with tempfile.TemporaryDirectory(prefix="rgp_build_") as tmp:
         objs = []
         procs = []
         for src in SOURCES:
             obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
             lang = ["-x", "hip"] if src.endswith(".cpp") else []
-            cmd = [cc, *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [cc, *flags, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE,
@@ -62,14 +70,15 @@ def build(verbose: bool = False, jobs: int = 5) -> str:
                 raise RuntimeError(f"hipcc failed on {src}:\n{out}")
             if verbose and out.strip():
                 print(out)
-        tmp_lib = LIB + ".tmp"
-        cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp_lib]
+        tmp_lib = lib + ".tmp"
+        link_asan = ["-Xarch_host", "-fsanitize=address", "-shared-libasan"] if asan else []
+        cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *link_asan, *objs, "-o", tmp_lib]
         res = subprocess.run(cmd, capture_output=True, text=True)
         if res.returncode != 0:
             raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
-        os.replace(tmp_lib, LIB)
-    return LIB
+        os.replace(tmp_lib, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, asan="--asan" in sys.argv))
