@@ -158,12 +158,14 @@ __device__ __forceinline__ PcgSlot pcg_scalar_phase(const PcgScalarArgs& a, cons
   const int it = a.iter;
   PcgSlot cur;
   bool fin = false;
+  // reduced before the status is tested, so that the reduction need not wait for the slot
+  // (after the end of the solve the sums are stale and unused)
+  block_sum<7, BLK>(t);
   if (prev.status != kPcgRunning) {  // the solve has ended: carry the final slot forward
     cur = prev;
     cur.status = kPcgDone;
     fin = it == a.maxit;
   } else {
-    block_sum<7, BLK>(t);
     cur = pcg_advance(prev, t, it, a.maxit, a.rtol, fin);
   }
   if (vb.id == 0 && threadIdx.x == 0) {
@@ -226,6 +228,24 @@ __global__ __launch_bounds__(kReduceBlock) void k_pcg_scalars(PcgScalarArgs a) {
 __global__ __launch_bounds__(kReduceBlock) void k_pcg_scalars_batch(
     const PcgScalarArgs* __restrict__ tab) {
   pcg_scalars_body(tab[blockIdx.x]);
+}
+
+// Slot i of the array through vector loads: a scalar load would share its wait counter with the
+// LDS operations of the block reduction, which would then wait for the slot as well.
+__device__ __forceinline__ PcgSlot load_slot(const PcgSlot* slots, int i) {
+  static_assert(sizeof(PcgSlot) == 7 * sizeof(double), "slot layout");
+  const BRes r = bres(slots, (uint32_t)(2 * sizeof(PcgSlot)));
+  const uint32_t o = (uint32_t)(i * sizeof(PcgSlot));
+  PcgSlot v;
+  v.rz = bld<double>(r, o);
+  v.rr = bld<double>(r, o + 8);
+  v.bnorm2 = bld<double>(r, o + 16);
+  v.relres = bld<double>(r, o + 24);
+  v.alpha = bld<double>(r, o + 32);
+  v.beta = bld<double>(r, o + 40);
+  v.status = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)(o + 48), 0, 0);
+  v.iters = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)(o + 52), 0, 0);
+  return v;
 }
 
 // ---- main phase: plane-march PCG step -------------------------------------------------------
@@ -376,7 +396,7 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
   // are loaded first, then the first unit's planes, so that the reduction waits for the former
   // only and the latter arrive meanwhile.
   const bool fused = a.sc.fused;
-  const PcgSlot prev = a.sc.slots[(fused && !first) ? (it - 1) & 1 : it & 1];
+  const PcgSlot prev = load_slot(a.sc.slots, (fused && !first) ? (it - 1) & 1 : it & 1);
   double tsum[7], lsum[5];
   if (fused && !first) load_partials_cm<7>(tsum, a.sc.part_prev, a.sc.nprod, 7);
   if (fused && first && a.sc.gn_mode) load_partials_rm<5>(lsum, a.sc.lf.part, a.sc.lf.nprod);
