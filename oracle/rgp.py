@@ -481,6 +481,21 @@ def restrict_image(I: np.ndarray) -> np.ndarray:
     return S / N
 
 
+def restrict_image_T(g: np.ndarray, fine_shape: Sequence[int]) -> np.ndarray:
+    """Adjoint of restrict_image: fine cell f receives g at its coarse cell divided by the number
+    of existing fine cells of that cell's 2x2x2 block."""
+    m = tuple(int(s) for s in fine_shape)
+    mc = tuple((s + 1) // 2 for s in m)
+    g = np.asarray(g, dtype=np.float64)
+    assert g.shape == mc
+    pad = [(0, 2 * c - s) for s, c in zip(m, mc)]
+    N = np.pad(np.ones(m), pad).reshape(mc[0], 2, mc[1], 2, mc[2], 2).sum(axis=(1, 3, 5))
+    up = g / N
+    for ax in range(3):
+        up = np.repeat(up, 2, axis=ax)
+    return up[:m[0], :m[1], :m[2]]
+
+
 def _prolong_weights_cells(mf: int, mc: int) -> np.ndarray:
     """Fine-by-coarse linear interpolation matrix for a cell-centred axis (clamped ends)."""
     P = np.zeros((mf, mc))
@@ -696,6 +711,29 @@ def pyramid(Ip, Im, h, levels):
         P, M, hh = out[-1]
         out.append((restrict_image(P), restrict_image(M), tuple(2.0 * x for x in hh)))
     return out
+
+
+def pyramid_objective(Ip, Im, fields, pe, h, alpha=ALPHA, beta=BETA, weights=None):
+    """sum_l w_l J_l(R^l I+, R^l I-, b_l, 2^l h) over the levels of the pyramid (Sec. 3.4; the
+    field of each level given) and its gradients: (J, [dJ/db_l], dJ/dI+, dJ/dI-), the image
+    gradients carried to the finest level by the adjoint restriction, coarsest level first."""
+    L = len(fields)
+    w = [1.0] * L if weights is None else [float(x) for x in weights]
+    levels = pyramid(Ip, Im, h, L)
+    J = 0.0
+    gb, gi = [], []
+    for (P, M, hl), b, wl in zip(levels, fields, w):
+        obj, g, _ = objective_gradient(P, M, b, pe, hl, alpha, beta)
+        gp, gm = image_gradient(P, M, b, pe, hl)
+        J += wl * obj.J
+        gb.append(wl * g)
+        gi.append((wl * gp, wl * gm))
+    accp, accm = gi[-1]
+    for l in range(L - 2, -1, -1):
+        fine = levels[l][0].shape
+        accp = gi[l][0] + restrict_image_T(accp, fine)
+        accm = gi[l][1] + restrict_image_T(accm, fine)
+    return J, gb, accp, accm
 
 
 def solve(Ip, Im, pe, h=(1.0, 1.0, 1.0), *, alpha=ALPHA, beta=BETA, levels=1, gn_iters=5,

@@ -457,6 +457,79 @@ def test_restrict_invariants():
     assert R2[2, 3, 1] == pytest.approx(I2[4, 6, 2], rel=1e-15)   # corner block of one cell
 
 
+@pytest.mark.parametrize("shape", [(6, 8, 4), (5, 7, 3), (1, 3, 2), (3, 1, 5)])
+def test_restrict_adjoint_identity_and_dense_matrix(shape):
+    """R^T against the adjoint identity <R x, y> = <x, R^T y> and against the transpose of the
+    dense matrix whose columns are the restrictions of the unit images."""
+    rng = np.random.default_rng(16)
+    mc = tuple((m + 1) // 2 for m in shape)
+    x, y = rng.standard_normal(shape), rng.standard_normal(mc)
+    Ry = rgp.restrict_image_T(y, shape)
+    assert Ry.shape == shape
+    assert float(np.sum(rgp.restrict_image(x) * y)) == pytest.approx(float(np.sum(x * Ry)),
+                                                                      rel=1e-13)
+    n = int(np.prod(shape))
+    Rd = np.stack([rgp.restrict_image(e.reshape(shape)).ravel() for e in np.eye(n)], axis=1)
+    np.testing.assert_allclose(Ry.ravel(), Rd.T @ y.ravel(), rtol=1e-14, atol=1e-15)
+
+
+def _pyramid_case(seed, shape=(6, 8, 5), pe=1, levels=3):
+    rng = np.random.default_rng(seed)
+    Ip = 0.6 + 0.4 * rng.random(shape)
+    Im = 0.6 + 0.4 * rng.random(shape)
+    fields, s = [], tuple(shape)
+    for l in range(levels):
+        if l:
+            s = tuple((m + 1) // 2 for m in s)
+        ns = list(s)
+        ns[pe] += 1
+        fields.append(0.08 * rng.standard_normal(ns))
+    return Ip, Im, fields
+
+
+def test_pyramid_objective_gradients_against_central_differences():
+    """The objective summed over three pyramid levels: the field gradients against central
+    differences along random directions of all three fields, the image gradients (J is quadratic
+    in the finest images, which every level's images depend on linearly) exactly."""
+    pe, h, w = 1, (1.0, 1.2, 0.9), (1.0, 0.5, 2.0)
+    Ip, Im, fields = _pyramid_case(17, pe=pe)
+    J, gb, gp, gm = rgp.pyramid_objective(Ip, Im, fields, pe, h, weights=w)
+    rng = np.random.default_rng(18)
+    e = 1e-5
+    for _ in range(3):
+        d = [rng.standard_normal(b.shape) for b in fields]
+        Ju = rgp.pyramid_objective(Ip, Im, [b + e * x for b, x in zip(fields, d)], pe, h,
+                                   weights=w)[0]
+        Jd = rgp.pyramid_objective(Ip, Im, [b - e * x for b, x in zip(fields, d)], pe, h,
+                                   weights=w)[0]
+        an = sum(float(np.sum(g * x)) for g, x in zip(gb, d))
+        assert (Ju - Jd) / (2 * e) == pytest.approx(an, rel=1e-6)
+    e = 0.5
+    for _ in range(3):
+        dp, dm = rng.standard_normal(Ip.shape), rng.standard_normal(Im.shape)
+        Ju = rgp.pyramid_objective(Ip + e * dp, Im + e * dm, fields, pe, h, weights=w)[0]
+        Jd = rgp.pyramid_objective(Ip - e * dp, Im - e * dm, fields, pe, h, weights=w)[0]
+        assert (Ju - Jd) / (2 * e) == pytest.approx(float(np.sum(gp * dp + gm * dm)), rel=1e-10)
+
+
+def test_pyramid_objective_one_level_and_level_sum():
+    """One level is the plain objective and its gradients; more levels add the objectives of the
+    restricted pairs at doubled spacings."""
+    pe, h = 2, (0.9, 1.1, 1.0)
+    Ip, Im, fields = _pyramid_case(19, shape=(5, 6, 7), pe=pe, levels=2)
+    J1, gb1, gp1, gm1 = rgp.pyramid_objective(Ip, Im, fields[:1], pe, h)
+    obj, g, _ = rgp.objective_gradient(Ip, Im, fields[0], pe, h)
+    gp, gm = rgp.image_gradient(Ip, Im, fields[0], pe, h)
+    assert J1 == obj.J
+    np.testing.assert_array_equal(gb1[0], g)
+    np.testing.assert_array_equal(gp1, gp)
+    np.testing.assert_array_equal(gm1, gm)
+    J2 = rgp.pyramid_objective(Ip, Im, fields, pe, h)[0]
+    Jc = rgp.objective(rgp.restrict_image(Ip), rgp.restrict_image(Im), fields[1], pe,
+                       tuple(2 * x for x in h)).J
+    assert J2 == pytest.approx(obj.J + Jc, rel=1e-14)
+
+
 @pytest.mark.parametrize("pe", [0, 1, 2])
 def test_prolong_reproduces_linear_fields(pe):
     mf = [10, 9, 7]
