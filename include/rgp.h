@@ -169,6 +169,27 @@ rgp_status rgp_ot_init(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus
 rgp_status rgp_blur_field(const rgp_grid* grid, rgp_dtype real_t, const void* b_in, void* b_out,
                           void* stream);
 
+/* Restriction of one image to the next coarser level of the multilevel pyramid that the
+ * coarse-to-fine scheme solves on (Sec. 3.4; the same transfer rgp_correct applies between its
+ * levels): coarse cell c is the mean of the existing fine cells of its 2x2x2 block, ceil(m/2)
+ * cells per axis.  `grid` describes the FINE image; only its m is read (pe and h are ignored).
+ * src: device cell array of img_t in the fine shape; dst: device cell array of real_t in the
+ * coarse shape, written in full; distinct buffers.  Summed in FP64 and rounded once to real_t.
+ * Types as for rgp_loss_grad (img_t == real_t, or RGP_BF16 images with an RGP_F32 or RGP_F64
+ * result, or RGP_F32 images with an RGP_F64 result).  Enqueued on `stream`; no workspace. */
+rgp_status rgp_restrict_image(const rgp_grid* grid, rgp_dtype img_t, const void* src,
+                              rgp_dtype real_t, void* dst, void* stream);
+
+/* Adjoint of rgp_restrict_image, for gradients taken through the pyramid (differentiation
+ * extension): fine cell f receives g_coarse at its coarse cell divided by the number of existing
+ * fine cells of that cell's block (1, 2, 4 or 8).  `grid` describes the FINE image (only m is
+ * read).  g_coarse: device cell array of real_t (RGP_F32 or RGP_F64) in the coarse shape;
+ * g_fine: device cell array of real_t in the fine shape, overwritten, or added to when
+ * accumulate != 0; distinct buffers.  Enqueued on `stream`; no workspace. */
+rgp_status rgp_restrict_image_adjoint(const rgp_grid* grid, rgp_dtype real_t,
+                                      const void* g_coarse, void* g_fine, int32_t accumulate,
+                                      void* stream);
+
 /* Objective J = D + alpha S + beta P of Eq. (6) at b, with D the SSD of the mass-preserving
  * transforms of Eq. (1)-(2), S the smoothness term of Eq. (5) (seven-point negative Laplacian on
  * the staggered field, Neumann boundaries) and P the barrier of Eq. (3); all with weight vol/2.

@@ -698,6 +698,56 @@ rgp_status rgp_ot_init(const rgp_grid* grid, rgp_dtype img_t, const void* I_plus
   return RGP_OK;
 }
 
+// Shape checks of the image-only pyramid transfers: only m is read.
+static rgp_status check_image_grid(const rgp_grid* g, RestrictArgs* ra) {
+  if (!g) return RGP_EINVAL;
+  int64_t cells = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (g->m[d] < 1 || g->m[d] > (int64_t(1) << 24)) return RGP_ESHAPE;
+    cells *= g->m[d];
+    if (cells > (int64_t(1) << 28)) return RGP_ESHAPE;
+    ra->mf[d] = g->m[d];
+    ra->mc[d] = (g->m[d] + 1) / 2;
+  }
+  return RGP_OK;
+}
+
+rgp_status rgp_restrict_image(const rgp_grid* grid, rgp_dtype img_t, const void* src,
+                              rgp_dtype real_t, void* dst, void* stream) {
+  RestrictArgs ra{};
+  rgp_status st = check_image_grid(grid, &ra);
+  if (st != RGP_OK) return st;
+  DType di, dr;
+  if ((st = check_types(img_t, real_t, &di, &dr)) != RGP_OK) return st;
+  if (!src || !dst || src == dst) return RGP_EINVAL;
+  ra.src = src;
+  ra.dst = dst;
+  RGP_HIP(launch_restrict(ra, di, dr, static_cast<hipStream_t>(stream)));
+  return RGP_OK;
+}
+
+rgp_status rgp_restrict_image_adjoint(const rgp_grid* grid, rgp_dtype real_t,
+                                      const void* g_coarse, void* g_fine, int32_t accumulate,
+                                      void* stream) {
+  RestrictArgs ra{};
+  rgp_status st = check_image_grid(grid, &ra);
+  if (st != RGP_OK) return st;
+  DType dr;
+  if (!dtype_of(real_t, &dr)) return RGP_EINVAL;
+  if (dr == DType::BF16) return RGP_EDTYPE;
+  if (!g_coarse || !g_fine || g_coarse == g_fine) return RGP_EINVAL;
+  RestrictAdjArgs aa{};
+  aa.src = g_coarse;
+  aa.dst = g_fine;
+  for (int d = 0; d < 3; ++d) {
+    aa.mf[d] = ra.mf[d];
+    aa.mc[d] = ra.mc[d];
+  }
+  aa.accumulate = accumulate != 0;
+  RGP_HIP(launch_restrict_adjoint(aa, dr, static_cast<hipStream_t>(stream)));
+  return RGP_OK;
+}
+
 rgp_status rgp_blur_field(const rgp_grid* grid, rgp_dtype real_t, const void* b_in, void* b_out,
                           void* stream) {
   rgp_status st = check_grid(grid);

@@ -40,6 +40,26 @@ __global__ __launch_bounds__(kBlock) void k_restrict(RestrictArgs a) {
   dst[i] = from_real<TO>(sum / (double)cnt);
 }
 
+// Adjoint of the restriction: fine cell f takes the value of its coarse cell divided by the number
+// of existing fine cells in that cell's 2x2x2 block (1, 2, 4 or 8, so the division is exact), and
+// adds it to dst with `accumulate`.
+template <typename TR>
+__global__ __launch_bounds__(kBlock) void k_restrict_adjoint(RestrictAdjArgs a) {
+  const TR* __restrict__ src = static_cast<const TR*>(a.src);
+  TR* __restrict__ dst = static_cast<TR*>(a.dst);
+  const int64_t n = (int64_t)a.mf[0] * a.mf[1] * a.mf[2];
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int f2 = (int)(i % a.mf[2]);
+  const int f1 = (int)((i / a.mf[2]) % a.mf[1]);
+  const int f0 = (int)(i / ((int64_t)a.mf[2] * a.mf[1]));
+  const int c0 = f0 >> 1, c1 = f1 >> 1, c2 = f2 >> 1;
+  const int cnt = (2 * c0 + 1 < a.mf[0] ? 2 : 1) * (2 * c1 + 1 < a.mf[1] ? 2 : 1) *
+                  (2 * c2 + 1 < a.mf[2] ? 2 : 1);
+  const TR v = src[((int64_t)c0 * a.mc[1] + c1) * a.mc[2] + c2] / (TR)cnt;
+  dst[i] = a.accumulate ? dst[i] + v : v;
+}
+
 // 1D interpolation stencil of one axis: up to two coarse indices with weights.
 __device__ __forceinline__ void axis_weights(int j, int mc, bool node_axis, int& i0, int& i1,
                                              double& w1) {
@@ -158,6 +178,21 @@ hipError_t launch_restrict(const RestrictArgs& a, DType src, DType dst, hipStrea
   else if (src == DType::BF16 && dst == DType::F64) RGP_RESTRICT(bf16_t, double);
   else return hipErrorInvalidValue;
 #undef RGP_RESTRICT
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_adjoint(const RestrictAdjArgs& a, DType real, hipStream_t s) {
+  if (active_recorder())
+    return record_other([a, real](hipStream_t s2) { return launch_restrict_adjoint(a, real, s2); });
+  const int64_t n = (int64_t)a.mf[0] * a.mf[1] * a.mf[2];
+  const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+  if (nb == 0) return hipSuccess;
+  if (real == DType::F64)
+    hipLaunchKernelGGL((k_restrict_adjoint<double>), dim3(nb), dim3(kBlock), 0, s, a);
+  else if (real == DType::F32)
+    hipLaunchKernelGGL((k_restrict_adjoint<float>), dim3(nb), dim3(kBlock), 0, s, a);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -218,6 +218,13 @@ struct RestrictArgs {
   int32_t mf[3], mc[3];
 };
 
+struct RestrictAdjArgs {
+  const void* src;    // coarse cell array
+  void* dst;          // fine cell array
+  int32_t mf[3], mc[3];
+  int32_t accumulate;  // add to dst instead of overwriting it
+};
+
 struct ProlongArgs {
   const void* src;   // coarse field
   void* dst;         // fine field
@@ -430,6 +437,7 @@ hipError_t launch_blur(const BlurArgs& a, DType real, hipStream_t s);
 // Whether the OT kernel takes columns of mp cells along the PE axis (at most 8192).
 bool ot_column_supported(int mp);
 hipError_t launch_restrict(const RestrictArgs& a, DType src, DType dst, hipStream_t s);
+hipError_t launch_restrict_adjoint(const RestrictAdjArgs& a, DType real, hipStream_t s);
 hipError_t launch_prolong(const ProlongArgs& a, DType real, hipStream_t s);
 hipError_t launch_reset(const SetStateArgs& a, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);

@@ -63,7 +63,8 @@ EXPORTS = ("rgp_status_string", "rgp_last_hip_error", "rgp_default_opts", "rgp_w
            "rgp_apply_correction", "rgp_correct", "rgp_correct_plan", "rgp_plan_launch",
            "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop", "rgp_loss_grad_images",
            "rgp_batch_workspace_size", "rgp_correct_batch_plan", "rgp_autotune", "rgp_blur_field",
-           "rgp_loss_grad_noalloc", "rgp_correct_batch", "rgp_correct_lsq")
+           "rgp_loss_grad_noalloc", "rgp_correct_batch", "rgp_correct_lsq", "rgp_restrict_image",
+           "rgp_restrict_image_adjoint")
 
 # rgp_kernel_kind
 KERNEL_PCG_STEP, KERNEL_LOSS_GRAD, KERNEL_TRIAL, KERNEL_HVP, KERNEL_OT, KERNEL_SHIFT, \
@@ -124,7 +125,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                     vp]
     lib.rgp_timing_stop.argtypes = [ctypes.POINTER(TimingRecord), i32, ctypes.POINTER(i32)]
     lib.rgp_blur_field.argtypes = [gp, ctypes.c_int, vp, vp, vp]
-    for name in ("rgp_blur_field", "rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
+    lib.rgp_restrict_image.argtypes = [gp, ctypes.c_int, vp, ctypes.c_int, vp, vp]
+    lib.rgp_restrict_image_adjoint.argtypes = [gp, ctypes.c_int, vp, vp, i32, vp]
+    for name in ("rgp_restrict_image", "rgp_restrict_image_adjoint", "rgp_blur_field", "rgp_ot_init", "rgp_loss_grad", "rgp_gn_hvp", "rgp_pcg_solve",
                  "rgp_apply_correction", "rgp_correct", "rgp_workspace_size", "rgp_correct_plan",
                  "rgp_loss_grad_noalloc", "rgp_correct_batch", "rgp_correct_lsq",
                  "rgp_plan_launch", "rgp_plan_destroy", "rgp_timing_start", "rgp_timing_stop",
@@ -320,6 +323,45 @@ def loss_grad_images(I_plus, I_minus, b, pe, h=(1.0, 1.0, 1.0), *, stream=None):
         ctypes.byref(g), dtype_code(I_plus.dtype), _ptr(I_plus), _ptr(I_minus),
         dtype_code(b.dtype), _ptr(b), _ptr(gp), _ptr(gm), _stream_ptr(stream)))
     return gp, gm
+
+
+def coarse_shape(shape: Sequence[int]) -> Tuple[int, int, int]:
+    """Cell shape of the next coarser pyramid level: ceil(m / 2) per axis."""
+    return tuple((int(m) + 1) // 2 for m in shape)
+
+
+def restrict_image(I, real_dtype=None, *, stream=None):
+    """The image on the next coarser pyramid level (rgp_restrict_image): means of 2x2x2 blocks,
+    in real_dtype (default: the image's dtype, FP32 for BF16 images)."""
+    _dev_check(I)
+    if real_dtype is None:
+        real_dtype = torch.float32 if I.dtype == torch.bfloat16 else I.dtype
+    out = torch.empty(coarse_shape(I.shape), dtype=real_dtype, device=I.device)
+    g = make_grid(tuple(I.shape), 0)
+    _check("rgp_restrict_image", load().rgp_restrict_image(
+        ctypes.byref(g), dtype_code(I.dtype), _ptr(I), dtype_code(real_dtype), _ptr(out),
+        _stream_ptr(stream)))
+    return out
+
+
+def restrict_image_adjoint(g_coarse, fine_shape, *, out=None, accumulate=False, stream=None):
+    """R^T g_coarse in the fine shape (rgp_restrict_image_adjoint); with `accumulate` it is added
+    to `out`, which then must be given."""
+    if accumulate and out is None:
+        raise ValueError("accumulate needs out")
+    fine_shape = tuple(int(m) for m in fine_shape)
+    if tuple(g_coarse.shape) != coarse_shape(fine_shape):
+        raise ValueError("g_coarse does not have the coarse shape of fine_shape")
+    if out is None:
+        out = torch.empty(fine_shape, dtype=g_coarse.dtype, device=g_coarse.device)
+    elif tuple(out.shape) != fine_shape or out.dtype != g_coarse.dtype:
+        raise ValueError("out must have the fine shape and g_coarse's dtype")
+    _dev_check(g_coarse, out)
+    g = make_grid(fine_shape, 0)
+    _check("rgp_restrict_image_adjoint", load().rgp_restrict_image_adjoint(
+        ctypes.byref(g), dtype_code(g_coarse.dtype), _ptr(g_coarse), _ptr(out),
+        1 if accumulate else 0, _stream_ptr(stream)))
+    return out
 
 
 def pcg_solve(hdiag, hoff, rhs, shape, pe, h=(1.0, 1.0, 1.0), alpha=300.0, *, maxit=10,

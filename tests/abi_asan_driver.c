@@ -111,6 +111,15 @@ int main(void) {
   EXPECT(rgp_correct(&g, RGP_F32, fake, fake, RGP_F32, &o, NULL, fake, NULL, NULL, NULL,
                      (void*)0x1004, 1 << 30, NULL), RGP_EWORKSPACE);
   EXPECT(rgp_blur_field(&g, RGP_F32, fake, fake, NULL), RGP_EINVAL);
+  /* pyramid transfers of images: distinct buffers, field-type results, extents >= 1 */
+  EXPECT(rgp_restrict_image(&g, RGP_F32, fake, RGP_F32, fake, NULL), RGP_EINVAL);
+  EXPECT(rgp_restrict_image(&g, RGP_F32, fake, RGP_BF16, (void*)0x2000, NULL), RGP_EDTYPE);
+  EXPECT(rgp_restrict_image(NULL, RGP_F32, fake, RGP_F32, (void*)0x2000, NULL), RGP_EINVAL);
+  rgp_grid g0 = grid(0, 4, 4, 1);
+  EXPECT(rgp_restrict_image(&g0, RGP_F32, fake, RGP_F32, (void*)0x2000, NULL), RGP_ESHAPE);
+  EXPECT(rgp_restrict_image_adjoint(&g, RGP_BF16, fake, (void*)0x2000, 0, NULL), RGP_EDTYPE);
+  EXPECT(rgp_restrict_image_adjoint(&g, RGP_F64, fake, fake, 1, NULL), RGP_EINVAL);
+  EXPECT(rgp_restrict_image_adjoint(&g, RGP_F64, NULL, fake, 0, NULL), RGP_EINVAL);
   EXPECT(rgp_plan_launch(NULL, NULL), RGP_EINVAL);
   if (failures) {
     fprintf(stderr, "%d unexpected status codes\n", failures);

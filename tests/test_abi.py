@@ -144,6 +144,19 @@ def test_entry_points_reject_bad_arguments_without_device(lib):
     assert lib.rgp_blur_field(ctypes.byref(g), rgp.F32, fake, fake, None) == -1
     assert lib.rgp_blur_field(ctypes.byref(g), rgp.BF16, fake, ctypes.c_void_p(0x2000), None) == -3
     assert lib.rgp_blur_field(None, rgp.F32, fake, ctypes.c_void_p(0x2000), None) == -1
+    # pyramid transfers of images: distinct buffers, field-type results, extents >= 1
+    assert lib.rgp_restrict_image(ctypes.byref(g), rgp.F32, fake, rgp.F32, fake, None) == -1
+    assert lib.rgp_restrict_image(ctypes.byref(g), rgp.F32, fake, rgp.BF16,
+                                  ctypes.c_void_p(0x2000), None) == -3
+    assert lib.rgp_restrict_image(ctypes.byref(g), rgp.F64, fake, rgp.F32,
+                                  ctypes.c_void_p(0x2000), None) == -3
+    g0 = rgp.make_grid((0, 4, 4), 1)
+    assert lib.rgp_restrict_image(ctypes.byref(g0), rgp.F32, fake, rgp.F32,
+                                  ctypes.c_void_p(0x2000), None) == -2
+    assert lib.rgp_restrict_image_adjoint(ctypes.byref(g), rgp.BF16, fake,
+                                          ctypes.c_void_p(0x2000), 0, None) == -3
+    assert lib.rgp_restrict_image_adjoint(ctypes.byref(g), rgp.F64, fake, fake, 1, None) == -1
+    assert lib.rgp_restrict_image_adjoint(ctypes.byref(g), rgp.F64, None, fake, 0, None) == -1
     # OT columns beyond the kernel's 8192 cells: RGP_ESHAPE before anything is launched
     gl = rgp.make_grid((9000, 2, 2), 0)
     assert lib.rgp_ot_init(ctypes.byref(gl), rgp.F32, fake, fake, rgp.F32, fake, 1e-3, 1, None,

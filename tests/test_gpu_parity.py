@@ -665,6 +665,170 @@ def test_autograd_c2_bf16_directional_fd():
     say(f"[autograd c2 bf16] worst |fd - g.d| / |fd| = {worst:.2e} (|grad J| = {gn:.3e})")
 
 
+# ---- the objective over the pyramid levels, checkpointed per level ----------------------------
+
+@pytest.mark.parametrize("shape", [(7, 5, 6), (8, 8, 8), (1, 3, 2), (37, 29, 23)])
+@pytest.mark.parametrize("img,real", [("f64", "f64"), ("f32", "f32"), ("bf16", "f32"),
+                                      ("f32", "f64")])
+def test_restrict_image_parity(shape, img, real):
+    """rgp_restrict_image against the oracle's 2x2x2 block means (FP64 sums rounded once)."""
+    rgp = _rgp()
+    say(f"[restrict] shape={shape} img={img} real={real}")
+    it, dt = IMG[img], REAL[real]
+    I = rounded(np.random.default_rng(81).standard_normal(shape), it)
+    out = rgp.restrict_image(to_dev(I, it), dt)
+    ref = orc.restrict_image(I)
+    assert tuple(out.shape) == ref.shape and out.dtype == dt
+    tol = 2e-15 if real == "f64" else 1.2e-7
+    assert np.max(np.abs(to_host(out) - ref)) <= tol * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("shape", [(7, 5, 6), (8, 8, 8), (1, 3, 2), (37, 29, 23)])
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_restrict_image_adjoint_parity(shape, real):
+    """rgp_restrict_image_adjoint against the oracle's R^T, written and accumulated."""
+    rgp = _rgp()
+    say(f"[restrict adjoint] shape={shape} real={real}")
+    dt = REAL[real]
+    rng = np.random.default_rng(82)
+    g = rounded(rng.standard_normal(rgp.coarse_shape(shape)), dt)
+    base = rounded(rng.standard_normal(shape), dt)
+    ref = orc.restrict_image_T(g, shape)
+    out = rgp.restrict_image_adjoint(to_dev(g, dt), shape)
+    np.testing.assert_array_equal(to_host(out), ref)   # division by 1, 2, 4 or 8: exact
+    acc = to_dev(base, dt)
+    rgp.restrict_image_adjoint(to_dev(g, dt), shape, out=acc, accumulate=True)
+    # one correctly rounded addition per element
+    np.testing.assert_allclose(to_host(acc), base + ref, rtol=_tol(real, 2.3e-16, 1.2e-7), atol=0)
+
+
+def _pyramid_fields(shape, pe, levels, dt, seed, amp=1.0):
+    fields, s = [], tuple(shape)
+    for l in range(levels):
+        if l:
+            s = tuple((m + 1) // 2 for m in s)
+        fields.append(rounded(smooth_field(s, pe, seed=seed + l, amp=amp, max_slope=0.3), dt))
+    return fields
+
+
+@pytest.mark.parametrize("real,img", [("f64", "f64"), ("f32", "f32"), ("f32", "bf16")])
+@pytest.mark.parametrize("shape,pe", [SHAPES[1], SHAPES[3]])
+def test_pyramid_autograd_matches_oracle(shape, pe, real, img):
+    """The objective summed over three pyramid levels: the value, every level's field gradient
+    and the finest images' gradients against the oracle on the same rounded inputs."""
+    from paper_2403_10706_amd import autograd as ag
+    _rgp()
+    say(f"[pyramid autograd] shape={shape} pe={pe} real={real} img={img}")
+    p = _pair(shape, pe, seed=83)
+    h, w = (1.0, 1.2, 0.9), (1.0, 0.5, 2.0)
+    it, dt = IMG[img], REAL[real]
+    Ip, Im = rounded(p.I_plus, it), rounded(p.I_minus, it)
+    fields = _pyramid_fields(shape, pe, 3, dt, seed=84)
+    tIp = to_dev(Ip, it).requires_grad_()
+    tIm = to_dev(Im, it).requires_grad_()
+    tb = [to_dev(b, dt).requires_grad_() for b in fields]
+    J = ag.pyramid_objective(tIp, tIm, tb, pe, h, weights=w)
+    J.backward()
+    if real == "f64":
+        Jr, gb, gp, gm = orc.pyramid_objective(Ip, Im, fields, pe, h, weights=w)
+    else:   # the device restricts into the field type level by level: the oracle takes the same
+        # rounded coarse images (each the FP32 rounding of the block means of the level above)
+        levels, P, M = [], np.asarray(Ip, np.float64), np.asarray(Im, np.float64)
+        for l in range(3):
+            if l:
+                P, M = rounded(orc.restrict_image(P), dt), rounded(orc.restrict_image(M), dt)
+            levels.append((P, M))
+        Jr, gb = 0.0, []
+        gi = []
+        for l, ((P, M), b) in enumerate(zip(levels, fields)):
+            hl = tuple(x * 2 ** l for x in h)
+            obj, g, _ = orc.objective_gradient(P, M, b, pe, hl)
+            gpl, gml = orc.image_gradient(P, M, b, pe, hl)
+            Jr += w[l] * obj.J
+            gb.append(w[l] * g)
+            gi.append((w[l] * gpl, w[l] * gml))
+        gp, gm = gi[2]
+        for l in (1, 0):
+            fine = levels[l][0].shape
+            gp = gi[l][0] + orc.restrict_image_T(gp, fine)
+            gm = gi[l][1] + orc.restrict_image_T(gm, fine)
+    assert float(J.detach()) == pytest.approx(Jr, rel=_tol(real, 1e-12, J_RTOL))
+    for l in range(3):
+        assert rel2(to_host(tb[l].grad), gb[l]) <= _tol(real, 1e-11, VEC_RTOL), l
+    tol_img = {"f64": 1e-11, "f32": VEC_RTOL, "bf16": 1e-2}[img]
+    assert tIp.grad.dtype == it and tIm.grad.dtype == it
+    assert rel2(to_host(tIp.grad), gp) <= tol_img
+    assert rel2(to_host(tIm.grad), gm) <= tol_img
+
+
+def test_pyramid_autograd_gradcheck_fp64():
+    """torch.autograd.gradcheck of the per-level checkpointed backward, FP64, two levels of a
+    tiny grid: both images with steps of 1e-3 (J is quadratic in them, and J ~ 6e3 here would
+    leave smaller steps at the rounding level), both fields with steps of 1e-6."""
+    from paper_2403_10706_amd import autograd as ag
+    _rgp()
+    shape, pe, h = (6, 7, 5), 1, (1.0, 0.9, 1.1)
+    p = _pair(shape, pe, seed=85)
+    dt = torch.float64
+    fields = [to_dev(b, dt) for b in _pyramid_fields(shape, pe, 2, dt, seed=86, amp=0.5)]
+    Ip, Im = to_dev(p.I_plus, dt), to_dev(p.I_minus, dt)
+    assert torch.autograd.gradcheck(
+        lambda a, c: ag.pyramid_objective(a, c, fields, pe, h),
+        (Ip.clone().requires_grad_(), Im.clone().requires_grad_()), eps=1e-3, atol=1e-7,
+        rtol=1e-5)
+    assert torch.autograd.gradcheck(
+        lambda b0, b1: ag.pyramid_objective(Ip, Im, [b0, b1], pe, h),
+        tuple(b.clone().requires_grad_() for b in fields), eps=1e-6, atol=1e-7, rtol=1e-5)
+
+
+@pytest.mark.timeout(900)
+def test_pyramid_autograd_c2_bf16_directional_fd():
+    """The 144x168x111 pair with BF16 images and FP32 fields on three levels: the field gradients
+    against the oracle's FP64 gradients on the same inputs, and 16 seeded directions through all
+    three fields against central differences (h = 1e-3) of the oracle's level sum within 1e-3
+    relative; the image gradient along 2 directions against the oracle's exact central
+    difference (the level sum is quadratic in the finest images)."""
+    from paper_2403_10706_amd import autograd as ag
+    _rgp()
+    p = synth.make_workload("c2")
+    bf, f32 = torch.bfloat16, torch.float32
+    h = (1.0, 1.0, 1.0)
+    Ip, Im = rounded(p.I_plus, bf), rounded(p.I_minus, bf)
+    fields = _pyramid_fields(p.shape, p.pe, 3, f32, seed=87, amp=3.0)
+    tIp = to_dev(Ip, bf).requires_grad_()
+    tb = [to_dev(b, f32).requires_grad_() for b in fields]
+    J = ag.pyramid_objective(tIp, to_dev(Im, bf), tb, p.pe, h)
+    J.backward()
+    Jr, gb, gp, _ = orc.pyramid_objective(Ip, Im, fields, p.pe, h)
+    assert float(J.detach()) == pytest.approx(Jr, rel=J_RTOL)
+    g = [to_host(t.grad) for t in tb]
+    for l in range(3):
+        assert rel2(g[l], gb[l]) <= VEC_RTOL, l
+    rng = np.random.default_rng(1001)
+    worst = 0.0
+    say("[pyramid c2 bf16] 16 field directions against oracle central differences")
+    for k in range(16):
+        d = [rng.standard_normal(b.shape) for b in fields]
+        d = [x / np.abs(x).max() for x in d]
+        Jp = orc.pyramid_objective(Ip, Im, [b + 1e-3 * x for b, x in zip(fields, d)], p.pe, h,
+                                   grad=False)[0]
+        Jm = orc.pyramid_objective(Ip, Im, [b - 1e-3 * x for b, x in zip(fields, d)], p.pe, h,
+                                   grad=False)[0]
+        fd = (Jp - Jm) / 2e-3
+        an = sum(float(np.sum(gl * x)) for gl, x in zip(g, d))
+        worst = max(worst, abs(fd - an) / abs(fd))
+        assert abs(fd - an) <= 1e-3 * abs(fd), (k, fd, an)
+    gI = to_host(tIp.grad).astype(np.float64)
+    for k in range(2):
+        dI = rng.standard_normal(Ip.shape)
+        Jp = orc.pyramid_objective(Ip + 0.5 * dI, Im, fields, p.pe, h, grad=False)[0]
+        Jm = orc.pyramid_objective(Ip - 0.5 * dI, Im, fields, p.pe, h, grad=False)[0]
+        fd = (Jp - Jm) / 1.0
+        assert float(np.sum(gI * dI)) == pytest.approx(fd, rel=1e-2), k
+        assert float(np.sum(gp * dI)) == pytest.approx(fd, rel=1e-9), k
+    say(f"[pyramid c2 bf16] worst |fd - g.d| / |fd| = {worst:.2e}")
+
+
 # ---- batching: pairs of uneven shapes and PE axes in shared launches -------------------------
 
 BATCH_SPECS = [((40, 48, 36), 1), ((45, 30, 26), 0), ((33, 41, 29), 1), ((28, 36, 44), 0),

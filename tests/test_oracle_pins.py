@@ -528,6 +528,8 @@ def test_pyramid_objective_one_level_and_level_sum():
     Jc = rgp.objective(rgp.restrict_image(Ip), rgp.restrict_image(Im), fields[1], pe,
                        tuple(2 * x for x in h)).J
     assert J2 == pytest.approx(obj.J + Jc, rel=1e-14)
+    assert rgp.pyramid_objective(Ip, Im, fields, pe, h, grad=False)[0] == pytest.approx(J2,
+                                                                                       rel=1e-14)
 
 
 @pytest.mark.parametrize("pe", [0, 1, 2])
