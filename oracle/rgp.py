@@ -713,13 +713,18 @@ def pyramid(Ip, Im, h, levels):
     return out
 
 
-def pyramid_objective(Ip, Im, fields, pe, h, alpha=ALPHA, beta=BETA, weights=None):
+def pyramid_objective(Ip, Im, fields, pe, h, alpha=ALPHA, beta=BETA, weights=None, grad=True):
     """sum_l w_l J_l(R^l I+, R^l I-, b_l, 2^l h) over the levels of the pyramid (Sec. 3.4; the
     field of each level given) and its gradients: (J, [dJ/db_l], dJ/dI+, dJ/dI-), the image
-    gradients carried to the finest level by the adjoint restriction, coarsest level first."""
+    gradients carried to the finest level by the adjoint restriction, coarsest level first.
+    With grad=False: (J, None, None, None)."""
     L = len(fields)
     w = [1.0] * L if weights is None else [float(x) for x in weights]
     levels = pyramid(Ip, Im, h, L)
+    if not grad:
+        J = sum(wl * objective(P, M, b, pe, hl, alpha, beta).J
+                for (P, M, hl), b, wl in zip(levels, fields, w))
+        return J, None, None, None
     J = 0.0
     gb, gi = [], []
     for (P, M, hl), b, wl in zip(levels, fields, w):
