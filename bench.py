@@ -724,6 +724,28 @@ def main():
         f"{nonlinear['steps_that_backtracked']} of {len(trials_nl)} steps backtracked")
     del Ip_nl, Im_nl
 
+    # ---- the 7T-shaped pair: 200x200x132, PE dim 0, 4 levels, same schedule; its own plan ----
+    pair3 = synth.make_workload("c3")
+    opts3 = rgp.Options(levels=4, gn_iters=GN_ITERS, pcg_iters=PCG_ITERS, pcg_rtol=0.0)
+    Ip3 = torch.as_tensor(pair3.I_plus).to(dev, dt).contiguous()
+    Im3 = torch.as_tensor(pair3.I_minus).to(dev, dt).contiguous()
+    ws3 = torch.zeros(rgp.workspace_size(rgp.OP_CORRECT, pair3.shape, pair3.pe, (1.0, 1.0, 1.0),
+                                         dt, opts3.to_c()), dtype=torch.uint8, device=dev)
+    b3 = torch.empty(rgp.field_shape(pair3.shape, pair3.pe), dtype=dt, device=dev)
+    xl3 = rgp.autotune(pair3.shape, pair3.pe, dt, opts3, ws=ws3, stream=side)
+    plan3 = rgp.Plan(Ip3, Im3, pair3.pe, opts3, b3, torch.empty_like(Ip3), torch.empty_like(Im3),
+                     ws3, stream=side)
+    for _ in range(max(1, args.warmup)):
+        plan3.launch(side)
+    wall3, _ = timed(lambda: plan3.launch(side), args.steps)
+    plan3.close()
+    c3 = dict(workload="200x200x132 pair, PE dim 0, FP32, 4 levels x 10 GN x 20 PCG (7T-shaped)",
+              value=round(args.steps / wall3, 3), unit="pairs/s",
+              ms_per_step=round(1e3 * wall3 / args.steps, 4), tuned_march=list(xl3),
+              max_abs_b=round(float(torch.max(torch.abs(b3))), 4))
+    log(f"bench: 200x200x132 pair {c3['value']:.2f} pairs/s ({c3['ms_per_step']:.3f} ms)")
+    del Ip3, Im3, ws3, b3
+
     # ---- eager pass with kernel timing: per-kernel durations from HIP events ----
     ne = max(1, args.eager_steps)
     rgp.timing_start(1 << 16)
@@ -810,7 +832,8 @@ def main():
                     shape=list(shape), pe_dim=pe, levels=LEVELS, gn_iters=GN_ITERS,
                     pcg_iters=PCG_ITERS, global_batch=1, pcg_march_lengths=tuned_xl),
         gpu_ms_per_step=round(gpu_ms / args.steps, 4), eager_ms_per_step=round(eager_ms, 4),
-        roofline=roofline, kernels=kernels, nonlinear=nonlinear, batch=batch, cpu_baseline=cpu,
+        roofline=roofline, kernels=kernels, nonlinear=nonlinear, c3=c3, batch=batch,
+        cpu_baseline=cpu,
         device=torch.cuda.get_device_name(0),
     )
     print(json.dumps(line), flush=True)
