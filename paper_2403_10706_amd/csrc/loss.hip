@@ -766,8 +766,9 @@ hipError_t launch_loss_grad(const LossGradArgs& a0, DType img, DType real, hipSt
   // timing tag 1: the launch also applies the previous step (reads q, writes b + gamma q)
   const int tag = a.step ? 1 : 0;
   if (active_recorder()) {
-    record_launch(RecKind::kLossGrad, a, L.grid, L.block, 0, (int)img, (int)real, 0,
+    const hipError_t e = record_launch(RecKind::kLossGrad, a, L.grid, L.block, 0, (int)img, (int)real, 0,
                   [a, img, real](hipStream_t s2) { return launch_loss_grad(a, img, real, s2); });
+    if (e != hipSuccess) return e;
     return note_volume(a.g.ncell, a.g.nnode, tag);
   }
 #define RGP_LG(RUN, STEP)                                                                    \
@@ -799,8 +800,9 @@ hipError_t launch_loss_final(const LossFinalArgs& a, hipStream_t s) {
 hipError_t launch_trial(const TrialArgs& a, DType img, DType real, hipStream_t s) {
   const Launch L = plan_trial(a.g, real, a.nc);
   if (active_recorder()) {
-    record_launch(RecKind::kTrial, a, L.grid, L.block, 0, (int)img, (int)real, a.nc,
+    const hipError_t e = record_launch(RecKind::kTrial, a, L.grid, L.block, 0, (int)img, (int)real, a.nc,
                   [a, img, real](hipStream_t s2) { return launch_trial(a, img, real, s2); });
+    if (e != hipSuccess) return e;
     return note_volume(a.g.ncell, a.g.nnode, a.nc);
   }
 #define RGP_TRIAL_P(NC, B, P)                                                              \

@@ -718,8 +718,9 @@ hipError_t launch_pcg_step(const PcgArgs& a, DType real, hipStream_t s) {
 
 hipError_t launch_pcg_step_plan(const PcgArgs& a, DType real, const PcgPlan& L, hipStream_t s) {
   if (active_recorder()) {
-    record_launch(RecKind::kPcgStep, a, L.grid, L.block, L.lds, (int)real, L.npt, L.hmax,
+    const hipError_t e = record_launch(RecKind::kPcgStep, a, L.grid, L.block, L.lds, (int)real, L.npt, L.hmax,
                   [a, real](hipStream_t s2) { return launch_pcg_step(a, real, s2); }, &L.m);
+    if (e != hipSuccess) return e;
     return note_volume(a.g.ncell, a.g.nnode, a.sc.iter);
   }
   if (2 * L.m.nb > L.hmax * (int)L.block) return hipErrorInvalidValue;
