@@ -739,12 +739,22 @@ def main():
         plan3.launch(side)
     wall3, _ = timed(lambda: plan3.launch(side), args.steps)
     plan3.close()
+    # one eager correction with kernel timing: the finest level's kernels (5.3 M nodes)
+    Tp3, Tm3 = torch.empty_like(Ip3), torch.empty_like(Im3)
+    rgp.timing_start(1 << 14)
+    timed(lambda: rgp.correct_into(Ip3, Im3, pair3.pe, opts3, b3, Tp3, Tm3, ws3, stream=side), 1)
+    recs3 = rgp.timing_stop(1 << 14)
+    nb3 = int(np.prod(rgp.field_shape(pair3.shape, pair3.pe)))
+    k3 = {name: rec for name, rec in summarize_records(recs3).items() if rec["nodes"] == nb3}
     c3 = dict(workload="200x200x132 pair, PE dim 0, FP32, 4 levels x 10 GN x 20 PCG (7T-shaped)",
               value=round(args.steps / wall3, 3), unit="pairs/s",
               ms_per_step=round(1e3 * wall3 / args.steps, 4), tuned_march=list(xl3),
-              max_abs_b=round(float(torch.max(torch.abs(b3))), 4))
+              max_abs_b=round(float(torch.max(torch.abs(b3))), 4), kernels=k3)
     log(f"bench: 200x200x132 pair {c3['value']:.2f} pairs/s ({c3['ms_per_step']:.3f} ms)")
-    del Ip3, Im3, ws3, b3
+    for name, rec in k3.items():
+        log(f"bench: 200x200x132 {name:28s} n={rec['launches']:4d} {rec['us_mean']:8.2f} us  "
+            f"{rec['achieved_GBps']:7.1f} GB/s  frac {rec['frac']:.3f}")
+    del Ip3, Im3, ws3, b3, Tp3, Tm3
 
     # ---- eager pass with kernel timing: per-kernel durations from HIP events ----
     ne = max(1, args.eager_steps)
