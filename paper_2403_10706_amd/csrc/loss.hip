@@ -241,7 +241,11 @@ __device__ __forceinline__ void loss_grad_body(const LossGradArgs& a, VBlock vb)
     }
 
     // 4. per node k = k0 + s: cells k-1 (index s, its upper node) and k (index s+1, its lower
-    //    node), the Laplacian (Neumann) and the forward differences of S
+    //    node), the Laplacian (Neumann) and the forward differences of S.  The cross-axis terms
+    //    take the column's weights, 0 for a missing neighbour: adding a zero term leaves every
+    //    sum exactly as skipping it would, without a select per node and term.
+    const TR wxm = c.hasxm ? wx2 : TR(0), wxp = c.hasxp ? wx2 : TR(0);
+    const TR wym = c.hasym ? wy2 : TR(0), wyp = c.hasyp ? wy2 : TR(0);
     TR tst = TR(0), tg2 = TR(0);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -254,10 +258,16 @@ __device__ __forceinline__ void loss_grad_body(const LossGradArgs& a, VBlock vb)
       TR lap = TR(0), ldg = TR(0), st = TR(0);
       if (lo) { lap = fma(dpm, wp2, lap); ldg += wp2; }
       if (up) { lap = fma(-dpp, wp2, lap); ldg += wp2; st = fma(dpp * dpp, wp2, st); }
-      if (c.hasxm) { lap = fma(dxm, wx2, lap); ldg += wx2; }
-      if (c.hasxp) { lap = fma(-dxp, wx2, lap); ldg += wx2; st = fma(dxp * dxp, wx2, st); }
-      if (c.hasym) { lap = fma(dym, wy2, lap); ldg += wy2; }
-      if (c.hasyp) { lap = fma(-dyp, wy2, lap); ldg += wy2; st = fma(dyp * dyp, wy2, st); }
+      lap = fma(dxm, wxm, lap);
+      ldg += wxm;
+      lap = fma(-dxp, wxp, lap);
+      ldg += wxp;
+      st = fma(dxp * dxp, wxp, st);
+      lap = fma(dym, wym, lap);
+      ldg += wym;
+      lap = fma(-dyp, wyp, lap);
+      ldg += wyp;
+      st = fma(dyp * dyp, wyp, st);
       TR gk = (lo ? gU[s] : TR(0)) + (up ? gD[s + 1] : TR(0)) + avol * lap;
       TR dk = (lo ? dU[s] : TR(0)) + (up ? dD[s + 1] : TR(0)) + avol * ldg;
       if (prox) {   // (rho vol / 2)|b - c|^2: gradient rho vol e, diagonal rho vol
@@ -425,15 +435,14 @@ __device__ __forceinline__ void trial_body(const TrialArgs& a, VBlock vb) {
           sbq = fma(db * dq, wp2, sbq);
           sqq = fma(dq * dq, wp2, sqq);
         }
-        if (c.hasxp) {
-          const TR db = bxp[s] - bk, dq = qxp[s] - qk;
-          sbq = fma(db * dq, wx2, sbq);
-          sqq = fma(dq * dq, wx2, sqq);
-        }
-        if (c.hasyp) {
-          const TR db = by - bk, dq = qy - qk;
-          sbq = fma(db * dq, wy2, sbq);
-          sqq = fma(dq * dq, wy2, sqq);
+        {  // cross-axis terms with weight 0 for a missing neighbour (an exact no-op)
+          const TR wxp = c.hasxp ? wx2 : TR(0), wyp = c.hasyp ? wy2 : TR(0);
+          const TR dbx = bxp[s] - bk, dqx = qxp[s] - qk;
+          sbq = fma(dbx * dqx, wxp, sbq);
+          sqq = fma(dqx * dqx, wxp, sqq);
+          const TR dby = by - bk, dqy = qy - qk;
+          sbq = fma(dby * dqy, wyp, sbq);
+          sqq = fma(dqy * dqy, wyp, sqq);
         }
         if (prox) {   // the proximal term as part of S: (rho / alpha)(e q, q^2) with e = b - c
           const TR e = bk - bld<TR>(rC, noff(min(k, mp)));
