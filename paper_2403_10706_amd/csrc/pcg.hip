@@ -408,11 +408,23 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
   if (sl.status == kPcgDone) return;
   const TR al = first ? TR(0) : (TR)sl.alpha, be = first ? TR(0) : (TR)sl.beta;
   if (sl.status == kPcgFinish) {  // last update x += a p of the previous iteration (pointwise)
-    TR* __restrict__ x = static_cast<TR*>(a.x);
-    const TR* __restrict__ pi = static_cast<const TR*>(a.p_in);
+    // kFin nodes per thread and round, all loads in flight together (past the end: kNullOff)
+    constexpr int kFin = 8;
     const int64_t stride = (int64_t)vb.n * blockDim.x;
-    for (int64_t i = (int64_t)vb.id * blockDim.x + threadIdx.x; i < g.nnode; i += stride)
-      x[i] = x[i] + al * pi[i];
+    for (int64_t i0 = (int64_t)vb.id * blockDim.x + threadIdx.x; i0 < g.nnode;
+         i0 += kFin * stride) {
+      uint32_t o[kFin];
+      TR xv[kFin], pv[kFin];
+#pragma unroll
+      for (int u = 0; u < kFin; ++u) {
+        const int64_t i = i0 + u * stride;
+        o[u] = off_at(i < g.nnode, i);
+        xv[u] = bld<TR>(rX, o[u]);
+        pv[u] = bld<TR>(rPi, o[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kFin; ++u) bst<TR>(rX, o[u], xv[u] + al * pv[u]);
+    }
     return;
   }
   const TR sgn = (TR)a.rhs_sign;
