@@ -392,16 +392,17 @@ __device__ __forceinline__ void pcg_step_body(const PcgArgs& a, const MarchGeo& 
     }
   };
 
-  // Fused: the previous iteration's block sums (iteration 0: loss_grad's, in Gauss-Newton mode)
-  // are loaded first, then the first unit's planes, so that the reduction waits for the former
-  // only and the latter arrive meanwhile.
+  // Fused: the previous iteration's block sums are loaded first, then the first unit's planes, so
+  // that the reduction waits for the former only and the latter arrive meanwhile.
   const bool fused = a.sc.fused;
   const PcgSlot prev = load_slot(a.sc.slots, (fused && !first) ? (it - 1) & 1 : it & 1);
   double tsum[7], lsum[5];
   if (fused && !first) load_partials_cm<7>(tsum, a.sc.part_prev, a.sc.nprod, 7);
-  if (fused && first && a.sc.gn_mode) load_partials_rm<5>(lsum, a.sc.lf.part, a.sc.lf.nprod);
   int64_t u = ulo + lb;
   if (u < uhi) begin_unit(u);
+  // iteration 0: loss_grad's block sums after the unit's loads, so that one round trip covers
+  // both (their loop waits for everything issued before it)
+  if (fused && first && a.sc.gn_mode) load_partials_rm<5>(lsum, a.sc.lf.part, a.sc.lf.nprod);
   const PcgSlot sl = !fused ? prev
                             : (first ? pcg_first_phase<BLK>(a.sc, lsum, vb)
                                      : pcg_scalar_phase<BLK>(a.sc, prev, tsum, vb));
