@@ -1671,10 +1671,10 @@ rgp_status rgp_autotune(const rgp_grid* grid, rgp_dtype real_t, const rgp_solver
   Level lv[kMaxLevels];
   if (make_levels(grid, o.levels, lv) != 0) return RGP_ESHAPE;
   const CorrectWs w = carve_correct(ws, lv, o.levels, dr, &o);
-  // Each candidate runs 2 untimed and kReps timed launches; a timed launch carries its own pair
-  // of events, recorded by the launch at the kernel's start and end (kernel time only, whatever
-  // the host's launch rate), and the candidate's figure is the median launch.
-  constexpr int kReps = 9;
+  // Each candidate runs 2 untimed and kReps timed launches per round; a timed launch carries its
+  // own pair of events, recorded by the launch at the kernel's start and end (kernel time only,
+  // whatever the host's launch rate).
+  constexpr int kReps = 9, kRounds = 3;
   hipEvent_t te0[kReps], te1[kReps];
   int nev = 0;
   hipError_t e = hipSuccess;
@@ -1696,52 +1696,66 @@ rgp_status rgp_autotune(const rgp_grid* grid, rgp_dtype real_t, const rgp_solver
     const PcgPlan H = plan_pcg_xl(g, dr, -1);  // the untuned choice
     set_tuned_march(g, dr, 0);
     const int64_t cap = 4096 / ((int64_t)H.block / kWave);
-    int best_xl = H.m.XL;
-    float best_ms = 1e30f;
+    // candidates, timed in kRounds interleaved rounds (so that a slow spell of the device does
+    // not fall on one candidate only); a candidate's figure is the median of all its launches
+    int cand[sizeof(kMarchLengths) / sizeof(int)];
+    int nc = 0;
     for (int xl : kMarchLengths) {
-      if (e != hipSuccess) break;
       const PcgPlan L = plan_pcg_xl(g, dr, xl);
       if (xl > L.m.no || L.m.units > 4 * cap || (L.m.units < cap / 16 && xl != H.m.XL)) continue;
-      PcgArgs pa{};
-      pa.g = g;
-      pa.diag = w.Dg;
-      pa.off = w.Of;
-      pa.rhs = w.G;
-      pa.rhs_sign = -1.0;
-      pa.x = w.X;
-      pa.r_in = w.R[1];
-      pa.p_in = w.P[1];
-      pa.w_in = w.W[1];
-      pa.r_out = w.R[0];
-      pa.p_out = w.P[0];
-      pa.w_out = w.W[0];
-      pa.alpha = o.alpha;
-      pa.part = w.ctl.slot(kPartPcg0);
-      pa.sc.st = w.ctl.st;
-      pa.sc.slots = w.ctl.slots;
-      pa.sc.part_prev = w.ctl.slot(kPartPcg1);
-      pa.sc.nprod = L.grid;
-      pa.sc.iter = 2;              // reads slot 1 and the sums above, writes slot 0
-      pa.sc.maxit = 1 << 30;
-      pa.sc.rtol = 0.0;
-      pa.sc.fused = 1;
-      for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_pcg_step_plan(pa, dr, L, s);
-      t_tune = TuneTiming{te0, te1, kReps, 0};
-      for (int r = 0; r < kReps && e == hipSuccess; ++r) e = launch_pcg_step_plan(pa, dr, L, s);
-      const int timed = t_tune.used;
-      t_tune = TuneTiming{};
-      if (e == hipSuccess && timed != kReps) e = hipErrorUnknown;
-      float t[kReps];
-      for (int r = 0; r < kReps && e == hipSuccess; ++r) {
-        e = hipEventSynchronize(te1[r]);
-        if (e == hipSuccess) e = hipEventElapsedTime(&t[r], te0[r], te1[r]);
+      cand[nc++] = xl;
+    }
+    std::vector<float> samples((size_t)nc * kRounds * kReps);
+    for (int round = 0; round < kRounds && e == hipSuccess; ++round) {
+      for (int ci = 0; ci < nc && e == hipSuccess; ++ci) {
+        const int xl = cand[ci];
+        const PcgPlan L = plan_pcg_xl(g, dr, xl);
+        PcgArgs pa{};
+        pa.g = g;
+        pa.diag = w.Dg;
+        pa.off = w.Of;
+        pa.rhs = w.G;
+        pa.rhs_sign = -1.0;
+        pa.x = w.X;
+        pa.r_in = w.R[1];
+        pa.p_in = w.P[1];
+        pa.w_in = w.W[1];
+        pa.r_out = w.R[0];
+        pa.p_out = w.P[0];
+        pa.w_out = w.W[0];
+        pa.alpha = o.alpha;
+        pa.part = w.ctl.slot(kPartPcg0);
+        pa.sc.st = w.ctl.st;
+        pa.sc.slots = w.ctl.slots;
+        pa.sc.part_prev = w.ctl.slot(kPartPcg1);
+        pa.sc.nprod = L.grid;
+        pa.sc.iter = 2;              // reads slot 1 and the sums above, writes slot 0
+        pa.sc.maxit = 1 << 30;
+        pa.sc.rtol = 0.0;
+        pa.sc.fused = 1;
+        for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_pcg_step_plan(pa, dr, L, s);
+        t_tune = TuneTiming{te0, te1, kReps, 0};
+        for (int r = 0; r < kReps && e == hipSuccess; ++r) e = launch_pcg_step_plan(pa, dr, L, s);
+        const int timed = t_tune.used;
+        t_tune = TuneTiming{};
+        if (e == hipSuccess && timed != kReps) e = hipErrorUnknown;
+        for (int r = 0; r < kReps && e == hipSuccess; ++r) {
+          e = hipEventSynchronize(te1[r]);
+          if (e == hipSuccess)
+            e = hipEventElapsedTime(&samples[((size_t)ci * kRounds + round) * kReps + r], te0[r],
+                                    te1[r]);
+        }
       }
-      if (e != hipSuccess) break;
-      std::sort(t, t + kReps);
-      const float ms = t[kReps / 2];
+    }
+    int best_xl = H.m.XL;
+    float best_ms = 1e30f;
+    for (int ci = 0; ci < nc && e == hipSuccess; ++ci) {
+      float* t = samples.data() + (size_t)ci * kRounds * kReps;
+      std::sort(t, t + kRounds * kReps);
+      const float ms = t[kRounds * kReps / 2];
       if (ms < best_ms) {
         best_ms = ms;
-        best_xl = xl;
+        best_xl = cand[ci];
       }
     }
     if (e == hipSuccess) {
