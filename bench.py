@@ -34,6 +34,7 @@ Other modes (profiling helpers; their output goes under profiles/):
 """
 import argparse
 import csv
+import dataclasses
 import glob
 import hashlib
 import json
@@ -53,6 +54,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pcg_step_c2_traffic.json")
 KERNEL_SOURCES = ("paper_2403_10706_amd/csrc/pcg.hip", "paper_2403_10706_amd/csrc/rgp_internal.hpp",
                   "paper_2403_10706_amd/csrc/rgp_launch.hpp")
 COPY_MIB = 256
+BATCH_LONG_MARCH = 16  # minimum PCG march of the second batched graph (option batch_march)
 
 
 def log(*a):
@@ -555,6 +557,14 @@ def batch_bench(pairs, steps, scale):
     torch.cuda.synchronize()
     recs = rgp.timing_stop(1 << 16)
     batch.close()
+    # the same batch with the batched PCG launches marching at least BATCH_LONG_MARCH planes
+    # per unit (option batch_march): fewer, longer units on the coarse levels
+    opts_long = dataclasses.replace(opts, batch_march=BATCH_LONG_MARCH)
+    batch_long = rgp.BatchPlan(Ip, Im, pes, opts_long, stream=side)
+    batch_long.launch(side)
+    t_long = timed(lambda: batch_long.launch(side), steps)
+    d_lp = [float(torch.max(torch.abs(batch_long.b[i] - bp_out[i]))) for i in range(n)]
+    batch_long.close()
     kernels = {}
     for name, rec in summarize_records(recs).items():
         if rec["kernel"] not in ("pcg_step", "loss_grad", "trial"):
@@ -582,11 +592,17 @@ def batch_bench(pairs, steps, scale):
                speedup=round(t_plain / t_batch, 3), ms_batched=round(1e3 * t_batch, 3),
                ms_plain=round(1e3 * t_plain, 3), steps=steps, cells=cells,
                max_abs_b_batched_vs_plain=max(d_bp),
+               long_march=dict(batch_march=BATCH_LONG_MARCH, batched=round(n / t_long, 3),
+                               ms_batched=round(1e3 * t_long, 3),
+                               speedup=round(t_plain / t_long, 3),
+                               max_abs_b_vs_plain=max(d_lp)),
                rms_error_vs_true_plain=round(float(np.mean(e_plain)), 6),
                rms_error_vs_true_batched=round(float(np.mean(e_batch)), 6),
                kernels=kernels)
     log(f"bench batch: plain {n / t_plain:.2f} pairs/s, batched {n / t_batch:.2f} pairs/s "
         f"(x{t_plain / t_batch:.2f}); max|b_batched - b_plain| = {max(d_bp):.2e}")
+    log(f"bench batch: batch_march={BATCH_LONG_MARCH}: batched {n / t_long:.2f} pairs/s "
+        f"(x{t_plain / t_long:.2f}); max|b - b_plain| = {max(d_lp):.2e}")
     return out
 
 

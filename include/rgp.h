@@ -97,7 +97,15 @@ typedef struct {
                             the Gauss-Newton solve.  In a stats record the PCG iteration field
                             holds the pairs used and the PCG residual field holds H0's scale
                             (1 / max|g| without pairs). */
-  int32_t reserved;
+  int32_t batch_march;   /* batched corrections (rgp_correct_batch_plan, rgp_correct_batch), 0..64:
+                            0 (the default) gives every pair's PCG launches the plane march of
+                            its own rgp_correct, so a pair's field is bitwise its solo result;
+                            N > 0 makes each batched PCG step march at least min(N, planes)
+                            planes per work unit (fewer, longer units: a batch has units to
+                            spare on coarse levels, where a solo plan keeps them short to fill
+                            the chip), which reorders the FP64 block sums of the PCG scalars, so
+                            a pair's field then agrees with its solo one to rounding only.
+                            Ignored by the single-pair calls.  Else RGP_EINVAL. */
   double admm_rho0;      /* RGP_SOLVER_ADMM: initial augmentation parameter rho on every level
                             (<= 0: alpha).  With ADMM, gn_iters counts ADMM iterations per level,
                             each one Gauss-Newton step on F(b) + (rho vol / 2)|b - z + u|^2 with

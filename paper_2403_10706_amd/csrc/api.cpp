@@ -30,6 +30,10 @@ bool& rgp::batch_plans() {
   thread_local bool b = false;
   return b;
 }
+int& rgp::batch_march_min() {
+  thread_local int m = 0;
+  return m;
+}
 
 namespace {
 
@@ -262,6 +266,7 @@ rgp_status check_opts(const rgp_solver_opts* o) {
     return RGP_EINVAL;
   if (o->solver == RGP_SOLVER_LBFGS && (o->lbfgs_memory < 1 || o->lbfgs_memory > kLbfgsMaxMem))
     return RGP_EINVAL;
+  if (o->batch_march < 0 || o->batch_march > kMarchMax) return RGP_EINVAL;
   return RGP_OK;
 }
 
@@ -1363,8 +1368,15 @@ constexpr int kBatchMaxContig = 256;  // nodes along the contiguous axis (one PC
 
 struct BatchPlansScope {
   bool saved;
-  BatchPlansScope() : saved(batch_plans()) { batch_plans() = true; }
-  ~BatchPlansScope() { batch_plans() = saved; }
+  int saved_march;
+  explicit BatchPlansScope(int march_min) : saved(batch_plans()), saved_march(batch_march_min()) {
+    batch_plans() = true;
+    batch_march_min() = march_min;
+  }
+  ~BatchPlansScope() {
+    batch_plans() = saved;
+    batch_march_min() = saved_march;
+  }
 };
 struct RecorderScope {
   Recorder* saved;
@@ -1421,7 +1433,7 @@ rgp_status record_batch(int32_t n, const rgp_grid* grids, rgp_dtype img_t,
   recs.assign((size_t)n, Recorder{});
   size_t off = 0;
   {
-    BatchPlansScope bp;
+    BatchPlansScope bp(opts->batch_march);
     for (int p = 0; p < n; ++p) {
       RecorderScope rs(&recs[(size_t)p]);
       rgp_status st = enqueue_correct(&grids[p], img_t, I_plus[p], I_minus[p], real_t, opts,

@@ -44,6 +44,7 @@ struct Recorder {
 
 Recorder*& active_recorder();
 bool& batch_plans();
+int& batch_march_min();  // while batch_plans(): minimum PCG march length (0: none)
 
 template <typename A>
 inline hipError_t record_launch(RecKind kind, const A& a, unsigned grid, unsigned block,

@@ -671,6 +671,9 @@ PcgPlan plan_pcg_xl(const Geom& g, DType real, int xl_force) {
       }
     }
   }
+  // a batched launch may ask for longer marches than the solo plan (never for a forced length)
+  const int xl_b = batch_plans() && xl_force <= 0 ? batch_march_min() : 0;
+  if (xl_b > m.XL) m = march_geo(g, T, xl_b < m.no ? xl_b : m.no);
   L.m = m;
   int64_t grid = m.units < kMaxGrid ? m.units : kMaxGrid;
   grid = (grid + 7) / 8 * 8;  // whole XCD rounds

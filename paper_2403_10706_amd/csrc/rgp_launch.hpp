@@ -243,6 +243,7 @@ Launch plan_trial(const Geom& g, DType real, int nc);
 PcgPlan plan_pcg(const Geom& g, DType real);
 // Candidate march lengths (planes per work unit) of the PCG step.
 constexpr int kMarchLengths[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+constexpr int kMarchMax = 64;  // longest march a caller may ask for
 PcgPlan plan_pcg_xl(const Geom& g, DType real, int xl);  // xl <= 0: tuned or heuristic
 void set_tuned_march(const Geom& g, DType real, int xl);  // xl <= 0 forgets the entry
 int tuned_march(const Geom& g, DType real);               // 0 when not tuned

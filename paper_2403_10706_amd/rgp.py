@@ -55,7 +55,7 @@ class SolverOpts(ctypes.Structure):
                 ("ot_eps", ctypes.c_double), ("ot_guard", ctypes.c_int32),
                 ("use_b_init", ctypes.c_int32), ("ot_blur", ctypes.c_int32),
                 ("solver", ctypes.c_int32), ("lbfgs_memory", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("admm_rho0", ctypes.c_double)]
+                ("batch_march", ctypes.c_int32), ("admm_rho0", ctypes.c_double)]
 
 
 EXPORTS = ("rgp_status_string", "rgp_last_hip_error", "rgp_default_opts", "rgp_workspace_size",
@@ -427,6 +427,7 @@ class Options:
     solver: str = "gn"          # "gn" (Gauss-Newton-PCG), "lbfgs" or "admm"
     lbfgs_memory: int = 10
     admm_rho0: float = 0.0      # <= 0: alpha
+    batch_march: int = 0        # batched plans: minimum PCG march length (0: the solo plans')
 
     def to_c(self, use_b_init: bool = False) -> SolverOpts:
         o = SolverOpts()
@@ -440,6 +441,7 @@ class Options:
         o.solver = SOLVERS[self.solver]
         o.lbfgs_memory = int(self.lbfgs_memory)
         o.admm_rho0 = float(self.admm_rho0)
+        o.batch_march = int(self.batch_march)
         return o
 
 

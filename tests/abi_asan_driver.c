@@ -51,6 +51,13 @@ int main(void) {
   o.lbfgs_memory = 40;
   EXPECT(rgp_workspace_size(RGP_OP_CORRECT, &g, RGP_F32, &o, &n), RGP_EINVAL);
   rgp_default_opts(&o);
+  o.batch_march = 65;
+  EXPECT(rgp_workspace_size(RGP_OP_CORRECT, &g, RGP_F32, &o, &n), RGP_EINVAL);
+  o.batch_march = -1;
+  EXPECT(rgp_workspace_size(RGP_OP_CORRECT, &g, RGP_F32, &o, &n), RGP_EINVAL);
+  o.batch_march = 64;
+  EXPECT(rgp_workspace_size(RGP_OP_CORRECT, &g, RGP_F32, &o, &n), RGP_OK);
+  rgp_default_opts(&o);
   rgp_grid bad = grid(144, 1, 111, 1);
   EXPECT(rgp_workspace_size(RGP_OP_LOSS_GRAD, &bad, RGP_F32, NULL, &n), RGP_ESHAPE);
   bad = grid(16, 16, 513, 1);

@@ -189,3 +189,9 @@ def test_batch_workspace_size_and_limits(lib):
     c.use_b_init = 1
     g = (rgp.Grid * 1)(rgp.make_grid((16, 16, 20), 1))
     assert lib.rgp_batch_workspace_size(1, g, rgp.F32, ctypes.byref(c), ctypes.byref(n)) == -1
+    # the batch's minimum march length: 0..64
+    g = (rgp.Grid * 1)(rgp.make_grid((16, 16, 20), 1))
+    for march, want in ((0, 0), (16, 0), (64, 0), (-1, -1), (65, -1)):
+        c = rgp.Options(levels=2, gn_iters=2, pcg_iters=3, batch_march=march).to_c()
+        assert lib.rgp_batch_workspace_size(1, g, rgp.F32, ctypes.byref(c),
+                                            ctypes.byref(n)) == want, march

@@ -932,6 +932,44 @@ def test_batch_mixed_marches_bitwise():
     bp.close()
 
 
+
+@pytest.mark.parametrize("real", ["f32", "f64"])
+def test_batch_long_marches_option(real):
+    """batch_march = 16: the batched PCG launches march at least 16 planes per unit, so the
+    coarse level's shared launches run fewer workgroups than with the solo plans' marches, and
+    every pair's field still agrees with its solo correction (to the rounding of the reordered
+    FP64 block sums; the default keeps them bitwise equal, tested above)."""
+    rgp = _rgp()
+    specs = [((188, 144, 80), 0), ((200, 200, 160), 0)]
+    pairs = [_pair(sh, pe, seed=74 + i, scale=30.0) for i, (sh, pe) in enumerate(specs)]
+    pes = [pe for _, pe in specs]
+    dt = REAL[real]
+    Ip = [to_dev(p.I_plus, dt) for p in pairs]
+    Im = [to_dev(p.I_minus, dt) for p in pairs]
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    grids, fields = {}, {}
+    for march in (0, 16):
+        opts = rgp.Options(levels=2, gn_iters=2, pcg_iters=6, pcg_rtol=0.0, batch_march=march)
+        with torch.cuda.stream(s):
+            bp = rgp.BatchPlan(Ip, Im, pes, opts, stream=s, real_dtype=dt)
+            rgp.timing_start()
+            bp.run_eager(s)
+            s.synchronize()
+            recs = rgp.timing_stop()
+        grids[march] = sorted({r["grid"] for r in recs if r["kernel"] == "pcg_step"})
+        fields[march] = [b.clone() for b in bp.b]
+        bp.close()
+    say(f"[batch march {real}] PCG step grids: default {grids[0]}, batch_march=16 {grids[16]}")
+    assert min(grids[16]) < min(grids[0]), grids
+    opts = rgp.Options(levels=2, gn_iters=2, pcg_iters=6, pcg_rtol=0.0)
+    for i, (sh, pe) in enumerate(specs):
+        ref = rgp.correct(Ip[i], Im[i], pe, opts=opts, real_dtype=dt)
+        assert torch.equal(fields[0][i], ref["b"]), i
+        d = float(torch.max(torch.abs(fields[16][i] - ref["b"])))
+        say(f"[batch march {real}] pair {i} {sh}: max|b_long - b_pair| = {d:.3e}")
+        assert d <= _tol(real, 1e-9, 1e-3), (i, d)
+
 def test_autotune_then_correct():
     """The autotuner picks one march length per level from the candidates; afterwards the
     correction (plain and batched) still matches the untuned result up to the order of the block
