@@ -31,6 +31,8 @@ Other modes (profiling helpers; their output goes under profiles/):
                               against one batched graph (its own JSON line)
   --batch-profile-summary D   per-kernel GB/s of the batched launches from a rocprofv3
                               --kernel-trace run of --batch 32 in D
+  --range-summary D           per-level host and GPU time of the eager corrections from a
+                              rocprofv3 --marker-trace --hip-runtime-trace --kernel-trace run in D
 """
 import argparse
 import csv
@@ -373,6 +375,53 @@ def profile_summary(d):
               f"{statistics.median(v):9.2f} {sum(v) / 1e3:9.3f}")
 
 
+def range_summary(d):
+    """Per-level figures of the eager corrections in a rocprofv3 --marker-trace
+    --hip-runtime-trace --kernel-trace run: the library's ROCTx ranges ("rgp: correction",
+    "rgp: level L", "rgp: Gauss-Newton step k") give each launch its correction, level and step
+    (through the launch call's correlation id).  Per Gauss-Newton step: the host time spent
+    enqueueing it, the GPU span of its kernels (first start to last end) and their summed
+    duration; corrections are grouped by their number of levels."""
+    import bisect
+    marks = _csv_rows(d, "*marker_api_trace.csv")
+    api = _csv_rows(d, "*hip_api_trace.csv")
+    kern = _csv_rows(d, "*kernel_trace.csv")
+    ranges = [(r["Function"], int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+              for r in marks if r.get("Function", "").startswith("rgp:")]
+    launch_t = {r["Correlation_Id"]: int(r["Start_Timestamp"]) for r in api}
+    launches = sorted((launch_t[r["Correlation_Id"]], int(r["Start_Timestamp"]),
+                       int(r["End_Timestamp"])) for r in kern if r["Correlation_Id"] in launch_t)
+    times = [t for t, _, _ in launches]
+
+    def inside(a, b):
+        return launches[bisect.bisect_left(times, a):bisect.bisect_right(times, b)]
+
+    def within(name, a, b):
+        return [(m, x, y) for m, x, y in ranges if m.startswith(name) and a <= x and y <= b]
+
+    table = {}
+    for _, ca, cb in [r for r in ranges if r[0] == "rgp: correction"]:
+        if not inside(ca, cb):
+            continue   # recorded into a graph: nothing launched
+        lvs = within("rgp: level ", ca, cb)
+        nlev = len(lvs)
+        for m, la, lb in lvs:
+            for _, sa, sb in within("rgp: Gauss-Newton step", la, lb):
+                ks = inside(sa, sb)
+                if ks:
+                    table.setdefault((nlev, int(m.split()[-1])), []).append((sb - sa, ks))
+    print("== eager corrections by level (library ROCTx ranges; means per Gauss-Newton step) ==")
+    print(f"{'levels':>6s} {'level':>5s} {'steps':>6s} {'kernels':>8s} {'host_enqueue_us':>16s} "
+          f"{'gpu_span_us':>12s} {'gpu_busy_us':>12s}")
+    for (nlev, lv), rows in sorted(table.items(), key=lambda kv: (kv[0][0], -kv[0][1])):
+        n = len(rows)
+        host = sum(h for h, _ in rows) / n / 1e3
+        span = sum(max(e for _, _, e in ks) - min(s0 for _, s0, _ in ks) for _, ks in rows) / n / 1e3
+        busy = sum(sum(e - s0 for _, s0, e in ks) for _, ks in rows) / n / 1e3
+        nk = sum(len(ks) for _, ks in rows) / n
+        print(f"{nlev:6d} {lv:5d} {n:6d} {nk:8.1f} {host:16.1f} {span:12.1f} {busy:12.1f}")
+
+
 def copy_reference(dev, stream, reps=10):
     """Measured bandwidth of a plain device-to-device copy (torch's copy kernel) at two sizes:
     one that fits the 256 MB Infinity Cache together with its source (like the PCG step's working
@@ -620,6 +669,7 @@ def main():
     ap.add_argument("--profile-summary", metavar="DIR")
     ap.add_argument("--counter-summary", metavar="DIR")
     ap.add_argument("--batch-profile-summary", metavar="DIR")
+    ap.add_argument("--range-summary", metavar="DIR")
     ap.add_argument("--batch", type=int, metavar="N", default=0,
                     help="the batching benchmark over N uneven pairs instead of the headline")
     ap.add_argument("--batch-scale", type=float, default=1000.0)
@@ -630,6 +680,8 @@ def main():
         return traffic_summary(*args.traffic_summary)
     if args.profile_summary:
         return profile_summary(args.profile_summary)
+    if args.range_summary:
+        return range_summary(args.range_summary)
     if args.counter_summary:
         return counter_summary(args.counter_summary)
     if args.batch_profile_summary:

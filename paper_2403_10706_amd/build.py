@@ -32,6 +32,11 @@ HIPCC_FLAGS = [
 ]
 
 
+# ROCTx (named host ranges for tracers), found at run time through the ROCm library directory
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+LINK_LIBS = ["-L", ROCM_LIB, "-Wl,-rpath," + ROCM_LIB, "-lrocprofiler-sdk-roctx"]
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -72,7 +77,8 @@ def build(verbose: bool = False, jobs: int = 5, asan: bool = False) -> str:
                 print(out)
         tmp_lib = lib + ".tmp"
         link_asan = ["-Xarch_host", "-fsanitize=address", "-shared-libasan"] if asan else []
-        cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *link_asan, *objs, "-o", tmp_lib]
+        cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *link_asan, *objs, *LINK_LIBS,
+               "-o", tmp_lib]
         res = subprocess.run(cmd, capture_output=True, text=True)
         if res.returncode != 0:
             raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")

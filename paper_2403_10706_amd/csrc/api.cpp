@@ -1,9 +1,12 @@
 // C ABI of librgp: argument validation, workspace layout and the launch sequences of the hot path.
 #include <hip/hip_runtime.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -38,6 +41,21 @@ int& rgp::batch_march_min() {
 namespace {
 
 thread_local int g_last_hip = 0;
+
+// Named host ranges (ROCTx) around the phases of a correction while they are enqueued (or
+// recorded): a tracer (rocprofv3 --marker-trace) shows them beside the launches they issue.  The
+// calls return at once when no tracer is attached.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  Range(const char* fmt, int v) {
+    char buf[48];
+    std::snprintf(buf, sizeof buf, fmt, v);
+    roctxRangePushA(buf);
+  }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 // ---- kernel timing registry -------------------------------------------------------------
 struct TimingRec {
@@ -516,6 +534,7 @@ hipError_t run_level(const CorrectWs& w, const Geom& g, const void* Ip, const vo
   const Launch Llg = plan_loss_grad(g, real);
   const PcgPlan Lpcg = plan_pcg(g, real);
   for (int it = 0; it < o->gn_iters; ++it) {
+    const Range range("rgp: Gauss-Newton step %d", it);
     double* rec = records ? records + (size_t)it * kStatFields : nullptr;
     LossGradArgs la{};
     la.g = g;
@@ -1078,6 +1097,7 @@ rgp_status enqueue_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_
   if (make_levels(grid, L, lv) != 0) return RGP_ESHAPE;
   CorrectWs w = carve_correct(ws, lv, L, dr, opts);
   const size_t rs = dsize(dr);
+  const Range range("rgp: correction");
 
   RGP_HIP(launch_reset(SetStateArgs{w.ctl.st, w.ctl.guarded}, s));
   const int64_t nrec = (int64_t)L * opts->gn_iters;
@@ -1091,6 +1111,7 @@ rgp_status enqueue_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_
   imgs[0][1] = I_minus;
   ity[0] = di;
   for (int l = 1; l < L; ++l) {
+    const Range rl("rgp: restrict to level %d", l);
     for (int i = 0; i < 2; ++i) {
       RestrictArgs ra{};
       ra.src = imgs[l - 1][i];
@@ -1108,6 +1129,7 @@ rgp_status enqueue_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_
   // Initial field on the coarsest level.
   const Level& top = lv[L - 1];
   if (opts->use_b_init) {
+    const Range ri("rgp: b_init");
     RGP_HIP(copy_d2d(w.B[0], b_init, top.g.nnode * rs, s));
     // input scan for non-finite values (the OT path does it in its shift kernel)
     RGP_HIP(launch_shift(ShiftArgs{imgs[L - 1][0], imgs[L - 1][1], top.g.ncell,
@@ -1115,6 +1137,7 @@ rgp_status enqueue_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_
                          ity[L - 1], s));
     RGP_HIP(launch_scan_status(w.ctl.slot(kPartShift), shift_grid(top.g.ncell), w.ctl.st, s));
   } else {
+    const Range ri("rgp: OT init");
     RGP_HIP(launch_shift(ShiftArgs{imgs[L - 1][0], imgs[L - 1][1], top.g.ncell,
                                    w.ctl.slot(kPartShift), w.ctl.guarded},
                          ity[L - 1], s));
@@ -1144,6 +1167,7 @@ rgp_status enqueue_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_
     cur = 1;
   }
   for (int l = L - 1; l >= 0; --l) {
+    const Range rl("rgp: level %d", l);
     if (l < L - 1) {
       ProlongArgs pa{};
       pa.src = w.B[cur];

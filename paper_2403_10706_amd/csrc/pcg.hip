@@ -622,7 +622,8 @@ Launch plan_hvp(const Geom& g, DType real) {
 // per thread.  XL is the shortest march that keeps every unit resident at once (at most 16
 // wavefronts per CU over 256 CUs): the halo planes cost less than a second wave of workgroups
 // (measured on 144x168x111 and 200x200x132).  Batched launches use the same shapes (so a batched
-// pair computes exactly what it computes alone) with two halo slots for every pair.
+// pair computes exactly what it computes alone) with two halo slots for every pair, unless the
+// batch asks for a longer minimum march (batch_march_min), which regroups the block sums.
 // Marches chosen by the autotuner (rgp_autotune), per volume geometry and field type.
 namespace {
 struct TuneKey {

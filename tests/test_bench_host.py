@@ -160,3 +160,48 @@ def test_batch_profile_summary_rates_against_level_bytes(tmp_path):
         assert r["GBps"] == pytest.approx(lv[r["level"]]["pcg_step"] / (durs[r["grid"]] * 1.0),
                                           rel=1e-3)
     assert not [r for r in out if r["kernel"] == "trial"]  # multi-candidate passes are skipped
+
+
+def test_range_summary_attributes_launches_to_levels_and_steps(tmp_path):
+    # one eager correction of 2 levels (level 1 first), 2 Gauss-Newton steps each with 3 launches
+    # (enqueue 10 us apart, kernels of 4 us each, 5 us apart), and one correction recorded into a
+    # graph (ranges, no launches), which the summary leaves out
+    marks, api, kern = [], [], []
+    cid, t = 0, 1_000_000
+
+    def rng(name, a, b):
+        marks.append(dict(Domain="MARKER_CORE_RANGE_API", Function=name, Process_Id=1,
+                          Thread_Id=1, Correlation_Id=0, Start_Timestamp=a, End_Timestamp=b))
+
+    c0 = t
+    for lv in (1, 0):
+        l0 = t
+        for k in range(2):
+            s0 = t
+            for j in range(3):
+                cid += 1
+                api.append(dict(Domain="HIP_RUNTIME_API_EXT", Function="hipLaunchKernel",
+                                Process_Id=1, Thread_Id=1, Correlation_Id=cid,
+                                Start_Timestamp=t + 1000, End_Timestamp=t + 2000))
+                gs = 50_000_000 + cid * 9000
+                kern.append(dict(Correlation_Id=cid, Kernel_Name="k", Start_Timestamp=gs,
+                                 End_Timestamp=gs + 4000))
+                t += 10_000
+            rng(f"rgp: Gauss-Newton step {k}", s0, t)
+        rng(f"rgp: level {lv}", l0, t)
+    rng("rgp: correction", c0, t)
+    g0 = t + 1000
+    rng("rgp: Gauss-Newton step 0", g0 + 10, g0 + 20)
+    rng("rgp: level 0", g0, g0 + 30)
+    rng("rgp: correction", g0, g0 + 40)
+    _write_csv(str(tmp_path / "run_marker_api_trace.csv"), marks)
+    _write_csv(str(tmp_path / "run_hip_api_trace.csv"), api)
+    _write_csv(str(tmp_path / "run_kernel_trace.csv"), kern)
+    buf = io.StringIO()
+    with redirect_stdout(buf):
+        bench.range_summary(str(tmp_path))
+    rows = [ln.split() for ln in buf.getvalue().splitlines()[2:]]
+    assert [r[:4] for r in rows] == [["2", "1", "2", "3.0"], ["2", "0", "2", "3.0"]]
+    for r in rows:
+        # host 30 us per step; GPU span 2 x 9 us + 4 us; busy 3 x 4 us
+        assert [float(v) for v in r[4:]] == pytest.approx([30.0, 22.0, 12.0])

@@ -933,6 +933,44 @@ def test_batch_mixed_marches_bitwise():
 
 
 
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_batch_random_mix_bitwise(seed):
+    """A seeded random batch: 6 pairs of random shapes (8..56 cells per axis) with PE along any
+    of the three axes, PCG stopping early on its residual (rtol 0.1, so the pairs stop at
+    iterations of their own).  Every pair's field and statistics are bitwise those of its solo
+    correction, in the captured plan and in the eager batched call."""
+    rgp = _rgp()
+    rng = np.random.default_rng(900 + seed)
+    specs = [(tuple(int(v) for v in rng.integers(8, 57, size=3)), int(rng.integers(0, 3)))
+             for _ in range(6)]
+    say(f"[batch mix {seed}] {specs}")
+    pairs = [_pair(sh, pe, seed=300 + 10 * seed + i, scale=30.0) for i, (sh, pe) in enumerate(specs)]
+    pes = [pe for _, pe in specs]
+    opts = rgp.Options(levels=2, gn_iters=3, pcg_iters=10, pcg_rtol=0.1)
+    dt = torch.float32
+    Ip = [to_dev(p.I_plus, dt) for p in pairs]
+    Im = [to_dev(p.I_minus, dt) for p in pairs]
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        bp = rgp.BatchPlan(Ip, Im, pes, opts, stream=s, want_stats=True)
+        bp.launch(s)
+        s.synchronize()
+        b_plan = [b.clone() for b in bp.b]
+        st_plan = [t.clone() for t in bp.stats]
+        bp.run_eager(s)
+        s.synchronize()
+    for i, (sh, pe) in enumerate(specs):
+        ref = rgp.correct(Ip[i], Im[i], pe, opts=opts, real_dtype=dt)
+        d = float(torch.max(torch.abs(b_plan[i] - ref["b"])))
+        say(f"[batch mix {seed}] pair {i} {sh} pe {pe}: max|b_batch - b_pair| = {d:.3e}")
+        assert torch.equal(b_plan[i], ref["b"]), (i, sh, pe, d)
+        assert torch.equal(torch.nan_to_num(st_plan[i], nan=-1.0),
+                           torch.nan_to_num(ref["stats"], nan=-1.0)), (i, sh, pe)
+        assert torch.equal(bp.b[i], b_plan[i]), i
+    bp.close()
+
 @pytest.mark.parametrize("real", ["f32", "f64"])
 def test_batch_long_marches_option(real):
     """batch_march = 16: the batched PCG launches march at least 16 planes per unit, so the
