@@ -837,8 +837,8 @@ BATCH_SPECS = [((40, 48, 36), 1), ((45, 30, 26), 0), ((33, 41, 29), 1), ((28, 36
 
 def test_batch_plan_with_ot_blur_matches_per_pair():
     """The optional blur of the OT field inside a batched plan (it runs pair by pair in the shared
-    graph): every pair's final field equals its per-pair correction with the same option, and
-    the first pair agrees with the oracle's solve with the blur."""
+    graph): every pair's final field is bitwise its per-pair correction with the same option,
+    and the first pair agrees with the oracle's solve with the blur."""
     rgp = _rgp()
     specs = BATCH_SPECS[:3]
     pairs = [_pair(sh, pe, seed=60 + i, scale=30.0) for i, (sh, pe) in enumerate(specs)]
@@ -857,7 +857,7 @@ def test_batch_plan_with_ot_blur_matches_per_pair():
     for i, (sh, pe) in enumerate(specs):
         ref = rgp.correct(Ip[i], Im[i], pe, opts=opts, real_dtype=dt)
         err = float(torch.max(torch.abs(bp.b[i] - ref["b"])))
-        assert err <= 1e-3, (i, err)
+        assert torch.equal(bp.b[i], ref["b"]), (i, err)
     a, c = host[0]
     ora = orc.solve(a, c, pes[0], levels=2, gn_iters=3, pcg_iters=8, pcg_rtol=0.0, ot_blur=True)
     assert float(np.max(np.abs(to_host(bp.b[0]) - ora.b))) <= BFINAL_ATOL
@@ -866,9 +866,10 @@ def test_batch_plan_with_ot_blur_matches_per_pair():
 @pytest.mark.parametrize("img", ["f32", "bf16"])
 def test_batch_plan_matches_per_pair(img):
     """Five pairs of different shapes, PE along dims 0 and 1, one captured graph whose
-    Gauss-Newton kernels each cover all pairs: every pair's final field equals the per-pair
-    correction up to the order of the block sums (1e-3 voxel; the oracle bar is 1e-2), every
-    replay is bitwise the same, and the first pair is checked against the oracle too."""
+    Gauss-Newton kernels each cover all pairs: every pair's final field, corrected images and
+    statistics are bitwise those of its per-pair correction (the shared launches keep each pair's
+    tile shapes and the order of its block sums), every replay is bitwise the same, and the first
+    pair is checked against the oracle too."""
     rgp = _rgp()
     it, dt = IMG[img], torch.float32
     pairs = [_pair(sh, pe, seed=50 + i, scale=30.0) for i, (sh, pe) in enumerate(BATCH_SPECS)]
@@ -894,11 +895,11 @@ def test_batch_plan_matches_per_pair(img):
         ref = rgp.correct(Ip[i], Im[i], pe, opts=opts, real_dtype=dt)
         err = float(torch.max(torch.abs(bp.b[i] - ref["b"])))
         worst = max(worst, err)
-        assert err <= 1e-3, (i, err)
-        assert rel2(to_host(bp.T_plus[i]), to_host(ref["T_plus"])) <= 1e-3
-        _, recs = rgp.parse_stats(bp.stats[i], 2, 4)
-        _, recs_ref = rgp.parse_stats(ref["stats"], 2, 4)
-        assert recs[-1][-1]["J"] == pytest.approx(recs_ref[-1][-1]["J"], rel=J_RTOL)
+        assert torch.equal(bp.b[i], ref["b"]), (i, err)
+        assert torch.equal(bp.T_plus[i], ref["T_plus"]), i
+        assert torch.equal(bp.T_minus[i], ref["T_minus"]), i
+        assert torch.equal(torch.nan_to_num(bp.stats[i], nan=-1.0),
+                           torch.nan_to_num(ref["stats"], nan=-1.0)), i
     say(f"[batch {img}] max over pairs of max|b_batch - b_pair| = {worst:.3e} voxel")
     a, c = host[0]
     ora = orc.solve(a, c, pes[0], levels=2, gn_iters=4, pcg_iters=8, pcg_rtol=0.0)
