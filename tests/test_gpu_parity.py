@@ -12,7 +12,7 @@ import torch
 
 import synth
 from oracle import rgp as orc
-from tests.gpu_helpers import (B0_ATOL, BFINAL_ATOL, J_RTOL, VEC_RTOL, rel2, rounded, say,
+from tests.gpu_helpers import (B0_ATOL, BFINAL_ATOL, DEV, J_RTOL, VEC_RTOL, rel2, rounded, say,
                                smooth_field, to_dev, to_host)
 
 pytestmark = pytest.mark.gpu
@@ -1400,3 +1400,106 @@ def test_batch_plan_admm_matches_per_pair():
     for i, (sh, pe) in enumerate(specs):
         ref = rgp.correct(Ip[i], Im[i], pe, opts=opts, real_dtype=dt)
         assert torch.equal(bp.b[i], ref["b"]), i
+
+
+# ---- the largest grid the library accepts ---------------------------------------------------------
+
+MAX_SHAPE, MAX_PE = (1024, 512, 511), 2   # 1024 x 512 x 512 = 2^28 field nodes, 512 along the
+                                          # contiguous axis: both limits of the C ABI at once
+
+
+def _separable(shape, nodes_axis, rng, base, amp, waves, dtype):
+    """base + amp * prod_d sin(2 pi k_d x_d / n_d + phase_d) on the device (seeded, smooth)."""
+    dims = list(shape)
+    if nodes_axis is not None:
+        dims[nodes_axis] += 1
+    out = None
+    for d, n in enumerate(dims):
+        k = float(rng.integers(1, waves + 1))
+        ph = float(rng.uniform(0.0, 2.0 * np.pi))
+        x = torch.arange(n, device=DEV, dtype=torch.float64)
+        f = torch.sin(2.0 * np.pi * k * x / n + ph)
+        view = [1, 1, 1]
+        view[d] = n
+        f = f.view(view)
+        out = f if out is None else out * f
+    return (base + amp * out).to(dtype).contiguous()
+
+
+def _max_inputs(dt, seed):
+    rng = np.random.default_rng(seed)
+    Ip = _separable(MAX_SHAPE, None, rng, 1.0, 0.3, 6, dt)
+    Im = _separable(MAX_SHAPE, None, rng, 1.0, 0.3, 6, dt)
+    b = _separable(MAX_SHAPE, MAX_PE, rng, 0.0, 0.8, 2, dt)   # |D b| <= 0.8 * 2 pi 2 / 511 < 0.02
+    v = _separable(MAX_SHAPE, MAX_PE, rng, 0.0, 1.0, 8, dt)
+    return Ip, Im, b, v
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("real", ["f32", "f64"])
+def test_max_grid_sampled_against_oracle(real):
+    """loss_grad and gn_hvp on 2^28 field nodes (FP64: 2 GiB per field array, the byte offsets
+    at their 32-bit limit).  A node's gradient, Jacobi diagonal and H v depend on its own PE column
+    and its four cross-axis neighbours only, so on windows of 6 x 6 whole columns (at the low
+    corner, in the middle, at the high corner) the oracle run on the window alone gives every node
+    whose cross-axis neighbours lie inside the window (or outside the grid)."""
+    rgp = _rgp()
+    dt = REAL[real]
+    nx, ny, _ = MAX_SHAPE
+    need = rgp.workspace_size(rgp.OP_LOSS_GRAD, MAX_SHAPE, MAX_PE, (1.0, 1.0, 1.0), dt)
+    say(f"[max grid {real}] {MAX_SHAPE} PE {MAX_PE}: loss_grad workspace {need / 2**20:.1f} MiB")
+    Ip, Im, b, v = _max_inputs(dt, 41)
+    jdsp, g, hd, ho = rgp.loss_grad(Ip, Im, b, MAX_PE)
+    Hv, _ = rgp.gn_hvp(hd, ho, v, MAX_SHAPE, MAX_PE)
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(to_host(jdsp)))
+    w = 6
+    for x0, y0 in ((0, 0), (nx // 2 - 3, ny // 2 - 3), (nx - w, ny - w)):
+        sl = (slice(x0, x0 + w), slice(y0, y0 + w), slice(None))
+        ip, im = to_host(Ip[sl]), to_host(Im[sl])
+        bs, vs = to_host(b[sl]), to_host(v[sl])
+        _, gref, lin = orc.objective_gradient(ip, im, bs, MAX_PE, (1.0, 1.0, 1.0))
+        dref = orc.gn_diag(lin, MAX_PE)
+        href = orc.gn_matvec(lin, vs, MAX_PE)
+        keep = np.ones(bs.shape, bool)
+        if x0 > 0:
+            keep[0] = False
+        if x0 + w < nx:
+            keep[-1] = False
+        if y0 > 0:
+            keep[:, 0] = False
+        if y0 + w < ny:
+            keep[:, -1] = False
+        for name, got, ref in (("grad", g, gref), ("diag", hd, dref), ("Hv", Hv, href)):
+            e = rel2(to_host(got[sl])[keep], ref[keep])
+            say(f"[max grid {real}] window ({x0}, {y0}) {name}: rel err {e:.2e}")
+            assert e <= _tol(real, 1e-11, VEC_RTOL), (x0, y0, name, e)
+    del Ip, Im, b, v, g, hd, ho, Hv
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+def test_max_grid_correction_properties():
+    """A whole correction (3 levels x 3 GN x 10 PCG, FP32) on 2^28 field nodes: the solve ends
+    with status OK, every Gauss-Newton record is finite, every accepted step lowered J, and the
+    field and corrected images are finite."""
+    rgp = _rgp()
+    Ip, Im, _, _ = _max_inputs(torch.float32, 43)
+    opts = rgp.Options(levels=3, gn_iters=3, pcg_iters=10, pcg_rtol=0.0)
+    out = rgp.correct(Ip, Im, MAX_PE, opts=opts)
+    torch.cuda.synchronize()
+    head, recs = rgp.parse_stats(out["stats"], 3, 3)
+    say(f"[max grid correction] status {head['status']}, J per level "
+        f"{[[round(r['J'], 3) for r in lv] for lv in recs]}")
+    assert head["status"] == 0
+    for lv in recs:
+        prev = None
+        for r in lv:   # J of a record is the objective at the start of its step
+            assert math.isfinite(r["J"]) and math.isfinite(r["gnorm"]), r
+            if prev is not None and prev["accepted"] == 1.0:
+                assert r["J"] < prev["J"], (prev, r)
+            prev = r
+    for t in (out["b"], out["T_plus"], out["T_minus"]):
+        assert bool(torch.isfinite(t).all())
+    del out, Ip, Im
+    torch.cuda.empty_cache()
