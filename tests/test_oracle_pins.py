@@ -249,6 +249,34 @@ def test_loops_match_vectorised(seed):
     np.testing.assert_allclose(d, np.diag(H), rtol=1e-13)
 
 
+
+def test_knot_rule_is_right_sided():
+    """Where a sample position is a whole number (every cell at b = 0, and at a field of whole
+    voxels) the image slope is the right-sided one, (I_{j+1} - I_j) / h with I = 0 past the last
+    cell (R1, R2): the linearisation's c1 = I+' + I-' at b = 0 written out, and the gradient and
+    GN operator against the plain-loop brute force at both fields."""
+    rng = np.random.default_rng(21)
+    hc = (1.1, 0.9, 1.3)
+    Ip = rng.uniform(0.2, 1.0, (3, 4, 6))
+    Im = rng.uniform(0.2, 1.0, (3, 4, 6))
+
+    def right_slope(I):
+        nxt = np.concatenate([I[..., 1:], np.zeros(I.shape[:-1] + (1,))], axis=-1)
+        return (nxt - I) / hc[2]
+
+    for b in (np.zeros((3, 4, 7)), np.full((3, 4, 7), 2.0 * hc[2])):
+        _, g, lin = rgp.objective_gradient_cols(Ip, Im, b, hc, ALPHA, BETA)
+        if not np.any(b):
+            np.testing.assert_allclose(lin.c1, right_slope(Ip) + right_slope(Im), rtol=1e-14,
+                                       atol=1e-14)
+        # (rounding-level bars: r = T+ - T- cancels, and the two sides sum in different orders)
+        gl = loops.gradient(Ip, Im, b, hc, ALPHA, BETA)
+        assert np.linalg.norm(g - gl) <= 1e-11 * np.linalg.norm(gl)
+        H = loops.gn_hessian(Ip, Im, b, hc, ALPHA, BETA)
+        v = rng.standard_normal(b.shape)
+        ref = H @ v.ravel()
+        assert np.linalg.norm(rgp.gn_matvec_cols(lin, v).ravel() - ref) <= 1e-11 * np.linalg.norm(ref)
+
 def test_gn_operator_dense_4x5x6_with_pe_first():
     """Brute-force H_J on a 4x5x6 grid with the PE axis first in caller layout."""
     rng = np.random.default_rng(9)
@@ -613,6 +641,32 @@ def test_gauss_newton_stops_with_b_unchanged_when_no_trial_is_accepted():
     J_trial = loops.objective(Pc, Mc, bcol + q, hc, rgp.ALPHA, rgp.BETA)[0]
     assert J_trial > obj.J + 1e-4 * float(np.sum(g * q))
 
+
+
+def test_armijo_rejects_a_finite_increase_and_takes_the_largest_halving():
+    """One column (16 cells) with alpha = 0.1, beta = 1, where the full Gauss-Newton step raises J
+    to a finite value: the line search must reject gamma = 1 and accept the largest
+    gamma = 2^-k with J(b + gamma q) <= J(b) + c gamma g^T q (R14).  Every candidate is re-evaluated
+    with the plain-loop objective."""
+    rng = np.random.default_rng(0)
+    m, hc, alpha, beta, c = 16, (1.0, 1.0, 1.0), 0.1, 1.0, 1e-4
+    Ip = rng.uniform(0.0, 1.0, (1, 1, m))
+    Im = np.roll(Ip, 1, axis=-1) + 0.3 * rng.uniform(0.0, 1.0, (1, 1, m))
+    b = 0.05 * rng.standard_normal((1, 1, m + 1))
+    b1, hist = rgp.gauss_newton_cols(Ip, Im, b, hc, alpha=alpha, beta=beta, gn_iters=1,
+                                     pcg_iters=20, armijo_c=c)
+    st = hist[0]
+    assert st.accepted and st.trials >= 2 and st.gamma == 2.0 ** (1 - st.trials)
+    q = (b1 - b) / st.gamma
+    J0 = loops.objective(Ip, Im, b, hc, alpha, beta)[0]
+    assert J0 == pytest.approx(st.J, rel=1e-13)
+    for k in range(st.trials):
+        g_k = 2.0 ** -k
+        J_k = loops.objective(Ip, Im, b + g_k * q, hc, alpha, beta)[0]
+        ok = J_k <= J0 + c * g_k * st.gq
+        assert ok == (k == st.trials - 1), (k, J_k, J0)
+        if k == 0:
+            assert math.isfinite(J_k) and J_k > J0   # the rejected full step is a finite increase
 
 def test_ot_shift_with_negative_intensities():
     """Hand-computed shifts (R7): s = max(0, -min) + eps * max|.| over both images, where the
