@@ -246,12 +246,27 @@ def _tri_matvec_lower_band_shifted(diag, off, v):
     return out
 
 
+def _pyramid_spacing_kept(Ip, Im, h, levels):
+    return [(P, M, tuple(float(x) for x in h)) for P, M, _ in ORIG["pyramid"](Ip, Im, h, levels)]
+
+
+def _prolong_skipped(bc, fine_shape, pe):
+    # the coarse field resampled by nearest coarse index only (no interpolation)
+    out = np.asarray(bc, dtype=np.float64)
+    for ax in range(3):
+        n_f = int(fine_shape[ax]) + (1 if ax == pe else 0)
+        idx = np.minimum(np.arange(n_f) // 2, out.shape[ax] - 1)
+        out = np.take(out, idx, axis=ax)
+    return out
+
+
 from oracle import admm as _admm   # noqa: E402
 from oracle import lbfgs as _lb    # noqa: E402
 from oracle import lsq as _lsq     # noqa: E402
 
 ORIG["ot_init"] = rgp.ot_init
 ORIG["gauss_newton_cols"] = rgp.gauss_newton_cols
+ORIG["pyramid"] = rgp.pyramid
 ORIG_LB = {"two_loop": _lb.two_loop}
 ORIG_LSQ = {"push": _lsq.push}
 
@@ -336,6 +351,13 @@ MUTATIONS = {
         {"gauss_newton_cols": _gn_accepts_every_finite_trial},
         [pins.test_armijo_rejects_a_finite_increase_and_takes_the_largest_halving,
          pins.test_gauss_newton_stops_with_b_unchanged_when_no_trial_is_accepted]),
+    "coarse levels keep the fine spacing": (
+        {"pyramid": _pyramid_spacing_kept},
+        [pins.test_two_level_ot_of_a_shifted_bump_keeps_physical_units]),
+    "prolongation by nearest coarse value": (
+        {"prolong_field": _prolong_skipped},
+        [lambda: pins.test_prolong_reproduces_linear_fields(1),
+         pins.test_two_level_ot_of_a_shifted_bump_keeps_physical_units]),
     "L-BFGS with H0 = I": (
         {(_lb, "two_loop"): _two_loop_unit_h0},
         [pins.test_lbfgs_two_loop_equals_dense_bfgs_updates]),

@@ -748,6 +748,28 @@ def test_solve_status_barrier_and_line_search():
 # End to end: a pair distorted with a known field gets that field back
 # ------------------------------------------------------------------------------------------
 
+
+def test_two_level_ot_of_a_shifted_bump_keeps_physical_units():
+    """A bump shifted by +-2 fine cells along PE: restricted to the coarse level it is shifted by
+    +-1 coarse cell, so OT there gives b = +1 coarse cell = +2 in physical units (the coarse
+    spacing is 2h, R16, and b keeps physical units), and the prolonged field is +2 too."""
+    m = 40
+    x = np.arange(m, dtype=np.float64)
+
+    def bump(c):
+        return np.exp(-0.5 * ((x - c) / 2.5) ** 2) * (np.abs(x - c) < 9.0)
+
+    Ip = np.broadcast_to(bump(20.0 + 2.0)[None, :, None], (4, m, 3)).copy()
+    Im = np.broadcast_to(bump(20.0 - 2.0)[None, :, None], (4, m, 3)).copy()
+    r = rgp.solve(Ip, Im, 1, (1.0, 1.0, 1.0), levels=2, gn_iters=0, ot_eps=1e-12,
+                  ot_guard=False)
+    assert r.b_ot.shape == (2, 21, 2)
+    bulk = slice(7, 14)                       # coarse nodes well inside both bumps' mass
+    np.testing.assert_allclose(r.b_ot[:, bulk, :], 2.0, rtol=0, atol=1e-9)
+    assert r.b.shape == (4, 41, 3)
+    np.testing.assert_allclose(r.b[:, 2 * bulk.start + 1:2 * bulk.stop - 1, :], 2.0, rtol=0,
+                               atol=1e-9)
+
 def test_known_field_recovery():
     import synth
     p = synth.make_workload("c1", scale=1000.0)
