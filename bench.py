@@ -33,6 +33,8 @@ Other modes (profiling helpers; their output goes under profiles/):
                               --kernel-trace run of --batch 32 in D
   --range-summary D           per-level host and GPU time of the eager corrections from a
                               rocprofv3 --marker-trace --hip-runtime-trace --kernel-trace run in D
+  --sweep                     pairs/s and the finest PCG step's GB/s for volumes from 64x64x48 to
+                              320x320x256 (same schedule, FP32, PE dim 1)
 """
 import argparse
 import csv
@@ -656,6 +658,91 @@ def batch_bench(pairs, steps, scale):
 
 
 # ---------------------------------------------------------------------------------------------
+# size sweep: the same schedule on volumes from 64x64x48 to 320x320x256
+
+SWEEP_SHAPES = [(64, 64, 48), (96, 112, 74), (144, 168, 111), (200, 200, 132), (256, 256, 192),
+                (320, 320, 256)]
+
+
+def _sweep_images(shape, pe, dev, seed):
+    """Smooth seeded stand-ins built on the device (the phantom generator is too slow on the
+    host for the largest sizes): I- is I+ shifted by 3 cells along PE, scaled x1000."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(seed)
+    out = None
+    for d, n in enumerate(shape):
+        k = float(rng.integers(2, 5))
+        ph = float(rng.uniform(0.0, 2.0 * np.pi))
+        x = torch.arange(n, device=dev, dtype=torch.float32)
+        f = 1.0 + 0.5 * torch.sin(2.0 * np.pi * k * x / n + ph)
+        view = [1, 1, 1]
+        view[d] = n
+        f = f.view(view)
+        out = f if out is None else out * f
+    Ip = (1000.0 * out).contiguous()
+    Im = torch.roll(Ip, shifts=3, dims=pe).contiguous()
+    return Ip, Im
+
+
+def size_sweep(steps):
+    """Graph-replay throughput of the 3-level x 10 GN x 20 PCG correction (FP32, PE dim 1) per
+    volume size, and the finest level's PCG step (median full iteration of one eager correction
+    with kernel timing) against its 40 B/node."""
+    import torch
+
+    from paper_2403_10706_amd import rgp
+    rgp.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(side)
+    dt, pe = torch.float32, 1
+    opts = rgp.Options(levels=LEVELS, gn_iters=GN_ITERS, pcg_iters=PCG_ITERS, pcg_rtol=0.0)
+    rows = []
+    print(f"{'shape':>16s} {'field nodes':>12s} {'ms/pair':>9s} {'pairs/s':>9s} "
+          f"{'PCG us':>8s} {'PCG GB/s':>9s} {'frac':>6s} {'march XL':>12s}")
+    for i, shape in enumerate(SWEEP_SHAPES):
+        Ip, Im = _sweep_images(shape, pe, dev, 50 + i)
+        ws = torch.zeros(rgp.workspace_size(rgp.OP_CORRECT, shape, pe, (1.0, 1.0, 1.0), dt,
+                                            opts.to_c()), dtype=torch.uint8, device=dev)
+        b = torch.empty(rgp.field_shape(shape, pe), dtype=dt, device=dev)
+        Tp, Tm = torch.empty_like(Ip), torch.empty_like(Im)
+        xl = rgp.autotune(shape, pe, dt, opts, ws=ws, stream=side)
+        plan = rgp.Plan(Ip, Im, pe, opts, b, Tp, Tm, ws, stream=side)
+        for _ in range(2):
+            plan.launch(side)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.launch(side)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        plan.close()
+        rgp.timing_start(1 << 14)
+        rgp.correct_into(Ip, Im, pe, opts, b, Tp, Tm, ws, stream=side)
+        torch.cuda.synchronize()
+        recs = rgp.timing_stop(1 << 14)
+        nb = max(r["nodes"] for r in recs if r["kernel"] == "pcg_step")
+        full = [r["ms"] * 1e3 for r in recs if r["kernel"] == "pcg_step" and r["nodes"] == nb
+                and 0 < r["tag"] < PCG_ITERS]
+        us = statistics.median(full)
+        gbps = 40.0 * nb / (us * 1e3)
+        row = dict(shape=list(shape), nodes=int(nb), ms_per_pair=round(1e3 * wall, 3),
+                   pairs_per_s=round(1.0 / wall, 2), pcg_us=round(us, 2),
+                   pcg_GBps=round(gbps, 1), pcg_frac=round(gbps / HBM_PEAK_GBPS, 3),
+                   march_xl=list(xl))
+        rows.append(row)
+        print(f"{'x'.join(map(str, shape)):>16s} {nb:12d} {1e3 * wall:9.3f} {1.0 / wall:9.2f} "
+              f"{us:8.2f} {gbps:9.1f} {gbps / HBM_PEAK_GBPS:6.3f} {str(list(xl)):>12s}",
+              flush=True)
+        del Ip, Im, ws, b, Tp, Tm
+        torch.cuda.empty_cache()
+    print(json.dumps(dict(sweep=rows)))
+
+
+# ---------------------------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
@@ -670,6 +757,7 @@ def main():
     ap.add_argument("--counter-summary", metavar="DIR")
     ap.add_argument("--batch-profile-summary", metavar="DIR")
     ap.add_argument("--range-summary", metavar="DIR")
+    ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--batch", type=int, metavar="N", default=0,
                     help="the batching benchmark over N uneven pairs instead of the headline")
     ap.add_argument("--batch-scale", type=float, default=1000.0)
@@ -682,6 +770,8 @@ def main():
         return profile_summary(args.profile_summary)
     if args.range_summary:
         return range_summary(args.range_summary)
+    if args.sweep:
+        return size_sweep(max(3, min(args.steps, 10)))
     if args.counter_summary:
         return counter_summary(args.counter_summary)
     if args.batch_profile_summary:
