@@ -19,6 +19,7 @@
 
 namespace rgp {
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_stats_header(double* stats, const State* st, const unsigned long long* guarded,
                                hipStream_t s);
 }  // namespace rgp
@@ -1079,9 +1080,7 @@ rgp_status check_correct(const rgp_grid* grid, rgp_dtype img_t, const void* I_pl
 }
 
 hipError_t copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
-  if (active_recorder())
-    return record_other([dst, src, bytes](hipStream_t s2) { return copy_d2d(dst, src, bytes, s2); });
-  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+  return launch_copy(dst, src, bytes, s);
 }
 
 // Enqueues the whole correction (arguments already validated).

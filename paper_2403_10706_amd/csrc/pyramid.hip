@@ -145,6 +145,41 @@ __global__ void k_stats_header(double* stats, const State* st, const unsigned lo
   }
 }
 
+// Device-to-device copy of n 16-byte words (both ends 16-byte aligned): kU words per thread and
+// round, all loads in flight before the stores.
+__global__ __launch_bounds__(kBlock) void k_copy16(const uint4* __restrict__ src,
+                                                   uint4* __restrict__ dst, int64_t n) {
+  constexpr int kU = 4;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x; i0 < n; i0 += kU * stride) {
+    uint4 v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < n) v[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < n) dst[i] = v[u];
+    }
+  }
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (active_recorder())
+    return record_other([dst, src, bytes](hipStream_t s2) { return launch_copy(dst, src, bytes, s2); });
+  if (bytes == 0) return hipSuccess;
+  if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src) | bytes) & 15u)
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+  const int64_t n = (int64_t)(bytes / 16);
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  const unsigned grid = (unsigned)(blocks < 2048 ? blocks : 2048);
+  hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(kBlock), 0, s, static_cast<const uint4*>(src),
+                     static_cast<uint4*>(dst), n);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
   if (active_recorder())
     return record_other([p, n, v](hipStream_t s2) { return launch_fill(p, n, v, s2); });
