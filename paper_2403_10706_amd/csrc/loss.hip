@@ -145,7 +145,7 @@ __device__ __forceinline__ void loss_grad_body(const LossGradArgs& a, VBlock vb)
   for (WaveIter it = wave_iter(ntiles, vb); it.t < it.end; it.t += it.stride) {
     ColTile c = col_tile(g, it.t, S);
     if (prox) c.hasxm = c.hasxp = c.hasym = c.hasyp = false;  // F_rho: PE smoothness only
-    const int k0 = c.k0;
+    const int k0 = __builtin_amdgcn_readfirstlane(c.k0);  // uniform: one tile per wavefront
     auto noff = [&](int k) -> uint32_t { return (c.nb + (uint32_t)k * nps) * kSr; };
 
     // 1. b (and q) at nodes k0-1 .. k0+S clamped into the column, the x neighbours and the
@@ -371,7 +371,7 @@ __device__ __forceinline__ void trial_body(const TrialArgs& a, VBlock vb) {
   for (WaveIter it = wave_iter(ntiles, vb); it.t < it.end; it.t += it.stride) {
     ColTile c = col_tile(g, it.t, S);
     if (prox) c.hasxm = c.hasxp = c.hasym = c.hasyp = false;  // F_rho: PE smoothness only
-    const int k0 = c.k0;
+    const int k0 = __builtin_amdgcn_readfirstlane(c.k0);  // uniform: one tile per wavefront
     auto noff = [&](int k) -> uint32_t { return (c.nb + (uint32_t)k * nps) * kSr; };
     // b, q at nodes k0 .. k0+S (clamped to mp); first pass: grad and the upper x and y neighbours
     // (y on the last lane of the wavefront; the others take it from the next lane)
