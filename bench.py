@@ -111,7 +111,7 @@ def algorithmic_bytes(rec, f=4, fi=4, maxit=PCG_ITERS):
     return 0
 
 
-def survey_bytes(rec, f=4, fi=4):
+def table_rule_bytes(rec, f=4, fi=4):
     """Algorithmic bytes per launch under the hot-path measurement table's per-unit figures
     (N cells, Nb field nodes): a PCG iteration (HVP and CG vector updates, ~13 array passes)
     52 N; loss_grad with the Jacobi diagonal 2 N s_img + 3 Nb f, without it 2 N s_img + 2 Nb f;
@@ -966,7 +966,7 @@ def main():
     traffic = measured_traffic()
     # achieved: the measurement table's per-unit figure for a PCG iteration (52 B per cell)
     # over the measured mean launch; moved_bytes: what this fused kernel must move (40 B/node)
-    sb = survey_bytes(dict(kernel="pcg_step", nodes=dom["nodes"], cells=dom["cells"], tag=1))
+    sb = table_rule_bytes(dict(kernel="pcg_step", nodes=dom["nodes"], cells=dom["cells"], tag=1))
     s_gbps = sb / (dom["us_mean"] * 1e3)
     roofline = dict(bound="hbm", achieved=round(s_gbps, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(s_gbps / HBM_PEAK_GBPS, 4), traffic=traffic,
