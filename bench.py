@@ -16,7 +16,9 @@ The same line carries the batched leg (`batch`, unless --batch-pairs 0): 32 unev
 (BF16 images scaled x1000, FP32 field, same schedule) corrected by one batched graph against one
 graph per pair, and the batched Gauss-Newton launches timed in an eager batched correction (their
 working set is HBM-resident, ~2.8 GB per finest-level PCG iteration), and `cpu_baseline`: the
-FP64 oracle's whole correction of the headline pair on one thread of the host.
+FP64 oracle's whole correction of the headline pair on one thread of the host.  `solvers` holds
+the other per-level solvers on the headline pair and schedule (L-BFGS, ADMM: pairs/s of their own
+captured plans) and the least-squares correction of the Gauss-Newton field (ms per call).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 
@@ -658,6 +660,60 @@ def batch_bench(pairs, steps, scale):
 
 
 # ---------------------------------------------------------------------------------------------
+# the other per-level solvers and the least-squares correction on the bench pair
+
+def solver_legs(Ip, Im, pe, b_gn, side, steps):
+    """L-BFGS (memory 10) and ADMM (PCG 20 per column) on the same pair and schedule (3 levels x
+    10 iterations), each captured into its own plan and timed over `steps` replays (pairs/s,
+    the status and the last level's final objective), and the least-squares correction (CGLS, at
+    most 30 iterations, rtol 1e-6) of the Gauss-Newton field, timed over `steps` calls."""
+    import torch
+
+    from paper_2403_10706_amd import rgp
+    shape = tuple(Ip.shape)
+    dt = Ip.dtype
+    out = dict(workload="the bench pair, 3 levels x 10 iterations of each solver (PCG 20, rtol 0)")
+    for name, extra in (("lbfgs", dict(solver="lbfgs", lbfgs_memory=10)),
+                        ("admm", dict(solver="admm"))):
+        opts = rgp.Options(levels=LEVELS, gn_iters=GN_ITERS, pcg_iters=PCG_ITERS, pcg_rtol=0.0,
+                           **extra)
+        ws = torch.zeros(rgp.workspace_size(rgp.OP_CORRECT, shape, pe, (1.0, 1.0, 1.0), dt,
+                                            opts.to_c()), dtype=torch.uint8, device=Ip.device)
+        b = torch.empty(rgp.field_shape(shape, pe), dtype=dt, device=Ip.device)
+        st = torch.empty(rgp.STAT_HEADER + LEVELS * GN_ITERS * rgp.STAT_FIELDS,
+                         dtype=torch.float64, device=Ip.device)
+        plan = rgp.Plan(Ip, Im, pe, opts, b, torch.empty_like(Ip), torch.empty_like(Im), ws,
+                        stats=st, stream=side)
+        plan.launch(side)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.launch(side)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        plan.close()
+        head, recs = rgp.parse_stats(st, LEVELS, GN_ITERS)
+        out[name] = dict(pairs_per_s=round(1.0 / wall, 3), ms_per_pair=round(1e3 * wall, 3),
+                         status=head["status"], J_last_step=recs[-1][-1]["J"])
+        log(f"bench: {name}: {1.0 / wall:.2f} pairs/s ({1e3 * wall:.2f} ms), status "
+            f"{head['status']}")
+        del ws, b, st
+    rgp.correct_lsq(Ip, Im, b_gn, pe, stream=side)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(side)
+    for _ in range(steps):
+        _, its = rgp.correct_lsq(Ip, Im, b_gn, pe, stream=side)
+    e1.record(side)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    out["lsq"] = dict(ms_per_call=round(ms, 3), cgls_iterations_max=int(its.max()))
+    log(f"bench: least-squares correction {ms:.3f} ms (CGLS <= {int(its.max())} iterations)")
+    return out
+
+
+# ---------------------------------------------------------------------------------------------
 # size sweep: the same schedule on volumes from 64x64x48 to 320x320x256
 
 SWEEP_SHAPES = [(64, 64, 48), (96, 112, 74), (144, 168, 111), (200, 200, 132), (256, 256, 192),
@@ -979,6 +1035,8 @@ def main():
                                      achieved=dom["achieved_GBps"], frac=dom["frac"]),
                     copy_reference=copy)
 
+    solvers = solver_legs(Ip, Im, pe, b, side, max(2, args.steps // 4))
+    solvers["gn"] = dict(pairs_per_s=round(value, 3), ms_per_pair=round(ms_per_step, 3))
     plan.close()
     batch = None
     if batch_pairs:
@@ -1000,7 +1058,8 @@ def main():
                     shape=list(shape), pe_dim=pe, levels=LEVELS, gn_iters=GN_ITERS,
                     pcg_iters=PCG_ITERS, global_batch=1, pcg_march_lengths=tuned_xl),
         gpu_ms_per_step=round(gpu_ms / args.steps, 4), eager_ms_per_step=round(eager_ms, 4),
-        roofline=roofline, kernels=kernels, nonlinear=nonlinear, c3=c3, batch=batch,
+        roofline=roofline, kernels=kernels, nonlinear=nonlinear, c3=c3, solvers=solvers,
+        batch=batch,
         cpu_baseline=cpu,
         device=torch.cuda.get_device_name(0),
     )

@@ -5,11 +5,18 @@
 // its moved length), and the corrected image minimises |M+ I - I+|^2 + |M- I - I-|^2.  It is
 // found by CGLS from I = 0 (conjugate gradients on the normal equations, Hestenes-Stiefel form).
 //
-// One thread owns one column: the field, the iterate and the CGLS vectors of its column live in
-// LDS for the whole solve, laid out [vector][k][thread] so that the lanes of a wavefront touch
-// consecutive words whenever they index the same k.  The matrices are never stored: every sweep
-// recomputes each moved cell's (at most three) overlaps from the field.  Inner products are
-// accumulated in FP64.
+// Columns of up to 512 cells: one wavefront (one workgroup) per column.  Lane l owns the cells
+// l*CPL .. l*CPL+CPL-1 and keeps their CGLS vectors in registers; the moved node positions of both
+// polarities and the vectors that other lanes read (p, r+, r-) sit in LDS.  M^T r is a gather over
+// each owned cell's (at most three) output cells; M p is a gather too: output cell i sums w(i, j) p_j
+// over the moved cells j that overlap it, in ascending j - the order in which a scatter over j would
+// add them - starting from the first j whose moved interval ends beyond i (a binary search over the
+// monotone moved nodes, once per solve).  Inner products are FP64 (per lane in cell order, then
+// across the wavefront in a fixed tree).
+// Longer columns: one thread owns one column, its field, iterate and CGLS vectors in LDS for the
+// whole solve, laid out [vector][k][thread] so that the lanes of a wavefront touch consecutive
+// words whenever they index the same k.  Neither form stores the matrices: every sweep recomputes
+// each moved cell's overlaps from the field.
 #include <hip/hip_runtime.h>
 
 #include "rgp_internal.hpp"
@@ -143,6 +150,161 @@ __global__ __launch_bounds__(kLsqMaxCols) void k_lsq(LsqArgs a) {
   if (a.iters) a.iters[col] = it;
 }
 
+// FP64 sum over the 64 lanes of a wavefront in a fixed order (DPP stages; every lane gets it).
+__device__ __forceinline__ double wave_sum(double v) {
+  double t[1] = {v};
+  wave_sums<1>(t);
+  return t[0];
+}
+
+template <typename TI, typename TR, int CPL>
+__global__ __launch_bounds__(kWave) void k_lsq_wave(LsqArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const Geom g = a.g;
+  const int m = g.mp;
+  const int64_t col = blockIdx.x;
+  const int lane = threadIdx.x;
+  TR* yv[2];
+  yv[0] = reinterpret_cast<TR*>(lds_raw);  // moved node positions (cells), + polarity: m + 1
+  yv[1] = yv[0] + (m + 1);                 // - polarity
+  TR* sp = yv[1] + (m + 1);                // p, read by the lanes that gather it: m
+  TR* sr[2] = {sp + m, sp + 2 * m};        // r+, r-: m each
+
+  const int ix = (int)(col / g.ny), iy = (int)(col - (int64_t)ix * g.ny);
+  const int64_t cb = ix * g.cxs + iy * g.cys, nb = ix * g.nxs + iy * g.nys;
+  const TI* __restrict__ Ip = static_cast<const TI*>(a.Ip);
+  const TI* __restrict__ Im = static_cast<const TI*>(a.Im);
+  const TR* __restrict__ bg = static_cast<const TR*>(a.b);
+  const TR inv_hp = TR(1) / (TR)g.hp;
+  for (int k = lane; k <= m; k += kWave) {
+    const TR bk = bg[nb + (int64_t)k * g.nps] * inv_hp;   // in cells
+    yv[0][k] = TR(k) + bk;
+    yv[1][k] = TR(k) - bk;
+  }
+  const int j0 = lane * CPL;
+  TR x[CPL], p[CPL], r[2][CPL], t[2][CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    const int j = j0 + c;
+    const bool own = j < m;
+    x[c] = TR(0);
+    r[0][c] = own ? to_real(Ip[cb + (int64_t)j * g.cps], TR()) : TR(0);
+    r[1][c] = own ? to_real(Im[cb + (int64_t)j * g.cps], TR()) : TR(0);
+  }
+  __syncthreads();
+  // first moved cell whose interval ends beyond each owned output cell, per polarity
+  int jlo[2][CPL];
+#pragma unroll
+  for (int pol = 0; pol < 2; ++pol) {
+    const TR* y = yv[pol];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const TR i = TR(j0 + c);
+      int lo = 1, hi = m + 1;   // smallest k in [1, m] with y[k] > i (m + 1: none)
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (y[mid] > i) hi = mid; else lo = mid + 1;
+      }
+      jlo[pol][c] = lo - 1;
+    }
+  }
+  // s = M+^T r+ + M-^T r- for the owned cells (r staged in LDS); returns the wavefront's |s|^2
+  auto grad = [&](TR (&s)[CPL]) -> double {
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int j = j0 + c;
+      if (j < m) {
+        sr[0][j] = r[0][c];
+        sr[1][j] = r[1][c];
+      }
+    }
+    __syncthreads();
+    double gg = 0.0;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int j = j0 + c;
+      TR acc = TR(0);
+      if (j < m) {
+#pragma unroll
+        for (int pol = 0; pol < 2; ++pol) {
+          TR w[3];
+          int i0;
+          overlaps(yv[pol][j], yv[pol][j + 1], m, i0, w);
+#pragma unroll
+          for (int tt = 0; tt < 3; ++tt)
+            if (w[tt] != TR(0)) acc += w[tt] * sr[pol][i0 + tt];
+        }
+      }
+      s[c] = acc;
+      gg += (double)acc * (double)acc;
+    }
+    __syncthreads();   // the staging area is rewritten next
+    return wave_sum(gg);
+  };
+
+  TR s[CPL];
+  double gam = grad(s);
+  const double gam0 = gam;
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) p[c] = s[c];
+  int it = 0;
+  bool active = gam > 0.0;
+  while (active && it < a.maxit) {
+    // t = M p for the owned output cells (p staged in LDS), delta = |t|^2
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+      if (j0 + c < m) sp[j0 + c] = p[c];
+    __syncthreads();
+    double dl = 0.0;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int i = j0 + c;
+#pragma unroll
+      for (int pol = 0; pol < 2; ++pol) {
+        TR acc = TR(0);
+        if (i < m) {
+          const TR* y = yv[pol];
+          for (int j = jlo[pol][c]; j < m && y[j] < TR(i + 1); ++j) {
+            TR w[3];
+            int i0;
+            overlaps(y[j], y[j + 1], m, i0, w);
+            const int tt = i - i0;
+            const TR wt = tt == 0 ? w[0] : (tt == 1 ? w[1] : (tt == 2 ? w[2] : TR(0)));
+            if (wt != TR(0)) acc += wt * sp[j];
+          }
+        }
+        t[pol][c] = acc;
+        dl += (double)acc * (double)acc;
+      }
+    }
+    __syncthreads();
+    const double delta = wave_sum(dl);
+    if (!(delta > 0.0)) break;
+    const TR al = (TR)(gam / delta);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      x[c] += al * p[c];
+      r[0][c] -= al * t[0][c];
+      r[1][c] -= al * t[1][c];
+    }
+    ++it;
+    const double gnew = grad(s);
+    if (sqrt(gnew) < a.rtol * sqrt(gam0)) break;
+    const TR be = (TR)(gnew / gam);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) p[c] = s[c] + be * p[c];
+    gam = gnew;
+  }
+
+  TI* __restrict__ out = static_cast<TI*>(a.I_out);
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    const int j = j0 + c;
+    if (j < m) out[cb + (int64_t)j * g.cps] = from_real<TI>(x[c]);
+  }
+  if (a.iters && lane == 0) a.iters[col] = it;
+}
+
 }  // namespace
 
 // Columns per workgroup so that one workgroup's vectors fit kLsqLds bytes (0: a column alone
@@ -154,6 +316,24 @@ int lsq_cols_per_block(int mp, DType real) {
 }
 
 hipError_t launch_lsq(const LsqArgs& a0, DType img, DType real, hipStream_t s) {
+  const int m = a0.g.mp;
+  if (m <= 8 * kWave) {   // one wavefront per column
+    const unsigned grid = (unsigned)a0.g.ncol;
+    const size_t lds = (size_t)(5 * m + 2) * (real == DType::F64 ? 8 : 4);
+#define RGP_LSQ_W(CPL)                                                                  \
+  RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_lsq_wave<TI, TR, CPL>), dim3(grid), \
+                                                   dim3(kWave), lds, s, a0))
+    if (m <= kWave)
+      RGP_LSQ_W(1);
+    else if (m <= 2 * kWave)
+      RGP_LSQ_W(2);
+    else if (m <= 4 * kWave)
+      RGP_LSQ_W(4);
+    else
+      RGP_LSQ_W(8);
+#undef RGP_LSQ_W
+    return hipGetLastError();
+  }
   LsqArgs a = a0;
   a.cols_per_block = lsq_cols_per_block(a.g.mp, real);
   if (a.cols_per_block < 1) return hipErrorInvalidValue;

@@ -1255,7 +1255,10 @@ def test_batch_plan_lbfgs_matches_per_pair():
 
 # ---- least-squares correction (Sec. 2.4.7) ----------------------------------------------------
 
-LSQ_CASES = [((32, 32, 24), 1), ((37, 29, 23), 0), ((19, 26, 41), 2), ((70, 9, 130), 0)]
+# columns of 32 to 600 cells: one wavefront per column with 1, 2, 4 or 8 cells per lane up to 512,
+# one thread per column beyond
+LSQ_CASES = [((32, 32, 24), 1), ((37, 29, 23), 0), ((19, 26, 41), 2), ((70, 9, 130), 0),
+             ((6, 200, 5), 1), ((5, 300, 4), 1), ((3, 600, 2), 1)]
 
 
 @pytest.mark.parametrize("img,real", [("f64", "f64"), ("f32", "f32"), ("bf16", "f32")])
@@ -1271,7 +1274,10 @@ def test_correct_lsq_parity(shape, pe, img, real):
     it_t, dt = IMG[img], REAL[real]
     Ip, Im = rounded(p.I_plus, it_t), rounded(p.I_minus, it_t)
     b = rounded(p.b_true, dt)
-    for maxit, rtol in ((12, 0.0), (200, 1e-5)):
+    # FP32 CGLS levels off near 1e-6 of the initial |M^T r| on 300-cell columns, so its stop
+    # decision at 1e-5 can fall two iterations from the FP64 one: FP32 stops at 1e-4 instead
+    rtol_stop = 1e-5 if real == "f64" else 1e-4
+    for maxit, rtol in ((12, 0.0), (200, rtol_stop)):
         out, its = rgp.correct_lsq(to_dev(Ip, it_t), to_dev(Im, it_t), to_dev(b, dt), pe,
                                    maxit=maxit, rtol=rtol)
         ref, ref_it = olsq.lsq_correct(Ip, Im, b, pe, maxit=maxit, rtol=rtol)
