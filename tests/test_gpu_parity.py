@@ -1274,8 +1274,9 @@ def test_correct_lsq_parity(shape, pe, img, real):
     it_t, dt = IMG[img], REAL[real]
     Ip, Im = rounded(p.I_plus, it_t), rounded(p.I_minus, it_t)
     b = rounded(p.b_true, dt)
-    # FP32 CGLS levels off near 1e-6 of the initial |M^T r| on 300-cell columns, so its stop
-    # decision at 1e-5 can fall two iterations from the FP64 one: FP32 stops at 1e-4 instead
+    # the CGLS stop of the least-squares correction (Sec. 2.4.7; relative |M^T r|): FP32 CGLS
+    # levels off near 1e-6 of the initial |M^T r| on 300-cell columns, so its stop decision at 1e-5
+    # can fall two iterations from the FP64 one; FP32 stops at 1e-4 instead
     rtol_stop = 1e-5 if real == "f64" else 1e-4
     for maxit, rtol in ((12, 0.0), (200, rtol_stop)):
         out, its = rgp.correct_lsq(to_dev(Ip, it_t), to_dev(Im, it_t), to_dev(b, dt), pe,
