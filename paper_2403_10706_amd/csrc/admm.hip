@@ -216,7 +216,7 @@ template <typename TR>
 __global__ __launch_bounds__(kDhtBlock) void k_dht(DhtArgs a) {
   if (load_flag(&a.st->gn_stop)) return;
   __shared__ TR xs[kDhtElems];
-  __shared__ TR cas[kDhtMaxN];
+  __shared__ TR cs[2 * kDhtMaxN];   // cos, sin of 2 pi j / n (scaled by 1/sqrt(n)), interleaved
   const int t = a.axis;
   const int n = a.n[t];
   const int64_t s[3] = {(int64_t)a.n[1] * a.n[2], (int64_t)a.n[2], 1};
@@ -228,7 +228,9 @@ __global__ __launch_bounds__(kDhtBlock) void k_dht(DhtArgs a) {
   for (int j = threadIdx.x; j < n; j += kDhtBlock) {
     double sv, cv;
     sincospi(2.0 * (double)j / (double)n, &sv, &cv);
-    cas[j] = (TR)((cv + sv) / sqrt((double)n));
+    const double rn = 1.0 / sqrt((double)n);
+    cs[2 * j] = (TR)(cv * rn);
+    cs[2 * j + 1] = (TR)(sv * rn);
   }
   const bool contig = s[t] == 1;
   const TR* __restrict__ src = static_cast<const TR*>(a.src);
@@ -254,16 +256,7 @@ __global__ __launch_bounds__(kDhtBlock) void k_dht(DhtArgs a) {
       xs[li * n + j] = a.mode == kDhtFirst ? trho * (b[ad] + u[ad]) : src[ad];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < nl * n; e += kDhtBlock) {
-      const int li = contig ? e / n : e % nl, l = contig ? e % n : e / nl;
-      const TR* xl = xs + li * n;
-      TR v = TR(0);
-      int idx = 0;
-      for (int j = 0; j < n; ++j) {
-        v = fma(xl[j], cas[idx], v);
-        idx += l;
-        if (idx >= n) idx -= n;
-      }
+    auto emit = [&](int li, int l, TR v) {
       const int64_t ad = addr(li, l);
       if (a.mode == kDhtScale) {
         // frequencies: l along this axis, the line's coordinate along the other cross axis
@@ -287,6 +280,45 @@ __global__ __launch_bounds__(kDhtBlock) void k_dht(DhtArgs a) {
         acc[1] = fmad64(du, du, acc[1]);
       } else {
         dst[ad] = v;
+      }
+    };
+    // H x at frequency l is C + S and at n - l it is C - S, with C and S the sums of x_j times
+    // cos and sin of 2 pi j l / n: one pass over j serves both frequencies, and the index j l mod n
+    // is shared by the kDhtLines lines of a work item (consecutive items: consecutive l)
+    constexpr int kDhtLines = 2;
+    const int nh = n / 2 + 1;
+    const int ngr = (nl + kDhtLines - 1) / kDhtLines;
+    for (int e = threadIdx.x; e < ngr * nh; e += kDhtBlock) {
+      const int gi = e / nh, l = e - gi * nh;
+      const TR* xl[kDhtLines];
+      TR C[kDhtLines], S[kDhtLines];
+#pragma unroll
+      for (int q = 0; q < kDhtLines; ++q) {
+        const int li = gi * kDhtLines + q;
+        xl[q] = xs + (li < nl ? li : nl - 1) * n;   // past the tile: a valid line, not stored
+        C[q] = S[q] = TR(0);
+      }
+      int idx = 0;
+      for (int j = 0; j < n; ++j) {
+        const TR c = cs[2 * idx], sn = cs[2 * idx + 1];
+#pragma unroll
+        for (int q = 0; q < kDhtLines; ++q) {
+          const TR x = xl[q][j];
+          C[q] = fma(x, c, C[q]);
+          S[q] = fma(x, sn, S[q]);
+        }
+        idx += l;
+        if (idx >= n) idx -= n;
+      }
+#pragma unroll
+      for (int q = 0; q < kDhtLines; ++q) {
+        const int li = gi * kDhtLines + q;
+        if (li >= nl) continue;
+        const int nout = (l > 0 && 2 * l != n) ? 2 : 1;
+        for (int o = 0; o < nout; ++o) {
+          const int lo = o == 0 ? l : n - l;
+          emit(li, lo, o == 0 ? C[q] + S[q] : C[q] - S[q]);
+        }
       }
     }
   }
