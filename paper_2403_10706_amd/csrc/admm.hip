@@ -17,9 +17,10 @@
 // differences of their axis, are symmetric and are their own inverses, so
 // z = (H_A x H_B) diag(1 / (alpha (lambda_A + lambda_B) + rho)) (H_A x H_B) rho (b + u) with
 // lambda(k) = (2 - 2 cos(2 pi k / n)) / h^2 - the same solution as the FFT of the paper.  Four
-// passes of k_dht, each transforming lines along one axis in LDS (a cas table of n entries
-// indexed by j l mod n): B (from rho (b + u)), A with the scaling, A, B (fused with the
-// multiplier update and the residual sums of the rho adaptation).
+// passes of k_dht, each transforming lines along one axis in LDS (a table of n cosine and sine
+// pairs indexed by j l mod n; the cosine and sine sums of frequency l give H x at l and at n - l):
+// B (from rho (b + u)), A with the scaling, A, B (fused with the multiplier update and the
+// residual sums of the rho adaptation).
 #include <hip/hip_runtime.h>
 
 #include "batch.hpp"
