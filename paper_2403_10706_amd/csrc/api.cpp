@@ -210,12 +210,13 @@ struct CorrectWs {
   void* R[2];
   void* P[2];
   void* W[2];
-  // L-BFGS only: the gradient of the previous step, the pair rings (mem + 1 slots each) and the
-  // metadata of two consecutive steps
+  // L-BFGS only: the gradient of the previous step, the pair rings (mem + 1 slots each), the
+  // metadata of two consecutive steps and the block sums of a step's inner products
   void* G2 = nullptr;
   void* S = nullptr;
   void* Y = nullptr;
   LbfgsMeta* meta = nullptr;
+  double* lb_part = nullptr;
 };
 
 // Lays the correction's buffers out from ws (a null ws only counts); *bytes: the total size.
@@ -247,6 +248,8 @@ CorrectWs carve_correct(void* ws, const Level* lv, int levels, DType real,
     w.S = c.take(nb * (size_t)(o->lbfgs_memory + 1));
     w.Y = c.take(nb * (size_t)(o->lbfgs_memory + 1));
     w.meta = static_cast<LbfgsMeta*>(c.take(2 * sizeof(LbfgsMeta)));
+    w.lb_part = static_cast<double*>(
+        c.take((size_t)kLbfgsSums(o->lbfgs_memory) * kMaxGrid * sizeof(double)));
   }
   if (bytes) *bytes = align_up(c.off);
   return w;
@@ -346,7 +349,7 @@ hipError_t run_level_lbfgs(const CorrectWs& w, const Geom& g, const void* Ip, co
   hipError_t e;
   const Control& k = w.ctl;
   const Launch Llg = plan_loss_grad(g, real);
-  const unsigned nblk = lbfgs_grid(g.nnode);
+  const unsigned nblk_dots = lbfgs_dots_grid(g.nnode);
   const int mem = o->lbfgs_memory;
   void* grads[2] = {w.G, w.G2};
   for (int it = 0; it < o->gn_iters; ++it) {
@@ -369,7 +372,6 @@ hipError_t run_level_lbfgs(const CorrectWs& w, const Geom& g, const void* Ip, co
     if ((e = launch_loss_grad(la, img, real, s)) != hipSuccess) return e;
     if (it > 0) cur = 1 - cur;
 
-    const int np = std::min(it, mem);
     LbfgsArgs a{};
     a.n = g.nnode;
     a.g = gcur;
@@ -379,32 +381,23 @@ hipError_t run_level_lbfgs(const CorrectWs& w, const Geom& g, const void* Ip, co
     a.Y = w.Y;
     a.meta_prev = w.meta + ((it + 1) & 1);
     a.meta = w.meta + (it & 1);
+    a.part = w.lb_part;
     a.part_max = k.slot(kPartHvp);
+    a.nprod = nblk_dots;
     a.st = k.st;
     a.mem = mem;
-    a.np = np;
-    a.nprod_in = nblk;
-    int slot = 0;   // partial-sum slot the next kernel writes (they alternate)
-    auto chain = [&](int phase, int j, bool last) -> hipError_t {
-      a.phase = phase;
-      a.j = j;
-      a.last = last ? 1 : 0;
-      a.part_in = k.slot(kPartPcg0 + (1 - slot));
-      a.part_out = k.slot(kPartPcg0 + slot);
-      slot = 1 - slot;
-      return launch_lbfgs(a, real, s);
-    };
+    a.pair = it > 0 ? 1 : 0;
     // the new pair needs gamma of the previous step: before the state is reset below
-    if (it > 0 && (e = chain(kLbPair, 0, false)) != hipSuccess) return e;
+    a.phase = kLbDots;
+    if ((e = launch_lbfgs(a, real, s)) != hipSuccess) return e;
     if ((e = launch_loss_final(LossFinalArgs{k.slot(kPartLoss), Llg.grid, g.vol, o->alpha,
                                              o->beta, k.st, nullptr, rec, 1},
                                s)) != hipSuccess)
       return e;
-    for (int j = 0; j <= np; ++j)
-      if ((e = chain(kLbLoop1, j, false)) != hipSuccess) return e;
-    if ((e = chain(kLbMid, 0, np == 0)) != hipSuccess) return e;
-    for (int t = 1; t <= np; ++t)
-      if ((e = chain(kLbLoop2, t, t == np)) != hipSuccess) return e;
+    a.phase = kLbScalar;
+    if ((e = launch_lbfgs(a, real, s)) != hipSuccess) return e;
+    a.phase = kLbCombine;
+    if ((e = launch_lbfgs(a, real, s)) != hipSuccess) return e;
     if ((e = armijo_passes(w, g, Ip, Im, img, real, o, w.B[cur], gcur, rec, s)) != hipSuccess)
       return e;
   }

@@ -288,35 +288,42 @@ bool timing_slot(int kind, int tag, unsigned grid, int64_t cells, int64_t nodes,
 constexpr int kLbfgsMaxMem = 32;
 constexpr double kLbfgsCurvature = 1e-10;
 struct LbfgsMeta {
-  double rho[kLbfgsMaxMem + 1];    // 1 / s^T y per ring slot
-  double alpha[kLbfgsMaxMem + 1];  // first-loop coefficients, by newest-first pair index
-  double h0;                       // s^T y / y^T y of the newest pair kept
-  int32_t head;                    // the free ring slot (the next pair is written there)
-  int32_t count;                   // pairs kept
+  double rho[kLbfgsMaxMem + 1];                    // 1 / s^T y per ring slot
+  double sy[kLbfgsMaxMem + 1][kLbfgsMaxMem + 1];   // s_i^T y_j per ring slots (kept pairs valid)
+  double yy[kLbfgsMaxMem + 1][kLbfgsMaxMem + 1];   // y_i^T y_j
+  double cs[kLbfgsMaxMem + 1], cy[kLbfgsMaxMem + 1];  // d = cg g + sum over kept slots of
+  double cg;                                       //   cs s + cy y
+  double h0;                                       // s^T y / y^T y of the newest pair kept
+  int32_t head;                                    // the free ring slot (the next pair goes there)
+  int32_t count;                                   // pairs kept
 };
-enum LbfgsPhase : int32_t { kLbPair = 0, kLbLoop1 = 1, kLbMid = 2, kLbLoop2 = 3 };
+// kLbDots: the new pair (s = gamma x, y = g - g_old into the free slot) and the block sums of its
+// inner products with every pair of the window and of g with them; kLbScalar (one block): the
+// sums, the admission of the pair, the two-loop recursion on those inner products, the direction's
+// coefficients; kLbCombine: d = cg g + sum (cs s + cy y).
+enum LbfgsPhase : int32_t { kLbDots = 0, kLbScalar = 1, kLbCombine = 2 };
 struct LbfgsArgs {
   int64_t n;                  // field nodes
   const void* g;              // gradient at the current iterate
-  const void* g_old;          // gradient at the previous iterate (kLbPair)
-  void* x;                    // previous direction (kLbPair); q, r in the loops; d at the end
+  const void* g_old;          // gradient at the previous iterate (kLbDots with a pair)
+  void* x;                    // previous direction (kLbDots); d (kLbCombine)
   void* S;                    // ring of mem + 1 slots of n values each
   void* Y;
   LbfgsMeta* meta_prev;       // metadata of the previous step of the level
   LbfgsMeta* meta;            // metadata of this step
-  const double* part_in;      // column-major block sums of the previous kernel of the chain
-  unsigned nprod_in;
-  double* part_out;           // this kernel's block sums
-  double* part_max;           // block maxima of |g| (kLbLoop1 j = 0 writes, kLbMid reads)
+  double* part;               // kLbDots' column-major block sums (sum k of block b at
+                              // part[k * kMaxGrid + b]), 3 + 5 (mem + 1) sums
+  double* part_max;           // kLbDots' block maxima of |g|
+  unsigned nprod;             // kLbDots' blocks (kLbScalar reads that many)
   State* st;
   int32_t mem;                // pairs kept at most
   int32_t phase;
-  int32_t j;                  // loop index (kLbLoop1: 0..np, kLbLoop2: 1..np)
-  int32_t np;                 // pairs this step can have at most (min(step, mem))
-  int32_t last;               // this kernel ends the chain: it writes d = -r
+  int32_t pair;               // this step forms a pair (every step but the first of a level)
   unsigned nblk;              // set by the launcher
 };
 unsigned lbfgs_grid(int64_t n);
+unsigned lbfgs_dots_grid(int64_t n);
+constexpr int kLbfgsSums(int mem) { return 3 + 5 * (mem + 1); }
 
 // ADMM (admm.hip).
 constexpr double kAdmmMu = 10.0, kAdmmTau = 2.0;  // rho adaptation: ratio and factor
