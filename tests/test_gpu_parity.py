@@ -1210,10 +1210,16 @@ def _check_lbfgs_records(recs, ref_levels, real):
 
 @pytest.mark.parametrize("real", ["f64", "f32"])
 @pytest.mark.parametrize("scale,levels,iters,memory", [(1.0, 1, 12, 4), (1000.0, 2, 10, 3),
-                                                       (30.0, 1, 25, 10)])
+                                                       (30.0, 1, 25, 10), (30.0, 1, 40, 32)])
 def test_correct_lbfgs_parity(real, scale, levels, iters, memory):
     """L-BFGS steps per level instead of Gauss-Newton: the field, and per step the objective,
-    the pairs used, H0's scale, the trial count and the step size, equal the oracle's."""
+    the pairs used, H0's scale, the trial count and the step size, equal the oracle's.  The
+    memory-32 case (40 steps: the ring fills and evicts) runs in FP64 only: over 40 steps the
+    FP32 pairs y = g - g_old lose digits to cancellation as |g| falls, and H0's scale drifts
+    from the FP64 oracle's by a few 1e-3 (the objective still within 1e-5)."""
+    if memory == 32 and real == "f32":
+        pytest.skip("long FP32 runs drift from the FP64 oracle in H0's scale (y = g - g_old "
+                    "cancels); the ring's eviction is checked in FP64")
     rgp = _rgp()
     say(f"[lbfgs] real={real} scale={scale} levels={levels} iters={iters} memory={memory}")
     p = synth.make_workload("c1", scale=scale)
