@@ -1215,8 +1215,9 @@ def test_correct_lbfgs_parity(real, scale, levels, iters, memory):
     """L-BFGS steps per level instead of Gauss-Newton: the field, and per step the objective,
     the pairs used, H0's scale, the trial count and the step size, equal the oracle's.  The
     memory-32 case (40 steps: the ring fills and evicts) runs in FP64 only: over 40 steps the
-    FP32 pairs y = g - g_old lose digits to cancellation as |g| falls, and H0's scale drifts
-    from the FP64 oracle's by a few 1e-3 (the objective still within 1e-5)."""
+    FP32 pairs y = g - g_old lose digits to cancellation as |g| falls, and H0's scale drifted
+    from the FP64 oracle's by 3e-3 (at that step the objective, trial count and pairs used still
+    matched)."""
     if memory == 32 and real == "f32":
         pytest.skip("long FP32 runs drift from the FP64 oracle in H0's scale (y = g - g_old "
                     "cancels); the ring's eviction is checked in FP64")
