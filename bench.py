@@ -834,7 +834,7 @@ def main():
         batch_profile_summary(args.batch_profile_summary)
         return None
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the "
               "per-pair work is independent, so pairs shard across GPUs with no communication.",
               file=sys.stderr)
         sys.exit(2)
