@@ -44,6 +44,7 @@ import dataclasses
 import glob
 import hashlib
 import json
+import math
 import os
 import statistics
 import sys
@@ -110,6 +111,10 @@ def algorithmic_bytes(rec, f=4, fi=4, maxit=PCG_ITERS):
         return 2 * fi * c
     if k == "blur":            # reads b, writes the blurred b
         return 2 * f * n
+    if k == "block_pcg":       # reads diag, off, grad; writes d (every iteration in registers)
+        return 4 * f * n
+    if k == "lsq":             # reads I+, I-, b; writes the corrected image
+        return 3 * fi * c + f * n
     return 0
 
 
@@ -136,6 +141,8 @@ BYTES_RULE = {
     "ot": "reads I+,I-, writes b0 (8 B/cell + 4 B/node)",
     "shift": "reads I+,I- (8 B/cell)",
     "blur": "reads b, writes blurred b (8 B/node)",
+    "block_pcg": "reads diag,off,grad, writes d (16 B/node); the iterations run in registers",
+    "lsq": "reads I+,I-,b, writes the corrected image (12 B/cell + 4 B/node)",
 }
 
 
@@ -697,7 +704,16 @@ def solver_legs(Ip, Im, pe, b_gn, side, steps):
                          status=head["status"], J_last_step=recs[-1][-1]["J"])
         log(f"bench: {name}: {1.0 / wall:.2f} pairs/s ({1e3 * wall:.2f} ms), status "
             f"{head['status']}")
-        del ws, b, st
+        # one eager correction with kernel timing: the solver's own kernels at the finest level
+        rgp.timing_start(1 << 14)
+        eager = rgp.correct(Ip, Im, pe, opts=opts, want_images=False, stream=side)
+        side.synchronize()
+        timed = rgp.timing_stop(1 << 14)
+        _, erecs = rgp.parse_stats(eager["stats"], LEVELS, GN_ITERS)
+        out[name]["kernels"] = leg_kernels(name, timed, erecs)
+        for kname, kr in out[name]["kernels"].items():
+            log(f"bench: {name} {kname}: {kr['achieved']} {kr['unit']} (frac {kr['frac']})")
+        del ws, b, st, eager
     rgp.correct_lsq(Ip, Im, b_gn, pe, stream=side)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -710,6 +726,136 @@ def solver_legs(Ip, Im, pe, b_gn, side, steps):
     ms = e0.elapsed_time(e1) / steps
     out["lsq"] = dict(ms_per_call=round(ms, 3), cgls_iterations_max=int(its.max()))
     log(f"bench: least-squares correction {ms:.3f} ms (CGLS <= {int(its.max())} iterations)")
+    rgp.timing_start(64)
+    rgp.correct_lsq(Ip, Im, b_gn, pe, stream=side)
+    side.synchronize()
+    out["lsq"]["kernels"] = leg_kernels("lsq", rgp.timing_stop(64), None)
+    return out
+
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def dht_flops(rec):
+    """Flops of one Hartley pass by direct summation: every output of a line of length n is an
+    n-term multiply-add sum (2 n flops), over every node of the field."""
+    return 2 * (rec["tag"] >> 2) * rec["nodes"]
+
+
+def _timed(recs, us, **kw):
+    n = len(recs)
+    return dict(launches=n, us_mean=round(us / max(n, 1), 3), **kw)
+
+
+def leg_kernels(name, recs, levels_stats, f=4, fi=4):
+    """The solver's own kernels at the finest level from one eager run with kernel timing:
+    the Hartley passes (ALU: direct sums) and the block PCG of ADMM, the three direction launches
+    of an L-BFGS step (bytes from the pairs each step used, read off the stats records), the
+    least-squares kernel."""
+    out = {}
+    own = [r["nodes"] for r in recs if r["kernel"] in ("dht", "block_pcg", "lbfgs", "lsq")]
+    if not own:
+        return out
+    top = max(own)
+    fin = [r for r in recs if r["nodes"] == top]
+    if name == "admm":
+        dht = [r for r in fin if r["kernel"] == "dht"]
+        if dht:
+            us = 1e3 * sum(r["ms"] for r in dht)
+            fl = sum(dht_flops(r) for r in dht)
+            tf = fl / (us * 1e-6) / 1e12
+            out["dht"] = _timed(dht, us, nodes=top, bound="alu", flops_per_launch=fl // len(dht),
+                                achieved=round(tf, 2), peak=FP32_VECTOR_PEAK_TFLOPS,
+                                unit="TFLOP/s", frac=round(tf / FP32_VECTOR_PEAK_TFLOPS, 4),
+                                rule="2 n flops per node and pass (n-term sums along lines of "
+                                     "length n); FP32 FMA, packed FP32 off")
+        bp = [r for r in fin if r["kernel"] == "block_pcg"]
+        if bp:
+            us = 1e3 * sum(r["ms"] for r in bp)
+            b = algorithmic_bytes(bp[0], f, fi)
+            gbps = b * len(bp) / (us * 1e-6) / 1e9
+            out["block_pcg"] = _timed(bp, us, nodes=top, bound="hbm", bytes_per_launch=b,
+                                      achieved=round(gbps, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
+                                      frac=round(gbps / HBM_PEAK_GBPS, 4),
+                                      rule=BYTES_RULE["block_pcg"],
+                                      pcg_iters=bp[0]["tag"])
+    elif name == "lbfgs":
+        lb = [r for r in fin if r["kernel"] == "lbfgs"]
+        st = levels_stats[-1] if levels_stats else []
+        if lb and len(lb) == 3 * len(st) and all(math.isfinite(x["pcg_iters"]) for x in st):
+            steps, us, byt, prev = [], 0.0, 0, 0
+            for k, rec in enumerate(st):
+                cnt = int(rec["pcg_iters"])
+                dots = 4 * top if k == 0 else (20 + 8 * prev) * top
+                comb = (8 + 8 * cnt) * top
+                t = 1e3 * sum(r["ms"] for r in lb[3 * k:3 * k + 3])
+                steps.append(dict(pairs=cnt, us=round(t, 3), bytes=dots + comb))
+                us += t
+                byt += dots + comb
+                prev = cnt
+            gbps = byt / (us * 1e-6) / 1e9
+            out["direction"] = dict(
+                nodes=top, steps=len(st), us_mean_per_step=round(us / len(st), 3), bound="hbm",
+                bytes_per_step_mean=byt // len(st), achieved=round(gbps, 1), peak=HBM_PEAK_GBPS,
+                unit="GB/s", frac=round(gbps / HBM_PEAK_GBPS, 4),
+                rule="per step: pair and inner products (reads g, g_old, d and the window's s, y; "
+                     "writes s, y: 20 + 8 p B/node), scalar recursion (one block), combination "
+                     "(reads g and the kept s, y; writes d: 8 + 8 c B/node)",
+                per_step=steps)
+    elif name == "lsq":
+        lq = [r for r in fin if r["kernel"] == "lsq"]
+        if lq:
+            us = 1e3 * sum(r["ms"] for r in lq)
+            b = algorithmic_bytes(lq[0], f, fi)
+            gbps = b * len(lq) / (us * 1e-6) / 1e9
+            out["lsq"] = _timed(lq, us, nodes=top, cells=lq[0]["cells"], bound="hbm",
+                                bytes_per_launch=b, achieved=round(gbps, 1), peak=HBM_PEAK_GBPS,
+                                unit="GB/s", frac=round(gbps / HBM_PEAK_GBPS, 4),
+                                rule=BYTES_RULE["lsq"])
+    return out
+
+
+def solver_cpu_baselines(pair, b_field, levels, iters, pcg_iters, sample=None):
+    """The FP64 oracle on bounded samples of the solver legs, one thread: the whole correction
+    with `sample[s]` of the `iters` iterations per level, and with none (pyramid, OT,
+    prolongations and the correction alone), scaled linearly to `iters` iterations per level;
+    the least-squares correction of the given field whole."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import lsq as olsq
+    from oracle import rgp as orc
+
+    sample = sample or dict(lbfgs=3, admm=2)
+    Ip = pair.I_plus.astype(np.float32).astype(np.float64)
+    Im = pair.I_minus.astype(np.float32).astype(np.float64)
+    out = {}
+    model, ncpu, avail = host_cpu()
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        orc.solve(Ip, Im, pair.pe, pair.h, levels=levels, gn_iters=0, pcg_iters=pcg_iters)
+        fixed = time.perf_counter() - t0
+        for name, extra in (("lbfgs", dict(solver="lbfgs", lbfgs_memory=10)),
+                            ("admm", dict(solver="admm"))):
+            k = sample[name]
+            t0 = time.perf_counter()
+            orc.solve(Ip, Im, pair.pe, pair.h, levels=levels, gn_iters=k, pcg_iters=pcg_iters,
+                      pcg_rtol=0.0, **extra)
+            tk = time.perf_counter() - t0
+            per_pair = fixed + (tk - fixed) * iters / k
+            out[name] = dict(value=1.0 / per_pair, unit="pairs/s", cores=1, kind="oracle",
+                             sample=(f"{k} of {iters} iterations per level ({levels} levels, PCG "
+                                     f"{pcg_iters}) {tk:.1f} s, without iterations {fixed:.1f} s; "
+                                     f"per pair {per_pair:.1f} s scaled linearly in the "
+                                     "iterations; FP64 NumPy, one thread"),
+                             host_cpu=model)
+        t0 = time.perf_counter()
+        olsq.lsq_correct(Ip, Im, np.asarray(b_field, dtype=np.float64), pair.pe, pair.h)
+        tl = time.perf_counter() - t0
+        out["lsq"] = dict(value=round(1e3 * tl, 1), unit="ms per call", cores=1, kind="oracle",
+                          sample="one whole least-squares correction (CGLS, at most 30 iterations, "
+                                 f"rtol 1e-6) of the same field, {tl:.1f} s; FP64 NumPy, one thread",
+                          host_cpu=model)
     return out
 
 
@@ -1036,6 +1182,7 @@ def main():
                     copy_reference=copy)
 
     solvers = solver_legs(Ip, Im, pe, b, side, max(2, args.steps // 4))
+    b_host = b.double().cpu().numpy()
     solvers["gn"] = dict(pairs_per_s=round(value, 3), ms_per_pair=round(ms_per_step, 3))
     plan.close()
     batch = None
@@ -1048,6 +1195,10 @@ def main():
         log("bench: timing the FP64 oracle on one whole correction (about 25 s)")
         cpu = cpu_baseline(pair, LEVELS, GN_ITERS, PCG_ITERS)
         log(f"bench: oracle {1.0 / cpu['value']:.1f} s/pair ({cpu['host_cpu']})")
+        log("bench: timing the FP64 oracle on samples of the solver legs (about 30 s)")
+        for name, base in solver_cpu_baselines(pair, b_host, LEVELS, GN_ITERS, PCG_ITERS).items():
+            solvers[name]["cpu_baseline"] = base
+            log(f"bench: oracle {name}: {base['value']:.4g} {base['unit']}")
 
     line = dict(
         metric=METRIC, value=round(value, 3), unit="pairs/s", n_gpus=1, steps=args.steps,

@@ -374,12 +374,19 @@ typedef enum {
   RGP_KERNEL_HVP = 3,        /* stand-alone GN Hessian-vector product */
   RGP_KERNEL_OT = 4,         /* column-wise optimal-transport initialisation (Sec. 2.2) */
   RGP_KERNEL_SHIFT = 5,      /* positivity shift of the OT initialisation */
-  RGP_KERNEL_BLUR = 6        /* optional Gaussian blur of the OT field */
+  RGP_KERNEL_BLUR = 6,       /* optional Gaussian blur of the OT field */
+  RGP_KERNEL_DHT = 7,        /* ADMM z-update: one Hartley pass along a cross axis (Sec. 2.3.2) */
+  RGP_KERNEL_BLOCK_PCG = 8,  /* ADMM b-update: per-column Jacobi PCG (Sec. 2.3.2) */
+  RGP_KERNEL_LBFGS = 9,      /* L-BFGS direction, one of its three phases (Sec. 2.3.3) */
+  RGP_KERNEL_LSQ = 10        /* least-squares correction, CGLS per column (Sec. 2.4.7) */
 } rgp_kernel_kind;
 typedef struct {
   int32_t kernel;
   int32_t tag;       /* PCG step: the PCG iteration (0 = first); trial: candidates; loss_grad:
-                        1 when it also applies the previous step; else 0 */
+                        1 when it also applies the previous step; Hartley pass: the pass mode
+                        (0 first, 1 scaling, 2 plain, 3 last) + 4 x the transform length; block
+                        PCG: the iteration limit; L-BFGS: the phase (0 pair and inner products,
+                        1 scalar recursion, 2 combination); else 0 */
   uint32_t grid;     /* workgroups */
   uint32_t pad;
   int64_t cells;

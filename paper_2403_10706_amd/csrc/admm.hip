@@ -414,8 +414,8 @@ hipError_t launch_block_pcg(const BlockPcgArgs& a0, DType real, hipStream_t s) {
   if (active_recorder())
     return record_other([a, real](hipStream_t s2) { return launch_block_pcg(a, real, s2); });
   const int npl = block_pcg_npl(a.g.mp);
-#define RGP_BP(TR, NPL) \
-  hipLaunchKernelGGL((k_block_pcg<TR, NPL>), dim3(a.nblk), dim3(kBpBlock), 0, s, a)
+#define RGP_BP(TR, NPL)                                                                \
+  RGP_LAUNCH_T(kKindBlockPcg, a.maxit, a.g, (k_block_pcg<TR, NPL>), a.nblk, kBpBlock, 0, s, a)
 #define RGP_BP_T(TR)                           \
   switch (npl) {                               \
     case 1: RGP_BP(TR, 1); break;              \
@@ -456,10 +456,12 @@ hipError_t launch_dht(const DhtArgs& a0, DType real, hipStream_t s) {
   a.nblk = dht_grid(a.n, a.axis, &a.lines_per_block);
   if (active_recorder())
     return record_other([a, real](hipStream_t s2) { return launch_dht(a, real, s2); });
+  const int64_t nodes = (int64_t)a.n[0] * a.n[1] * a.n[2];
+  const int tag = a.mode + 4 * a.n[a.axis];
   if (real == DType::F64)
-    hipLaunchKernelGGL(k_dht<double>, dim3(a.nblk), dim3(kDhtBlock), 0, s, a);
+    RGP_LAUNCH_TN(kKindDht, tag, 0, nodes, k_dht<double>, a.nblk, kDhtBlock, 0, s, a);
   else if (real == DType::F32)
-    hipLaunchKernelGGL(k_dht<float>, dim3(a.nblk), dim3(kDhtBlock), 0, s, a);
+    RGP_LAUNCH_TN(kKindDht, tag, 0, nodes, k_dht<float>, a.nblk, kDhtBlock, 0, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -321,9 +321,9 @@ hipError_t launch_lbfgs(const LbfgsArgs& a0, DType real, hipStream_t s) {
   if (active_recorder())
     return record_other([a, real](hipStream_t s2) { return launch_lbfgs(a, real, s2); });
   if (real == DType::F64)
-    hipLaunchKernelGGL(k_lbfgs<double>, dim3(a.nblk), dim3(kLbBlock), 0, s, a);
+    RGP_LAUNCH_TN(kKindLbfgs, a.phase, 0, a.n, k_lbfgs<double>, a.nblk, kLbBlock, 0, s, a);
   else if (real == DType::F32)
-    hipLaunchKernelGGL(k_lbfgs<float>, dim3(a.nblk), dim3(kLbBlock), 0, s, a);
+    RGP_LAUNCH_TN(kKindLbfgs, a.phase, 0, a.n, k_lbfgs<float>, a.nblk, kLbBlock, 0, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -321,8 +321,8 @@ hipError_t launch_lsq(const LsqArgs& a0, DType img, DType real, hipStream_t s) {
     const unsigned grid = (unsigned)a0.g.ncol;
     const size_t lds = (size_t)(5 * m + 2) * (real == DType::F64 ? 8 : 4);
 #define RGP_LSQ_W(CPL)                                                                  \
-  RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_lsq_wave<TI, TR, CPL>), dim3(grid), \
-                                                   dim3(kWave), lds, s, a0))
+  RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH(kKindLsq, a0.g, (k_lsq_wave<TI, TR, CPL>), grid, \
+                                           kWave, lds, s, a0))
     if (m <= kWave)
       RGP_LSQ_W(1);
     else if (m <= 2 * kWave)
@@ -339,8 +339,8 @@ hipError_t launch_lsq(const LsqArgs& a0, DType img, DType real, hipStream_t s) {
   if (a.cols_per_block < 1) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)((a.g.ncol + a.cols_per_block - 1) / a.cols_per_block);
   const size_t lds = (size_t)(7 * a.g.mp + 1) * a.cols_per_block * (real == DType::F64 ? 8 : 4);
-  RGP_DISPATCH_TYPES(img, real, hipLaunchKernelGGL((k_lsq<TI, TR>), dim3(grid),
-                                                   dim3(kLsqMaxCols), lds, s, a));
+  RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH(kKindLsq, a.g, (k_lsq<TI, TR>), grid, kLsqMaxCols,
+                                           lds, s, a));
   return hipGetLastError();
 }
 

@@ -253,7 +253,9 @@ unsigned shift_grid(int64_t n);
 // Kernel timing (instrumentation behind rgp_timing_start/stop): when it is enabled and the stream
 // is not being captured, timing_slot hands out a pair of HIP events that hipExtLaunchKernelGGL
 // records at the start and the end of the kernel itself, and notes the launch (tag: the PCG
-// iteration of a PCG step, the candidate count of a trial pass, else 0).
+// iteration of a PCG step, the candidate count of a trial pass, the pass mode plus 4 times the
+// line length of a Hartley pass, the iteration limit of a block PCG, the phase of an L-BFGS
+// launch, else 0).
 enum KernelKind : int {
   kKindPcgStep = 0,
   kKindLossGrad = 1,
@@ -262,7 +264,11 @@ enum KernelKind : int {
   kKindOt = 4,
   kKindShift = 5,
   kKindBlur = 6,
-  kKindCount = 7
+  kKindDht = 7,
+  kKindBlockPcg = 8,
+  kKindLbfgs = 9,
+  kKindLsq = 10,
+  kKindCount = 11
 };
 bool timing_slot(int kind, int tag, unsigned grid, int64_t cells, int64_t nodes, hipStream_t s,
                  hipEvent_t* e0, hipEvent_t* e1);

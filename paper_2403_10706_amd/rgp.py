@@ -69,7 +69,8 @@ EXPORTS = ("rgp_status_string", "rgp_last_hip_error", "rgp_default_opts", "rgp_w
 # rgp_kernel_kind
 KERNEL_PCG_STEP, KERNEL_LOSS_GRAD, KERNEL_TRIAL, KERNEL_HVP, KERNEL_OT, KERNEL_SHIFT, \
     KERNEL_BLUR = range(7)
-KERNEL_NAMES = ("pcg_step", "loss_grad", "trial", "hvp", "ot", "shift", "blur")
+KERNEL_NAMES = ("pcg_step", "loss_grad", "trial", "hvp", "ot", "shift", "blur", "dht", "block_pcg",
+                "lbfgs", "lsq")
 
 
 class TimingRecord(ctypes.Structure):

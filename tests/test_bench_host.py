@@ -60,6 +60,36 @@ def test_summarize_records_keeps_full_iterations_and_first_trial_passes():
     assert step["launches"] == 2 and step["us_median"] == pytest.approx(23.0)
 
 
+def test_solver_leg_kernels_at_the_finest_level():
+    """Hartley passes as direct sums (2 n flops per node and pass), the block PCG's 16 B/node,
+    and the L-BFGS direction's bytes per step from the pairs each step used."""
+    coarse = NB_C2 // 8
+    recs = [_rec("dht", 3 + 4 * 144, ms=0.030), _rec("dht", 2 + 4 * 111, ms=0.020),
+            _rec("dht", 2 + 4 * 72, ms=0.010, nodes=coarse), _rec("block_pcg", 20, ms=0.1),
+            _rec("loss_grad", 0)]
+    k = bench.leg_kernels("admm", recs, None)
+    fl = 2 * 144 * NB_C2 + 2 * 111 * NB_C2
+    assert k["dht"]["launches"] == 2 and k["dht"]["flops_per_launch"] == fl // 2
+    assert k["dht"]["achieved"] == pytest.approx(fl / 50e-6 / 1e12, rel=1e-3)
+    assert k["dht"]["frac"] == pytest.approx(k["dht"]["achieved"] / 157.3, rel=1e-3)
+    assert k["block_pcg"]["bytes_per_launch"] == 16 * NB_C2
+    assert k["block_pcg"]["achieved"] == pytest.approx(16 * NB_C2 / 100e-6 / 1e9, rel=1e-3)
+    # three launches per L-BFGS step; step 0 reads g only, then 20 + 8 p and 8 + 8 c B/node
+    lb = [_rec("lbfgs", ph, ms=0.01) for _ in range(3) for ph in range(3)]
+    stats = [[], [dict(pcg_iters=0.0), dict(pcg_iters=1.0), dict(pcg_iters=2.0)]]
+    d = bench.leg_kernels("lbfgs", lb, stats)["direction"]
+    want = [4 + 8, (20 + 0) + (8 + 8), (20 + 8) + (8 + 16)]
+    assert [st["bytes"] for st in d["per_step"]] == [w * NB_C2 for w in want]
+    assert d["us_mean_per_step"] == pytest.approx(30.0)
+    assert d["achieved"] == pytest.approx(sum(want) * NB_C2 / 90e-6 / 1e9, rel=1e-3)
+    # a stopped solve (NaN records) or a launch count that does not match gives no figure
+    stats_nan = [[], [dict(pcg_iters=float("nan"))] * 3]
+    assert "direction" not in bench.leg_kernels("lbfgs", lb, stats_nan)
+    assert "direction" not in bench.leg_kernels("lbfgs", lb[:-1], stats)
+    q = bench.leg_kernels("lsq", [_rec("lsq", 0, ms=0.27)], None)["lsq"]
+    assert q["bytes_per_launch"] == 12 * N_C2 + 4 * NB_C2
+
+
 def test_batch_level_bytes_sum_the_per_pair_rules():
     from synth.phantom import batch_specs
     lv = bench.batch_level_bytes(n=3)
