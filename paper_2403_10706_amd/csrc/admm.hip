@@ -213,17 +213,24 @@ __global__ __launch_bounds__(kBpBlock) void k_block_pcg_stats(BlockPcgArgs a) {
 
 // ---- z-update ---------------------------------------------------------------------------------
 
+// A tile of consecutive lines (line stride n | 1, odd) sits in LDS; a work item is two lines and
+// one frequency pair, with the line pairs varying fastest across the lanes, so the lanes of a
+// wavefront read few distinct table entries (multicast) and lines in distinct banks.  Element,
+// line and work-item indices split by multiply-shift divisions in 32 bits (a field has at most
+// 2^28 nodes).
 template <typename TR>
 __global__ __launch_bounds__(kDhtBlock) void k_dht(DhtArgs a) {
   if (load_flag(&a.st->gn_stop)) return;
   __shared__ TR xs[kDhtElems];
   __shared__ TR cs[2 * kDhtMaxN];   // cos, sin of 2 pi j / n (scaled by 1/sqrt(n)), interleaved
   const int t = a.axis;
-  const int n = a.n[t];
-  const int64_t s[3] = {(int64_t)a.n[1] * a.n[2], (int64_t)a.n[2], 1};
+  const int n = a.n[t], ns = n | 1;
   // the two other axes, slower first
   const int u0 = t == 0 ? 1 : 0, u1 = t == 2 ? 1 : 2;
-  const int64_t nlines = (int64_t)a.n[u0] * a.n[u1];
+  const uint32_t st3[3] = {(uint32_t)a.n[1] * (uint32_t)a.n[2], (uint32_t)a.n[2], 1u};
+  const uint32_t su0 = st3[u0], su1 = st3[u1], sj = st3[t];
+  const uint32_t nu1 = (uint32_t)a.n[u1];
+  const uint32_t nlines = (uint32_t)a.n[u0] * nu1;
   const int lpb = a.lines_per_block;
   const double rho = a.st->admm_rho;
   for (int j = threadIdx.x; j < n; j += kDhtBlock) {
@@ -233,7 +240,7 @@ __global__ __launch_bounds__(kDhtBlock) void k_dht(DhtArgs a) {
     cs[2 * j] = (TR)(cv * rn);
     cs[2 * j + 1] = (TR)(sv * rn);
   }
-  const bool contig = s[t] == 1;
+  const bool contig = sj == 1;
   const TR* __restrict__ src = static_cast<const TR*>(a.src);
   const TR* __restrict__ b = static_cast<const TR*>(a.b);
   TR* __restrict__ u = static_cast<TR*>(a.u);
@@ -241,28 +248,41 @@ __global__ __launch_bounds__(kDhtBlock) void k_dht(DhtArgs a) {
   TR* __restrict__ zc = static_cast<TR*>(a.c);
   const TR trho = (TR)rho;
   double acc[2] = {0.0, 0.0};   // final pass: sum (b - z)^2, sum (z - z_old)^2
-  for (int64_t l0 = (int64_t)blockIdx.x * lpb; l0 < nlines; l0 += (int64_t)gridDim.x * lpb) {
-    const int nl = (int)(nlines - l0 < lpb ? nlines - l0 : lpb);
-    // element e of the tile: line l0 + li, position j; consecutive threads take consecutive
-    // addresses (along the line when it is contiguous, across lines otherwise)
-    auto addr = [&](int li, int j) -> int64_t {
-      const int64_t L = l0 + li;
-      const int64_t c0 = L / a.n[u1], c1 = L - c0 * a.n[u1];
-      return c0 * s[u0] + c1 * s[u1] + (int64_t)j * s[t];
+  for (uint32_t l0 = blockIdx.x * (uint32_t)lpb; l0 < nlines; l0 += gridDim.x * (uint32_t)lpb) {
+    const int nl = (int)(nlines - l0 < (uint32_t)lpb ? nlines - l0 : (uint32_t)lpb);
+    // element (li, j) of the tile: consecutive threads take consecutive addresses (along the
+    // line when it is contiguous, across lines otherwise; e = li + lpb j there, with li >= nl
+    // skipped in the last tile)
+    auto split = [&](uint32_t e, int& li, int& j) {
+      if (contig) {
+        li = (int)fdiv(e, a.by_n);
+        j = (int)e - li * n;
+      } else {
+        j = (int)fdiv(e, a.by_lpb);
+        li = (int)e - j * lpb;
+      }
     };
+    auto addr = [&](int li, int j) -> uint32_t {
+      const uint32_t L = l0 + (uint32_t)li;
+      const uint32_t c0 = fdiv(L, a.by_nu1), c1 = L - c0 * nu1;
+      return c0 * su0 + c1 * su1 + (uint32_t)j * sj;
+    };
+    const uint32_t nel = (uint32_t)(contig ? nl : lpb) * (uint32_t)n;
     __syncthreads();
-    for (int e = threadIdx.x; e < nl * n; e += kDhtBlock) {
-      const int li = contig ? e / n : e % nl, j = contig ? e % n : e / nl;
-      const int64_t ad = addr(li, j);
-      xs[li * n + j] = a.mode == kDhtFirst ? trho * (b[ad] + u[ad]) : src[ad];
+    for (uint32_t e = threadIdx.x; e < nel; e += kDhtBlock) {
+      int li, j;
+      split(e, li, j);
+      if (li >= nl) continue;
+      const uint32_t ad = addr(li, j);
+      xs[li * ns + j] = a.mode == kDhtFirst ? trho * (b[ad] + u[ad]) : src[ad];
     }
     __syncthreads();
     auto emit = [&](int li, int l, TR v) {
-      const int64_t ad = addr(li, l);
+      const uint32_t ad = addr(li, l);
       if (a.mode == kDhtScale) {
         // frequencies: l along this axis, the line's coordinate along the other cross axis
-        const int64_t L = l0 + li;
-        const int64_t c0 = L / a.n[u1], c1 = L - c0 * a.n[u1];
+        const uint32_t L = l0 + (uint32_t)li;
+        const uint32_t c0 = fdiv(L, a.by_nu1), c1 = L - c0 * nu1;
         const int ko = (int)(a.other_axis == u0 ? c0 : c1);
         const int no = a.n[a.other_axis];
         const double lt = (2.0 - 2.0 * cospi(2.0 * l / (double)n)) * a.inv_h2[0];
@@ -285,18 +305,20 @@ __global__ __launch_bounds__(kDhtBlock) void k_dht(DhtArgs a) {
     };
     // H x at frequency l is C + S and at n - l it is C - S, with C and S the sums of x_j times
     // cos and sin of 2 pi j l / n: one pass over j serves both frequencies, and the index j l mod n
-    // is shared by the kDhtLines lines of a work item (consecutive items: consecutive l)
+    // is shared by the kDhtLines lines of a work item
     constexpr int kDhtLines = 2;
     const int nh = n / 2 + 1;
-    const int ngr = (nl + kDhtLines - 1) / kDhtLines;
-    for (int e = threadIdx.x; e < ngr * nh; e += kDhtBlock) {
-      const int gi = e / nh, l = e - gi * nh;
+    const int ngr = (lpb + kDhtLines - 1) / kDhtLines;   // line pairs of a full tile
+    const int ngl = (nl + kDhtLines - 1) / kDhtLines;    // of this tile
+    for (uint32_t e = threadIdx.x; e < (uint32_t)(ngr * nh); e += kDhtBlock) {
+      const int l = (int)fdiv(e, a.by_ngr), gi = (int)e - l * ngr;
+      if (gi >= ngl) continue;
       const TR* xl[kDhtLines];
       TR C[kDhtLines], S[kDhtLines];
 #pragma unroll
       for (int q = 0; q < kDhtLines; ++q) {
         const int li = gi * kDhtLines + q;
-        xl[q] = xs + (li < nl ? li : nl - 1) * n;   // past the tile: a valid line, not stored
+        xl[q] = xs + (li < nl ? li : nl - 1) * ns;   // past the tile: a valid line, not stored
         C[q] = S[q] = TR(0);
       }
       int idx = 0;
@@ -444,7 +466,7 @@ hipError_t launch_block_pcg(const BlockPcgArgs& a0, DType real, hipStream_t s) {
 unsigned dht_grid(const int32_t n[3], int axis, int* lines_per_block) {
   const int u0 = axis == 0 ? 1 : 0, u1 = axis == 2 ? 1 : 2;
   const int64_t nlines = (int64_t)n[u0] * n[u1];
-  const int lpb = kDhtElems / n[axis] < 1 ? 1 : kDhtElems / n[axis];
+  const int lpb = kDhtElems / (n[axis] | 1) < 1 ? 1 : kDhtElems / (n[axis] | 1);
   *lines_per_block = lpb;
   const int64_t b = (nlines + lpb - 1) / lpb;
   return (unsigned)(b > kMaxGrid ? kMaxGrid : b);
@@ -454,6 +476,11 @@ hipError_t launch_dht(const DhtArgs& a0, DType real, hipStream_t s) {
   DhtArgs a = a0;
   if (a.n[a.axis] > kDhtMaxN) return hipErrorInvalidValue;
   a.nblk = dht_grid(a.n, a.axis, &a.lines_per_block);
+  const int u1 = a.axis == 2 ? 1 : 2;
+  a.by_n = make_fastdiv((uint32_t)a.n[a.axis]);
+  a.by_nu1 = make_fastdiv((uint32_t)a.n[u1]);
+  a.by_lpb = make_fastdiv((uint32_t)a.lines_per_block);
+  a.by_ngr = make_fastdiv((uint32_t)((a.lines_per_block + 1) / 2));
   if (active_recorder())
     return record_other([a, real](hipStream_t s2) { return launch_dht(a, real, s2); });
   const int64_t nodes = (int64_t)a.n[0] * a.n[1] * a.n[2];

@@ -363,6 +363,8 @@ struct DhtArgs {           // one pass of the z-update (normalised Hartley trans
   double* part;            // kDhtLast: block sums of (b - z)^2 and (z - z_old)^2
   int32_t lines_per_block; // set by the launcher
   unsigned nblk;           // set by the launcher
+  FastDiv by_n, by_nu1, by_lpb, by_ngr;  // set by the launcher: divisions by n[axis], by the
+                                         // faster other extent, by lines_per_block, by its pairs
 };
 struct AdmmRhoArgs {
   State* st;

@@ -1356,11 +1356,13 @@ def test_correct_lsq_c2_sampled_columns():
 @pytest.mark.parametrize("real", ["f64", "f32"])
 @pytest.mark.parametrize("shape,pe,scale,levels,iters", [
     ((32, 32, 24), 1, 1.0, 1, 8), ((37, 29, 23), 0, 30.0, 1, 10), ((19, 26, 41), 2, 30.0, 1, 8),
-    ((32, 32, 24), 1, 1000.0, 2, 6)])
+    ((32, 32, 24), 1, 1000.0, 2, 6), ((6, 300, 20), 2, 30.0, 1, 6)])
 def test_correct_admm_parity(real, shape, pe, scale, levels, iters):
     """ADMM iterations per level instead of Gauss-Newton: the field and, per iteration, the
     b-update's objective, the largest column PCG iteration count and residual, the step size,
-    the trial count and the rho used, equal the oracle's (column PCG 10 iterations, rtol 0.1)."""
+    the trial count and the rho used, equal the oracle's (column PCG 10 iterations, rtol 0.1).
+    The 6 x 300 x 20 case transforms lines of 300 (too long for the line-per-lane Hartley
+    kernel's LDS: the item-per-frequency kernel) and of 6 in the same z-update."""
     rgp = _rgp()
     say(f"[admm] real={real} shape={shape} pe={pe} scale={scale} levels={levels} iters={iters}")
     p = _pair(shape, pe, seed=44, scale=scale)
