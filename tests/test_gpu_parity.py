@@ -1361,8 +1361,8 @@ def test_correct_admm_parity(real, shape, pe, scale, levels, iters):
     """ADMM iterations per level instead of Gauss-Newton: the field and, per iteration, the
     b-update's objective, the largest column PCG iteration count and residual, the step size,
     the trial count and the rho used, equal the oracle's (column PCG 10 iterations, rtol 0.1).
-    The 6 x 300 x 20 case transforms lines of 300 (too long for the line-per-lane Hartley
-    kernel's LDS: the item-per-frequency kernel) and of 6 in the same z-update."""
+    The 6 x 300 x 20 case transforms lines of 300 (six per LDS tile) and of 6 (292 per tile, the
+    last tile partial) in the same z-update."""
     rgp = _rgp()
     say(f"[admm] real={real} shape={shape} pe={pe} scale={scale} levels={levels} iters={iters}")
     p = _pair(shape, pe, seed=44, scale=scale)
