@@ -418,9 +418,12 @@ unsigned vec_grid(int64_t n) {
 
 }  // namespace
 
+// Nodes per lane: the shortest run in kBpRuns whose 16 lanes cover the column (169 nodes take
+// 12 per lane, 192 slots, where powers of two alone would take 16, 256 slots).
+constexpr int kBpRuns[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
 int block_pcg_npl(int mp) {
   const int n = mp + 1;
-  for (int npl = 1; npl <= 32; npl *= 2)
+  for (int npl : kBpRuns)
     if (16 * npl >= n) return npl;
   return 0;
 }
@@ -442,9 +445,13 @@ hipError_t launch_block_pcg(const BlockPcgArgs& a0, DType real, hipStream_t s) {
   switch (npl) {                               \
     case 1: RGP_BP(TR, 1); break;              \
     case 2: RGP_BP(TR, 2); break;              \
+    case 3: RGP_BP(TR, 3); break;              \
     case 4: RGP_BP(TR, 4); break;              \
+    case 6: RGP_BP(TR, 6); break;              \
     case 8: RGP_BP(TR, 8); break;              \
+    case 12: RGP_BP(TR, 12); break;            \
     case 16: RGP_BP(TR, 16); break;            \
+    case 24: RGP_BP(TR, 24); break;            \
     case 32: RGP_BP(TR, 32); break;            \
     default: return hipErrorInvalidValue;      \
   }
