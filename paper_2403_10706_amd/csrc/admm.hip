@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBpBlock) void k_block_pcg(BlockPcgArgs a) {
     const int64_t cc = colok ? col : 0;
     const int64_t ix = cc / g.ny, iy = cc - ix * g.ny;
     const int64_t nb = ix * g.nxs + iy * g.nys;
-    TR d[NPL], o[NPL], r[NPL], x[NPL], p[NPL];
+    TR d[NPL], di[NPL], o[NPL], r[NPL], x[NPL], p[NPL];   // di = 1/d: the Jacobi step is r di
     double rr0 = 0.0;
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
@@ -94,6 +94,7 @@ __global__ __launch_bounds__(kBpBlock) void k_block_pcg(BlockPcgArgs a) {
       const bool ok = colok && k <= mp;
       const int64_t e = nb + (int64_t)(ok ? k : 0) * g.nps;
       d[i] = ok ? dg[e] : TR(1);
+      di[i] = TR(1) / d[i];
       o[i] = ok && k < mp ? og[e] : TR(0);
       r[i] = ok ? -gg[e] : TR(0);
       x[i] = TR(0);
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(kBpBlock) void k_block_pcg(BlockPcgArgs a) {
     double rz = 0.0;
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
-      p[i] = r[i] / d[i];
+      p[i] = r[i] * di[i];
       rz = fmad64((double)r[i], (double)p[i], rz);
     }
     rz = row_sum(rz);
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(kBpBlock) void k_block_pcg(BlockPcgArgs a) {
       TR z[NPL];
 #pragma unroll
       for (int i = 0; i < NPL; ++i) {
-        z[i] = r[i] / d[i];
+        z[i] = r[i] * di[i];
         rzn = fmad64((double)r[i], (double)z[i], rzn);
       }
       rzn = row_sum(rzn);
