@@ -11,12 +11,13 @@
 // each owned cell's (at most three) output cells; M p is a gather too: output cell i sums w(i, j) p_j
 // over the moved cells j that overlap it, in ascending j - the order in which a scatter over j would
 // add them - starting from the first j whose moved interval ends beyond i (a binary search over the
-// monotone moved nodes, once per solve).  Inner products are FP64 (per lane in cell order, then
-// across the wavefront in a fixed tree).
+// monotone moved nodes, once per solve).  Each moved cell's overlaps are formed once per solve
+// (registers for its own lane, LDS for the others).  Inner products are FP64 (per lane in cell
+// order, then across the wavefront in a fixed tree).
 // Longer columns: one thread owns one column, its field, iterate and CGLS vectors in LDS for the
 // whole solve, laid out [vector][k][thread] so that the lanes of a wavefront touch consecutive
-// words whenever they index the same k.  Neither form stores the matrices: every sweep recomputes
-// each moved cell's overlaps from the field.
+// words whenever they index the same k; every sweep recomputes each moved cell's overlaps from the
+// field there.
 #include <hip/hip_runtime.h>
 
 #include "rgp_internal.hpp"
@@ -169,6 +170,8 @@ __global__ __launch_bounds__(kWave) void k_lsq_wave(LsqArgs a) {
   yv[1] = yv[0] + (m + 1);                 // - polarity
   TR* sp = yv[1] + (m + 1);                // p, read by the lanes that gather it: m
   TR* sr[2] = {sp + m, sp + 2 * m};        // r+, r-: m each
+  TR* ww = sp + 3 * m;                     // overlap weights of moved cell j: [pol][j][3]
+  int* wi = reinterpret_cast<int*>(ww + 6 * m);   // and its first output cell: [pol][j]
 
   const int ix = (int)(col / g.ny), iy = (int)(col - (int64_t)ix * g.ny);
   const int64_t cb = ix * g.cxs + iy * g.cys, nb = ix * g.nxs + iy * g.nys;
@@ -192,6 +195,25 @@ __global__ __launch_bounds__(kWave) void k_lsq_wave(LsqArgs a) {
     r[1][c] = own ? to_real(Im[cb + (int64_t)j * g.cps], TR()) : TR(0);
   }
   __syncthreads();
+  // overlaps of the owned moved cells, once per solve: in registers for M^T r, in LDS for the
+  // lanes whose output cells they reach (M p)
+  TR wo[2][CPL][3];
+  int io[2][CPL];
+#pragma unroll
+  for (int pol = 0; pol < 2; ++pol) {
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int j = j0 + c;
+      io[pol][c] = 0;
+      wo[pol][c][0] = wo[pol][c][1] = wo[pol][c][2] = TR(0);
+      if (j < m) {
+        overlaps(yv[pol][j], yv[pol][j + 1], m, io[pol][c], wo[pol][c]);
+        wi[pol * m + j] = io[pol][c];
+#pragma unroll
+        for (int tt = 0; tt < 3; ++tt) ww[(pol * m + j) * 3 + tt] = wo[pol][c][tt];
+      }
+    }
+  }
   // first moved cell whose interval ends beyond each owned output cell, per polarity
   int jlo[2][CPL];
 #pragma unroll
@@ -227,12 +249,10 @@ __global__ __launch_bounds__(kWave) void k_lsq_wave(LsqArgs a) {
       if (j < m) {
 #pragma unroll
         for (int pol = 0; pol < 2; ++pol) {
-          TR w[3];
-          int i0;
-          overlaps(yv[pol][j], yv[pol][j + 1], m, i0, w);
+          const int i0 = io[pol][c];
 #pragma unroll
           for (int tt = 0; tt < 3; ++tt)
-            if (w[tt] != TR(0)) acc += w[tt] * sr[pol][i0 + tt];
+            if (wo[pol][c][tt] != TR(0)) acc += wo[pol][c][tt] * sr[pol][i0 + tt];
         }
       }
       s[c] = acc;
@@ -265,11 +285,8 @@ __global__ __launch_bounds__(kWave) void k_lsq_wave(LsqArgs a) {
         if (i < m) {
           const TR* y = yv[pol];
           for (int j = jlo[pol][c]; j < m && y[j] < TR(i + 1); ++j) {
-            TR w[3];
-            int i0;
-            overlaps(y[j], y[j + 1], m, i0, w);
-            const int tt = i - i0;
-            const TR wt = tt == 0 ? w[0] : (tt == 1 ? w[1] : (tt == 2 ? w[2] : TR(0)));
+            const int tt = i - wi[pol * m + j];
+            const TR wt = (tt >= 0 && tt < 3) ? ww[(pol * m + j) * 3 + tt] : TR(0);
             if (wt != TR(0)) acc += wt * sp[j];
           }
         }
@@ -319,7 +336,7 @@ hipError_t launch_lsq(const LsqArgs& a0, DType img, DType real, hipStream_t s) {
   const int m = a0.g.mp;
   if (m <= 8 * kWave) {   // one wavefront per column
     const unsigned grid = (unsigned)a0.g.ncol;
-    const size_t lds = (size_t)(5 * m + 2) * (real == DType::F64 ? 8 : 4);
+    const size_t lds = (size_t)(11 * m + 2) * (real == DType::F64 ? 8 : 4) + (size_t)2 * m * 4;
 #define RGP_LSQ_W(CPL)                                                                  \
   RGP_DISPATCH_TYPES(img, real, RGP_LAUNCH(kKindLsq, a0.g, (k_lsq_wave<TI, TR, CPL>), grid, \
                                            kWave, lds, s, a0))
