@@ -6,7 +6,8 @@
 // found by CGLS from I = 0 (conjugate gradients on the normal equations, Hestenes-Stiefel form).
 //
 // Columns of up to 512 cells: one wavefront (one workgroup) per column.  Lane l owns the cells
-// l*CPL .. l*CPL+CPL-1 and keeps their CGLS vectors in registers; the moved node positions of both
+// l*CPL .. l*CPL+CPL-1 (CPL = 1, 2, 3, 4, 6 or 8, the fewest that cover the column) and keeps
+// their CGLS vectors in registers; the moved node positions of both
 // polarities and the vectors that other lanes read (p, r+, r-) sit in LDS.  M^T r is a gather over
 // each owned cell's (at most three) output cells; M p is a gather too: output cell i sums w(i, j) p_j
 // over the moved cells j that overlap it, in ascending j - the order in which a scatter over j would
@@ -344,8 +345,12 @@ hipError_t launch_lsq(const LsqArgs& a0, DType img, DType real, hipStream_t s) {
       RGP_LSQ_W(1);
     else if (m <= 2 * kWave)
       RGP_LSQ_W(2);
+    else if (m <= 3 * kWave)
+      RGP_LSQ_W(3);
     else if (m <= 4 * kWave)
       RGP_LSQ_W(4);
+    else if (m <= 6 * kWave)
+      RGP_LSQ_W(6);
     else
       RGP_LSQ_W(8);
 #undef RGP_LSQ_W
