@@ -1041,6 +1041,49 @@ def test_batch_long_marches_option(real):
         say(f"[batch march {real}] pair {i} {sh}: max|b_long - b_pair| = {d:.3e}")
         assert d <= _tol(real, 1e-9, 1e-3), (i, d)
 
+def test_timing_records_of_the_solver_kernels():
+    """Kernel timing covers the solver legs' own kernels: per ADMM iteration four Hartley passes
+    (modes first, scaling, plain, last; tag = mode + 4 n) and one block PCG (tag = its iteration
+    limit), per L-BFGS step its three phases in order, one least-squares launch per call; the
+    fields equal the untimed runs'."""
+    rgp = _rgp()
+    shape, pe, levels, iters = (24, 30, 20), 1, 2, 3
+    p = _pair(shape, pe, seed=61, scale=30.0)
+    dt = torch.float32
+    Ip, Im = to_dev(p.I_plus, dt), to_dev(p.I_minus, dt)
+    fine = rgp.field_shape(shape, pe)
+    nodes_fine = int(np.prod(fine))
+    for solver in ("admm", "lbfgs"):
+        opts = rgp.Options(levels=levels, gn_iters=iters, pcg_iters=10, solver=solver)
+        ref = rgp.correct(Ip, Im, pe, opts=opts)
+        torch.cuda.synchronize()
+        rgp.timing_start()
+        out = rgp.correct(Ip, Im, pe, opts=opts)
+        torch.cuda.synchronize()
+        recs = rgp.timing_stop()
+        assert torch.equal(out["b"], ref["b"]), solver
+        top = [r for r in recs if r["nodes"] == nodes_fine]
+        if solver == "admm":
+            dht = [r for r in top if r["kernel"] == "dht"]
+            assert len(dht) == 4 * iters
+            for k in range(iters):   # lines along the cross axes of PE dim 1 (0 and 2)
+                modes = [r["tag"] & 3 for r in dht[4 * k:4 * k + 4]]
+                assert modes == [0, 1, 2, 3], modes
+                assert {r["tag"] >> 2 for r in dht[4 * k:4 * k + 4]} <= {shape[0], shape[2]}
+            bp = [r for r in top if r["kernel"] == "block_pcg"]
+            assert len(bp) == iters and all(r["tag"] == 10 for r in bp)
+            assert all(r["ms"] > 0 for r in dht + bp)
+        else:
+            lb = [r for r in top if r["kernel"] == "lbfgs"]
+            assert [r["tag"] for r in lb] == [0, 1, 2] * iters
+            assert all(r["ms"] > 0 for r in lb)
+    rgp.timing_start()
+    rgp.correct_lsq(Ip, Im, ref["b"], pe)
+    torch.cuda.synchronize()
+    lq = [r for r in rgp.timing_stop() if r["kernel"] == "lsq"]
+    assert len(lq) == 1 and lq[0]["cells"] == int(np.prod(shape)) and lq[0]["nodes"] == nodes_fine
+
+
 def test_autotune_then_correct():
     """The autotuner picks one march length per level from the candidates; afterwards the
     correction (plain and batched) still matches the untuned result up to the order of the block
