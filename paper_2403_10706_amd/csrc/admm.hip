@@ -222,10 +222,15 @@ __global__ __launch_bounds__(kBpBlock) void k_block_pcg_stats(BlockPcgArgs a) {
 template <typename TR>
 __global__ __launch_bounds__(kDhtBlock) void k_dht(DhtArgs a) {
   if (load_flag(&a.st->gn_stop)) return;
-  __shared__ TR xs[kDhtElems];
-  __shared__ TR cs[2 * kDhtMaxN];   // cos, sin of 2 pi j / n (scaled by 1/sqrt(n)), interleaved
   const int t = a.axis;
   const int n = a.n[t], ns = n | 1;
+  const bool scale = a.mode == kDhtScale;
+  // LDS sized to n: the scaling pass's eigenvalue terms of this axis (n doubles), the table of
+  // cos, sin of 2 pi j / n (scaled by 1/sqrt(n), interleaved), the tile
+  extern __shared__ __align__(16) unsigned char dht_lds[];
+  double* __restrict__ lt = reinterpret_cast<double*>(dht_lds);
+  TR* __restrict__ cs = reinterpret_cast<TR*>(lt + (scale ? n : 0));
+  TR* __restrict__ xs = cs + 2 * n;
   // the two other axes, slower first
   const int u0 = t == 0 ? 1 : 0, u1 = t == 2 ? 1 : 2;
   const uint32_t st3[3] = {(uint32_t)a.n[1] * (uint32_t)a.n[2], (uint32_t)a.n[2], 1u};
@@ -240,6 +245,7 @@ __global__ __launch_bounds__(kDhtBlock) void k_dht(DhtArgs a) {
     const double rn = 1.0 / sqrt((double)n);
     cs[2 * j] = (TR)(cv * rn);
     cs[2 * j + 1] = (TR)(sv * rn);
+    if (scale) lt[j] = (2.0 - 2.0 * cospi(2.0 * j / (double)n)) * a.inv_h2[0];
   }
   const bool contig = sj == 1;
   const TR* __restrict__ src = static_cast<const TR*>(a.src);
@@ -278,18 +284,19 @@ __global__ __launch_bounds__(kDhtBlock) void k_dht(DhtArgs a) {
       xs[li * ns + j] = a.mode == kDhtFirst ? trho * (b[ad] + u[ad]) : src[ad];
     }
     __syncthreads();
-    auto emit = [&](int li, int l, TR v) {
+    // the scaling pass's eigenvalue term of the other cross axis for line li (its coordinate
+    // there is the line's frequency along that axis)
+    auto other_term = [&](int li) -> double {
+      const uint32_t L = l0 + (uint32_t)li;
+      const uint32_t c0 = fdiv(L, a.by_nu1), c1 = L - c0 * nu1;
+      const int ko = (int)(a.other_axis == u0 ? c0 : c1);
+      const int no = a.n[a.other_axis];
+      return (2.0 - 2.0 * cospi(2.0 * ko / (double)no)) * a.inv_h2[1];
+    };
+    // output v at position l of line li (lo: other_term(li) in the scaling pass)
+    auto emit = [&](int li, int l, TR v, double lo) {
       const uint32_t ad = addr(li, l);
-      if (a.mode == kDhtScale) {
-        // frequencies: l along this axis, the line's coordinate along the other cross axis
-        const uint32_t L = l0 + (uint32_t)li;
-        const uint32_t c0 = fdiv(L, a.by_nu1), c1 = L - c0 * nu1;
-        const int ko = (int)(a.other_axis == u0 ? c0 : c1);
-        const int no = a.n[a.other_axis];
-        const double lt = (2.0 - 2.0 * cospi(2.0 * l / (double)n)) * a.inv_h2[0];
-        const double lo = (2.0 - 2.0 * cospi(2.0 * ko / (double)no)) * a.inv_h2[1];
-        v = (TR)((double)v / (a.alpha * (lt + lo) + rho));
-      }
+      if (scale) v = (TR)((double)v / (a.alpha * (lt[l] + lo) + rho));
       if (a.mode == kDhtLast) {
         // z_new = v; u <- u + b - z; c = z - u; residual sums
         const TR zo = dst[ad], bv = b[ad];
@@ -338,10 +345,11 @@ __global__ __launch_bounds__(kDhtBlock) void k_dht(DhtArgs a) {
       for (int q = 0; q < kDhtLines; ++q) {
         const int li = gi * kDhtLines + q;
         if (li >= nl) continue;
+        const double lo = scale ? other_term(li) : 0.0;
         const int nout = (l > 0 && 2 * l != n) ? 2 : 1;
         for (int o = 0; o < nout; ++o) {
-          const int lo = o == 0 ? l : n - l;
-          emit(li, lo, o == 0 ? C[q] + S[q] : C[q] - S[q]);
+          const int lout = o == 0 ? l : n - l;
+          emit(li, lout, o == 0 ? C[q] + S[q] : C[q] - S[q], lo);
         }
       }
     }
@@ -493,10 +501,13 @@ hipError_t launch_dht(const DhtArgs& a0, DType real, hipStream_t s) {
     return record_other([a, real](hipStream_t s2) { return launch_dht(a, real, s2); });
   const int64_t nodes = (int64_t)a.n[0] * a.n[1] * a.n[2];
   const int tag = a.mode + 4 * a.n[a.axis];
+  const int n = a.n[a.axis];
+  const size_t e = real == DType::F64 ? 8 : 4;
+  const size_t lds = (a.mode == kDhtScale ? (size_t)n * 8 : 0) + (size_t)(2 * n + kDhtElems) * e;
   if (real == DType::F64)
-    RGP_LAUNCH_TN(kKindDht, tag, 0, nodes, k_dht<double>, a.nblk, kDhtBlock, 0, s, a);
+    RGP_LAUNCH_TN(kKindDht, tag, 0, nodes, k_dht<double>, a.nblk, kDhtBlock, lds, s, a);
   else if (real == DType::F32)
-    RGP_LAUNCH_TN(kKindDht, tag, 0, nodes, k_dht<float>, a.nblk, kDhtBlock, 0, s, a);
+    RGP_LAUNCH_TN(kKindDht, tag, 0, nodes, k_dht<float>, a.nblk, kDhtBlock, lds, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
