@@ -36,6 +36,7 @@ constexpr int kBpBlock = 256;          // 4 wavefronts, 16 columns per block
 constexpr int kBpColsPerBlock = 16;
 constexpr int kDhtBlock = 256;
 constexpr int kDhtElems = 2048;        // line elements per workgroup (LDS)
+constexpr int kDhtLines = 2;           // lines per Hartley work item (they share the table index)
 
 __device__ __forceinline__ double fmad64(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -314,7 +315,6 @@ __global__ __launch_bounds__(kDhtBlock) void k_dht(DhtArgs a) {
     // H x at frequency l is C + S and at n - l it is C - S, with C and S the sums of x_j times
     // cos and sin of 2 pi j l / n: one pass over j serves both frequencies, and the index j l mod n
     // is shared by the kDhtLines lines of a work item
-    constexpr int kDhtLines = 2;
     const int nh = n / 2 + 1;
     const int ngr = (lpb + kDhtLines - 1) / kDhtLines;   // line pairs of a full tile
     const int ngl = (nl + kDhtLines - 1) / kDhtLines;    // of this tile
@@ -496,7 +496,7 @@ hipError_t launch_dht(const DhtArgs& a0, DType real, hipStream_t s) {
   a.by_n = make_fastdiv((uint32_t)a.n[a.axis]);
   a.by_nu1 = make_fastdiv((uint32_t)a.n[u1]);
   a.by_lpb = make_fastdiv((uint32_t)a.lines_per_block);
-  a.by_ngr = make_fastdiv((uint32_t)((a.lines_per_block + 1) / 2));
+  a.by_ngr = make_fastdiv((uint32_t)((a.lines_per_block + kDhtLines - 1) / kDhtLines));
   if (active_recorder())
     return record_other([a, real](hipStream_t s2) { return launch_dht(a, real, s2); });
   const int64_t nodes = (int64_t)a.n[0] * a.n[1] * a.n[2];
